@@ -1,0 +1,151 @@
+"""Input generators for the vortex-particle workloads.
+
+Every function is seeded (numpy PCG64 ``default_rng``) and returns a dict with
+float32 SoA arrays ``x, y, z, ax, ay, az, sigma`` plus metadata.  Values are
+drawn in float64 and rounded once to float32; consumers that need float64 (the
+oracle) widen those float32 values exactly.
+
+Workload shapes follow the paper's test conditions (Sec. 4.2): a periodic cube
+of side 2*pi, particles on a uniform lattice, Gaussian cores sigma tied to the
+lattice spacing.  The paper's own turbulence initial condition came from an
+external spectral code that is not available; ``turbulence_case`` stands in
+for it with a random-phase solenoidal field of prescribed spectrum, which is
+how the paper describes constructing its validation initial conditions
+(Sec. 2.2).
+"""
+import numpy as np
+
+TWO_PI = 2.0 * np.pi
+
+
+def _pack(x, y, z, ax, ay, az, sigma, **meta):
+    d = dict(
+        x=np.ascontiguousarray(x, dtype=np.float32),
+        y=np.ascontiguousarray(y, dtype=np.float32),
+        z=np.ascontiguousarray(z, dtype=np.float32),
+        ax=np.ascontiguousarray(ax, dtype=np.float32),
+        ay=np.ascontiguousarray(ay, dtype=np.float32),
+        az=np.ascontiguousarray(az, dtype=np.float32),
+        sigma=np.ascontiguousarray(sigma, dtype=np.float32),
+    )
+    d.update(meta)
+    d["n"] = int(d["x"].shape[0])
+    return d
+
+
+def lattice_positions(n, L=TWO_PI):
+    """Cell-centred lattice (i+1/2)h, h=L/n, flattened with index order [i, j, k]
+    (x index slowest).  Returns float64 arrays (x, y, z) and h."""
+    h = L / n
+    c = (np.arange(n, dtype=np.float64) + 0.5) * h
+    X, Y, Z = np.meshgrid(c, c, c, indexing="ij")
+    return X.ravel(), Y.ravel(), Z.ravel(), h
+
+
+def taylor_green_case(n=32, L=TWO_PI, core=1.5, periodic=False):
+    """Plain tiny configuration: Taylor-Green vorticity sampled on an n^3 lattice.
+
+    omega = (-cos x sin y sin z, -sin x cos y sin z, 2 sin x sin y cos z) is the
+    curl of u = (sin x cos y cos z, -cos x sin y cos z, 0); strengths are
+    alpha = omega(x_j) h^3 and every core is sigma = core*h."""
+    x, y, z, h = lattice_positions(n, L)
+    wx = -np.cos(x) * np.sin(y) * np.sin(z)
+    wy = -np.sin(x) * np.cos(y) * np.sin(z)
+    wz = 2.0 * np.sin(x) * np.sin(y) * np.cos(z)
+    v = h ** 3
+    sig = np.full(x.shape, core * h)
+    return _pack(x, y, z, wx * v, wy * v, wz * v, sig, h=h, L=L, lattice_n=n,
+                 periodic=periodic, box_lo=(0.0, 0.0, 0.0), kind="taylor_green")
+
+
+def turbulence_case(n=128, seed=2, k0=4.0, L=TWO_PI, core=1.5):
+    """Isotropic-turbulence-shaped lattice field.
+
+    A random-phase solenoidal velocity is drawn in Fourier space with energy
+    spectrum E(k) ~ k^4 exp(-2 (k/k0)^2): complex Gaussian modes projected
+    onto the plane normal to k, Nyquist modes dropped, scaled so the sampled
+    field has u_rms = 1.  Vorticity omega = curl u is evaluated spectrally at
+    the cell centres (i+1/2)h, strengths are alpha_j = omega(x_j) h^3 with the
+    float64 mean removed (a periodic vorticity field has zero mean), then
+    rounded to float32.  Box [0, L)^3, cores sigma = core*h."""
+    rng = np.random.default_rng(seed)
+    h = L / n
+    kf = np.fft.fftfreq(n, d=1.0 / n)  # integer wavenumbers, centred order
+    KX, KY, KZ = np.meshgrid(kf, kf, kf, indexing="ij")
+    k2 = KX ** 2 + KY ** 2 + KZ ** 2
+    kmag = np.sqrt(k2)
+    nyq = (np.abs(KX) == n // 2) | (np.abs(KY) == n // 2) | (np.abs(KZ) == n // 2)
+    xi = (rng.standard_normal((3,) + k2.shape) + 1j * rng.standard_normal((3,) + k2.shape))
+    kk = np.where(k2 == 0, 1.0, k2)
+    kdotxi = (KX * xi[0] + KY * xi[1] + KZ * xi[2]) / kk
+    xi[0] -= KX * kdotxi
+    xi[1] -= KY * kdotxi
+    xi[2] -= KZ * kdotxi
+    spec = kmag ** 4 * np.exp(-2.0 * (kmag / k0) ** 2)
+    amp = np.sqrt(spec / (8.0 * np.pi * np.where(k2 == 0, 1.0, k2)))
+    amp[(k2 == 0) | nyq] = 0.0
+    uh = xi * amp
+    del xi, kdotxi
+    # evaluate at cell centres: phase shift by h/2 in each direction
+    kw = TWO_PI / L
+    shift = np.exp(1j * kw * (KX + KY + KZ) * (0.5 * h))
+    u = np.real(np.fft.ifftn(uh * shift, axes=(1, 2, 3)))
+    urms = np.sqrt(np.mean(np.sum(u ** 2, axis=0)) / 3.0)
+    uh /= urms
+    # omega_hat = i k x u_hat  (k in physical units)
+    wxh = 1j * kw * (KY * uh[2] - KZ * uh[1])
+    wyh = 1j * kw * (KZ * uh[0] - KX * uh[2])
+    wzh = 1j * kw * (KX * uh[1] - KY * uh[0])
+    del uh
+    w = [np.real(np.fft.ifftn(c * shift)) for c in (wxh, wyh, wzh)]
+    del wxh, wyh, wzh, shift
+    v = h ** 3
+    a = [(wi.ravel() * v) for wi in w]
+    a = [ai - ai.mean() for ai in a]
+    x, y, z, _ = lattice_positions(n, L)
+    sig = np.full(x.shape, core * h)
+    return _pack(x, y, z, a[0], a[1], a[2], sig, h=h, L=L, lattice_n=n,
+                 periodic=True, box_lo=(0.0, 0.0, 0.0), kind="turbulence", seed=seed)
+
+
+def ring_case(nb, rng, radius=1.0, core=0.1, jitter=0.02, circulation=1.0):
+    """One Gaussian vortex-ring cloud in the z=0 plane, circulation Gamma.
+
+    phi_j = 2 pi j / N, x_j = R (cos phi_j, sin phi_j, 0) + U(-jitter, jitter)^3,
+    alpha_j = Gamma (2 pi R / N) (-sin phi_j, cos phi_j, 0), sigma_j = core."""
+    phi = TWO_PI * np.arange(nb, dtype=np.float64) / nb
+    j = rng.uniform(-jitter, jitter, size=(3, nb))
+    x = radius * np.cos(phi) + j[0]
+    y = radius * np.sin(phi) + j[1]
+    z = j[2]
+    s = circulation * TWO_PI * radius / nb
+    ax = -s * np.sin(phi)
+    ay = s * np.cos(phi)
+    az = np.zeros(nb)
+    sig = np.full(nb, core)
+    return _pack(x, y, z, ax, ay, az, sig, periodic=False, kind="ring")
+
+
+def ring_batch(nprob=512, seed=4, nmin=1024, nmax=65536):
+    """Batch of independent free-space ring problems with log-uniform sizes.
+
+    Returns (list_of_problem_dicts, offsets) where offsets[b] is the first
+    particle of problem b in the concatenated arrays."""
+    rng = np.random.default_rng(seed)
+    sizes = np.rint(np.exp(rng.uniform(np.log(nmin), np.log(nmax), size=nprob))).astype(np.int64)
+    probs = [ring_case(int(nb), rng) for nb in sizes]
+    offsets = np.zeros(nprob + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(sizes)
+    return probs, offsets
+
+
+def random_cloud(n, seed=0, L=1.0, core=0.05, lo=(0.0, 0.0, 0.0), zero_mean=False, periodic=False):
+    """Uniform random particles in [lo, lo+L)^3 with Gaussian-random strengths."""
+    rng = np.random.default_rng(seed)
+    p = rng.uniform(0.0, L, size=(3, n)) + np.asarray(lo, dtype=np.float64)[:, None]
+    a = rng.standard_normal((3, n)) * (L ** 3 / max(n, 1))
+    if zero_mean:
+        a -= a.mean(axis=1, keepdims=True)
+    sig = np.full(n, core)
+    return _pack(p[0], p[1], p[2], a[0], a[1], a[2], sig, L=L, periodic=periodic,
+                 box_lo=tuple(lo), kind="random")
