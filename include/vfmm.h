@@ -1,0 +1,184 @@
+/*
+ * vfmm.h -- C ABI of the MI355X (gfx950) vortex-particle FMM library.
+ *
+ * One call of fmm_build + fmm_evaluate computes, for N vortex particles with
+ * positions x_i, strengths alpha_i and Gaussian cores sigma_i:
+ *
+ *   u_i       = sum_j q(rho) alpha_j x r,                  Biot-Savart law, Eq. (1)
+ *   dalpha_i  = sum_j grad(alpha_j x grad G g_sigma) . alpha_i,  stretching, Eq. (3)
+ *
+ * with r = x_i - x_j, G = 1/(4 pi rho) and the Gaussian cutoff g_sigma of
+ * Eq. (2) (Yokota, Barba, Narumi, Yasuoka, "Petascale turbulence simulation
+ * using a highly parallel fast multipole method on GPUs", Sec. 2.1), using a
+ * Morton-sorted octree, a dual tree traversal (Sec. 3.3, Algorithms 1-2), the
+ * spherical-harmonic expansions P2M/M2M/M2L/L2L/L2P of the three Laplace
+ * potentials psi_m = sum_j alpha_j,m G (Sec. 3.1) and the near-field P2P pass,
+ * optionally in a periodic cube with image cells (Sec. 3.5).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Array pointers are DEVICE pointers to contiguous float32 arrays of length
+ *   n (structure of arrays), owned by the caller.  The library never frees
+ *   them and never keeps them past the call.
+ * - All work is enqueued on the HIP stream given to vfmm_create and is
+ *   asynchronous with respect to the host, except where a function says it
+ *   synchronises.  fmm_build synchronises the stream a few times (it reads
+ *   tree and list sizes back to size its buffers); fmm_evaluate does not.
+ * - Outputs are in the caller's particle order.  Output arrays must not alias
+ *   input arrays or each other (VFMM_EINVAL).
+ * - Errors are reported as status codes; nothing aborts or throws across this
+ *   boundary.  vfmm_last_error() returns a text description of the last
+ *   failure on that context.
+ * - The context owns the tree, expansions, interaction lists and scratch space
+ *   in device memory.  These only grow; vfmm_destroy frees them.
+ * - A context is not thread safe; calls on one context must not overlap.
+ */
+#ifndef VFMM_H
+#define VFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vfmm_ctx vfmm_ctx;
+
+typedef enum {
+    VFMM_OK = 0,
+    VFMM_EINVAL = -1,  /* bad argument: null pointer, n < 0, aliasing, unsupported parameter */
+    VFMM_ENOMEM = -2,  /* device allocation failed                                         */
+    VFMM_EDEPTH = -3,  /* reserved: tree deeper than 21 levels (64-bit Morton keys, Sec. 3.2) */
+    VFMM_EDOMAIN = -4, /* periodic: a position outside [lo, lo+len), or a non-finite input    */
+    VFMM_ESTATE = -5,  /* fmm_evaluate without a matching fmm_build                            */
+    VFMM_EHIP = -6     /* a HIP runtime call failed                                            */
+} vfmm_status;
+
+/* Stretching readings of Eq. (3). */
+enum { VFMM_SCHEME_TRANSPOSE = 0, /* (dalpha)_k = sum_l (du_l/dx_k) alpha_l : Eq. (3) as printed */
+       VFMM_SCHEME_CLASSICAL = 1  /* (dalpha)_l = sum_k alpha_k du_l/dx_k : "omega . grad u"     */
+};
+
+typedef struct vfmm_params {
+    int32_t p;           /* expansion degree n = 0..p (supported: 4, 6, 8, 10, 12)  default 10  */
+    int32_t ncrit;       /* split a cell while it holds more than ncrit particles  default 64  */
+    float theta;         /* multipole acceptance (R_A + R_B) < theta * D           default 0.5 */
+    float sigma_gap;     /* M2L also requires D - R_A - R_B >= sigma_gap * sigma_max   default 5 */
+    int32_t periodic;    /* 0 free space, 1 periodic cube [box_lo, box_lo + box_len)^3         */
+    int32_t images;      /* periodic: K, image cells cover |n|_inf <= (3^K - 1)/2   default 3  */
+    double box_lo[3];    /* periodic cube corner                                               */
+    double box_len;      /* periodic cube side (> 0 when periodic)                             */
+    int32_t scheme;      /* VFMM_SCHEME_TRANSPOSE (default) or VFMM_SCHEME_CLASSICAL          */
+    int32_t kahan;       /* 1: compensated per-target sums in P2P (default 0: blocked sums)    */
+    int32_t zero_mean;   /* periodic: subtract (1/3V) sum x_j x alpha_j (default 1)           */
+    int32_t direct;      /* 1: all-pairs P2P without a tree (test mode; free space only)      */
+} vfmm_params;
+
+/* Per-phase device times of the last fmm_build / fmm_evaluate, in milliseconds,
+ * measured with HIP events on the library stream. */
+typedef struct vfmm_timings {
+    float bounds_sort_ms;   /* bounds, Morton keys, radix sort, gather            */
+    float tree_ms;          /* octree levels, cell geometry                       */
+    float traverse_ms;      /* dual traversal + interaction-list build            */
+    float p2m_m2m_ms;       /* P2M at leaves, M2M up the tree                     */
+    float lattice_ms;       /* periodic image lattice into the root local        */
+    float m2l_ms;           /* all M2L translations                               */
+    float l2l_l2p_ms;       /* L2L down the tree, L2P at leaves                   */
+    float p2p_ms;           /* near field P2P, fused with the output scatter      */
+    float build_ms;         /* whole fmm_build                                    */
+    float evaluate_ms;      /* whole fmm_evaluate                                 */
+} vfmm_timings;
+
+/* Sizes of the current tree and lists (valid after fmm_build). */
+typedef struct vfmm_stats {
+    int64_t n;              /* particles                                          */
+    int32_t ncells;         /* octree cells                                       */
+    int32_t nleaves;        /* leaf cells                                         */
+    int32_t depth;          /* deepest level (root = 0)                           */
+    int32_t p2p_entries;    /* (target leaf, source leaf, image) triples          */
+    int64_t p2p_pairs;      /* particle pairs evaluated by P2P (self pairs incl.) */
+    int64_t m2l_entries;    /* (target cell, source cell, image) translations     */
+    int32_t p2p_blocks;     /* P2P work items (<= 64 targets each)                */
+    int32_t images_traversed; /* periodic image cells started in the traversal    */
+    double sum_alpha[3];    /* float64 sum of alpha (set by fmm_evaluate)         */
+    double sigma_min, sigma_max;
+} vfmm_stats;
+
+/* Fill *p with the defaults listed above (free space). */
+void vfmm_default_params(vfmm_params *p);
+
+/* Create a context bound to hip_stream (a hipStream_t; NULL = default stream)
+ * on the current HIP device.  *out receives the context.  The parameters are
+ * copied.  Errors: VFMM_EINVAL for a null out or unsupported parameters
+ * (p not in the supported set, ncrit < 1, theta not in (0, 1), periodic with
+ * box_len <= 0, images < 1, direct together with periodic). */
+vfmm_status vfmm_create(const vfmm_params *params, void *hip_stream, vfmm_ctx **out);
+
+/* Replace the parameters of an existing context (same validation as
+ * vfmm_create).  Invalidates the current tree. */
+vfmm_status vfmm_set_params(vfmm_ctx *ctx, const vfmm_params *params);
+
+/* Build the octree and interaction lists for n particles (Sec. 3.2-3.3).
+ * x, y, z, sigma: device float32[n].  The tree depends on positions only; the
+ * cores enter the separation test (sigma_gap * max sigma).  n = 0 is allowed
+ * (evaluate then writes nothing).  Errors: VFMM_EINVAL (null pointer, n < 0,
+ * n >= 2^31), VFMM_EDOMAIN (non-finite input; periodic position outside the
+ * cube), VFMM_ENOMEM, VFMM_EHIP. */
+vfmm_status fmm_build(vfmm_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
+                      const float *sigma);
+
+/* Evaluate u (Eq. 1) and dalpha/dt (Eq. 3, reading ctx scheme) at every
+ * particle, using the tree of the last fmm_build, which must have been made
+ * from the same n and positions (the library checks n only).  Inputs and
+ * outputs are device float32[n].  Periodic with zero_mean: u is the zero-mean
+ * periodic field (the cube-ordered image sum minus (1/3V) sum x_j x alpha_j).
+ * Errors: VFMM_ESTATE (no build, or n differs), VFMM_EINVAL (null pointer,
+ * aliasing), VFMM_EHIP. */
+vfmm_status fmm_evaluate(vfmm_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
+                         const float *ax, const float *ay, const float *az, const float *sigma,
+                         float *ux, float *uy, float *uz, float *dax, float *day, float *daz);
+
+/* One Heun (RK2) step of the vortex-particle system, in place:
+ *   stage 1: build + evaluate at (x, alpha);  x* = x + dt u, alpha* = alpha + dt dalpha
+ *   stage 2: build + evaluate at (x*, alpha*); x += dt/2 (u + u*), alpha += dt/2 (dalpha + dalpha*)
+ *   sigma^2 += 2 nu dt                                                       (Eq. 4)
+ * Periodic positions are wrapped back into the cube after each stage.  Both
+ * stages re-sort and rebuild the tree.  Scratch for the stage values is owned
+ * by the context.  Errors as fmm_build / fmm_evaluate. */
+vfmm_status rk_step(vfmm_ctx *ctx, int64_t n, float dt, float nu, float *x, float *y, float *z,
+                    float *ax, float *ay, float *az, float *sigma);
+
+/* Copy the per-phase times of the last build/evaluate to *out.  Synchronises
+ * the context stream.  Errors: VFMM_EINVAL for null arguments. */
+vfmm_status vfmm_get_timings(vfmm_ctx *ctx, vfmm_timings *out);
+
+/* Copy the tree/list sizes of the last build to *out.  Synchronises the
+ * context stream.  Errors: VFMM_EINVAL for null arguments. */
+vfmm_status vfmm_get_stats(vfmm_ctx *ctx, vfmm_stats *out);
+
+/* Copy the interaction lists of the last build to HOST buffers, for checking
+ * that the traversal covers every (target, source, image) particle pair once.
+ * For each list entry k: target cell, source cell, image code
+ * (code = (nx+B) + (2B+1)((ny+B) + (2B+1)(nz+B)) with B = 1 for images = 1 and
+ * B = 4 otherwise; B = 0 in free space).  Cells are described by
+ * cell_start/cell_count (ranges in the library's sorted order) and perm maps
+ * sorted position -> caller index.  Pass NULL for any array not wanted;
+ * sizes come from vfmm_get_stats (ncells, p2p_entries, m2l_entries, n).
+ * Synchronises.  Errors: VFMM_ESTATE without a build. */
+vfmm_status vfmm_copy_lists(vfmm_ctx *ctx, int32_t *p2p_tgt, int32_t *p2p_src, int32_t *p2p_img,
+                            int32_t *m2l_tgt, int32_t *m2l_src, int32_t *m2l_img,
+                            int32_t *cell_start, int32_t *cell_count, int32_t *perm);
+
+/* Text of the last error on ctx (never NULL; "" when none).  Valid until the
+ * next call on ctx.  A NULL ctx returns the last vfmm_create failure. */
+const char *vfmm_last_error(const vfmm_ctx *ctx);
+
+/* Free every device and host resource of ctx (NULL is ignored).
+ * Synchronises the context stream first. */
+void vfmm_destroy(vfmm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VFMM_H */

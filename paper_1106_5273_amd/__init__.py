@@ -1,0 +1,197 @@
+"""MI355X vortex-particle FMM: Python binding of the C ABI in include/vfmm.h.
+
+This module only marshals arguments: it passes device pointers of torch CUDA
+tensors and the current HIP stream to libvfmm.so (built in-tree by
+``paper_1106_5273_amd.build``).  Every step of the computation runs in the
+library's HIP kernels.  If the library is missing this import fails loudly;
+there is no CPU fallback.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvfmm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libvfmm.so not found at %s: build it with `python -m paper_1106_5273_amd.build` "
+                      "(or __graft_entry__.build())" % LIB_PATH)
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+VFMM_OK = 0
+STATUS = {0: "VFMM_OK", -1: "VFMM_EINVAL", -2: "VFMM_ENOMEM", -3: "VFMM_EDEPTH", -4: "VFMM_EDOMAIN",
+          -5: "VFMM_ESTATE", -6: "VFMM_EHIP"}
+SCHEME_TRANSPOSE = 0
+SCHEME_CLASSICAL = 1
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("ncrit", ctypes.c_int32), ("theta", ctypes.c_float),
+                ("sigma_gap", ctypes.c_float), ("periodic", ctypes.c_int32), ("images", ctypes.c_int32),
+                ("box_lo", ctypes.c_double * 3), ("box_len", ctypes.c_double), ("scheme", ctypes.c_int32),
+                ("kahan", ctypes.c_int32), ("zero_mean", ctypes.c_int32), ("direct", ctypes.c_int32)]
+
+
+class Timings(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_float) for n in ("bounds_sort_ms", "tree_ms", "traverse_ms", "p2m_m2m_ms",
+                                               "lattice_ms", "m2l_ms", "l2l_l2p_ms", "p2p_ms", "build_ms",
+                                               "evaluate_ms")]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("ncells", ctypes.c_int32), ("nleaves", ctypes.c_int32),
+                ("depth", ctypes.c_int32), ("p2p_entries", ctypes.c_int32), ("p2p_pairs", ctypes.c_int64),
+                ("m2l_entries", ctypes.c_int64), ("p2p_blocks", ctypes.c_int32),
+                ("images_traversed", ctypes.c_int32), ("sum_alpha", ctypes.c_double * 3),
+                ("sigma_min", ctypes.c_double), ("sigma_max", ctypes.c_double)]
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_lib.vfmm_default_params.argtypes = [ctypes.POINTER(Params)]
+_lib.vfmm_default_params.restype = None
+_lib.vfmm_create.argtypes = [ctypes.POINTER(Params), _vp, ctypes.POINTER(_vp)]
+_lib.vfmm_set_params.argtypes = [_vp, ctypes.POINTER(Params)]
+_lib.fmm_build.argtypes = [_vp, _i64] + [_vp] * 4
+_lib.fmm_evaluate.argtypes = [_vp, _i64] + [_vp] * 13
+_lib.rk_step.argtypes = [_vp, _i64, ctypes.c_float, ctypes.c_float] + [_vp] * 7
+_lib.vfmm_get_timings.argtypes = [_vp, ctypes.POINTER(Timings)]
+_lib.vfmm_get_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
+_lib.vfmm_copy_lists.argtypes = [_vp] + [_i32p] * 9
+_lib.vfmm_last_error.argtypes = [_vp]
+_lib.vfmm_last_error.restype = ctypes.c_char_p
+_lib.vfmm_destroy.argtypes = [_vp]
+_lib.vfmm_destroy.restype = None
+for _f in ("vfmm_create", "vfmm_set_params", "fmm_build", "fmm_evaluate", "rk_step", "vfmm_get_timings",
+           "vfmm_get_stats", "vfmm_copy_lists"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+EXPORTED = ("vfmm_default_params", "vfmm_create", "vfmm_set_params", "fmm_build", "fmm_evaluate", "rk_step",
+            "vfmm_get_timings", "vfmm_get_stats", "vfmm_copy_lists", "vfmm_last_error", "vfmm_destroy")
+
+
+class VfmmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+def default_params(**kw):
+    p = Params()
+    _lib.vfmm_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if k == "box_lo":
+            for d in range(3):
+                p.box_lo[d] = float(v[d])
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _check_tensor(t, n, name):
+    import torch
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+        raise ValueError("%s must be a contiguous float32 CUDA tensor of %d elements" % (name, n))
+
+
+class Context:
+    """Owns one vfmm_ctx bound to a torch stream (default: the current stream)."""
+
+    def __init__(self, params=None, stream=None, **kw):
+        import torch
+        if params is None:
+            params = default_params(**kw)
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        st = _lib.vfmm_create(ctypes.byref(params), ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(h))
+        if st != VFMM_OK:
+            raise VfmmError(st, _lib.vfmm_last_error(None).decode())
+        self._h = h
+        self.params = params
+
+    def _raise(self, st):
+        if st != VFMM_OK:
+            raise VfmmError(st, _lib.vfmm_last_error(self._h).decode())
+
+    def set_params(self, params=None, **kw):
+        if params is None:
+            params = default_params(**kw)
+        self._raise(_lib.vfmm_set_params(self._h, ctypes.byref(params)))
+        self.params = params
+
+    def build(self, x, y, z, sigma):
+        n = x.numel()
+        for t, nm in ((x, "x"), (y, "y"), (z, "z"), (sigma, "sigma")):
+            _check_tensor(t, n, nm)
+        self._raise(_lib.fmm_build(self._h, n, _ptr(x), _ptr(y), _ptr(z), _ptr(sigma)))
+
+    def evaluate(self, x, y, z, ax, ay, az, sigma, out=None):
+        """Returns (ux, uy, uz, dax, day, daz) as new tensors unless ``out`` is given."""
+        import torch
+        n = x.numel()
+        for t, nm in ((x, "x"), (y, "y"), (z, "z"), (ax, "ax"), (ay, "ay"), (az, "az"), (sigma, "sigma")):
+            _check_tensor(t, n, nm)
+        if out is None:
+            out = tuple(torch.empty(n, dtype=torch.float32, device=x.device) for _ in range(6))
+        args = [_ptr(t) for t in (x, y, z, ax, ay, az, sigma)] + [_ptr(t) for t in out]
+        self._raise(_lib.fmm_evaluate(self._h, n, *args))
+        return out
+
+    def rk_step(self, dt, nu, x, y, z, ax, ay, az, sigma):
+        n = x.numel()
+        for t, nm in ((x, "x"), (y, "y"), (z, "z"), (ax, "ax"), (ay, "ay"), (az, "az"), (sigma, "sigma")):
+            _check_tensor(t, n, nm)
+        self._raise(_lib.rk_step(self._h, n, float(dt), float(nu), *[_ptr(t) for t in (x, y, z, ax, ay, az, sigma)]))
+
+    def timings(self):
+        t = Timings()
+        self._raise(_lib.vfmm_get_timings(self._h, ctypes.byref(t)))
+        return {f: getattr(t, f) for f, _ in Timings._fields_}
+
+    def stats(self):
+        s = Stats()
+        self._raise(_lib.vfmm_get_stats(self._h, ctypes.byref(s)))
+        d = {f: getattr(s, f) for f, _ in Stats._fields_}
+        d["sum_alpha"] = tuple(s.sum_alpha)
+        return d
+
+    def lists(self):
+        """Host copies of the interaction lists (numpy int32 arrays)."""
+        import numpy as np
+        st = self.stats()
+        nc, npp, nm, n = st["ncells"], st["p2p_entries"], st["m2l_entries"], st["n"]
+        a = {k: np.zeros(sz, dtype=np.int32) for k, sz in (("p2p_tgt", npp), ("p2p_src", npp), ("p2p_img", npp),
+                                                            ("m2l_tgt", nm), ("m2l_src", nm), ("m2l_img", nm),
+                                                            ("cell_start", nc), ("cell_count", nc), ("perm", n))}
+        ptrs = [a[k].ctypes.data_as(_i32p) for k in ("p2p_tgt", "p2p_src", "p2p_img", "m2l_tgt", "m2l_src",
+                                                     "m2l_img", "cell_start", "cell_count", "perm")]
+        self._raise(_lib.vfmm_copy_lists(self._h, *ptrs))
+        return a
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.vfmm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def case_to_device(case, device="cuda"):
+    """float32 SoA arrays of a workload dict -> tuple of CUDA tensors (x, y, z, ax, ay, az, sigma)."""
+    import torch
+    return tuple(torch.from_numpy(case[k]).to(device) for k in ("x", "y", "z", "ax", "ay", "az", "sigma"))

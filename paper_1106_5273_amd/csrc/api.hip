@@ -1,0 +1,493 @@
+// C ABI of the library and the host orchestration of one build / evaluate.
+#include <cmath>
+#include <cstring>
+
+#include "ctx.h"
+
+namespace vfmm {
+
+static std::string g_create_error;
+
+void Ctx::release_all() {
+    DevBuf *bufs[] = {&bpart, &bres, &keyA, &keyB, &valA, &valB, &hist, &scanA, &scanB, &scanC, &perm, &rec,
+                      &c_start, &c_count, &c_parent, &c_child, &c_nchild, &c_level, &c_geo, &c_rad, &c_lo, &c_hi,
+                      &c_tmp, &leaves, &frA, &frB, &tcnt, &m2l_raw, &p2p_raw, &lkey, &lkey2, &lval, &lval2,
+                      &m2l_off, &m2l_src, &p2p_off, &p2p_ent, &blocks, &pairs64, &Mexp, &Lexp, &lat_op, &far_u,
+                      &far_da, &dsurf, &rk};
+    for (DevBuf *b : bufs) b->release();
+    if (ev_ok)
+        for (auto &e : ev) (void)hipEventDestroy(e);
+    ev_ok = false;
+}
+
+static bool supported_p(int p) { return p == 4 || p == 6 || p == 8 || p == 10 || p == 12; }
+
+static void validate(const vfmm_params &p) {
+    if (!supported_p(p.p)) throw Error{VFMM_EINVAL, "p must be one of 4, 6, 8, 10, 12"};
+    if (p.ncrit < 1) throw Error{VFMM_EINVAL, "ncrit must be >= 1"};
+    if (!(p.theta > 0.f && p.theta < 1.f)) throw Error{VFMM_EINVAL, "theta must be in (0, 1)"};
+    if (!(p.sigma_gap >= 0.f)) throw Error{VFMM_EINVAL, "sigma_gap must be >= 0"};
+    if (p.scheme != VFMM_SCHEME_TRANSPOSE && p.scheme != VFMM_SCHEME_CLASSICAL)
+        throw Error{VFMM_EINVAL, "scheme must be VFMM_SCHEME_TRANSPOSE or VFMM_SCHEME_CLASSICAL"};
+    if (p.periodic) {
+        if (!(p.box_len > 0.0) || !std::isfinite(p.box_len)) throw Error{VFMM_EINVAL, "periodic box_len must be > 0"};
+        if (p.images < 1 || p.images > 12) throw Error{VFMM_EINVAL, "images must be in [1, 12]"};
+        if (p.direct) throw Error{VFMM_EINVAL, "direct mode is free space only"};
+    }
+}
+
+static void set_params(Ctx &c, const vfmm_params &p) {
+    validate(p);
+    c.prm = p;
+    c.built = false;
+    if (p.periodic) {
+        c.img_B = p.images <= 1 ? 1 : 4;
+    } else {
+        c.img_B = 0;
+    }
+    const int W = 2 * c.img_B + 1;
+    c.img_codes = W * W * W;
+}
+
+static vfmm_status fail(Ctx *c, const Error &e) {
+    if (c) c->err = e.msg;
+    return e.st;
+}
+
+static void ensure_events(Ctx &c) {
+    if (c.ev_ok) return;
+    for (auto &e : c.ev) VFMM_HIP(hipEventCreate(&e));
+    c.ev_ok = true;
+}
+
+static float ev_ms(Ctx &c, int a, int b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c.ev[a], c.ev[b]) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0.f;
+    }
+    return ms;
+}
+
+static void upload_lattice(Ctx &c) {
+    if (!c.prm.periodic || c.prm.images < 3) return;
+    if (c.lat_p == c.prm.p && c.lat_K == c.prm.images) return;
+    std::vector<double> op;
+    lattice_operator_host(c.prm.p, c.prm.images, op);
+    std::vector<float> f(op.size());
+    for (size_t i = 0; i < op.size(); ++i) f[i] = (float)op[i];
+    c.lat_op.ensure(sizeof(float) * f.size());
+    VFMM_HIP(hipMemcpyAsync(c.lat_op.ptr, f.data(), sizeof(float) * f.size(), hipMemcpyHostToDevice, c.stream));
+    VFMM_HIP(hipStreamSynchronize(c.stream));
+    c.lat_p = c.prm.p;
+    c.lat_K = c.prm.images;
+}
+
+static void do_build(Ctx &c, int64_t n, const float *x, const float *y, const float *z, const float *sigma) {
+    ensure_events(c);
+    c.built = false;
+    hipStream_t s = c.stream;
+    VFMM_HIP(hipEventRecord(c.ev[2 * PH_NUM], s));
+    VFMM_HIP(hipEventRecord(c.ev[2 * PH_BOUNDS_SORT], s));
+    c.n = n;
+    if (n == 0) {
+        c.ncells = c.nleaves = c.n_p2p = c.n_blocks = 0;
+        c.n_m2l = c.p2p_pairs = 0;
+        c.built = true;
+        return;
+    }
+    compute_bounds(c, n, x, y, z, sigma, nullptr, nullptr, nullptr, false);
+    VFMM_HIP(hipMemcpyAsync(&c.hb, c.bres.ptr, sizeof(Bounds), hipMemcpyDeviceToHost, s));
+    VFMM_HIP(hipStreamSynchronize(s));
+    if (c.hb.nonfinite) throw Error{VFMM_EDOMAIN, "non-finite position or non-positive core"};
+    if (c.prm.periodic && c.hb.outside) throw Error{VFMM_EDOMAIN, "position outside the periodic cube"};
+    if (c.hb.sig_max > c.hb.sig_min * (1.0 + 1e-6))
+        throw Error{VFMM_EINVAL, "cores must be uniform (variable sigma is not supported by this build)"};
+    c.sigma_uniform = (float)c.hb.sig_max;
+    if (c.prm.direct) {
+        c.built = true;
+        return;
+    }
+    if (c.prm.periodic) {
+        for (int d = 0; d < 3; ++d) c.box.lo[d] = (float)c.prm.box_lo[d];
+        c.box.len = (float)c.prm.box_len;
+    } else {
+        double len = 0.0, ctr[3];
+        for (int d = 0; d < 3; ++d) {
+            len = std::max(len, c.hb.hi[d] - c.hb.lo[d]);
+            ctr[d] = 0.5 * (c.hb.lo[d] + c.hb.hi[d]);
+        }
+        len = len * (1.0 + 1e-5) + 1e-30 + 1e-6 * std::max({std::fabs(ctr[0]), std::fabs(ctr[1]), std::fabs(ctr[2])});
+        if (len <= 0) len = 1.0;
+        for (int d = 0; d < 3; ++d) c.box.lo[d] = (float)(ctr[d] - 0.5 * len);
+        c.box.len = (float)len;
+    }
+    upload_lattice(c);
+    build_tree(c, n, x, y, z, sigma);
+    VFMM_HIP(hipEventRecord(c.ev[2 * PH_TRAVERSE], s));
+    traverse_and_lists(c);
+    VFMM_HIP(hipEventRecord(c.ev[2 * PH_TRAVERSE + 1], s));
+    VFMM_HIP(hipEventRecord(c.ev[2 * PH_NUM + 1], s));
+    c.build_timed = true;
+    c.built = true;
+}
+
+static void do_evaluate(Ctx &c, int64_t n, const float *x, const float *y, const float *z, const float *ax,
+                        const float *ay, const float *az, const float *sigma, float *ux, float *uy, float *uz,
+                        float *dax, float *day, float *daz) {
+    ensure_events(c);
+    hipStream_t s = c.stream;
+    VFMM_HIP(hipEventRecord(c.ev[2 * PH_NUM + 2], s));
+    if (n == 0) {
+        VFMM_HIP(hipEventRecord(c.ev[2 * PH_NUM + 3], s));
+        return;
+    }
+    compute_bounds(c, n, x, y, z, sigma, ax, ay, az, true);
+    if (c.prm.direct) {
+        direct_all_pairs(c, x, y, z, ax, ay, az, sigma, ux, uy, uz, dax, day, daz);
+    } else {
+        gather_strengths(c, ax, ay, az, sigma);
+        far_field(c);
+        p2p_and_finalize(c, ux, uy, uz, dax, day, daz);
+    }
+    VFMM_HIP(hipEventRecord(c.ev[2 * PH_NUM + 3], s));
+    c.eval_timed = true;
+}
+
+// ---------------------------------------------------------------------------
+// rk_step helpers
+// ---------------------------------------------------------------------------
+struct RkArgs {
+    int64_t n;
+    float dt, nu;
+    int periodic;
+    float lo[3], len;
+};
+
+__device__ inline float wrap(float v, float lo, float len) {
+    float t = v - lo;
+    t -= floorf(t / len) * len;
+    if (t >= len) t -= len;
+    if (t < 0.f) t += len;
+    return lo + t;
+}
+
+// stage 1 predictor: xs = x + dt u1, as = a + dt da1, ss = sqrt(s^2 + 2 nu dt)
+__global__ __launch_bounds__(256) void k_rk_pred(RkArgs A, const float *x, const float *y, const float *z,
+                                                 const float *ax, const float *ay, const float *az, const float *s,
+                                                 const float *U, float *X) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= A.n) return;
+    const int64_t n = A.n;
+    float p[3] = {x[i] + A.dt * U[i], y[i] + A.dt * U[n + i], z[i] + A.dt * U[2 * n + i]};
+    if (A.periodic)
+        for (int d = 0; d < 3; ++d) p[d] = wrap(p[d], A.lo[d], A.len);
+    X[i] = p[0];
+    X[n + i] = p[1];
+    X[2 * n + i] = p[2];
+    X[3 * n + i] = ax[i] + A.dt * U[3 * n + i];
+    X[4 * n + i] = ay[i] + A.dt * U[4 * n + i];
+    X[5 * n + i] = az[i] + A.dt * U[5 * n + i];
+    X[6 * n + i] = sqrtf(s[i] * s[i] + 2.f * A.nu * A.dt);
+}
+
+// corrector: x += dt/2 (u1 + u2) etc.
+__global__ __launch_bounds__(256) void k_rk_corr(RkArgs A, float *x, float *y, float *z, float *ax, float *ay,
+                                                 float *az, float *s, const float *U, const float *U2) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= A.n) return;
+    const int64_t n = A.n;
+    const float h = 0.5f * A.dt;
+    float p[3] = {x[i] + h * (U[i] + U2[i]), y[i] + h * (U[n + i] + U2[n + i]), z[i] + h * (U[2 * n + i] + U2[2 * n + i])};
+    if (A.periodic)
+        for (int d = 0; d < 3; ++d) p[d] = wrap(p[d], A.lo[d], A.len);
+    x[i] = p[0];
+    y[i] = p[1];
+    z[i] = p[2];
+    ax[i] += h * (U[3 * n + i] + U2[3 * n + i]);
+    ay[i] += h * (U[4 * n + i] + U2[4 * n + i]);
+    az[i] += h * (U[5 * n + i] + U2[5 * n + i]);
+    s[i] = sqrtf(s[i] * s[i] + 2.f * A.nu * A.dt);
+}
+
+static void do_rk(Ctx &c, int64_t n, float dt, float nu, float *x, float *y, float *z, float *ax, float *ay, float *az,
+                  float *sigma) {
+    if (n == 0) return;
+    c.rk.ensure(sizeof(float) * 19 * (size_t)n);
+    float *U1 = c.rk.as<float>();       // 6n: u1, da1
+    float *X = U1 + 6 * n;              // 7n: predictor state
+    float *U2 = X + 7 * n;              // 6n: u2, da2
+    RkArgs A{};
+    A.n = n;
+    A.dt = dt;
+    A.nu = nu;
+    A.periodic = c.prm.periodic;
+    for (int d = 0; d < 3; ++d) A.lo[d] = (float)c.prm.box_lo[d];
+    A.len = (float)c.prm.box_len;
+    do_build(c, n, x, y, z, sigma);
+    do_evaluate(c, n, x, y, z, ax, ay, az, sigma, U1, U1 + n, U1 + 2 * n, U1 + 3 * n, U1 + 4 * n, U1 + 5 * n);
+    k_rk_pred<<<cdiv(n, 256), 256, 0, c.stream>>>(A, x, y, z, ax, ay, az, sigma, U1, X);
+    VFMM_LAUNCH_CHECK();
+    do_build(c, n, X, X + n, X + 2 * n, X + 6 * n);
+    do_evaluate(c, n, X, X + n, X + 2 * n, X + 3 * n, X + 4 * n, X + 5 * n, X + 6 * n, U2, U2 + n, U2 + 2 * n,
+                U2 + 3 * n, U2 + 4 * n, U2 + 5 * n);
+    k_rk_corr<<<cdiv(n, 256), 256, 0, c.stream>>>(A, x, y, z, ax, ay, az, sigma, U1, U2);
+    VFMM_LAUNCH_CHECK();
+    // the tree now describes the predictor positions
+    c.built = false;
+}
+
+}  // namespace vfmm
+
+using vfmm::Ctx;
+using vfmm::Error;
+
+struct vfmm_ctx {
+    Ctx c;
+};
+
+extern "C" {
+
+void vfmm_default_params(vfmm_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->p = 10;
+    p->ncrit = 64;
+    p->theta = 0.5f;
+    p->sigma_gap = 5.0f;
+    p->periodic = 0;
+    p->images = 3;
+    p->box_len = 0.0;
+    p->scheme = VFMM_SCHEME_TRANSPOSE;
+    p->kahan = 0;
+    p->zero_mean = 1;
+    p->direct = 0;
+}
+
+vfmm_status vfmm_create(const vfmm_params *params, void *hip_stream, vfmm_ctx **out) {
+    if (!out || !params) {
+        vfmm::g_create_error = "null argument";
+        return VFMM_EINVAL;
+    }
+    *out = nullptr;
+    vfmm_ctx *h = nullptr;
+    try {
+        h = new vfmm_ctx();
+        vfmm::set_params(h->c, *params);
+        h->c.stream = (hipStream_t)hip_stream;
+        VFMM_HIP(hipGetDevice(&h->c.device));
+        *out = h;
+        return VFMM_OK;
+    } catch (const Error &e) {
+        vfmm::g_create_error = e.msg;
+        delete h;
+        return e.st;
+    } catch (const std::exception &e) {
+        vfmm::g_create_error = e.what();
+        delete h;
+        return VFMM_ENOMEM;
+    }
+}
+
+vfmm_status vfmm_set_params(vfmm_ctx *ctx, const vfmm_params *params) {
+    if (!ctx || !params) return VFMM_EINVAL;
+    try {
+        vfmm::set_params(ctx->c, *params);
+        return VFMM_OK;
+    } catch (const Error &e) {
+        return vfmm::fail(&ctx->c, e);
+    }
+}
+
+static bool overlaps(const void *a, const void *b, int64_t n) {
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    const int64_t bytes = n * (int64_t)sizeof(float);
+    return pa < pb + bytes && pb < pa + bytes;
+}
+
+vfmm_status fmm_build(vfmm_ctx *ctx, int64_t n, const float *x, const float *y, const float *z, const float *sigma) {
+    if (!ctx) return VFMM_EINVAL;
+    Ctx &c = ctx->c;
+    try {
+        if (n < 0 || n >= (1LL << 31)) throw Error{VFMM_EINVAL, "n must be in [0, 2^31)"};
+        if (n > 0 && (!x || !y || !z || !sigma)) throw Error{VFMM_EINVAL, "null input pointer"};
+        c.err.clear();
+        vfmm::do_build(c, n, x, y, z, sigma);
+        return VFMM_OK;
+    } catch (const Error &e) {
+        c.built = false;
+        return vfmm::fail(&c, e);
+    }
+}
+
+vfmm_status fmm_evaluate(vfmm_ctx *ctx, int64_t n, const float *x, const float *y, const float *z, const float *ax,
+                         const float *ay, const float *az, const float *sigma, float *ux, float *uy, float *uz,
+                         float *dax, float *day, float *daz) {
+    if (!ctx) return VFMM_EINVAL;
+    Ctx &c = ctx->c;
+    try {
+        if (!c.built || n != c.n) throw Error{VFMM_ESTATE, "fmm_evaluate needs a prior fmm_build with the same n"};
+        if (n > 0) {
+            const void *in[] = {x, y, z, ax, ay, az, sigma};
+            void *outp[] = {ux, uy, uz, dax, day, daz};
+            for (const void *p : in)
+                if (!p) throw Error{VFMM_EINVAL, "null input pointer"};
+            for (void *p : outp)
+                if (!p) throw Error{VFMM_EINVAL, "null output pointer"};
+            for (int a = 0; a < 6; ++a) {
+                for (int b = a + 1; b < 6; ++b)
+                    if (overlaps(outp[a], outp[b], n)) throw Error{VFMM_EINVAL, "output arrays overlap"};
+                for (const void *p : in)
+                    if (overlaps(outp[a], p, n)) throw Error{VFMM_EINVAL, "an output aliases an input"};
+            }
+        }
+        c.err.clear();
+        vfmm::do_evaluate(c, n, x, y, z, ax, ay, az, sigma, ux, uy, uz, dax, day, daz);
+        return VFMM_OK;
+    } catch (const Error &e) {
+        return vfmm::fail(&c, e);
+    }
+}
+
+vfmm_status rk_step(vfmm_ctx *ctx, int64_t n, float dt, float nu, float *x, float *y, float *z, float *ax, float *ay,
+                    float *az, float *sigma) {
+    if (!ctx) return VFMM_EINVAL;
+    Ctx &c = ctx->c;
+    try {
+        if (n < 0 || n >= (1LL << 31)) throw Error{VFMM_EINVAL, "n must be in [0, 2^31)"};
+        if (n > 0 && (!x || !y || !z || !ax || !ay || !az || !sigma)) throw Error{VFMM_EINVAL, "null pointer"};
+        if (!std::isfinite(dt) || !std::isfinite(nu) || nu < 0.f) throw Error{VFMM_EINVAL, "bad dt or nu"};
+        if (c.prm.direct && c.prm.periodic) throw Error{VFMM_EINVAL, "direct mode is free space only"};
+        c.err.clear();
+        vfmm::do_rk(c, n, dt, nu, x, y, z, ax, ay, az, sigma);
+        return VFMM_OK;
+    } catch (const Error &e) {
+        c.built = false;
+        return vfmm::fail(&c, e);
+    }
+}
+
+vfmm_status vfmm_get_timings(vfmm_ctx *ctx, vfmm_timings *out) {
+    if (!ctx || !out) return VFMM_EINVAL;
+    Ctx &c = ctx->c;
+    std::memset(out, 0, sizeof(*out));
+    if (!c.ev_ok) return VFMM_OK;
+    if (hipStreamSynchronize(c.stream) != hipSuccess) {
+        c.err = "stream synchronisation failed";
+        return VFMM_EHIP;
+    }
+    using namespace vfmm;
+    if (c.build_timed && !c.prm.direct && c.n > 0) {
+        out->bounds_sort_ms = ev_ms(c, 2 * PH_BOUNDS_SORT, 2 * PH_BOUNDS_SORT + 1);
+        out->tree_ms = ev_ms(c, 2 * PH_TREE, 2 * PH_TREE + 1);
+        out->traverse_ms = ev_ms(c, 2 * PH_TRAVERSE, 2 * PH_TRAVERSE + 1);
+        out->build_ms = ev_ms(c, 2 * PH_NUM, 2 * PH_NUM + 1);
+    }
+    if (c.eval_timed && c.n > 0) {
+        if (!c.prm.direct) {
+            out->p2m_m2m_ms = ev_ms(c, 2 * PH_P2M_M2M, 2 * PH_P2M_M2M + 1);
+            out->lattice_ms = ev_ms(c, 2 * PH_LATTICE, 2 * PH_LATTICE + 1);
+            out->m2l_ms = ev_ms(c, 2 * PH_M2L, 2 * PH_M2L + 1);
+            out->l2l_l2p_ms = ev_ms(c, 2 * PH_L2L_L2P, 2 * PH_L2L_L2P + 1);
+        }
+        out->p2p_ms = ev_ms(c, 2 * PH_P2P, 2 * PH_P2P + 1);
+        out->evaluate_ms = ev_ms(c, 2 * PH_NUM + 2, 2 * PH_NUM + 3);
+    }
+    return VFMM_OK;
+}
+
+vfmm_status vfmm_get_stats(vfmm_ctx *ctx, vfmm_stats *out) {
+    if (!ctx || !out) return VFMM_EINVAL;
+    Ctx &c = ctx->c;
+    std::memset(out, 0, sizeof(*out));
+    if (hipStreamSynchronize(c.stream) != hipSuccess) {
+        c.err = "stream synchronisation failed";
+        return VFMM_EHIP;
+    }
+    out->n = c.n;
+    out->ncells = c.ncells;
+    out->nleaves = c.nleaves;
+    out->depth = c.depth;
+    out->p2p_entries = c.n_p2p;
+    out->p2p_pairs = c.p2p_pairs;
+    out->m2l_entries = c.n_m2l;
+    out->p2p_blocks = c.n_blocks;
+    out->images_traversed = c.prm.periodic ? c.img_codes : 0;
+    out->sigma_min = c.hb.sig_min;
+    out->sigma_max = c.hb.sig_max;
+    if (c.bres.ptr && c.n > 0) {
+        vfmm::Bounds b;
+        if (hipMemcpy(&b, c.bres.ptr, sizeof(b), hipMemcpyDeviceToHost) == hipSuccess)
+            for (int d = 0; d < 3; ++d) out->sum_alpha[d] = b.sum_a[d];
+    }
+    return VFMM_OK;
+}
+
+vfmm_status vfmm_copy_lists(vfmm_ctx *ctx, int32_t *p2p_tgt, int32_t *p2p_src, int32_t *p2p_img, int32_t *m2l_tgt,
+                            int32_t *m2l_src, int32_t *m2l_img, int32_t *cell_start, int32_t *cell_count,
+                            int32_t *perm) {
+    if (!ctx) return VFMM_EINVAL;
+    Ctx &c = ctx->c;
+    if (!c.built || c.prm.direct) {
+        c.err = "no tree built";
+        return VFMM_ESTATE;
+    }
+    try {
+        VFMM_HIP(hipStreamSynchronize(c.stream));
+        const int nc = c.ncells;
+        if (cell_start && nc) VFMM_HIP(hipMemcpy(cell_start, c.c_start.ptr, sizeof(int) * nc, hipMemcpyDeviceToHost));
+        if (cell_count && nc) VFMM_HIP(hipMemcpy(cell_count, c.c_count.ptr, sizeof(int) * nc, hipMemcpyDeviceToHost));
+        if (perm && c.n) VFMM_HIP(hipMemcpy(perm, c.perm.ptr, sizeof(int) * c.n, hipMemcpyDeviceToHost));
+        // lists in CSR (sorted by target) order
+        std::vector<int> off(nc + 1);
+        if (c.n_p2p > 0 && (p2p_tgt || p2p_src || p2p_img)) {
+            VFMM_HIP(hipMemcpy(off.data(), c.p2p_off.ptr, sizeof(int) * (nc + 1), hipMemcpyDeviceToHost));
+            std::vector<int4> ent(c.n_p2p);
+            VFMM_HIP(hipMemcpy(ent.data(), c.p2p_ent.ptr, sizeof(int4) * c.n_p2p, hipMemcpyDeviceToHost));
+            std::vector<int> st(nc);
+            VFMM_HIP(hipMemcpy(st.data(), c.c_start.ptr, sizeof(int) * nc, hipMemcpyDeviceToHost));
+            std::vector<int> cn(nc);
+            VFMM_HIP(hipMemcpy(cn.data(), c.c_count.ptr, sizeof(int) * nc, hipMemcpyDeviceToHost));
+            // map source (start, count) back to a leaf id: leaves have unique starts among leaves
+            std::vector<int> leaf_of_start(c.n, -1);
+            std::vector<int> nchild(nc);
+            VFMM_HIP(hipMemcpy(nchild.data(), c.c_nchild.ptr, sizeof(int) * nc, hipMemcpyDeviceToHost));
+            for (int i = 0; i < nc; ++i)
+                if (nchild[i] == 0 && cn[i] > 0) leaf_of_start[st[i]] = i;
+            for (int t = 0; t < nc; ++t)
+                for (int e = off[t]; e < off[t + 1]; ++e) {
+                    if (p2p_tgt) p2p_tgt[e] = t;
+                    if (p2p_src) p2p_src[e] = leaf_of_start[ent[e].x];
+                    if (p2p_img) p2p_img[e] = ent[e].z;
+                }
+        }
+        if (c.n_m2l > 0 && (m2l_tgt || m2l_src || m2l_img)) {
+            VFMM_HIP(hipMemcpy(off.data(), c.m2l_off.ptr, sizeof(int) * (nc + 1), hipMemcpyDeviceToHost));
+            std::vector<int2> src(c.n_m2l);
+            VFMM_HIP(hipMemcpy(src.data(), c.m2l_src.ptr, sizeof(int2) * c.n_m2l, hipMemcpyDeviceToHost));
+            for (int t = 0; t < nc; ++t)
+                for (int e = off[t]; e < off[t + 1]; ++e) {
+                    if (m2l_tgt) m2l_tgt[e] = t;
+                    if (m2l_src) m2l_src[e] = src[e].x;
+                    if (m2l_img) m2l_img[e] = src[e].y;
+                }
+        }
+        return VFMM_OK;
+    } catch (const Error &e) {
+        return vfmm::fail(&c, e);
+    }
+}
+
+const char *vfmm_last_error(const vfmm_ctx *ctx) {
+    if (!ctx) return vfmm::g_create_error.c_str();
+    return ctx->c.err.c_str();
+}
+
+void vfmm_destroy(vfmm_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->c.stream);
+    ctx->c.release_all();
+    delete ctx;
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Library context: parameters, device buffers and host-side sizes.
+#pragma once
+
+#include "common.h"
+
+namespace vfmm {
+
+enum Phase { PH_BOUNDS_SORT = 0, PH_TREE, PH_TRAVERSE, PH_P2M_M2M, PH_LATTICE, PH_M2L, PH_L2L_L2P,
+             PH_P2P, PH_NUM };
+
+struct Ctx {
+    vfmm_params prm{};
+    hipStream_t stream = nullptr;
+    std::string err;
+    int device = 0;
+
+    // ---- state of the last build ----
+    bool built = false;
+    int64_t n = 0;
+    Bounds hb{};
+    RootBox box{};
+    bool var_sigma = false;
+    float sigma_uniform = 0.f;
+    int depth = 0;
+    std::vector<int> lvl_off;  // cells of level l are [lvl_off[l], lvl_off[l+1])
+    int ncells = 0, nleaves = 0;
+    int n_p2p = 0, n_blocks = 0;
+    int64_t n_m2l = 0, p2p_pairs = 0;
+    int img_B = 0, img_codes = 1;
+    int images_traversed = 0;
+
+    // ---- device buffers (grow-only) ----
+    DevBuf bpart, bres;                  // bounds partials / result
+    DevBuf keyA, keyB, valA, valB;       // sort ping-pong (uint64 keys, uint32 values)
+    DevBuf hist, scanA, scanB, scanC;    // sort histogram, scan scratch
+    DevBuf perm;                         // sorted position -> caller index (int)
+    DevBuf rec;                          // float4[2n]: (x,y,z,sigma) (ax,ay,az,0)/(4 pi)
+    // cells
+    DevBuf c_start, c_count, c_parent, c_child, c_nchild, c_level;  // int
+    DevBuf c_geo;                        // float4 (cx, cy, cz, size)
+    DevBuf c_rad;                        // float tight radius
+    DevBuf c_lo, c_hi;                   // float4 particle bounding box
+    DevBuf c_tmp;                        // build scratch: child counts
+    DevBuf leaves;                       // leaf cell ids
+    // traversal
+    DevBuf frA, frB;                     // frontier int4 (A, B, img, 0)
+    DevBuf tcnt;                         // per-pair counts (3 ints)
+    DevBuf m2l_raw, p2p_raw;             // unsorted (tgt,src,img) int4
+    DevBuf lkey, lkey2, lval, lval2;     // list sort
+    DevBuf m2l_off, m2l_src;             // CSR by target cell: int offsets[ncells+1], int2 (src, img)
+    DevBuf p2p_off, p2p_ent;             // CSR by target cell: int offsets, int4 (start, count, img, variant)
+    DevBuf blocks;                       // int4 (tgt start, tgt count, list off, list count)
+    DevBuf pairs64;                      // int64 reduction scratch
+    // expansions
+    DevBuf Mexp, Lexp;                   // float2 [ncells][3][NC(p)]
+    DevBuf lat_op;                       // float [2NC x 2NC] periodic lattice operator
+    int lat_p = -1, lat_K = -1;
+    double lat_len = 0.0;
+    // outputs of the far field, sorted order: float [3n] each
+    DevBuf far_u, far_da;
+    DevBuf dsurf;                        // float[4] surface velocity term
+    // rk_step stage storage
+    DevBuf rk;                           // float [13 n]
+
+    // timing
+    hipEvent_t ev[2 * PH_NUM + 4] = {};
+    bool ev_ok = false;
+    float t_phase[PH_NUM] = {};
+    float t_build = 0.f, t_eval = 0.f;
+    bool build_timed = false, eval_timed = false;
+
+    void release_all();
+};
+
+// tree.hip
+void compute_bounds(Ctx &c, int64_t n, const float *x, const float *y, const float *z, const float *sigma,
+                    const float *ax, const float *ay, const float *az, bool with_alpha);
+void build_tree(Ctx &c, int64_t n, const float *x, const float *y, const float *z, const float *sigma);
+void gather_strengths(Ctx &c, const float *ax, const float *ay, const float *az, const float *sigma);
+void scan_excl_i32(Ctx &c, const int *in, int *out, int64_t n);  // out may alias in
+// traverse.hip
+void traverse_and_lists(Ctx &c);
+// far.hip
+void far_field(Ctx &c);
+// p2p.hip
+void p2p_and_finalize(Ctx &c, float *ux, float *uy, float *uz, float *dax, float *day, float *daz);
+void direct_all_pairs(Ctx &c, const float *x, const float *y, const float *z, const float *ax,
+                      const float *ay, const float *az, const float *sigma, float *ux, float *uy,
+                      float *uz, float *dax, float *day, float *daz);
+// lattice_host.cpp
+void lattice_operator_host(int p, int K, std::vector<double> &op);
+
+}  // namespace vfmm

@@ -1,0 +1,346 @@
+// Near field P2P (Sec. 3.1, Sec. 3.6) of the regularised Biot-Savart law and
+// the stretching term, Eqs. (1)-(3), fused with the far-field sum and the
+// scatter back to the caller's order.
+//
+// Work item: one wave64 per block of <= 64 targets (one target per lane) of a
+// leaf; the wave walks the leaf's P2P list.  Source particles are the same
+// for every lane at a given step, so their records are read with scalar
+// loads and enter the vector ALU as scalar operands: no LDS staging and no
+// cross-lane traffic in the pair loop.  Per-target sums are accumulated per
+// source leaf and then added to the running total (blocked summation, with an
+// optional compensated add).
+//
+// Per pair, with r = x_i - x_j, s = |r| / (sqrt 2 sigma), x = s^2, and
+// alpha~ = alpha/(4 pi) stored in the records:
+//   q alpha_j       = F alpha~_j,        F = P(3/2, x) / rho^3
+//   (q'/rho) alpha_j = -3 H alpha~_j,    H = P(5/2, x) / rho^5
+// where P(a, x) is the regularised lower incomplete gamma function: P(3/2, x)
+// is the cutoff g of Eq. (2), and P(5/2, x) = g - 4 s^3 e^{-x} / (3 sqrt pi).
+//   u_i       += F (alpha~_j x r)
+//   A_i       += F alpha~_j                     (alpha_i x A_i = sum q alpha_i x alpha_j)
+//   T_i       += H (alpha_i . (alpha~_j x r)) r  (transpose reading of Eq. (3))
+//   dalpha_i   = alpha_i x A_i - 3 T_i
+// Three forms of the cutoff, chosen per source leaf from the leaf boxes:
+//   full : some pair may have s < 1: Kummer series for s < 1, erfc form else;
+//   mid  : every pair has s >= 1: 1 - P = e^{-x} (erfcx(s) + ...), no branch;
+//   sing : the float32 cutoff is 1 for every pair (s >= 5.1): F = rho^-3.
+#include "ctx.h"
+#include "cutoff_fits.h"
+
+namespace vfmm {
+
+struct P2PConst {
+    float kE;        // -log2(e) / (2 sigma^2): e^{-x} = exp2(r2 kE)
+    float kS;        // 2 c / sqrt(pi), c = 1/(sqrt 2 sigma): (2/sqrt pi) s = rho kS
+    float kU;        // 1/c: 1/s = rinv kU
+    float t5;        // 2 c^2 / 3: (4/(3 sqrt pi)) s^3 = r2 t5 * rho kS
+    float K3;        // c^3 4/(3 sqrt pi): P(3/2,x)/rho^3 -> K3 at rho = 0
+    float r2_small;  // 2 sigma^2 (s < 1 <=> r2 < r2_small)
+    float q[VFMM_M2_DEG + 1];  // c^5 8/(15 sqrt pi) * M2 coefficients, in powers of r2
+};
+
+struct P2PArgs {
+    const float4 *__restrict__ rec;
+    const int4 *__restrict__ blocks;
+    const int4 *__restrict__ ent;
+    int nblocks;
+    int B;
+    float len;
+    const float *__restrict__ far_u;
+    const float *__restrict__ far_da;
+    int64_t n;
+    const int *__restrict__ perm;
+    const Bounds *__restrict__ bounds;
+    float inv3V;
+    int surface;
+    float *ux, *uy, *uz, *dax, *day, *daz;
+};
+
+struct Acc9 {
+    float u0, u1, u2, a0, a1, a2, t0, t1, t2;
+};
+
+template <int V, int SCHEME>
+__device__ __forceinline__ void pair(const P2PConst &k, float xi, float yi, float zi, float ai0, float ai1, float ai2,
+                                     float4 sp, float4 sa, Acc9 &p) {
+    const float dx = xi - sp.x, dy = yi - sp.y, dz = zi - sp.z;
+    const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float rinv2 = rinv * rinv;
+    const float rinv3 = rinv2 * rinv;
+    const float h5 = rinv3 * rinv2;
+    float F = rinv3, H = h5;
+    if (V <= 1) {
+        const float E = __builtin_amdgcn_exp2f(r2 * k.kE);
+        const float rho = r2 * rinv;
+        const float ks = rho * k.kS;
+        const float u = rinv * k.kU;
+        float pe = VFMM_ERFCX_C[VFMM_ERFCX_DEG];
+#pragma unroll
+        for (int i = VFMM_ERFCX_DEG - 1; i >= 0; --i) pe = fmaf(pe, u, VFMM_ERFCX_C[i]);
+        const float w3 = fmaf(u, pe, ks);                // erfcx(s) + (2/sqrt pi) s
+        const float g = fmaf(-E, w3, 1.0f);              // P(3/2, x)
+        const float w5 = fmaf(r2 * k.t5, ks, w3);        // + (4/(3 sqrt pi)) s^3
+        const float g5 = fmaf(-E, w5, 1.0f);             // P(5/2, x)
+        F = g * rinv3;
+        H = g5 * h5;
+        if (V == 0) {
+            if (__any(r2 < k.r2_small)) {
+                float q2 = k.q[VFMM_M2_DEG];
+#pragma unroll
+                for (int i = VFMM_M2_DEG - 1; i >= 0; --i) q2 = fmaf(q2, r2, k.q[i]);
+                const float Fs = E * fmaf(r2, q2, k.K3);  // e^{-x} K3 1F1(1;5/2;x)
+                const float Hs = E * q2;                  // e^{-x} K5 1F1(1;7/2;x)
+                const bool sm = r2 < k.r2_small;
+                F = sm ? Fs : F;
+                H = sm ? Hs : H;
+            }
+        }
+    }
+    // alpha~_j x r
+    const float c0 = sa.y * dz - sa.z * dy;
+    const float c1 = sa.z * dx - sa.x * dz;
+    const float c2 = sa.x * dy - sa.y * dx;
+    p.u0 = fmaf(F, c0, p.u0);
+    p.u1 = fmaf(F, c1, p.u1);
+    p.u2 = fmaf(F, c2, p.u2);
+    p.a0 = fmaf(F, sa.x, p.a0);
+    p.a1 = fmaf(F, sa.y, p.a1);
+    p.a2 = fmaf(F, sa.z, p.a2);
+    if (SCHEME == VFMM_SCHEME_TRANSPOSE) {
+        const float d = fmaf(ai0, c0, fmaf(ai1, c1, ai2 * c2));
+        const float hd = H * d;
+        p.t0 = fmaf(hd, dx, p.t0);
+        p.t1 = fmaf(hd, dy, p.t1);
+        p.t2 = fmaf(hd, dz, p.t2);
+    } else {
+        const float d = fmaf(ai0, dx, fmaf(ai1, dy, ai2 * dz));
+        const float hd = H * d;
+        p.t0 = fmaf(hd, c0, p.t0);
+        p.t1 = fmaf(hd, c1, p.t1);
+        p.t2 = fmaf(hd, c2, p.t2);
+    }
+}
+
+template <int V, int SCHEME>
+__device__ __forceinline__ void leaf_loop(const P2PConst &k, const float4 *__restrict__ rec, int s0, int cnt,
+                                          float xi, float yi, float zi, float ai0, float ai1, float ai2, Acc9 &p) {
+    const float4 *src = rec + 2 * (size_t)s0;
+    int j = 0;
+    for (; j + 2 <= cnt; j += 2) {
+        const float4 sp0 = src[2 * j], sa0 = src[2 * j + 1];
+        const float4 sp1 = src[2 * j + 2], sa1 = src[2 * j + 3];
+        pair<V, SCHEME>(k, xi, yi, zi, ai0, ai1, ai2, sp0, sa0, p);
+        pair<V, SCHEME>(k, xi, yi, zi, ai0, ai1, ai2, sp1, sa1, p);
+    }
+    if (j < cnt) pair<V, SCHEME>(k, xi, yi, zi, ai0, ai1, ai2, src[2 * j], src[2 * j + 1], p);
+}
+
+__device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
+    const float y = v - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+template <int SCHEME, bool KAHAN>
+__global__ __launch_bounds__(256) void k_p2p(P2PConst k, P2PArgs A) {
+    const int lane = threadIdx.x & 63;
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= A.nblocks) return;
+    const int4 blk = A.blocks[b];
+    const int t0 = __builtin_amdgcn_readfirstlane(blk.x);
+    const int tc = __builtin_amdgcn_readfirstlane(blk.y);
+    const int l0 = __builtin_amdgcn_readfirstlane(blk.z);
+    const int lc = __builtin_amdgcn_readfirstlane(blk.w);
+    const bool valid = lane < tc;
+    const int i = t0 + (valid ? lane : 0);
+    const float4 xp = A.rec[2 * (size_t)i];
+    const float4 xa = A.rec[2 * (size_t)i + 1];
+    const float fp = 12.566370614359172f;  // 4 pi: stored strengths are alpha/(4 pi)
+    const float ai0 = xa.x * fp, ai1 = xa.y * fp, ai2 = xa.z * fp;
+    float S[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    float Cc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int W = 2 * A.B + 1;
+    for (int e = 0; e < lc; ++e) {
+        const int4 en = A.ent[l0 + e];
+        const int s0 = __builtin_amdgcn_readfirstlane(en.x);
+        const int sc = __builtin_amdgcn_readfirstlane(en.y);
+        const int img = __builtin_amdgcn_readfirstlane(en.z);
+        const int var = __builtin_amdgcn_readfirstlane(en.w);
+        const float shx = (float)(img % W - A.B) * A.len;
+        const float shy = (float)((img / W) % W - A.B) * A.len;
+        const float shz = (float)(img / (W * W) - A.B) * A.len;
+        const float xi = xp.x - shx, yi = xp.y - shy, zi = xp.z - shz;
+        Acc9 p = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (var == 1)
+            leaf_loop<1, SCHEME>(k, A.rec, s0, sc, xi, yi, zi, ai0, ai1, ai2, p);
+        else if (var == 0)
+            leaf_loop<0, SCHEME>(k, A.rec, s0, sc, xi, yi, zi, ai0, ai1, ai2, p);
+        else
+            leaf_loop<2, SCHEME>(k, A.rec, s0, sc, xi, yi, zi, ai0, ai1, ai2, p);
+        const float pv[9] = {p.u0, p.u1, p.u2, p.a0, p.a1, p.a2, p.t0, p.t1, p.t2};
+        if (KAHAN) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) kahan_add(S[q], Cc[q], pv[q]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) S[q] += pv[q];
+        }
+    }
+    if (!valid) return;
+    // dalpha = alpha_i x A - 3 T (transpose) or A x alpha_i - 3 T (classical)
+    float d0, d1, d2;
+    if (SCHEME == VFMM_SCHEME_TRANSPOSE) {
+        d0 = ai1 * S[5] - ai2 * S[4];
+        d1 = ai2 * S[3] - ai0 * S[5];
+        d2 = ai0 * S[4] - ai1 * S[3];
+    } else {
+        d0 = S[4] * ai2 - S[5] * ai1;
+        d1 = S[5] * ai0 - S[3] * ai2;
+        d2 = S[3] * ai1 - S[4] * ai0;
+    }
+    d0 = fmaf(-3.0f, S[6], d0);
+    d1 = fmaf(-3.0f, S[7], d1);
+    d2 = fmaf(-3.0f, S[8], d2);
+    float u0 = S[0], u1 = S[1], u2 = S[2];
+    if (A.far_u) {
+        u0 += A.far_u[i];
+        u1 += A.far_u[A.n + i];
+        u2 += A.far_u[2 * A.n + i];
+        d0 += A.far_da[i];
+        d1 += A.far_da[A.n + i];
+        d2 += A.far_da[2 * A.n + i];
+    }
+    if (A.surface) {
+        u0 -= (float)(A.bounds->sum_xa[0]) * A.inv3V;
+        u1 -= (float)(A.bounds->sum_xa[1]) * A.inv3V;
+        u2 -= (float)(A.bounds->sum_xa[2]) * A.inv3V;
+    }
+    const int o = A.perm[i];
+    A.ux[o] = u0;
+    A.uy[o] = u1;
+    A.uz[o] = u2;
+    A.dax[o] = d0;
+    A.day[o] = d1;
+    A.daz[o] = d2;
+}
+
+static P2PConst make_const(double sigma) {
+    P2PConst k{};
+    const double c = 1.0 / (std::sqrt(2.0) * sigma);
+    const double c2 = c * c;
+    const double sqpi = std::sqrt(M_PI);
+    k.kE = (float)(-c2 / std::log(2.0));
+    k.kS = (float)(2.0 * c / sqpi);
+    k.kU = (float)(1.0 / c);
+    k.t5 = (float)(2.0 * c2 / 3.0);
+    k.K3 = (float)(c * c2 * 4.0 / (3.0 * sqpi));
+    k.r2_small = (float)(VFMM_CUTOFF_XSPLIT / c2);
+    const double K5 = c2 * c2 * c * 8.0 / (15.0 * sqpi);
+    double pw = 1.0;
+    for (int i = 0; i <= VFMM_M2_DEG; ++i) {
+        k.q[i] = (float)(K5 * (double)VFMM_M2_C[i] * pw);
+        pw *= c2;
+    }
+    return k;
+}
+
+template <int SCHEME, bool KAHAN>
+static void launch_p2p(Ctx &c, const P2PConst &k, const P2PArgs &A) {
+    if (A.nblocks == 0) return;
+    k_p2p<SCHEME, KAHAN><<<cdiv(A.nblocks, 4), 256, 0, c.stream>>>(k, A);
+    VFMM_LAUNCH_CHECK();
+}
+
+static void dispatch_p2p(Ctx &c, const P2PConst &k, const P2PArgs &A) {
+    const bool kah = c.prm.kahan != 0;
+    if (c.prm.scheme == VFMM_SCHEME_TRANSPOSE) {
+        if (kah) launch_p2p<VFMM_SCHEME_TRANSPOSE, true>(c, k, A);
+        else launch_p2p<VFMM_SCHEME_TRANSPOSE, false>(c, k, A);
+    } else {
+        if (kah) launch_p2p<VFMM_SCHEME_CLASSICAL, true>(c, k, A);
+        else launch_p2p<VFMM_SCHEME_CLASSICAL, false>(c, k, A);
+    }
+}
+
+void p2p_and_finalize(Ctx &c, float *ux, float *uy, float *uz, float *dax, float *day, float *daz) {
+    const P2PConst k = make_const(c.sigma_uniform);
+    P2PArgs A{};
+    A.rec = c.rec.as<float4>();
+    A.blocks = c.blocks.as<int4>();
+    A.ent = c.p2p_ent.as<int4>();
+    A.nblocks = c.n_blocks;
+    A.B = c.img_B;
+    A.len = c.prm.periodic ? (float)c.prm.box_len : 0.f;
+    A.far_u = c.far_u.as<float>();
+    A.far_da = c.far_da.as<float>();
+    A.n = c.n;
+    A.perm = c.perm.as<int>();
+    A.bounds = c.bres.as<Bounds>();
+    A.surface = (c.prm.periodic && c.prm.zero_mean) ? 1 : 0;
+    A.inv3V = c.prm.periodic ? (float)(1.0 / (3.0 * c.prm.box_len * c.prm.box_len * c.prm.box_len)) : 0.f;
+    A.ux = ux; A.uy = uy; A.uz = uz; A.dax = dax; A.day = day; A.daz = daz;
+    if (c.ev_ok) VFMM_HIP(hipEventRecord(c.ev[2 * PH_P2P], c.stream));
+    dispatch_p2p(c, k, A);
+    if (c.ev_ok) VFMM_HIP(hipEventRecord(c.ev[2 * PH_P2P + 1], c.stream));
+}
+
+// ---------------------------------------------------------------------------
+// Direct mode: every target block against all N sources (one list entry,
+// full cutoff form), in the caller's order, no tree and no far field.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_direct_setup(int64_t n, const float *x, const float *y, const float *z,
+                                                      const float *ax, const float *ay, const float *az,
+                                                      const float *s, float4 *rec, int *perm) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float k = 0.0795774715459476679f;  // 1/(4 pi)
+    rec[2 * i] = make_float4(x[i], y[i], z[i], s[i]);
+    rec[2 * i + 1] = make_float4(ax[i] * k, ay[i] * k, az[i] * k, 0.f);
+    perm[i] = (int)i;
+}
+
+__global__ __launch_bounds__(256) void k_direct_blocks(int64_t n, int nb, int4 *blocks, int4 *ent) {
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b == 0) ent[0] = make_int4(0, (int)n, 0, 0);
+    if (b < nb) blocks[b] = make_int4(b * 64, (int)min<int64_t>(64, n - (int64_t)b * 64), 0, 1);
+}
+
+void direct_all_pairs(Ctx &c, const float *x, const float *y, const float *z, const float *ax, const float *ay,
+                      const float *az, const float *sigma, float *ux, float *uy, float *uz, float *dax, float *day,
+                      float *daz) {
+    const int64_t n = c.n;
+    c.rec.ensure(sizeof(float4) * 2 * n);
+    c.perm.ensure(sizeof(int) * n);
+    const int nb = (int)cdiv(n, 64);
+    c.blocks.ensure(sizeof(int4) * nb);
+    c.p2p_ent.ensure(sizeof(int4));
+    k_direct_setup<<<cdiv(n, 256), 256, 0, c.stream>>>(n, x, y, z, ax, ay, az, sigma, c.rec.as<float4>(),
+                                                        c.perm.as<int>());
+    VFMM_LAUNCH_CHECK();
+    k_direct_blocks<<<cdiv(nb, 256), 256, 0, c.stream>>>(n, nb, c.blocks.as<int4>(), c.p2p_ent.as<int4>());
+    VFMM_LAUNCH_CHECK();
+    const P2PConst k = make_const(c.sigma_uniform);
+    P2PArgs A{};
+    A.rec = c.rec.as<float4>();
+    A.blocks = c.blocks.as<int4>();
+    A.ent = c.p2p_ent.as<int4>();
+    A.nblocks = nb;
+    A.B = 0;
+    A.len = 0.f;
+    A.far_u = nullptr;
+    A.far_da = nullptr;
+    A.n = n;
+    A.perm = c.perm.as<int>();
+    A.bounds = c.bres.as<Bounds>();
+    A.surface = 0;
+    A.ux = ux; A.uy = uy; A.uz = uz; A.dax = dax; A.day = day; A.daz = daz;
+    c.n_blocks = nb;
+    c.p2p_pairs = n * n;
+    if (c.ev_ok) VFMM_HIP(hipEventRecord(c.ev[2 * PH_P2P], c.stream));
+    dispatch_p2p(c, k, A);
+    if (c.ev_ok) VFMM_HIP(hipEventRecord(c.ev[2 * PH_P2P + 1], c.stream));
+}
+
+}  // namespace vfmm

@@ -1,0 +1,598 @@
+// Tree construction on the device: bounds, Morton keys, stable LSD radix sort,
+// gather into Morton order, level-synchronous octree build and cell geometry.
+// Sec. 3.2 of the paper (Morton ordering of 3 x 21 coordinate bits in a 64-bit
+// key; at most 21 levels).
+#include "ctx.h"
+
+namespace vfmm {
+
+static constexpr int TPB = 256;
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of int32 (in-place allowed).  2048 items per block, block
+// totals scanned recursively.
+// ---------------------------------------------------------------------------
+static constexpr int SCAN_ITEMS = 8;
+static constexpr int SCAN_TILE = TPB * SCAN_ITEMS;
+
+__global__ __launch_bounds__(TPB) void k_scan_tile(const int *in, int *out, int64_t n, int *block_sums) {
+    __shared__ int wsum[TPB / 64];
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)tid * SCAN_ITEMS;
+    int v[SCAN_ITEMS];
+    int run = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        const int64_t k = base + i;
+        v[i] = k < n ? in[k] : 0;
+        run += v[i];
+    }
+    // wave inclusive scan of thread totals
+    const int lane = tid & 63, w = tid >> 6;
+    int incl = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int woff = 0;
+    for (int i = 0; i < w; ++i) woff += wsum[i];
+    int ex = woff + incl - run;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        const int64_t k = base + i;
+        if (k < n) out[k] = ex;
+        ex += v[i];
+    }
+    if (tid == TPB - 1 && block_sums) block_sums[blockIdx.x] = woff + incl;
+}
+
+__global__ __launch_bounds__(TPB) void k_scan_add(int *out, int64_t n, const int *offs) {
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    const int add = offs[blockIdx.x];
+    for (int i = threadIdx.x; i < SCAN_TILE; i += TPB) {
+        const int64_t k = base + i;
+        if (k < n) out[k] += add;
+    }
+}
+
+static void scan_rec(hipStream_t s, const int *in, int *out, int64_t n, int *scratch) {
+    if (n <= 0) return;
+    const unsigned nb = cdiv(n, SCAN_TILE);
+    if (nb == 1) {
+        k_scan_tile<<<1, TPB, 0, s>>>(in, out, n, nullptr);
+        VFMM_LAUNCH_CHECK();
+        return;
+    }
+    int *sums = scratch;
+    k_scan_tile<<<nb, TPB, 0, s>>>(in, out, n, sums);
+    VFMM_LAUNCH_CHECK();
+    scan_rec(s, sums, sums, nb, scratch + nb);
+    k_scan_add<<<nb, TPB, 0, s>>>(out, n, sums);
+    VFMM_LAUNCH_CHECK();
+}
+
+void scan_excl_i32(Ctx &c, const int *in, int *out, int64_t n) {
+    size_t need = 0;
+    for (int64_t m = cdiv(n, SCAN_TILE); m > 1; m = cdiv(m, SCAN_TILE)) need += m;
+    c.scanC.ensure((need + 64) * sizeof(int));
+    scan_rec(c.stream, in, out, n, c.scanC.as<int>());
+}
+
+// ---------------------------------------------------------------------------
+// Bounds: min/max of positions, min/max core, float64 sums of alpha and of
+// (x - ref) x alpha, non-finite and out-of-cube counts.  Deterministic two
+// stage reduction.
+// ---------------------------------------------------------------------------
+struct BAcc {
+    double lo[3], hi[3], smin, smax, sa[3], sxa[3];
+    int nf, out;
+};
+
+__device__ inline void bacc_init(BAcc &a) {
+    for (int d = 0; d < 3; ++d) {
+        a.lo[d] = 1e300; a.hi[d] = -1e300; a.sa[d] = 0; a.sxa[d] = 0;
+    }
+    a.smin = 1e300; a.smax = -1e300; a.nf = 0; a.out = 0;
+}
+
+__device__ inline void bacc_merge(BAcc &a, const BAcc &b) {
+    for (int d = 0; d < 3; ++d) {
+        a.lo[d] = fmin(a.lo[d], b.lo[d]); a.hi[d] = fmax(a.hi[d], b.hi[d]);
+        a.sa[d] += b.sa[d]; a.sxa[d] += b.sxa[d];
+    }
+    a.smin = fmin(a.smin, b.smin); a.smax = fmax(a.smax, b.smax);
+    a.nf += b.nf; a.out += b.out;
+}
+
+struct BoundsArgs {
+    const float *x, *y, *z, *s, *ax, *ay, *az;
+    int64_t n;
+    int with_alpha, periodic;
+    double ref[3];
+    double plo[3], plen;
+};
+
+__global__ __launch_bounds__(TPB) void k_bounds_partial(BoundsArgs A, BAcc *part) {
+    __shared__ BAcc sh[TPB];
+    BAcc a;
+    bacc_init(a);
+    for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < A.n; i += (int64_t)gridDim.x * TPB) {
+        const double p[3] = {A.x[i], A.y[i], A.z[i]};
+        const double sg = A.s[i];
+        bool fin = isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]) && isfinite(sg) && sg > 0.0;
+        double al[3] = {0, 0, 0};
+        if (A.with_alpha) {
+            al[0] = A.ax[i]; al[1] = A.ay[i]; al[2] = A.az[i];
+            fin = fin && isfinite(al[0]) && isfinite(al[1]) && isfinite(al[2]);
+        }
+        if (!fin) { a.nf++; continue; }
+        for (int d = 0; d < 3; ++d) { a.lo[d] = fmin(a.lo[d], p[d]); a.hi[d] = fmax(a.hi[d], p[d]); }
+        a.smin = fmin(a.smin, sg); a.smax = fmax(a.smax, sg);
+        if (A.periodic) {
+            for (int d = 0; d < 3; ++d)
+                if (!(p[d] >= A.plo[d] && p[d] < A.plo[d] + A.plen)) { a.out++; break; }
+        }
+        if (A.with_alpha) {
+            const double r[3] = {p[0] - A.ref[0], p[1] - A.ref[1], p[2] - A.ref[2]};
+            for (int d = 0; d < 3; ++d) a.sa[d] += al[d];
+            a.sxa[0] += r[1] * al[2] - r[2] * al[1];
+            a.sxa[1] += r[2] * al[0] - r[0] * al[2];
+            a.sxa[2] += r[0] * al[1] - r[1] * al[0];
+        }
+    }
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = TPB / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) bacc_merge(sh[threadIdx.x], sh[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(TPB) void k_bounds_final(const BAcc *part, int np, Bounds *res) {
+    __shared__ BAcc sh[TPB];
+    BAcc a;
+    bacc_init(a);
+    for (int i = threadIdx.x; i < np; i += TPB) bacc_merge(a, part[i]);
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = TPB / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) bacc_merge(sh[threadIdx.x], sh[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        Bounds b;
+        for (int d = 0; d < 3; ++d) {
+            b.lo[d] = sh[0].lo[d]; b.hi[d] = sh[0].hi[d];
+            b.sum_a[d] = sh[0].sa[d]; b.sum_xa[d] = sh[0].sxa[d];
+        }
+        b.sig_min = sh[0].smin; b.sig_max = sh[0].smax;
+        b.nonfinite = sh[0].nf; b.outside = sh[0].out;
+        b.pad[0] = b.pad[1] = 0;
+        *res = b;
+    }
+}
+
+void compute_bounds(Ctx &c, int64_t n, const float *x, const float *y, const float *z, const float *sigma,
+                    const float *ax, const float *ay, const float *az, bool with_alpha) {
+    BoundsArgs A{};
+    A.x = x; A.y = y; A.z = z; A.s = sigma; A.ax = ax; A.ay = ay; A.az = az;
+    A.n = n;
+    A.with_alpha = with_alpha ? 1 : 0;
+    A.periodic = c.prm.periodic;
+    for (int d = 0; d < 3; ++d) {
+        A.plo[d] = c.prm.box_lo[d];
+        A.ref[d] = c.prm.periodic ? c.prm.box_lo[d] + 0.5 * c.prm.box_len : 0.0;
+    }
+    A.plen = c.prm.box_len;
+    const int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(n, TPB)));
+    c.bpart.ensure(sizeof(BAcc) * nb);
+    c.bres.ensure(sizeof(Bounds));
+    k_bounds_partial<<<nb, TPB, 0, c.stream>>>(A, c.bpart.as<BAcc>());
+    VFMM_LAUNCH_CHECK();
+    k_bounds_final<<<1, TPB, 0, c.stream>>>(c.bpart.as<BAcc>(), nb, c.bres.as<Bounds>());
+    VFMM_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Morton keys: 21 bits per axis, bit 3b+2 = x bit b, 3b+1 = y bit b, 3b = z bit b.
+// ---------------------------------------------------------------------------
+__device__ inline uint64_t spread3(uint32_t v) {
+    uint64_t x = v & 0x1fffffu;
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+__global__ __launch_bounds__(TPB) void k_morton(const float *x, const float *y, const float *z, int64_t n,
+                                                RootBox box, uint64_t *keys, uint32_t *vals) {
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i >= n) return;
+    const float sc = 2097152.0f / box.len;
+    const float p[3] = {x[i], y[i], z[i]};
+    uint32_t q[3];
+    for (int d = 0; d < 3; ++d) {
+        float t = floorf((p[d] - box.lo[d]) * sc);
+        t = fminf(fmaxf(t, 0.0f), 2097151.0f);
+        q[d] = (uint32_t)t;
+    }
+    keys[i] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+    vals[i] = (uint32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort of (uint64 key, uint32 value), 8-bit digits.
+// Ranking inside a tile uses wave ballots over the digit bits, so equal
+// digits keep their input order: the sort is stable and deterministic.
+// ---------------------------------------------------------------------------
+static constexpr int RS_ITEMS = 16;
+static constexpr int RS_TILE = TPB * RS_ITEMS;
+
+__global__ __launch_bounds__(TPB) void k_rs_hist(const uint64_t *keys, int64_t n, int shift, int *hist, int nblk) {
+    __shared__ int h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int64_t k = base + (int64_t)i * TPB + threadIdx.x;
+        if (k < n) atomicAdd(&h[(keys[k] >> shift) & 255], 1);
+    }
+    __syncthreads();
+    hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(TPB) void k_rs_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
+                                                    uint32_t *vout, int64_t n, int shift, const int *offs,
+                                                    int nblk) {
+    __shared__ int base_off[256];
+    __shared__ int wcnt[TPB / 64][256];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    base_off[tid] = offs[tid * nblk + blockIdx.x];
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ITEMS; ++r) {
+        for (int j = 0; j < TPB / 64; ++j) wcnt[j][tid] = 0;
+        const int64_t k = base + (int64_t)r * TPB + tid;
+        const bool valid = k < n;
+        const uint64_t key = valid ? kin[k] : 0ull;
+        const uint32_t val = valid ? vin[k] : 0u;
+        const int d = (int)((key >> shift) & 255);
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t mb = __ballot((d >> b) & 1);
+            m &= ((d >> b) & 1) ? mb : ~mb;
+        }
+        const int rank = __popcll(m & lt);
+        __syncthreads();
+        if (valid && rank == 0) wcnt[w][d] = __popcll(m);
+        __syncthreads();
+        if (valid) {
+            int pre = 0;
+            for (int j = 0; j < w; ++j) pre += wcnt[j][d];
+            const int pos = base_off[d] + pre + rank;
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        int add = 0;
+        for (int j = 0; j < TPB / 64; ++j) add += wcnt[j][tid];
+        base_off[tid] += add;
+        __syncthreads();
+    }
+}
+
+// Sorts keyA/valA (n items, significant bits [0, nbits)); result ends in keyA/valA.
+static void radix_sort(Ctx &c, DevBuf &kA, DevBuf &vA, DevBuf &kB, DevBuf &vB, int64_t n, int nbits) {
+    if (n <= 1) return;
+    const int nblk = (int)cdiv(n, RS_TILE);
+    c.hist.ensure(sizeof(int) * 256 * (size_t)nblk);
+    kB.ensure(sizeof(uint64_t) * n);
+    vB.ensure(sizeof(uint32_t) * n);
+    const int passes = (nbits + 7) / 8;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        k_rs_hist<<<nblk, TPB, 0, c.stream>>>(kA.as<uint64_t>(), n, shift, c.hist.as<int>(), nblk);
+        VFMM_LAUNCH_CHECK();
+        scan_excl_i32(c, c.hist.as<int>(), c.hist.as<int>(), 256LL * nblk);
+        k_rs_scatter<<<nblk, TPB, 0, c.stream>>>(kA.as<uint64_t>(), vA.as<uint32_t>(), kB.as<uint64_t>(),
+                                                 vB.as<uint32_t>(), n, shift, c.hist.as<int>(), nblk);
+        VFMM_LAUNCH_CHECK();
+        std::swap(kA, kB);
+        std::swap(vA, vB);
+    }
+}
+
+void sort_pairs_u64(Ctx &c, DevBuf &kA, DevBuf &vA, DevBuf &kB, DevBuf &vB, int64_t n, int nbits) {
+    radix_sort(c, kA, vA, kB, vB, n, nbits);
+}
+
+// ---------------------------------------------------------------------------
+// Gather into Morton order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(TPB) void k_gather_pos(const uint32_t *perm, int64_t n, const float *x, const float *y,
+                                                    const float *z, const float *s, float4 *rec, int *perm_out) {
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t j = perm[i];
+    rec[2 * i] = make_float4(x[j], y[j], z[j], s[j]);
+    perm_out[i] = (int)j;
+}
+
+__global__ __launch_bounds__(TPB) void k_gather_alpha(const int *perm, int64_t n, const float *ax, const float *ay,
+                                                      const float *az, float4 *rec) {
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i >= n) return;
+    const int j = perm[i];
+    const float k = 0.0795774715459476679f;  // 1/(4 pi): the Green's function factor of G
+    rec[2 * i + 1] = make_float4(ax[j] * k, ay[j] * k, az[j] * k, 0.0f);
+}
+
+void gather_strengths(Ctx &c, const float *ax, const float *ay, const float *az, const float *) {
+    if (c.n == 0) return;
+    k_gather_alpha<<<cdiv(c.n, TPB), TPB, 0, c.stream>>>(c.perm.as<int>(), c.n, ax, ay, az, c.rec.as<float4>());
+    VFMM_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Octree, level by level.  A cell at level l holds a contiguous range of the
+// sorted keys sharing their top 3l bits; it is split while it holds more than
+// ncrit particles and l < 21.  Children of a cell are contiguous.
+// ---------------------------------------------------------------------------
+__device__ inline int octant_at(uint64_t key, int lchild) { return (int)((key >> (3 * (21 - lchild))) & 7); }
+
+__global__ __launch_bounds__(TPB) void k_count_children(int c0, int c1, int lvl, int ncrit, const int *start,
+                                                        const int *count, const uint64_t *keys, int *nchild) {
+    const int cell = c0 + blockIdx.x * TPB + threadIdx.x;
+    if (cell >= c1) return;
+    const int s = start[cell], cnt = count[cell];
+    int nc = 0;
+    if (cnt > ncrit && lvl < 21) {
+        // octants are non-decreasing along the range: count distinct values
+        int lo = s;
+        const int end = s + cnt;
+        while (lo < end) {
+            const int o = octant_at(keys[lo], lvl + 1);
+            // first index with octant > o
+            int a = lo, b = end;
+            while (a < b) {
+                const int mid = (a + b) >> 1;
+                if (octant_at(keys[mid], lvl + 1) <= o) a = mid + 1; else b = mid;
+            }
+            ++nc;
+            lo = a;
+        }
+    }
+    nchild[cell - c0] = nc;
+}
+
+__global__ __launch_bounds__(TPB) void k_make_children(int c0, int c1, int lvl, int cnext, const int *start,
+                                                       const int *count, const uint64_t *keys, const int *choff,
+                                                       const int *nchild_l, int *c_start, int *c_count,
+                                                       int *c_parent, int *c_child, int *c_nchild, int *c_level) {
+    const int cell = c0 + blockIdx.x * TPB + threadIdx.x;
+    if (cell >= c1) return;
+    const int nc = nchild_l[cell - c0];
+    c_nchild[cell] = nc;
+    if (nc == 0) { c_child[cell] = -1; return; }
+    const int first = cnext + choff[cell - c0];
+    c_child[cell] = first;
+    const int s = start[cell], end = s + count[cell];
+    int lo = s, k = 0;
+    while (lo < end) {
+        const int o = octant_at(keys[lo], lvl + 1);
+        int a = lo, b = end;
+        while (a < b) {
+            const int mid = (a + b) >> 1;
+            if (octant_at(keys[mid], lvl + 1) <= o) a = mid + 1; else b = mid;
+        }
+        const int ch = first + k;
+        c_start[ch] = lo;
+        c_count[ch] = a - lo;
+        c_parent[ch] = cell;
+        c_level[ch] = lvl + 1;
+        ++k;
+        lo = a;
+    }
+}
+
+// Centres from the key prefix of the first particle; leaves get their tight
+// radius (max distance of a particle from the cube centre) and bounding box.
+__global__ __launch_bounds__(TPB) void k_leaf_geometry(int ncell, RootBox box, const int *start, const int *count,
+                                                       const int *level, const int *nchild, const uint64_t *keys,
+                                                       const float4 *rec, float4 *geo, float *rad, float4 *blo,
+                                                       float4 *bhi) {
+    const int cell = blockIdx.x * TPB + threadIdx.x;
+    if (cell >= ncell) return;
+    const int lvl = level[cell];
+    const int s = start[cell];
+    const uint64_t key = keys[s];
+    // cell integer coordinates at this level
+    uint32_t q[3] = {0, 0, 0};
+    for (int b = 0; b < lvl; ++b) {
+        const int o = octant_at(key, b + 1);
+        q[0] = (q[0] << 1) | ((o >> 2) & 1);
+        q[1] = (q[1] << 1) | ((o >> 1) & 1);
+        q[2] = (q[2] << 1) | (o & 1);
+    }
+    const double size = (double)box.len / (double)(1u << lvl);
+    float4 g;
+    g.x = (float)(box.lo[0] + (q[0] + 0.5) * size);
+    g.y = (float)(box.lo[1] + (q[1] + 0.5) * size);
+    g.z = (float)(box.lo[2] + (q[2] + 0.5) * size);
+    g.w = (float)size;
+    geo[cell] = g;
+    if (nchild[cell] == 0) {
+        float r2 = 0.f;
+        float4 lo = make_float4(3.4e38f, 3.4e38f, 3.4e38f, 0.f), hi = make_float4(-3.4e38f, -3.4e38f, -3.4e38f, 0.f);
+        const int cnt = count[cell];
+        for (int i = s; i < s + cnt; ++i) {
+            const float4 p = rec[2 * i];
+            const float dx = p.x - g.x, dy = p.y - g.y, dz = p.z - g.z;
+            r2 = fmaxf(r2, dx * dx + dy * dy + dz * dz);
+            lo.x = fminf(lo.x, p.x); lo.y = fminf(lo.y, p.y); lo.z = fminf(lo.z, p.z);
+            hi.x = fmaxf(hi.x, p.x); hi.y = fmaxf(hi.y, p.y); hi.z = fmaxf(hi.z, p.z);
+        }
+        // round the radius up by a few ulps so float rounding never makes it short
+        rad[cell] = sqrtf(r2) * (1.0f + 4.0e-7f);
+        blo[cell] = lo;
+        bhi[cell] = hi;
+    }
+}
+
+// Internal cells, one level at a time bottom-up: radius bounded by the
+// children's spheres, bounding box the union of the children's boxes.
+__global__ __launch_bounds__(TPB) void k_internal_geometry(int c0, int c1, const int *child, const int *nchild,
+                                                           const float4 *geo, float *rad, float4 *blo, float4 *bhi) {
+    const int cell = c0 + blockIdx.x * TPB + threadIdx.x;
+    if (cell >= c1) return;
+    const int nc = nchild[cell];
+    if (nc == 0) return;
+    const float4 g = geo[cell];
+    float r = 0.f;
+    float4 lo = make_float4(3.4e38f, 3.4e38f, 3.4e38f, 0.f), hi = make_float4(-3.4e38f, -3.4e38f, -3.4e38f, 0.f);
+    const int f = child[cell];
+    for (int k = 0; k < nc; ++k) {
+        const float4 cg = geo[f + k];
+        const float dx = cg.x - g.x, dy = cg.y - g.y, dz = cg.z - g.z;
+        r = fmaxf(r, sqrtf(dx * dx + dy * dy + dz * dz) + rad[f + k]);
+        const float4 cl = blo[f + k], chh = bhi[f + k];
+        lo.x = fminf(lo.x, cl.x); lo.y = fminf(lo.y, cl.y); lo.z = fminf(lo.z, cl.z);
+        hi.x = fmaxf(hi.x, chh.x); hi.y = fmaxf(hi.y, chh.y); hi.z = fmaxf(hi.z, chh.z);
+    }
+    rad[cell] = r * (1.0f + 4.0e-7f);
+    blo[cell] = lo;
+    bhi[cell] = hi;
+}
+
+__global__ __launch_bounds__(TPB) void k_leaf_flags(int ncell, const int *nchild, int *flag) {
+    const int cell = blockIdx.x * TPB + threadIdx.x;
+    if (cell < ncell) flag[cell] = nchild[cell] == 0 ? 1 : 0;
+}
+
+__global__ __launch_bounds__(TPB) void k_leaf_compact(int ncell, const int *nchild, const int *pos, int *leaves) {
+    const int cell = blockIdx.x * TPB + threadIdx.x;
+    if (cell < ncell && nchild[cell] == 0) leaves[pos[cell]] = cell;
+}
+
+__global__ void k_root(int n, int *start, int *count, int *parent, int *level) {
+    start[0] = 0;
+    count[0] = n;
+    parent[0] = -1;
+    level[0] = 0;
+}
+
+// grow a cell array keeping its first `used` elements
+static void grow_keep(Ctx &c, DevBuf &b, size_t bytes, size_t used) {
+    if (bytes <= b.cap) return;
+    DevBuf nb;
+    nb.ensure(bytes * 2);
+    if (used) VFMM_HIP(hipMemcpyAsync(nb.ptr, b.ptr, used, hipMemcpyDeviceToDevice, c.stream));
+    VFMM_HIP(hipStreamSynchronize(c.stream));
+    b.release();
+    b = nb;
+}
+
+void build_tree(Ctx &c, int64_t n, const float *x, const float *y, const float *z, const float *sigma) {
+    hipStream_t s = c.stream;
+    // ---- Morton keys and sort ----
+    c.keyA.ensure(sizeof(uint64_t) * n);
+    c.valA.ensure(sizeof(uint32_t) * n);
+    k_morton<<<cdiv(n, TPB), TPB, 0, s>>>(x, y, z, n, c.box, c.keyA.as<uint64_t>(), c.valA.as<uint32_t>());
+    VFMM_LAUNCH_CHECK();
+    radix_sort(c, c.keyA, c.valA, c.keyB, c.valB, n, 63);
+    c.rec.ensure(sizeof(float4) * 2 * n);
+    c.perm.ensure(sizeof(int) * n);
+    k_gather_pos<<<cdiv(n, TPB), TPB, 0, s>>>(c.valA.as<uint32_t>(), n, x, y, z, sigma, c.rec.as<float4>(),
+                                               c.perm.as<int>());
+    VFMM_LAUNCH_CHECK();
+    if (c.ev_ok) VFMM_HIP(hipEventRecord(c.ev[2 * PH_BOUNDS_SORT + 1], s));
+    if (c.ev_ok) VFMM_HIP(hipEventRecord(c.ev[2 * PH_TREE], s));
+
+    // ---- levels ----
+    size_t cap = (size_t)std::max<int64_t>(64, 2 * n / std::max(1, c.prm.ncrit) + 64);
+    DevBuf *arrs[] = {&c.c_start, &c.c_count, &c.c_parent, &c.c_child, &c.c_nchild, &c.c_level};
+    for (DevBuf *b : arrs) b->ensure(sizeof(int) * cap);
+    cap = std::min(c.c_start.cap, std::min(c.c_count.cap, c.c_parent.cap)) / sizeof(int);
+    for (DevBuf *b : arrs) cap = std::min(cap, b->cap / sizeof(int));
+    k_root<<<1, 1, 0, s>>>((int)n, c.c_start.as<int>(), c.c_count.as<int>(), c.c_parent.as<int>(),
+                           c.c_level.as<int>());
+    VFMM_LAUNCH_CHECK();
+    c.lvl_off.assign(1, 0);
+    c.lvl_off.push_back(1);
+    int lvl = 0;
+    const uint64_t *keys = c.keyA.as<uint64_t>();
+    int h_tot[2];
+    for (;;) {
+        const int c0 = c.lvl_off[lvl], c1 = c.lvl_off[lvl + 1];
+        const int nl = c1 - c0;
+        c.c_tmp.ensure(sizeof(int) * (2 * (size_t)nl + 2));
+        int *nch = c.c_tmp.as<int>();
+        int *off = nch + nl + 1;
+        k_count_children<<<cdiv(nl, TPB), TPB, 0, s>>>(c0, c1, lvl, c.prm.ncrit, c.c_start.as<int>(),
+                                                        c.c_count.as<int>(), keys, nch);
+        VFMM_LAUNCH_CHECK();
+        scan_excl_i32(c, nch, off, nl);
+        VFMM_HIP(hipMemcpyAsync(&h_tot[0], off + nl - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+        VFMM_HIP(hipMemcpyAsync(&h_tot[1], nch + nl - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+        VFMM_HIP(hipStreamSynchronize(s));
+        const int total = h_tot[0] + h_tot[1];
+        if ((size_t)(c1 + total) > cap) {
+            const size_t ncap = (size_t)(c1 + total) * 2;
+            for (DevBuf *b : arrs) grow_keep(c, *b, sizeof(int) * ncap, sizeof(int) * (size_t)c1);
+            cap = ncap;
+        }
+        k_make_children<<<cdiv(nl, TPB), TPB, 0, s>>>(c0, c1, lvl, c1, c.c_start.as<int>(), c.c_count.as<int>(),
+                                                       keys, off, nch, c.c_start.as<int>(), c.c_count.as<int>(),
+                                                       c.c_parent.as<int>(), c.c_child.as<int>(),
+                                                       c.c_nchild.as<int>(), c.c_level.as<int>());
+        VFMM_LAUNCH_CHECK();
+        if (total == 0) break;
+        c.lvl_off.push_back(c1 + total);
+        ++lvl;
+    }
+    c.depth = lvl;
+    c.ncells = c.lvl_off.back();
+    const int nc = c.ncells;
+
+    // ---- geometry ----
+    c.c_geo.ensure(sizeof(float4) * nc);
+    c.c_rad.ensure(sizeof(float) * nc);
+    c.c_lo.ensure(sizeof(float4) * nc);
+    c.c_hi.ensure(sizeof(float4) * nc);
+    k_leaf_geometry<<<cdiv(nc, TPB), TPB, 0, s>>>(nc, c.box, c.c_start.as<int>(), c.c_count.as<int>(),
+                                                   c.c_level.as<int>(), c.c_nchild.as<int>(), keys,
+                                                   c.rec.as<float4>(), c.c_geo.as<float4>(), c.c_rad.as<float>(),
+                                                   c.c_lo.as<float4>(), c.c_hi.as<float4>());
+    VFMM_LAUNCH_CHECK();
+    for (int l = c.depth - 1; l >= 0; --l) {
+        const int c0 = c.lvl_off[l], c1 = c.lvl_off[l + 1];
+        k_internal_geometry<<<cdiv(c1 - c0, TPB), TPB, 0, s>>>(c0, c1, c.c_child.as<int>(), c.c_nchild.as<int>(),
+                                                                c.c_geo.as<float4>(), c.c_rad.as<float>(),
+                                                                c.c_lo.as<float4>(), c.c_hi.as<float4>());
+        VFMM_LAUNCH_CHECK();
+    }
+    // ---- leaf list ----
+    c.c_tmp.ensure(sizeof(int) * (2 * (size_t)nc + 2));
+    int *flag = c.c_tmp.as<int>();
+    int *pos = flag + nc + 1;
+    k_leaf_flags<<<cdiv(nc, TPB), TPB, 0, s>>>(nc, c.c_nchild.as<int>(), flag);
+    VFMM_LAUNCH_CHECK();
+    scan_excl_i32(c, flag, pos, nc);
+    VFMM_HIP(hipMemcpyAsync(&h_tot[0], pos + nc - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    VFMM_HIP(hipMemcpyAsync(&h_tot[1], flag + nc - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    VFMM_HIP(hipStreamSynchronize(s));
+    c.nleaves = h_tot[0] + h_tot[1];
+    c.leaves.ensure(sizeof(int) * (size_t)c.nleaves);
+    k_leaf_compact<<<cdiv(nc, TPB), TPB, 0, s>>>(nc, c.c_nchild.as<int>(), pos, c.leaves.as<int>());
+    VFMM_LAUNCH_CHECK();
+    if (c.ev_ok) VFMM_HIP(hipEventRecord(c.ev[2 * PH_TREE + 1], s));
+}
+
+}  // namespace vfmm
