@@ -21,7 +21,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FMM step time & P2P Gpair-interactions/s at 128^3 particles, p=10, ≤1e-4 err"
 PEAK_FP32_VALU_TFLOPS = 157.3        # 256 CU x 4 SIMD x 16 lanes x 2 (packed) x 2 (FMA) x 2.4 GHz
-FLOPS_PER_PAIR = 78                   # counted from the P2P kernel's main (s >= 1) pair body, FMA = 2
+FLOPS_PER_PAIR = 79                   # gfx950 ISA of the P2P pair body (s >= 1 form): 29 FMA + 16 MUL + 3 SUB + 2 TRANS, FMA = 2
 PAPER_FLOPS_PER_PAIR = 174            # Table 1 convention (70 + 104)
 
 
@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-check", action="store_true", help="skip the accuracy check against the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration for HBM bytes) and exit")
     return ap.parse_args()
 
 
@@ -94,6 +96,16 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}), flush=True)
+        return
 
     import paper_1106_5273_amd as vf
     import workloads as wl

@@ -287,8 +287,8 @@ void p2p_and_finalize(Ctx &c, float *ux, float *uy, float *uz, float *dax, float
 }
 
 // ---------------------------------------------------------------------------
-// Direct mode: every target block against all N sources (one list entry,
-// full cutoff form), in the caller's order, no tree and no far field.
+// Direct mode: every target block against all N sources (entries of 64
+// sources, full cutoff form), in the caller's order, no tree, no far field.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_direct_setup(int64_t n, const float *x, const float *y, const float *z,
                                                       const float *ax, const float *ay, const float *az,
@@ -301,10 +301,15 @@ __global__ __launch_bounds__(256) void k_direct_setup(int64_t n, const float *x,
     perm[i] = (int)i;
 }
 
+// Sources split into entries of 64 so that per-entry partial sums are blocked
+// exactly as in tree mode.
 __global__ __launch_bounds__(256) void k_direct_blocks(int64_t n, int nb, int4 *blocks, int4 *ent) {
     const int b = blockIdx.x * 256 + threadIdx.x;
-    if (b == 0) ent[0] = make_int4(0, (int)n, 0, 0);
-    if (b < nb) blocks[b] = make_int4(b * 64, (int)min<int64_t>(64, n - (int64_t)b * 64), 0, 1);
+    if (b < nb) {
+        const int cnt = (int)min<int64_t>(64, n - (int64_t)b * 64);
+        blocks[b] = make_int4(b * 64, cnt, 0, nb);
+        ent[b] = make_int4(b * 64, cnt, 0, 0);
+    }
 }
 
 void direct_all_pairs(Ctx &c, const float *x, const float *y, const float *z, const float *ax, const float *ay,
@@ -315,7 +320,7 @@ void direct_all_pairs(Ctx &c, const float *x, const float *y, const float *z, co
     c.perm.ensure(sizeof(int) * n);
     const int nb = (int)cdiv(n, 64);
     c.blocks.ensure(sizeof(int4) * nb);
-    c.p2p_ent.ensure(sizeof(int4));
+    c.p2p_ent.ensure(sizeof(int4) * nb);
     k_direct_setup<<<cdiv(n, 256), 256, 0, c.stream>>>(n, x, y, z, ax, ay, az, sigma, c.rec.as<float4>(),
                                                         c.perm.as<int>());
     VFMM_LAUNCH_CHECK();
