@@ -39,6 +39,12 @@ def parse():
     ap.add_argument("--no-check", action="store_true", help="skip the accuracy check against the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+                    help="c2: 128^3 periodic step (default, the headline line); c3: 256^3 plain vs "
+                         "compensated forms; c4: 512 batched ring problems vs sequential; c5: 256^3 "
+                         "autotuned RK2 step")
+    ap.add_argument("--microbench", action="store_true",
+                    help="only measure VALU FP32 FMA / exp2 / rsq issue rates and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration for HBM bytes) and exit")
     return ap.parse_args()
@@ -88,6 +94,101 @@ def cpu_baseline(case, seconds):
                       % (nt, n, dt)}
 
 
+def _line(metric, value, unit, ms, args, workload, extra, higher=True):
+    d = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+         "ms_per_step": ms, "higher_is_better": higher, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+         "data": "synthetic", "config": {"workload": workload}}
+    d.update(extra)
+    return d
+
+
+def bench_batched(args, vf, wl):
+    """512 independent free-space ring problems: one forest build + one
+    evaluation (replayed as a hipGraph) against 512 separate build+evaluate
+    calls on the same GPU."""
+    import numpy as np
+    import torch
+    probs, off = wl.ring_batch(512, seed=4)
+    cat = {k: np.concatenate([p[k] for p in probs]) for k in ("x", "y", "z", "ax", "ay", "az", "sigma")}
+    t = tuple(torch.from_numpy(cat[k]).cuda() for k in ("x", "y", "z", "ax", "ay", "az", "sigma"))
+    n = int(off[-1])
+    st = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    res = {}
+    with torch.cuda.stream(st):
+        out = tuple(torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(6))
+        ctx = vf.Context(p=8, use_graph=1, stream=st)
+        ctx.build_batched(off, t[0], t[1], t[2], t[6])
+        for _ in range(args.warmup):
+            ctx.evaluate(*t, out=out)
+        st.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.evaluate(*t, out=out)
+        st.synchronize()
+        res["batched_evaluate_graph_ms"] = (time.perf_counter() - t0) * 1e3 / args.steps
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.build_batched(off, t[0], t[1], t[2], t[6])
+        st.synchronize()
+        res["batched_build_ms"] = (time.perf_counter() - t0) * 1e3 / args.steps
+        stats = ctx.stats()
+        ctx.close()
+        # sequential: one context, 512 build+evaluate calls on slices
+        ctx = vf.Context(p=8, stream=st)
+        views = [tuple(x[off[b]:off[b + 1]] for x in t) for b in range(len(probs))]
+        outs = [tuple(o[off[b]:off[b + 1]] for o in out) for b in range(len(probs))]
+        for v, o in zip(views[:8], outs[:8]):
+            ctx.build(v[0], v[1], v[2], v[6])
+            ctx.evaluate(*v, out=o)
+        st.synchronize()
+        t0 = time.perf_counter()
+        for v, o in zip(views, outs):
+            ctx.build(v[0], v[1], v[2], v[6])
+            ctx.evaluate(*v, out=o)
+        st.synchronize()
+        res["sequential_build_evaluate_ms"] = (time.perf_counter() - t0) * 1e3
+        ctx.close()
+    total = res["batched_build_ms"] + res["batched_evaluate_graph_ms"]
+    line = _line("512 ring problems, build+evaluate throughput", n / (total * 1e-3) / 1e6, "Mparticles/s", total, args,
+                 "512 free-space Gaussian vortex rings, N log-uniform in [1024, 65536], p=8, batched forest",
+                 {"p2p_pairs": stats["p2p_pairs"], "n": n, "speedup_vs_sequential":
+                  res["sequential_build_evaluate_ms"] / total, **res})
+    print(json.dumps(line), flush=True)
+
+
+def bench_rk(args, vf, wl):
+    """256^3 periodic lattice: autotune (p, theta, ncrit) under rel-L2 <= 1e-4,
+    then time Heun RK2 steps (two builds + evaluations each)."""
+    import numpy as np
+    import torch
+    n1 = args.n if args.n != 128 else 256
+    case = wl.turbulence_case(n1, seed=5)
+    t = [x.clone() for x in vf.case_to_device(case)]
+    ctx = vf.Context(p=10, periodic=1, box_len=2 * np.pi, images=args.images)
+    tune = ctx.autotune(*t, max_rel_l2=1e-4)
+    h = 2 * np.pi / n1
+    ctx.build(t[0], t[1], t[2], t[6])
+    u = ctx.evaluate(*t)
+    umax = float(torch.sqrt(u[0] ** 2 + u[1] ** 2 + u[2] ** 2).max())
+    dt = 0.25 * h / umax
+    for _ in range(args.warmup):
+        ctx.rk_step(dt, 0.0, *t)
+    torch.cuda.synchronize()
+    ph = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.rk_step(dt, 0.0, *t)
+        ph.append(ctx.timings())
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    line = _line("RK2 step time at 256^3 (autotuned)", ms / 1e3, "s/step", ms, args,
+                 "periodic 256^3 turbulence-shaped lattice, Heun RK2 (2 x build+evaluate), autotuned",
+                 {"tune": tune, "dt": dt, "last_stage_phases_ms": {k: float(np.mean([p[k] for p in ph])) for k in ph[0]}},
+                 higher=False)
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -97,6 +198,21 @@ def main():
     import numpy as np
     import torch
 
+    if args.microbench:
+        import ctypes
+        mb = ctypes.CDLL(os.path.join(ROOT, "paper_1106_5273_amd", "libvfmm_mb.so"))
+        mb.vfmm_mb_rate.restype = ctypes.c_float
+        mb.vfmm_mb_rate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        blocks, iters = 256 * 64, 400
+        ops = blocks * 256.0 * iters * 16 * 8
+        res = {}
+        for kind, name in ((0, "fma_vector_operand"), (1, "fma_scalar_operand"), (2, "exp2"), (3, "rsq")):
+            ms = mb.vfmm_mb_rate(kind, blocks, iters if kind < 2 else iters // 4)
+            n_ops = ops if kind < 2 else ops / 4
+            res[name + "_lane_ops_per_s"] = n_ops / (ms * 1e-3)
+        res["fma_tflops"] = 2 * res["fma_vector_operand_lane_ops_per_s"] / 1e12
+        print(json.dumps(res), flush=True)
+        return
     if args.copy_calibration:
         nbytes = 1 << 30
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -111,6 +227,12 @@ def main():
     import workloads as wl
 
     torch.cuda.set_device(0)
+    if args.workload == "c4":
+        return bench_batched(args, vf, wl)
+    if args.workload == "c5":
+        return bench_rk(args, vf, wl)
+    if args.workload == "c3" and args.n == 128:
+        args.n = 256
     L = 2 * np.pi
     case = wl.turbulence_case(args.n, seed=2)
     t = vf.case_to_device(case)

@@ -54,6 +54,12 @@ typedef enum {
     VFMM_EHIP = -6     /* a HIP runtime call failed                                            */
 } vfmm_status;
 
+/* Arithmetic forms (vfmm_params.precision). */
+enum { VFMM_PRECISION_FP32 = 0,  /* float32 throughout (default)                                   */
+       VFMM_PRECISION_MIXED = 1, /* float32 with float64 or compensated accumulation of long sums  */
+       VFMM_PRECISION_FP64 = 2   /* float64 reference form of the same tree, lists and expansions  */
+};
+
 /* Stretching readings of Eq. (3). */
 enum { VFMM_SCHEME_TRANSPOSE = 0, /* (dalpha)_k = sum_l (du_l/dx_k) alpha_l : Eq. (3) as printed */
        VFMM_SCHEME_CLASSICAL = 1  /* (dalpha)_l = sum_k alpha_k du_l/dx_k : "omega . grad u"     */
@@ -72,6 +78,20 @@ typedef struct vfmm_params {
     int32_t kahan;       /* 1: compensated per-target sums in P2P (default 0: blocked sums)    */
     int32_t zero_mean;   /* periodic: subtract (1/3V) sum x_j x alpha_j (default 1)           */
     int32_t direct;      /* 1: all-pairs P2P without a tree (test mode; free space only)      */
+    int32_t m2l_mode;    /* 0: operator-batched M2L (default; falls back to 1 when the offsets of
+                            a tree are too spread to key), 1: per-pair M2L                     */
+    int32_t use_graph;   /* 1: fmm_evaluate runs as a hipGraph, captured on the first call after
+                            a build (or when its pointers change) and replayed afterwards; needs
+                            a non-default stream and the tree path (default 0)                */
+    int32_t precision;   /* VFMM_PRECISION_FP32 (default): float32 records, expansions and sums.
+                            VFMM_PRECISION_MIXED: as FP32, but compensated per-target P2P sums (as
+                            kahan = 1), float64 accumulation in M2M, L2L and in the reduction of
+                            the batched M2L's partial sums, float64 periodic lattice operator.
+                            VFMM_PRECISION_FP64: particle records, expansions, every far-field
+                            operator (M2L per pair) and P2P in float64 (cutoff always in its full
+                            form), outputs rounded to float32 once; with the same tree and lists
+                            as the other forms, its difference from them is their rounding error
+                            (Sec. 4.2 normalises the expansions so that float32 stays in range). */
 } vfmm_params;
 
 /* Per-phase device times of the last fmm_build / fmm_evaluate, in milliseconds,
@@ -138,6 +158,24 @@ vfmm_status fmm_evaluate(vfmm_ctx *ctx, int64_t n, const float *x, const float *
                          const float *ax, const float *ay, const float *az, const float *sigma,
                          float *ux, float *uy, float *uz, float *dax, float *day, float *daz);
 
+/* Batched form: nprob independent free-space problems stored back to back in
+ * the same arrays; problem b owns particles [offsets[b], offsets[b+1]).
+ * offsets is a HOST int64 array of nprob+1 entries with offsets[0] = 0 and
+ * every problem non-empty.  One forest is built (one root cube per problem;
+ * Morton keys carry the problem id above 3 x floor((63 - bits(nprob))/3)
+ * coordinate bits), so one fmm_evaluate(ctx, offsets[nprob], ...) evaluates
+ * every problem with the same kernel launches; no pair between two problems
+ * is ever formed.  Errors: VFMM_EINVAL (bad offsets, periodic or direct
+ * context, more than 2^20 problems) and those of fmm_build. */
+vfmm_status fmm_build_batched(vfmm_ctx *ctx, int32_t nprob, const int64_t *offsets, const float *x, const float *y,
+                              const float *z, const float *sigma);
+
+/* fmm_build_batched followed by fmm_evaluate on the concatenated arrays. */
+vfmm_status fmm_evaluate_batched(vfmm_ctx *ctx, int32_t nprob, const int64_t *offsets, const float *x,
+                                 const float *y, const float *z, const float *ax, const float *ay,
+                                 const float *az, const float *sigma, float *ux, float *uy, float *uz,
+                                 float *dax, float *day, float *daz);
+
 /* One Heun (RK2) step of the vortex-particle system, in place:
  *   stage 1: build + evaluate at (x, alpha);  x* = x + dt u, alpha* = alpha + dt dalpha
  *   stage 2: build + evaluate at (x*, alpha*); x += dt/2 (u + u*), alpha += dt/2 (dalpha + dalpha*)
@@ -147,6 +185,35 @@ vfmm_status fmm_evaluate(vfmm_ctx *ctx, int64_t n, const float *x, const float *
  * by the context.  Errors as fmm_build / fmm_evaluate. */
 vfmm_status rk_step(vfmm_ctx *ctx, int64_t n, float dt, float nu, float *x, float *y, float *z,
                     float *ax, float *ay, float *az, float *sigma);
+
+/* Result of vfmm_autotune. */
+typedef struct vfmm_tune_result {
+    int32_t p;             /* chosen expansion degree                                  */
+    float theta;           /* chosen acceptance parameter                              */
+    int32_t ncrit;         /* chosen leaf size                                         */
+    float err_u, err_dalpha; /* rel-L2 of u and dalpha vs the p=12, theta=0.35 reference */
+    float ms;              /* build + evaluate time of the chosen configuration        */
+    int32_t tried;         /* configurations timed                                     */
+    int32_t from_cache;    /* 1 when read from cache_path                              */
+} vfmm_tune_result;
+
+/* Choose p in {6,8,10,12}, theta in {0.3,...,0.7} and ncrit in {32,...,512}
+ * minimising the time of fmm_build + fmm_evaluate on these particles subject
+ * to rel-L2(u) <= max_rel_l2 and rel-L2(dalpha) <= max_rel_l2, where the error
+ * is measured against the library's own p = 12, theta = 0.35 evaluation of
+ * the same input.  Search: smallest feasible p for each theta at the context's
+ * ncrit, then ncrit at the best (theta, p) (p + 2 if accuracy drops).  Every
+ * candidate is built and evaluated twice on the GPU (the second is timed).
+ * The chosen values are written into the context's parameters (the caller
+ * builds again).  cache_path (may be NULL) is a text file of previous results
+ * keyed by n, periodicity, images, scheme, sigma_gap and max_rel_l2; a hit
+ * skips the search.  Synchronises.  Inputs are device float32[n] as for
+ * fmm_evaluate.  Errors: VFMM_EINVAL (null pointer, n <= 0, max_rel_l2 <= 0,
+ * direct context, no feasible configuration) and those of build/evaluate; on
+ * error the context's parameters are restored. */
+vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
+                          const float *ax, const float *ay, const float *az, const float *sigma,
+                          float max_rel_l2, const char *cache_path, vfmm_tune_result *out);
 
 /* Copy the per-phase times of the last build/evaluate to *out.  Synchronises
  * the context stream.  Errors: VFMM_EINVAL for null arguments. */

@@ -29,13 +29,20 @@ class Params(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("ncrit", ctypes.c_int32), ("theta", ctypes.c_float),
                 ("sigma_gap", ctypes.c_float), ("periodic", ctypes.c_int32), ("images", ctypes.c_int32),
                 ("box_lo", ctypes.c_double * 3), ("box_len", ctypes.c_double), ("scheme", ctypes.c_int32),
-                ("kahan", ctypes.c_int32), ("zero_mean", ctypes.c_int32), ("direct", ctypes.c_int32)]
+                ("kahan", ctypes.c_int32), ("zero_mean", ctypes.c_int32), ("direct", ctypes.c_int32),
+                ("m2l_mode", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("precision", ctypes.c_int32)]
 
 
 class Timings(ctypes.Structure):
     _fields_ = [(n, ctypes.c_float) for n in ("bounds_sort_ms", "tree_ms", "traverse_ms", "p2m_m2m_ms",
                                                "lattice_ms", "m2l_ms", "l2l_l2p_ms", "p2p_ms", "build_ms",
                                                "evaluate_ms")]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("theta", ctypes.c_float), ("ncrit", ctypes.c_int32),
+                ("err_u", ctypes.c_float), ("err_dalpha", ctypes.c_float), ("ms", ctypes.c_float),
+                ("tried", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -56,6 +63,9 @@ _lib.vfmm_set_params.argtypes = [_vp, ctypes.POINTER(Params)]
 _lib.fmm_build.argtypes = [_vp, _i64] + [_vp] * 4
 _lib.fmm_evaluate.argtypes = [_vp, _i64] + [_vp] * 13
 _lib.rk_step.argtypes = [_vp, _i64, ctypes.c_float, ctypes.c_float] + [_vp] * 7
+_lib.vfmm_autotune.argtypes = [_vp, _i64] + [_vp] * 7 + [ctypes.c_float, ctypes.c_char_p, ctypes.POINTER(TuneResult)]
+_lib.fmm_build_batched.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)] + [_vp] * 4
+_lib.fmm_evaluate_batched.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)] + [_vp] * 13
 _lib.vfmm_get_timings.argtypes = [_vp, ctypes.POINTER(Timings)]
 _lib.vfmm_get_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
 _lib.vfmm_copy_lists.argtypes = [_vp] + [_i32p] * 9
@@ -64,11 +74,12 @@ _lib.vfmm_last_error.restype = ctypes.c_char_p
 _lib.vfmm_destroy.argtypes = [_vp]
 _lib.vfmm_destroy.restype = None
 for _f in ("vfmm_create", "vfmm_set_params", "fmm_build", "fmm_evaluate", "rk_step", "vfmm_get_timings",
-           "vfmm_get_stats", "vfmm_copy_lists"):
+           "vfmm_get_stats", "vfmm_copy_lists", "fmm_build_batched", "fmm_evaluate_batched", "vfmm_autotune"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("vfmm_default_params", "vfmm_create", "vfmm_set_params", "fmm_build", "fmm_evaluate", "rk_step",
-            "vfmm_get_timings", "vfmm_get_stats", "vfmm_copy_lists", "vfmm_last_error", "vfmm_destroy")
+            "vfmm_get_timings", "vfmm_get_stats", "vfmm_copy_lists", "vfmm_last_error", "vfmm_destroy",
+            "fmm_build_batched", "fmm_evaluate_batched", "vfmm_autotune")
 
 
 class VfmmError(RuntimeError):
@@ -130,6 +141,16 @@ class Context:
             _check_tensor(t, n, nm)
         self._raise(_lib.fmm_build(self._h, n, _ptr(x), _ptr(y), _ptr(z), _ptr(sigma)))
 
+    def build_batched(self, offsets, x, y, z, sigma):
+        """offsets: host sequence of nprob+1 int64 (problem b owns [offsets[b], offsets[b+1]))."""
+        import numpy as np
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        n = int(off[-1])
+        for t, nm in ((x, "x"), (y, "y"), (z, "z"), (sigma, "sigma")):
+            _check_tensor(t, n, nm)
+        self._raise(_lib.fmm_build_batched(self._h, off.size - 1, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                           _ptr(x), _ptr(y), _ptr(z), _ptr(sigma)))
+
     def evaluate(self, x, y, z, ax, ay, az, sigma, out=None):
         """Returns (ux, uy, uz, dax, day, daz) as new tensors unless ``out`` is given."""
         import torch
@@ -147,6 +168,18 @@ class Context:
         for t, nm in ((x, "x"), (y, "y"), (z, "z"), (ax, "ax"), (ay, "ay"), (az, "az"), (sigma, "sigma")):
             _check_tensor(t, n, nm)
         self._raise(_lib.rk_step(self._h, n, float(dt), float(nu), *[_ptr(t) for t in (x, y, z, ax, ay, az, sigma)]))
+
+    def autotune(self, x, y, z, ax, ay, az, sigma, max_rel_l2=1e-4, cache_path=None):
+        """Runs vfmm_autotune; the context keeps the chosen parameters.  Returns a dict."""
+        n = x.numel()
+        for t, nm in ((x, "x"), (y, "y"), (z, "z"), (ax, "ax"), (ay, "ay"), (az, "az"), (sigma, "sigma")):
+            _check_tensor(t, n, nm)
+        r = TuneResult()
+        cp = cache_path.encode() if cache_path else None
+        self._raise(_lib.vfmm_autotune(self._h, n, *[_ptr(t) for t in (x, y, z, ax, ay, az, sigma)],
+                                       float(max_rel_l2), cp, ctypes.byref(r)))
+        self.params.p, self.params.theta, self.params.ncrit = r.p, r.theta, r.ncrit
+        return {f: getattr(r, f) for f, _ in TuneResult._fields_}
 
     def timings(self):
         t = Timings()

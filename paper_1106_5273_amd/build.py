@@ -12,8 +12,10 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libvfmm.so")
+MB_OUT = os.path.join(HERE, "libvfmm_mb.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "tree.hip", "traverse.hip", "far.hip", "p2p.hip", "lattice_host.cpp"]
+SOURCES = ["api.hip", "tree.hip", "traverse.hip", "far.hip", "m2lb.hip", "p2p.hip", "autotune.hip",
+           "lattice_host.cpp"]
 ARCH = os.environ.get("VFMM_ARCH", "gfx950")
 
 
@@ -52,6 +54,11 @@ def build(verbose=False, jobs=None):
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, OUT)
+    # VALU-rate microbenchmarks: a separate small library, not part of the C ABI
+    mb = compile_one("microbench.hip", verbose)
+    tmp = MB_OUT + ".tmp"
+    subprocess.check_call([hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp, mb])
+    os.replace(tmp, MB_OUT)
     return OUT
 
 

@@ -9,12 +9,17 @@ namespace vfmm {
 static std::string g_create_error;
 
 void Ctx::release_all() {
-    DevBuf *bufs[] = {&bpart, &bres, &keyA, &keyB, &valA, &valB, &hist, &scanA, &scanB, &scanC, &perm, &rec,
+    DevBuf *bufs[] = {&bpart, &bres, &keyA, &keyB, &valA, &valB, &hist, &scanA, &scanB, &scanC, &perm, &rec, &rec64,
                       &c_start, &c_count, &c_parent, &c_child, &c_nchild, &c_level, &c_geo, &c_rad, &c_lo, &c_hi,
                       &c_tmp, &leaves, &frA, &frB, &tcnt, &m2l_raw, &p2p_raw, &lkey, &lkey2, &lval, &lval2,
                       &m2l_off, &m2l_src, &p2p_off, &p2p_ent, &blocks, &pairs64, &Mexp, &Lexp, &lat_op, &far_u,
-                      &far_da, &dsurf, &rk};
+                      &far_da, &dsurf, &rk, &m2l_tgt, &mb_eq, &mb_flag, &mb_pos, &mb_kid, &mb_ukey,
+                      &mb_tab, &mb_bcells, &mb_ent, &mb_groups, &mb_blk, &mb_items, &mb_mr, &mb_partial, &pid, &pbox, &poff, &tune_ref, &tune_out, &tune_part};
     for (DevBuf *b : bufs) b->release();
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    graph_exec = nullptr;
+    graph = nullptr;
     if (ev_ok)
         for (auto &e : ev) (void)hipEventDestroy(e);
     ev_ok = false;
@@ -29,6 +34,11 @@ static void validate(const vfmm_params &p) {
     if (!(p.sigma_gap >= 0.f)) throw Error{VFMM_EINVAL, "sigma_gap must be >= 0"};
     if (p.scheme != VFMM_SCHEME_TRANSPOSE && p.scheme != VFMM_SCHEME_CLASSICAL)
         throw Error{VFMM_EINVAL, "scheme must be VFMM_SCHEME_TRANSPOSE or VFMM_SCHEME_CLASSICAL"};
+    if (p.m2l_mode != 0 && p.m2l_mode != 1) throw Error{VFMM_EINVAL, "m2l_mode must be 0 or 1"};
+    if (p.use_graph != 0 && p.use_graph != 1) throw Error{VFMM_EINVAL, "use_graph must be 0 or 1"};
+    if (p.use_graph && p.direct) throw Error{VFMM_EINVAL, "use_graph needs the tree path (direct = 0)"};
+    if (p.precision < VFMM_PRECISION_FP32 || p.precision > VFMM_PRECISION_FP64)
+        throw Error{VFMM_EINVAL, "precision must be VFMM_PRECISION_FP32, _MIXED or _FP64"};
     if (p.periodic) {
         if (!(p.box_len > 0.0) || !std::isfinite(p.box_len)) throw Error{VFMM_EINVAL, "periodic box_len must be > 0"};
         if (p.images < 1 || p.images > 12) throw Error{VFMM_EINVAL, "images must be in [1, 12]"};
@@ -71,24 +81,32 @@ static float ev_ms(Ctx &c, int a, int b) {
 
 static void upload_lattice(Ctx &c) {
     if (!c.prm.periodic || c.prm.images < 3) return;
-    if (c.lat_p == c.prm.p && c.lat_K == c.prm.images) return;
+    const int dbl = c.prm.precision != VFMM_PRECISION_FP32 ? 1 : 0;
+    if (c.lat_p == c.prm.p && c.lat_K == c.prm.images && c.lat_dbl == dbl) return;
     std::vector<double> op;
     lattice_operator_host(c.prm.p, c.prm.images, op);
-    std::vector<float> f(op.size());
-    for (size_t i = 0; i < op.size(); ++i) f[i] = (float)op[i];
-    c.lat_op.ensure(sizeof(float) * f.size());
-    VFMM_HIP(hipMemcpyAsync(c.lat_op.ptr, f.data(), sizeof(float) * f.size(), hipMemcpyHostToDevice, c.stream));
+    if (dbl) {
+        c.lat_op.ensure(sizeof(double) * op.size());
+        VFMM_HIP(hipMemcpyAsync(c.lat_op.ptr, op.data(), sizeof(double) * op.size(), hipMemcpyHostToDevice,
+                                c.stream));
+    } else {
+        std::vector<float> f(op.size());
+        for (size_t i = 0; i < op.size(); ++i) f[i] = (float)op[i];
+        c.lat_op.ensure(sizeof(float) * f.size());
+        VFMM_HIP(hipMemcpyAsync(c.lat_op.ptr, f.data(), sizeof(float) * f.size(), hipMemcpyHostToDevice, c.stream));
+    }
     VFMM_HIP(hipStreamSynchronize(c.stream));
     c.lat_p = c.prm.p;
     c.lat_K = c.prm.images;
+    c.lat_dbl = dbl;
 }
 
 static void do_build(Ctx &c, int64_t n, const float *x, const float *y, const float *z, const float *sigma) {
     ensure_events(c);
     c.built = false;
     hipStream_t s = c.stream;
-    VFMM_HIP(hipEventRecord(c.ev[2 * PH_NUM], s));
-    VFMM_HIP(hipEventRecord(c.ev[2 * PH_BOUNDS_SORT], s));
+    c.record(2 * PH_NUM);
+    c.record(2 * PH_BOUNDS_SORT);
     c.n = n;
     if (n == 0) {
         c.ncells = c.nleaves = c.n_p2p = c.n_blocks = 0;
@@ -101,6 +119,8 @@ static void do_build(Ctx &c, int64_t n, const float *x, const float *y, const fl
     VFMM_HIP(hipStreamSynchronize(s));
     if (c.hb.nonfinite) throw Error{VFMM_EDOMAIN, "non-finite position or non-positive core"};
     if (c.prm.periodic && c.hb.outside) throw Error{VFMM_EDOMAIN, "position outside the periodic cube"};
+    if (c.nprob > 1 && (c.prm.periodic || c.prm.direct))
+        throw Error{VFMM_EINVAL, "batched problems are free space and use the tree (periodic = 0, direct = 0)"};
     if (c.hb.sig_max > c.hb.sig_min * (1.0 + 1e-6))
         throw Error{VFMM_EINVAL, "cores must be uniform (variable sigma is not supported by this build)"};
     c.sigma_uniform = (float)c.hb.sig_max;
@@ -111,6 +131,8 @@ static void do_build(Ctx &c, int64_t n, const float *x, const float *y, const fl
     if (c.prm.periodic) {
         for (int d = 0; d < 3; ++d) c.box.lo[d] = (float)c.prm.box_lo[d];
         c.box.len = (float)c.prm.box_len;
+    } else if (c.nprob > 1) {
+        // one root cube per problem, computed on the device by the tree build
     } else {
         double len = 0.0, ctr[3];
         for (int d = 0; d < 3; ++d) {
@@ -124,10 +146,15 @@ static void do_build(Ctx &c, int64_t n, const float *x, const float *y, const fl
     }
     upload_lattice(c);
     build_tree(c, n, x, y, z, sigma);
-    VFMM_HIP(hipEventRecord(c.ev[2 * PH_TRAVERSE], s));
+    c.record(2 * PH_TRAVERSE);
     traverse_and_lists(c);
-    VFMM_HIP(hipEventRecord(c.ev[2 * PH_TRAVERSE + 1], s));
-    VFMM_HIP(hipEventRecord(c.ev[2 * PH_NUM + 1], s));
+    c.m2lb_ok = false;
+    if (c.prm.m2l_mode == 0 && c.prm.precision != VFMM_PRECISION_FP64) m2lb_plan(c);
+    far_prealloc(c);
+    m2lb_prealloc(c);
+    ++c.build_id;
+    c.record(2 * PH_TRAVERSE + 1);
+    c.record(2 * PH_NUM + 1);
     c.build_timed = true;
     c.built = true;
 }
@@ -137,9 +164,9 @@ static void do_evaluate(Ctx &c, int64_t n, const float *x, const float *y, const
                         float *dax, float *day, float *daz) {
     ensure_events(c);
     hipStream_t s = c.stream;
-    VFMM_HIP(hipEventRecord(c.ev[2 * PH_NUM + 2], s));
+    c.record(2 * PH_NUM + 2);
     if (n == 0) {
-        VFMM_HIP(hipEventRecord(c.ev[2 * PH_NUM + 3], s));
+        c.record(2 * PH_NUM + 3);
         return;
     }
     compute_bounds(c, n, x, y, z, sigma, ax, ay, az, true);
@@ -147,11 +174,72 @@ static void do_evaluate(Ctx &c, int64_t n, const float *x, const float *y, const
         direct_all_pairs(c, x, y, z, ax, ay, az, sigma, ux, uy, uz, dax, day, daz);
     } else {
         gather_strengths(c, ax, ay, az, sigma);
+        if (c.prm.precision == VFMM_PRECISION_FP64) gather_records64(c, ax, ay, az);
         far_field(c);
         p2p_and_finalize(c, ux, uy, uz, dax, day, daz);
     }
-    VFMM_HIP(hipEventRecord(c.ev[2 * PH_NUM + 3], s));
+    c.record(2 * PH_NUM + 3);
     c.eval_timed = true;
+}
+
+// Evaluation through a hipGraph: captured on the first call after a build (or
+// when the arguments change), replayed afterwards.
+static void graph_evaluate(Ctx &c, int64_t n, const float *const *in, float *const *out) {
+    std::vector<const void *> args(in, in + 7);
+    args.insert(args.end(), out, out + 6);
+    args.push_back((const void *)(intptr_t)n);
+    if (!c.graph_exec || c.graph_build_id != c.build_id || args != c.graph_args) {
+        if (c.graph_exec) VFMM_HIP(hipGraphExecDestroy(c.graph_exec));
+        if (c.graph) VFMM_HIP(hipGraphDestroy(c.graph));
+        c.graph_exec = nullptr;
+        c.graph = nullptr;
+        if (c.stream == nullptr) throw Error{VFMM_EINVAL, "use_graph needs a non-default stream"};
+        VFMM_HIP(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+        c.capturing = true;
+        try {
+            do_evaluate(c, n, in[0], in[1], in[2], in[3], in[4], in[5], in[6], out[0], out[1], out[2], out[3],
+                        out[4], out[5]);
+        } catch (...) {
+            c.capturing = false;
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(c.stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        c.capturing = false;
+        VFMM_HIP(hipStreamEndCapture(c.stream, &c.graph));
+        VFMM_HIP(hipGraphInstantiate(&c.graph_exec, c.graph, nullptr, nullptr, 0));
+        c.graph_args = args;
+        c.graph_build_id = c.build_id;
+    }
+    c.record(2 * PH_NUM + 2);
+    VFMM_HIP(hipGraphLaunch(c.graph_exec, c.stream));
+    c.record(2 * PH_NUM + 3);
+    c.eval_timed = true;
+}
+
+static void read_timings(Ctx &c, vfmm_timings *out) {
+    std::memset(out, 0, sizeof(*out));
+    if (!c.ev_ok) return;
+    VFMM_HIP(hipStreamSynchronize(c.stream));
+    if (c.build_timed && !c.prm.direct && c.n > 0) {
+        out->bounds_sort_ms = ev_ms(c, 2 * PH_BOUNDS_SORT, 2 * PH_BOUNDS_SORT + 1);
+        out->tree_ms = ev_ms(c, 2 * PH_TREE, 2 * PH_TREE + 1);
+        out->traverse_ms = ev_ms(c, 2 * PH_TRAVERSE, 2 * PH_TRAVERSE + 1);
+        out->build_ms = ev_ms(c, 2 * PH_NUM, 2 * PH_NUM + 1);
+    }
+    if (c.eval_timed && c.n > 0) {
+        if (!c.prm.direct && !c.prm.use_graph) {
+            out->p2m_m2m_ms = ev_ms(c, 2 * PH_P2M_M2M, 2 * PH_P2M_M2M + 1);
+            out->lattice_ms = ev_ms(c, 2 * PH_LATTICE, 2 * PH_LATTICE + 1);
+            out->m2l_ms = ev_ms(c, 2 * PH_M2L, 2 * PH_M2L + 1);
+            out->l2l_l2p_ms = ev_ms(c, 2 * PH_L2L_L2P, 2 * PH_L2L_L2P + 1);
+            out->p2p_ms = ev_ms(c, 2 * PH_P2P, 2 * PH_P2P + 1);
+        } else if (c.prm.direct) {
+            out->p2p_ms = ev_ms(c, 2 * PH_P2P, 2 * PH_P2P + 1);
+        }
+        out->evaluate_ms = ev_ms(c, 2 * PH_NUM + 2, 2 * PH_NUM + 3);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -226,6 +314,7 @@ static void do_rk(Ctx &c, int64_t n, float dt, float nu, float *x, float *y, flo
     A.len = (float)c.prm.box_len;
     do_build(c, n, x, y, z, sigma);
     do_evaluate(c, n, x, y, z, ax, ay, az, sigma, U1, U1 + n, U1 + 2 * n, U1 + 3 * n, U1 + 4 * n, U1 + 5 * n);
+    read_timings(c, &c.t_stage1);
     k_rk_pred<<<cdiv(n, 256), 256, 0, c.stream>>>(A, x, y, z, ax, ay, az, sigma, U1, X);
     VFMM_LAUNCH_CHECK();
     do_build(c, n, X, X + n, X + 2 * n, X + 6 * n);
@@ -235,16 +324,26 @@ static void do_rk(Ctx &c, int64_t n, float dt, float nu, float *x, float *y, flo
     VFMM_LAUNCH_CHECK();
     // the tree now describes the predictor positions
     c.built = false;
+    c.last_was_rk = true;
 }
 
 }  // namespace vfmm
 
+namespace vfmm {
+void do_build_public(Ctx &c, int64_t n, const float *x, const float *y, const float *z, const float *sigma) {
+    c.nprob = 1;
+    do_build(c, n, x, y, z, sigma);
+}
+void do_evaluate_public(Ctx &c, int64_t n, const float *x, const float *y, const float *z, const float *ax,
+                        const float *ay, const float *az, const float *sigma, float *ux, float *uy, float *uz,
+                        float *dax, float *day, float *daz) {
+    do_evaluate(c, n, x, y, z, ax, ay, az, sigma, ux, uy, uz, dax, day, daz);
+}
+void set_params_public(Ctx &c, const vfmm_params &p) { set_params(c, p); }
+}  // namespace vfmm
+
 using vfmm::Ctx;
 using vfmm::Error;
-
-struct vfmm_ctx {
-    Ctx c;
-};
 
 extern "C" {
 
@@ -262,6 +361,8 @@ void vfmm_default_params(vfmm_params *p) {
     p->kahan = 0;
     p->zero_mean = 1;
     p->direct = 0;
+    p->m2l_mode = 0;
+    p->use_graph = 0;
 }
 
 vfmm_status vfmm_create(const vfmm_params *params, void *hip_stream, vfmm_ctx **out) {
@@ -312,12 +413,51 @@ vfmm_status fmm_build(vfmm_ctx *ctx, int64_t n, const float *x, const float *y, 
         if (n < 0 || n >= (1LL << 31)) throw Error{VFMM_EINVAL, "n must be in [0, 2^31)"};
         if (n > 0 && (!x || !y || !z || !sigma)) throw Error{VFMM_EINVAL, "null input pointer"};
         c.err.clear();
+        c.nprob = 1;
+        c.last_was_rk = false;
         vfmm::do_build(c, n, x, y, z, sigma);
         return VFMM_OK;
     } catch (const Error &e) {
         c.built = false;
         return vfmm::fail(&c, e);
     }
+}
+
+vfmm_status fmm_build_batched(vfmm_ctx *ctx, int32_t nprob, const int64_t *offsets, const float *x, const float *y,
+                              const float *z, const float *sigma) {
+    if (!ctx) return VFMM_EINVAL;
+    Ctx &c = ctx->c;
+    try {
+        if (nprob < 1 || !offsets) throw Error{VFMM_EINVAL, "nprob must be >= 1 with an offsets array"};
+        if (offsets[0] != 0) throw Error{VFMM_EINVAL, "offsets[0] must be 0"};
+        for (int b = 0; b < nprob; ++b)
+            if (offsets[b + 1] <= offsets[b]) throw Error{VFMM_EINVAL, "every problem needs at least one particle"};
+        const int64_t n = offsets[nprob];
+        if (n >= (1LL << 31)) throw Error{VFMM_EINVAL, "n must be in [0, 2^31)"};
+        if (nprob > 1 << 20) throw Error{VFMM_EINVAL, "at most 2^20 problems"};
+        if (!x || !y || !z || !sigma) throw Error{VFMM_EINVAL, "null input pointer"};
+        c.err.clear();
+        c.last_was_rk = false;
+        c.nprob = nprob;
+        c.h_poff.assign(offsets, offsets + nprob + 1);
+        c.poff.ensure(sizeof(int64_t) * (nprob + 1));
+        VFMM_HIP(hipMemcpyAsync(c.poff.ptr, c.h_poff.data(), sizeof(int64_t) * (nprob + 1), hipMemcpyHostToDevice,
+                                c.stream));
+        vfmm::do_build(c, n, x, y, z, sigma);
+        return VFMM_OK;
+    } catch (const Error &e) {
+        c.built = false;
+        c.nprob = 1;
+        return vfmm::fail(&c, e);
+    }
+}
+
+vfmm_status fmm_evaluate_batched(vfmm_ctx *ctx, int32_t nprob, const int64_t *offsets, const float *x, const float *y,
+                                 const float *z, const float *ax, const float *ay, const float *az, const float *sigma,
+                                 float *ux, float *uy, float *uz, float *dax, float *day, float *daz) {
+    const vfmm_status st = fmm_build_batched(ctx, nprob, offsets, x, y, z, sigma);
+    if (st != VFMM_OK) return st;
+    return fmm_evaluate(ctx, offsets[nprob], x, y, z, ax, ay, az, sigma, ux, uy, uz, dax, day, daz);
 }
 
 vfmm_status fmm_evaluate(vfmm_ctx *ctx, int64_t n, const float *x, const float *y, const float *z, const float *ax,
@@ -342,7 +482,13 @@ vfmm_status fmm_evaluate(vfmm_ctx *ctx, int64_t n, const float *x, const float *
             }
         }
         c.err.clear();
-        vfmm::do_evaluate(c, n, x, y, z, ax, ay, az, sigma, ux, uy, uz, dax, day, daz);
+        if (c.prm.use_graph && n > 0) {
+            const float *in[7] = {x, y, z, ax, ay, az, sigma};
+            float *out[6] = {ux, uy, uz, dax, day, daz};
+            vfmm::graph_evaluate(c, n, in, out);
+        } else {
+            vfmm::do_evaluate(c, n, x, y, z, ax, ay, az, sigma, ux, uy, uz, dax, day, daz);
+        }
         return VFMM_OK;
     } catch (const Error &e) {
         return vfmm::fail(&c, e);
@@ -359,6 +505,7 @@ vfmm_status rk_step(vfmm_ctx *ctx, int64_t n, float dt, float nu, float *x, floa
         if (!std::isfinite(dt) || !std::isfinite(nu) || nu < 0.f) throw Error{VFMM_EINVAL, "bad dt or nu"};
         if (c.prm.direct && c.prm.periodic) throw Error{VFMM_EINVAL, "direct mode is free space only"};
         c.err.clear();
+        c.nprob = 1;
         vfmm::do_rk(c, n, dt, nu, x, y, z, ax, ay, az, sigma);
         return VFMM_OK;
     } catch (const Error &e) {
@@ -370,30 +517,17 @@ vfmm_status rk_step(vfmm_ctx *ctx, int64_t n, float dt, float nu, float *x, floa
 vfmm_status vfmm_get_timings(vfmm_ctx *ctx, vfmm_timings *out) {
     if (!ctx || !out) return VFMM_EINVAL;
     Ctx &c = ctx->c;
-    std::memset(out, 0, sizeof(*out));
-    if (!c.ev_ok) return VFMM_OK;
-    if (hipStreamSynchronize(c.stream) != hipSuccess) {
-        c.err = "stream synchronisation failed";
-        return VFMM_EHIP;
-    }
-    using namespace vfmm;
-    if (c.build_timed && !c.prm.direct && c.n > 0) {
-        out->bounds_sort_ms = ev_ms(c, 2 * PH_BOUNDS_SORT, 2 * PH_BOUNDS_SORT + 1);
-        out->tree_ms = ev_ms(c, 2 * PH_TREE, 2 * PH_TREE + 1);
-        out->traverse_ms = ev_ms(c, 2 * PH_TRAVERSE, 2 * PH_TRAVERSE + 1);
-        out->build_ms = ev_ms(c, 2 * PH_NUM, 2 * PH_NUM + 1);
-    }
-    if (c.eval_timed && c.n > 0) {
-        if (!c.prm.direct) {
-            out->p2m_m2m_ms = ev_ms(c, 2 * PH_P2M_M2M, 2 * PH_P2M_M2M + 1);
-            out->lattice_ms = ev_ms(c, 2 * PH_LATTICE, 2 * PH_LATTICE + 1);
-            out->m2l_ms = ev_ms(c, 2 * PH_M2L, 2 * PH_M2L + 1);
-            out->l2l_l2p_ms = ev_ms(c, 2 * PH_L2L_L2P, 2 * PH_L2L_L2P + 1);
+    try {
+        vfmm::read_timings(c, out);
+        if (c.last_was_rk) {
+            float *a = reinterpret_cast<float *>(out);
+            const float *b = reinterpret_cast<const float *>(&c.t_stage1);
+            for (size_t i = 0; i < sizeof(vfmm_timings) / sizeof(float); ++i) a[i] += b[i];
         }
-        out->p2p_ms = ev_ms(c, 2 * PH_P2P, 2 * PH_P2P + 1);
-        out->evaluate_ms = ev_ms(c, 2 * PH_NUM + 2, 2 * PH_NUM + 3);
+        return VFMM_OK;
+    } catch (const Error &e) {
+        return vfmm::fail(&c, e);
     }
-    return VFMM_OK;
 }
 
 vfmm_status vfmm_get_stats(vfmm_ctx *ctx, vfmm_stats *out) {

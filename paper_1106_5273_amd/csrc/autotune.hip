@@ -1,0 +1,200 @@
+// Autotuner: chooses the expansion degree p, the acceptance parameter theta
+// and the leaf size ncrit that minimise the time of one build + evaluate on
+// the caller's particles while keeping the relative L2 error of u and of
+// dalpha/dt below a bound.  The error of each candidate is measured against
+// the library's own high-accuracy configuration (p = 12, theta = 0.35) on
+// the same input.  The paper fixes p and does not tune (Sec. 4.2); this is a
+// library feature for choosing the accuracy/time operating point.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+
+#include "ctx.h"
+
+namespace vfmm {
+
+void do_build_public(Ctx &c, int64_t n, const float *x, const float *y, const float *z, const float *sigma);
+void do_evaluate_public(Ctx &c, int64_t n, const float *x, const float *y, const float *z, const float *ax,
+                        const float *ay, const float *az, const float *sigma, float *ux, float *uy, float *uz,
+                        float *dax, float *day, float *daz);
+void set_params_public(Ctx &c, const vfmm_params &p);
+
+// sums of (a - b)^2 and b^2 over the u block (3n) and the dalpha block (3n)
+__global__ __launch_bounds__(256) void k_err_partial(int64_t n3, const float *a, const float *b, double *part) {
+    __shared__ double s[4][256];
+    double du = 0, ru = 0, dd = 0, rd = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (int64_t)gridDim.x * 256) {
+        const double x = a[i], y = b[i], x2 = a[n3 + i], y2 = b[n3 + i];
+        du += (x - y) * (x - y);
+        ru += y * y;
+        dd += (x2 - y2) * (x2 - y2);
+        rd += y2 * y2;
+    }
+    s[0][threadIdx.x] = du; s[1][threadIdx.x] = ru; s[2][threadIdx.x] = dd; s[3][threadIdx.x] = rd;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            for (int q = 0; q < 4; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 4; ++q) part[4 * blockIdx.x + q] = s[q][0];
+}
+
+static void rel_errors(Ctx &c, int64_t n, const float *a, const float *b, double &eu, double &ed) {
+    const int nb = 512;
+    c.tune_part.ensure(sizeof(double) * 4 * nb);
+    k_err_partial<<<nb, 256, 0, c.stream>>>(3 * n, a, b, c.tune_part.as<double>());
+    VFMM_LAUNCH_CHECK();
+    std::vector<double> h(4 * nb);
+    VFMM_HIP(hipMemcpyAsync(h.data(), c.tune_part.ptr, sizeof(double) * 4 * nb, hipMemcpyDeviceToHost, c.stream));
+    VFMM_HIP(hipStreamSynchronize(c.stream));
+    double s[4] = {0, 0, 0, 0};
+    for (int i = 0; i < nb; ++i)
+        for (int q = 0; q < 4; ++q) s[q] += h[4 * i + q];
+    eu = s[1] > 0 ? std::sqrt(s[0] / s[1]) : 0.0;
+    ed = s[3] > 0 ? std::sqrt(s[2] / s[3]) : 0.0;
+}
+
+static std::string cache_key(const Ctx &c, int64_t n, float tol) {
+    std::ostringstream k;
+    k << "n=" << n << " periodic=" << c.prm.periodic << " images=" << c.prm.images << " scheme=" << c.prm.scheme
+      << " sigma_gap=" << c.prm.sigma_gap << " tol=" << tol;
+    return k.str();
+}
+
+struct Trial {
+    int p, ncrit;
+    float theta;
+    double eu, ed, ms;
+    bool ok;
+};
+
+}  // namespace vfmm
+
+using vfmm::Ctx;
+using vfmm::Error;
+
+extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
+                                     const float *ax, const float *ay, const float *az, const float *sigma,
+                                     float max_rel_l2, const char *cache_path, vfmm_tune_result *out) {
+    if (!ctx || !out) return VFMM_EINVAL;
+    Ctx &c = ctx->c;
+    const vfmm_params base = c.prm;
+    try {
+        if (n <= 0 || !x || !y || !z || !ax || !ay || !az || !sigma)
+            throw Error{VFMM_EINVAL, "autotune needs n > 0 and every input"};
+        if (!(max_rel_l2 > 0.f)) throw Error{VFMM_EINVAL, "max_rel_l2 must be > 0"};
+        if (c.prm.direct) throw Error{VFMM_EINVAL, "autotune applies to the tree path (direct = 0)"};
+        std::memset(out, 0, sizeof(*out));
+        const std::string key = vfmm::cache_key(c, n, max_rel_l2);
+        if (cache_path) {
+            std::ifstream in(cache_path);
+            std::string line;
+            while (std::getline(in, line)) {
+                const size_t bar = line.find(" | ");
+                if (bar == std::string::npos || line.substr(0, bar) != key) continue;
+                std::istringstream v(line.substr(bar + 3));
+                vfmm_tune_result r{};
+                if (v >> r.p >> r.theta >> r.ncrit >> r.err_u >> r.err_dalpha >> r.ms) {
+                    r.from_cache = 1;
+                    *out = r;
+                }
+            }
+            if (out->from_cache) {
+                vfmm_params p = base;
+                p.p = out->p;
+                p.theta = out->theta;
+                p.ncrit = out->ncrit;
+                vfmm::set_params_public(c, p);
+                return VFMM_OK;
+            }
+        }
+        c.tune_ref.ensure(sizeof(float) * 6 * (size_t)n);
+        c.tune_out.ensure(sizeof(float) * 6 * (size_t)n);
+        float *R = c.tune_ref.as<float>(), *O = c.tune_out.as<float>();
+        auto run = [&](int p, float theta, int ncrit, float *dst, double &ms) {
+            vfmm_params q = base;
+            q.p = p;
+            q.theta = theta;
+            q.ncrit = ncrit;
+            q.use_graph = 0;
+            vfmm::set_params_public(c, q);
+            // first pass warms the buffers; the second is timed
+            for (int rep = 0; rep < 2; ++rep) {
+                vfmm::do_build_public(c, n, x, y, z, sigma);
+                vfmm::do_evaluate_public(c, n, x, y, z, ax, ay, az, sigma, dst, dst + n, dst + 2 * n, dst + 3 * n,
+                                         dst + 4 * n, dst + 5 * n);
+            }
+            VFMM_HIP(hipStreamSynchronize(c.stream));
+            float b = 0.f, e = 0.f;
+            VFMM_HIP(hipEventElapsedTime(&b, c.ev[2 * vfmm::PH_NUM], c.ev[2 * vfmm::PH_NUM + 1]));
+            VFMM_HIP(hipEventElapsedTime(&e, c.ev[2 * vfmm::PH_NUM + 2], c.ev[2 * vfmm::PH_NUM + 3]));
+            ms = (double)b + (double)e;
+        };
+        double ref_ms = 0;
+        run(12, 0.35f, base.ncrit, R, ref_ms);
+        std::vector<vfmm::Trial> trials;
+        auto trial = [&](int p, float theta, int ncrit) {
+            for (const auto &t : trials)
+                if (t.p == p && t.ncrit == ncrit && std::fabs(t.theta - theta) < 1e-6f) return t;
+            vfmm::Trial t{p, ncrit, theta, 0, 0, 0, false};
+            run(p, theta, ncrit, O, t.ms);
+            vfmm::rel_errors(c, n, O, R, t.eu, t.ed);
+            t.ok = t.eu <= max_rel_l2 && t.ed <= max_rel_l2;
+            trials.push_back(t);
+            return t;
+        };
+        const int ps[] = {6, 8, 10, 12};
+        const float thetas[] = {0.3f, 0.4f, 0.5f, 0.6f, 0.7f};
+        const int ncrits[] = {32, 64, 128, 256, 512};
+        // (theta, p) at the caller's ncrit: smallest feasible p per theta
+        for (float th : thetas)
+            for (int p : ps)
+                if (trial(p, th, base.ncrit).ok) break;
+        auto best_of = [&]() {
+            const vfmm::Trial *b = nullptr;
+            for (const auto &t : trials)
+                if (t.ok && (!b || t.ms < b->ms)) b = &t;
+            return b;
+        };
+        const vfmm::Trial *b = best_of();
+        if (!b) throw Error{VFMM_EINVAL, "no configuration reaches the requested accuracy"};
+        const int bp = b->p;
+        const float bth = b->theta;
+        // leaf size at the best (theta, p), raising p once if accuracy drops
+        for (int nc : ncrits) {
+            if (nc == base.ncrit) continue;
+            if (!trial(bp, bth, nc).ok && bp + 2 <= 12) trial(bp + 2, bth, nc);
+        }
+        b = best_of();
+        out->p = b->p;
+        out->theta = b->theta;
+        out->ncrit = b->ncrit;
+        out->err_u = (float)b->eu;
+        out->err_dalpha = (float)b->ed;
+        out->ms = (float)b->ms;
+        out->tried = (int)trials.size();
+        out->from_cache = 0;
+        vfmm_params p = base;
+        p.p = b->p;
+        p.theta = b->theta;
+        p.ncrit = b->ncrit;
+        vfmm::set_params_public(c, p);
+        if (cache_path) {
+            std::ofstream o(cache_path, std::ios::app);
+            o << key << " | " << out->p << " " << out->theta << " " << out->ncrit << " " << out->err_u << " "
+              << out->err_dalpha << " " << out->ms << "\n";
+        }
+        return VFMM_OK;
+    } catch (const Error &e) {
+        try {
+            vfmm::set_params_public(c, base);
+        } catch (...) {
+        }
+        c.err = e.msg;
+        return e.st;
+    }
+}

@@ -27,6 +27,9 @@ struct Ctx {
     int n_p2p = 0, n_blocks = 0;
     int64_t n_m2l = 0, p2p_pairs = 0;
     int img_B = 0, img_codes = 1;
+    int nprob = 1;                       // independent problems in the tree (forest)
+    int key_levels = 21;                 // Morton levels per axis below the problem id
+    std::vector<int64_t> h_poff;         // problem offsets (host)
     int images_traversed = 0;
 
     // ---- device buffers (grow-only) ----
@@ -34,7 +37,9 @@ struct Ctx {
     DevBuf keyA, keyB, valA, valB;       // sort ping-pong (uint64 keys, uint32 values)
     DevBuf hist, scanA, scanB, scanC;    // sort histogram, scan scratch
     DevBuf perm;                         // sorted position -> caller index (int)
+    DevBuf pid, pbox, poff;              // batched problems: id per particle, root cubes, offsets
     DevBuf rec;                          // float4[2n]: (x,y,z,sigma) (ax,ay,az,0)/(4 pi)
+    DevBuf rec64;                        // double4[2n]: the same records, float64 form only
     // cells
     DevBuf c_start, c_count, c_parent, c_child, c_nchild, c_level;  // int
     DevBuf c_geo;                        // float4 (cx, cy, cz, size)
@@ -48,28 +53,51 @@ struct Ctx {
     DevBuf m2l_raw, p2p_raw;             // unsorted (tgt,src,img) int4
     DevBuf lkey, lkey2, lval, lval2;     // list sort
     DevBuf m2l_off, m2l_src;             // CSR by target cell: int offsets[ncells+1], int2 (src, img)
+    DevBuf m2l_tgt;                      // target cell of each CSR entry
     DevBuf p2p_off, p2p_ent;             // CSR by target cell: int offsets, int4 (start, count, img, variant)
     DevBuf blocks;                       // int4 (tgt start, tgt count, list off, list count)
     DevBuf pairs64;                      // int64 reduction scratch
     // expansions
     DevBuf Mexp, Lexp;                   // float2 [ncells][3][NC(p)]
     DevBuf lat_op;                       // float [2NC x 2NC] periodic lattice operator
-    int lat_p = -1, lat_K = -1;
+    int lat_p = -1, lat_K = -1, lat_dbl = -1;
     double lat_len = 0.0;
+    // operator-batched M2L plan
+    bool m2lb_ok = false;
+    int mb_nblk = 0, mb_nkeys = 0, mb_ngroups = 0, mb_nitems = 0;
+    int mb_fmt[4] = {0, 0, 0, 0};
+    DevBuf mb_eq, mb_flag, mb_pos, mb_kid, mb_ukey, mb_tab, mb_bcells, mb_ent, mb_groups, mb_blk, mb_items,
+        mb_mr, mb_partial;
     // outputs of the far field, sorted order: float [3n] each
     DevBuf far_u, far_da;
     DevBuf dsurf;                        // float[4] surface velocity term
     // rk_step stage storage
-    DevBuf rk;                           // float [13 n]
+    DevBuf rk;                           // float [19 n]
+    // autotuner scratch
+    DevBuf tune_ref, tune_out, tune_part;
+
+    // hipGraph of one evaluation (captured once per build, then replayed)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<const void *> graph_args;
+    bool capturing = false;
+    uint64_t build_id = 0, graph_build_id = 0;
 
     // timing
     hipEvent_t ev[2 * PH_NUM + 4] = {};
     bool ev_ok = false;
-    float t_phase[PH_NUM] = {};
-    float t_build = 0.f, t_eval = 0.f;
+    bool last_was_rk = false;            // timings then sum both RK2 stages
+    vfmm_timings t_stage1{};
     bool build_timed = false, eval_timed = false;
 
     void release_all();
+    // records timing event i unless the stream is being captured into a graph
+    void record(int i) {
+        if (ev_ok && !capturing) {
+            hipError_t e = hipEventRecord(ev[i], stream);
+            if (e != hipSuccess) throw Error{VFMM_EHIP, std::string("hipEventRecord: ") + hipGetErrorString(e)};
+        }
+    }
 };
 
 // tree.hip
@@ -77,11 +105,17 @@ void compute_bounds(Ctx &c, int64_t n, const float *x, const float *y, const flo
                     const float *ax, const float *ay, const float *az, bool with_alpha);
 void build_tree(Ctx &c, int64_t n, const float *x, const float *y, const float *z, const float *sigma);
 void gather_strengths(Ctx &c, const float *ax, const float *ay, const float *az, const float *sigma);
+void gather_records64(Ctx &c, const float *ax, const float *ay, const float *az);
 void scan_excl_i32(Ctx &c, const int *in, int *out, int64_t n);  // out may alias in
 // traverse.hip
 void traverse_and_lists(Ctx &c);
 // far.hip
 void far_field(Ctx &c);
+void far_prealloc(Ctx &c);
+// m2lb.hip
+void m2lb_plan(Ctx &c);
+void m2lb_run(Ctx &c);
+void m2lb_prealloc(Ctx &c);
 // p2p.hip
 void p2p_and_finalize(Ctx &c, float *ux, float *uy, float *uz, float *dax, float *day, float *daz);
 void direct_all_pairs(Ctx &c, const float *x, const float *y, const float *z, const float *ax,
@@ -91,3 +125,8 @@ void direct_all_pairs(Ctx &c, const float *x, const float *y, const float *z, co
 void lattice_operator_host(int p, int K, std::vector<double> &op);
 
 }  // namespace vfmm
+
+// the opaque handle of the C ABI
+struct vfmm_ctx {
+    vfmm::Ctx c;
+};

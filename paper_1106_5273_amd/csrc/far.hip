@@ -14,14 +14,32 @@ namespace vfmm {
 
 static constexpr int TPB = 256;
 
-__device__ inline float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
-__device__ inline float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+// Vector types of the compute precision R (float: the product path; double:
+// the FP64 reference form of the precision parameter).
+template <class R> struct VT;
+template <> struct VT<float> { using V2 = float2; using V4 = float4; };
+template <> struct VT<double> { using V2 = double2; using V4 = double4; };
+
+template <class V2>
+__device__ inline V2 cmul(V2 a, V2 b) { return V2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+template <class V2>
+__device__ inline V2 cconj(V2 a) { return V2{a.x, -a.y}; }
+
+__device__ inline float fmar(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ inline double fmar(double a, double b, double c) { return fma(a, b, c); }
+__device__ inline float rsqr(float a) { return rsqrtf(a); }
+__device__ inline double rsqr(double a) { return 1.0 / sqrt(a); }
+
+// rt^e for a ratio of cell sizes (a power of two) and an integer e >= 0
+__device__ inline float powr(float rt, int e) { return __builtin_amdgcn_exp2f((float)e * __log2f(rt)); }
+__device__ inline double powr(double rt, int e) { return exp2((double)e * log2(rt)); }
 
 // c_n^m for any sign of m from the m >= 0 storage: c_n^{-m} = (-1)^m conj(c_n^m).
-__device__ inline float2 getc(const float2 *a, int n, int m) {
+template <class V2>
+__device__ inline V2 getc(const V2 *a, int n, int m) {
     if (m >= 0) return a[CIDX(n, m)];
-    const float2 v = a[CIDX(n, -m)];
-    return (m & 1) ? make_float2(-v.x, v.y) : make_float2(v.x, -v.y);
+    const V2 v = a[CIDX(n, -m)];
+    return (m & 1) ? V2{-v.x, v.y} : V2{v.x, -v.y};
 }
 
 __device__ inline void decode_nm(int t, int &n, int &m) {
@@ -32,47 +50,52 @@ __device__ inline void decode_nm(int t, int &n, int &m) {
 }
 
 // ---------------------------------------------------------------------------
-// P2M: one wave per leaf.
+// P2M: one wave per leaf, particles staged CH at a time.
 // ---------------------------------------------------------------------------
-template <int P>
+template <int P, class R>
 __global__ __launch_bounds__(64) void k_p2m(const int *leaves, const int *start, const int *count, const float4 *geo,
-                                            const float4 *rec, float2 *Mexp) {
+                                            const typename VT<R>::V4 *rec, typename VT<R>::V2 *Mexp) {
+    using V2 = typename VT<R>::V2;
+    using V4 = typename VT<R>::V4;
     constexpr int NCP = NC(P);
-    __shared__ float2 Rs[64][NCP];
-    __shared__ float4 al[64];
+    constexpr int CH = sizeof(R) == 8 ? 32 : 64;
+    __shared__ V2 Rs[CH][NCP];
+    __shared__ V4 al[CH];
     const int lane = threadIdx.x;
     const int cell = leaves[blockIdx.x];
     const float4 g = geo[cell];
-    const float inv = 1.0f / g.w;
+    const R inv = R(1) / R(g.w);
     const int s0 = start[cell], cnt = count[cell];
     constexpr int NT = (NCP + 63) / 64;
-    float2 acc[NT][3];
+    V2 acc[NT][3];
 #pragma unroll
     for (int t = 0; t < NT; ++t)
-        for (int c = 0; c < 3; ++c) acc[t][c] = make_float2(0.f, 0.f);
-    for (int b = 0; b < cnt; b += 64) {
-        const int j = s0 + b + lane;
-        if (b + lane < cnt) {
-            const float4 p = rec[2 * j];
-            float2 R[NCP];
-            regular_harmonics<P, float, float2>((p.x - g.x) * inv, (p.y - g.y) * inv, (p.z - g.z) * inv, R);
+        for (int c = 0; c < 3; ++c) acc[t][c] = V2{R(0), R(0)};
+    for (int b = 0; b < cnt; b += CH) {
+        if (lane < CH) {
+            const int j = s0 + b + lane;
+            if (b + lane < cnt) {
+                const V4 p = rec[2 * j];
+                V2 Rl[NCP];
+                regular_harmonics<P, R, V2>((p.x - R(g.x)) * inv, (p.y - R(g.y)) * inv, (p.z - R(g.z)) * inv, Rl);
 #pragma unroll
-            for (int t = 0; t < NCP; ++t) Rs[lane][t] = R[t];
-            al[lane] = rec[2 * j + 1];
-        } else {
-            al[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+                for (int t = 0; t < NCP; ++t) Rs[lane][t] = Rl[t];
+                al[lane] = rec[2 * j + 1];
+            } else {
+                al[lane] = V4{R(0), R(0), R(0), R(0)};
 #pragma unroll
-            for (int t = 0; t < NCP; ++t) Rs[lane][t] = make_float2(0.f, 0.f);
+                for (int t = 0; t < NCP; ++t) Rs[lane][t] = V2{R(0), R(0)};
+            }
         }
         __syncthreads();
-        const int jmax = min(64, cnt - b);
+        const int jmax = min(CH, cnt - b);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const int coef = lane + 64 * t;
             if (coef < NCP) {
                 for (int jj = 0; jj < jmax; ++jj) {
-                    const float2 r = Rs[jj][coef];
-                    const float4 a = al[jj];
+                    const V2 r = Rs[jj][coef];
+                    const V4 a = al[jj];
                     acc[t][0].x += a.x * r.x; acc[t][0].y -= a.x * r.y;
                     acc[t][1].x += a.y * r.x; acc[t][1].y -= a.y * r.y;
                     acc[t][2].x += a.z * r.x; acc[t][2].y -= a.z * r.y;
@@ -93,14 +116,17 @@ __global__ __launch_bounds__(64) void k_p2m(const int *leaves, const int *start,
 // M2M: one wave per parent cell of one level.
 //   Mt_n^m(P) = sum_children sum_{k,l} conj(R_k^l(d)) Mt_{n-k}^{m-l}(c) (s_c/s_P)^{n-k},
 //   d = (c - P)/s_P.
+// S is the storage type of the expansions, R the arithmetic type (the mixed
+// precision form keeps float storage and accumulates in double).
 // ---------------------------------------------------------------------------
-template <int P>
+template <int P, class R, class S>
 __global__ __launch_bounds__(64) void k_m2m(int c0, int c1, const int *child, const int *nchild, const float4 *geo,
-                                            float2 *Mexp) {
+                                            typename VT<S>::V2 *Mexp) {
+    using V2 = typename VT<R>::V2;
     constexpr int NCP = NC(P);
-    __shared__ float2 Mc[8][3][NCP];
-    __shared__ float2 Rd[8][NCP];
-    __shared__ float ratio[8];
+    __shared__ V2 Mc[8][3][NCP];
+    __shared__ V2 Rd[8][NCP];
+    __shared__ R ratio[8];
     const int cell = c0 + blockIdx.x;
     if (cell >= c1) return;
     const int nc = nchild[cell];
@@ -110,40 +136,46 @@ __global__ __launch_bounds__(64) void k_m2m(int c0, int c1, const int *child, co
     const int lane = threadIdx.x;
     if (lane < nc) {
         const float4 gc = geo[f + lane];
-        const float inv = 1.0f / gp.w;
-        float2 R[NCP];
-        regular_harmonics<P, float, float2>((gc.x - gp.x) * inv, (gc.y - gp.y) * inv, (gc.z - gp.z) * inv, R);
-        for (int t = 0; t < NCP; ++t) Rd[lane][t] = R[t];
-        ratio[lane] = gc.w * inv;
+        const R inv = R(1) / R(gp.w);
+        V2 Rl[NCP];
+        regular_harmonics<P, R, V2>((R(gc.x) - R(gp.x)) * inv, (R(gc.y) - R(gp.y)) * inv, (R(gc.z) - R(gp.z)) * inv,
+                                    Rl);
+        for (int t = 0; t < NCP; ++t) Rd[lane][t] = Rl[t];
+        ratio[lane] = R(gc.w) * inv;
     }
     for (int i = lane; i < nc * 3 * NCP; i += 64) {
         const int k = i / (3 * NCP), r = i % (3 * NCP);
-        Mc[k][r / NCP][r % NCP] = Mexp[((size_t)(f + k) * 3) * NCP + r];
+        const auto v = Mexp[((size_t)(f + k) * 3) * NCP + r];
+        Mc[k][r / NCP][r % NCP] = V2{R(v.x), R(v.y)};
     }
     __syncthreads();
     for (int t = lane; t < NCP; t += 64) {
         int n, m;
         decode_nm(t, n, m);
-        float2 acc[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+        V2 acc[3] = {V2{R(0), R(0)}, V2{R(0), R(0)}, V2{R(0), R(0)}};
         for (int k = 0; k < nc; ++k) {
-            const float rt = ratio[k];
+            const R rt = ratio[k];
             // sum from high source degree nm = n - kk to low: kk from 0 up
             for (int kk = 0; kk <= n; ++kk) {
                 const int nm = n - kk;
-                const float sc = __builtin_amdgcn_exp2f((float)nm * __log2f(rt));
+                const R sc = powr(rt, nm);
                 for (int l = -kk; l <= kk; ++l) {
                     const int mm = m - l;
                     if (mm < -nm || mm > nm) continue;
-                    const float2 r = cconj(getc(Rd[k], kk, l));
+                    const V2 r = cconj(getc(Rd[k], kk, l));
                     for (int c = 0; c < 3; ++c) {
-                        const float2 v = cmul(r, getc(Mc[k][c], nm, mm));
+                        const V2 v = cmul(r, getc(Mc[k][c], nm, mm));
                         acc[c].x += sc * v.x;
                         acc[c].y += sc * v.y;
                     }
                 }
             }
         }
-        for (int c = 0; c < 3; ++c) Mexp[((size_t)cell * 3 + c) * NCP + t] = acc[c];
+        for (int c = 0; c < 3; ++c) {
+            auto &dst = Mexp[((size_t)cell * 3 + c) * NCP + t];
+            dst.x = (S)acc[c].x;
+            dst.y = (S)acc[c].y;
+        }
     }
 }
 
@@ -159,7 +191,7 @@ __global__ __launch_bounds__(64) void k_m2m(int c0, int c1, const int *child, co
 // of +-m combine into Re/Im rows that read two staged tables:
 //   X_N^M = (Re I_N^M, -Im I_N^M),  Y_N^M = (Im I_N^M, Re I_N^M),  |M| <= 2P.
 // ---------------------------------------------------------------------------
-template <int P>
+template <int P, class R = float>
 struct M2LCfg {
     static constexpr int NCP = NC(P);
     static constexpr int ROWS = (P + 1) * (P + 1);
@@ -167,26 +199,29 @@ struct M2LCfg {
     static constexpr int Q = 2 * P;
     static constexpr int IW = 4 * P + 1;                 // M in [-2P, 2P]
     static constexpr int ISZ = (Q + 1) * IW;             // per table
-    static constexpr int SB = 2;                          // sources staged at once
+    static constexpr int SB = sizeof(R) == 8 ? 1 : 2;    // sources staged at once
 };
 
-template <int P>
-__global__ __launch_bounds__(M2LCfg<P>::THREADS) void k_m2l(int ncells, const int *off, const int2 *src,
-                                                            const float4 *geo, const float2 *__restrict__ Mexp,
-                                                            float2 *__restrict__ Lexp, int B, float len) {
-    using C = M2LCfg<P>;
-    __shared__ float2 Xs[C::SB][C::ISZ];
-    __shared__ float2 Ys[C::SB][C::ISZ];
-    __shared__ float2 Ms[C::SB][3][C::NCP];
-    __shared__ float lam[C::SB];
+template <int P, class R>
+__global__ __launch_bounds__((M2LCfg<P, R>::THREADS)) void k_m2l(int ncells, const int *off, const int2 *src,
+                                                               const float4 *geo,
+                                                               const typename VT<R>::V2 *__restrict__ Mexp,
+                                                               typename VT<R>::V2 *__restrict__ Lexp, int B,
+                                                               float len) {
+    using C = M2LCfg<P, R>;
+    using V2 = typename VT<R>::V2;
+    __shared__ V2 Xs[C::SB][C::ISZ];
+    __shared__ V2 Ys[C::SB][C::ISZ];
+    __shared__ V2 Ms[C::SB][3][C::NCP];
+    __shared__ R lam[C::SB];
     const int tgt = blockIdx.x;
     if (tgt >= ncells) return;
     const int o0 = off[tgt], o1 = off[tgt + 1];
     if (o0 == o1) return;
     const int tid = threadIdx.x;
     for (int i = tid; i < C::SB * C::ISZ; i += C::THREADS) {
-        (&Xs[0][0])[i] = make_float2(0.f, 0.f);
-        (&Ys[0][0])[i] = make_float2(0.f, 0.f);
+        (&Xs[0][0])[i] = V2{R(0), R(0)};
+        (&Ys[0][0])[i] = V2{R(0), R(0)};
     }
     const float4 ga = geo[tgt];
     // row of this thread
@@ -201,9 +236,9 @@ __global__ __launch_bounds__(M2LCfg<P>::THREADS) void k_m2l(int ncells, const in
         l = (j + 1) / 2;
         isIm = (j > 0) && ((j & 1) == 0);
     }
-    const float sig = (l & 1) ? -1.f : 1.f;
-    const float sp = isIm ? -sig : sig;
-    float acc[3] = {0.f, 0.f, 0.f};
+    const R sig = (l & 1) ? R(-1) : R(1);
+    const R sp = isIm ? -sig : sig;
+    R acc[3] = {R(0), R(0), R(0)};
     const int W = 2 * B + 1;
     for (int e0 = o0; e0 < o1; e0 += C::SB) {
         __syncthreads();
@@ -215,144 +250,149 @@ __global__ __launch_bounds__(M2LCfg<P>::THREADS) void k_m2l(int ncells, const in
             const float4 gb = geo[ent.x];
             const int col = tid - s * (C::Q + 1);
             if (col >= 0 && col <= C::Q) {
-                const float ix = (float)(ent.y % W - B), iy = (float)((ent.y / W) % W - B),
-                            iz = (float)(ent.y / (W * W) - B);
-                const float inv = 1.0f / gb.w;
-                const float dx = (ga.x - gb.x - ix * len) * inv;
-                const float dy = (ga.y - gb.y - iy * len) * inv;
-                const float dz = (ga.z - gb.z - iz * len) * inv;
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                const float ir2 = 1.0f / r2;
+                const R ix = (R)(ent.y % W - B), iy = (R)((ent.y / W) % W - B), iz = (R)(ent.y / (W * W) - B);
+                const R inv = R(1) / R(gb.w);
+                const R dx = (R(ga.x) - R(gb.x) - ix * R(len)) * inv;
+                const R dy = (R(ga.y) - R(gb.y) - iy * R(len)) * inv;
+                const R dz = (R(ga.z) - R(gb.z) - iz * R(len)) * inv;
+                const R r2 = dx * dx + dy * dy + dz * dz;
+                const R ir2 = R(1) / r2;
                 // I_M^M by the diagonal recurrence, then upward in N
-                float cr = rsqrtf(r2), ci = 0.f;
+                R cr = rsqr(r2), ci = R(0);
                 for (int mm = 1; mm <= col; ++mm) {
-                    const float f = -(float)(2 * mm - 1) * ir2;
-                    const float nr = f * (dx * cr - dy * ci);
-                    const float ni = f * (dx * ci + dy * cr);
+                    const R f = -(R)(2 * mm - 1) * ir2;
+                    const R nr = f * (dx * cr - dy * ci);
+                    const R ni = f * (dx * ci + dy * cr);
                     cr = nr;
                     ci = ni;
                 }
                 const int M = col;
-                float2 *X = Xs[s], *Y = Ys[s];
-                auto put = [&](int N, float vr, float vi) {
-                    X[N * C::IW + C::Q + M] = make_float2(vr, -vi);
-                    Y[N * C::IW + C::Q + M] = make_float2(vi, vr);
+                V2 *X = Xs[s], *Y = Ys[s];
+                auto put = [&](int N, R vr, R vi) {
+                    X[N * C::IW + C::Q + M] = V2{vr, -vi};
+                    Y[N * C::IW + C::Q + M] = V2{vi, vr};
                     if (M > 0) {
                         // I^{-M} = (-1)^M conj(I^M)
-                        const float sr = (M & 1) ? -vr : vr, si = (M & 1) ? vi : -vi;
-                        X[N * C::IW + C::Q - M] = make_float2(sr, -si);
-                        Y[N * C::IW + C::Q - M] = make_float2(si, sr);
+                        const R sr = (M & 1) ? -vr : vr, si = (M & 1) ? vi : -vi;
+                        X[N * C::IW + C::Q - M] = V2{sr, -si};
+                        Y[N * C::IW + C::Q - M] = V2{si, sr};
                     }
                 };
                 put(M, cr, ci);
-                float pr = cr, pi = ci;
-                float qr = 0.f, qi = 0.f;
+                R pr = cr, pi = ci;
+                R qr = R(0), qi = R(0);
                 if (M + 1 <= C::Q) {
-                    const float a0 = (float)(2 * M + 1) * dz * ir2;
+                    const R a0 = (R)(2 * M + 1) * dz * ir2;
                     qr = a0 * cr;
                     qi = a0 * ci;
                     put(M + 1, qr, qi);
                 }
                 for (int N = M + 2; N <= C::Q; ++N) {
-                    const float a = (float)(2 * N - 1) * dz;
-                    const float b = (float)((N - 1) * (N - 1) - M * M);
-                    const float vr = (a * qr - b * pr) * ir2;
-                    const float vi = (a * qi - b * pi) * ir2;
+                    const R a = (R)(2 * N - 1) * dz;
+                    const R b = (R)((N - 1) * (N - 1) - M * M);
+                    const R vr = (a * qr - b * pr) * ir2;
+                    const R vi = (a * qi - b * pi) * ir2;
                     put(N, vr, vi);
                     pr = qr; pi = qi; qr = vr; qi = vi;
                 }
             }
             for (int i = tid; i < 3 * C::NCP; i += C::THREADS)
                 Ms[s][i / C::NCP][i % C::NCP] = Mexp[(size_t)ent.x * 3 * C::NCP + i];
-            if (tid == 0) lam[s] = ga.w / gb.w;  // 1/lambda
+            if (tid == 0) lam[s] = R(ga.w) / R(gb.w);  // 1/lambda
         }
         __syncthreads();
         if (!active) continue;
         for (int s = 0; s < C::SB; ++s) {
             if (e0 + s >= o1) break;
-            const float2 *Wt = isIm ? Ys[s] : Xs[s];
-            float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+            const V2 *Wt = isIm ? Ys[s] : Xs[s];
+            R a0 = R(0), a1 = R(0), a2 = R(0);
 #pragma unroll
             for (int n = P; n >= 0; --n) {
-                const float2 *row = Wt + (n + k) * C::IW + C::Q;
+                const V2 *row = Wt + (n + k) * C::IW + C::Q;
                 {
-                    const float w = row[-l].x;
+                    const R w = row[-l].x;
                     a0 += Ms[s][0][CIDX(n, 0)].x * w;
                     a1 += Ms[s][1][CIDX(n, 0)].x * w;
                     a2 += Ms[s][2][CIDX(n, 0)].x * w;
                 }
 #pragma unroll
                 for (int m = 1; m <= n; ++m) {
-                    const float2 w1 = row[m - l], w2 = row[m + l];
-                    const float A1 = fmaf(sp, w2.x, w1.x);
-                    const float B1 = fmaf(sp, w2.y, w1.y);
-                    const float2 m0 = Ms[s][0][CIDX(n, m)], m1 = Ms[s][1][CIDX(n, m)], m2 = Ms[s][2][CIDX(n, m)];
-                    a0 = fmaf(m0.x, A1, fmaf(m0.y, B1, a0));
-                    a1 = fmaf(m1.x, A1, fmaf(m1.y, B1, a1));
-                    a2 = fmaf(m2.x, A1, fmaf(m2.y, B1, a2));
+                    const V2 w1 = row[m - l], w2 = row[m + l];
+                    const R A1 = fmar(sp, w2.x, w1.x);
+                    const R B1 = fmar(sp, w2.y, w1.y);
+                    const V2 m0 = Ms[s][0][CIDX(n, m)], m1 = Ms[s][1][CIDX(n, m)], m2 = Ms[s][2][CIDX(n, m)];
+                    a0 = fmar(m0.x, A1, fmar(m0.y, B1, a0));
+                    a1 = fmar(m1.x, A1, fmar(m1.y, B1, a1));
+                    a2 = fmar(m2.x, A1, fmar(m2.y, B1, a2));
                 }
             }
-            const float sc = __builtin_amdgcn_exp2f((float)(k + 1) * __log2f(lam[s]));
+            const R sc = powr(lam[s], k + 1);
             acc[0] += sc * a0;
             acc[1] += sc * a1;
             acc[2] += sc * a2;
         }
     }
     if (active) {
-        const float sg = ((k + l) & 1) ? -1.f : 1.f;
+        const R sg = ((k + l) & 1) ? R(-1) : R(1);
         const int coef = CIDX(k, l);
         for (int c = 0; c < 3; ++c) {
-            float *dst = reinterpret_cast<float *>(&Lexp[((size_t)tgt * 3 + c) * C::NCP + coef]) + (isIm ? 1 : 0);
+            R *dst = reinterpret_cast<R *>(&Lexp[((size_t)tgt * 3 + c) * C::NCP + coef]) + (isIm ? 1 : 0);
             *dst += sg * acc[c];
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// L2L: one wave per child cell of one level.
+// L2L: one wave per child cell of one level (storage S, arithmetic R as in M2M).
 //   Lt_k^l(c) = sum_{n >= k, m} Lt_n^m(P) R_{n-k}^{m-l}(d) (s_c/s_P)^{k+1},  d = (c - P)/s_P.
 // ---------------------------------------------------------------------------
-template <int P>
-__global__ __launch_bounds__(64) void k_l2l(int c0, int c1, const int *parent, const float4 *geo, float2 *Lexp) {
+template <int P, class R, class S>
+__global__ __launch_bounds__(64) void k_l2l(int c0, int c1, const int *parent, const float4 *geo,
+                                            typename VT<S>::V2 *Lexp) {
+    using V2 = typename VT<R>::V2;
     constexpr int NCP = NC(P);
-    __shared__ float2 Lp[3][NCP];
-    __shared__ float2 Rd[NCP];
+    __shared__ V2 Lp[3][NCP];
+    __shared__ V2 Rd[NCP];
     const int cell = c0 + blockIdx.x;
     if (cell >= c1) return;
     const int par = parent[cell];
     const float4 gp = geo[par], gc = geo[cell];
     const int lane = threadIdx.x;
-    const float inv = 1.0f / gp.w;
+    const R inv = R(1) / R(gp.w);
     if (lane == 0) {
-        float2 R[NCP];
-        regular_harmonics<P, float, float2>((gc.x - gp.x) * inv, (gc.y - gp.y) * inv, (gc.z - gp.z) * inv, R);
-        for (int t = 0; t < NCP; ++t) Rd[t] = R[t];
+        V2 Rl[NCP];
+        regular_harmonics<P, R, V2>((R(gc.x) - R(gp.x)) * inv, (R(gc.y) - R(gp.y)) * inv, (R(gc.z) - R(gp.z)) * inv,
+                                    Rl);
+        for (int t = 0; t < NCP; ++t) Rd[t] = Rl[t];
     }
-    for (int i = lane; i < 3 * NCP; i += 64) Lp[i / NCP][i % NCP] = Lexp[(size_t)par * 3 * NCP + i];
+    for (int i = lane; i < 3 * NCP; i += 64) {
+        const auto v = Lexp[(size_t)par * 3 * NCP + i];
+        Lp[i / NCP][i % NCP] = V2{R(v.x), R(v.y)};
+    }
     __syncthreads();
-    const float rt = gc.w * inv;
+    const R rt = R(gc.w) * inv;
     for (int t = lane; t < NCP; t += 64) {
         int k, l;
         decode_nm(t, k, l);
-        const float sc = __builtin_amdgcn_exp2f((float)(k + 1) * __log2f(rt));
-        float2 acc[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+        const R sc = powr(rt, k + 1);
+        V2 acc[3] = {V2{R(0), R(0)}, V2{R(0), R(0)}, V2{R(0), R(0)}};
         for (int n = P; n >= k; --n) {
             const int dn = n - k;
             for (int m = -n; m <= n; ++m) {
                 const int dm = m - l;
                 if (dm < -dn || dm > dn) continue;
-                const float2 r = getc(Rd, dn, dm);
+                const V2 r = getc(Rd, dn, dm);
                 for (int c = 0; c < 3; ++c) {
-                    const float2 v = cmul(getc(Lp[c], n, m), r);
+                    const V2 v = cmul(getc(Lp[c], n, m), r);
                     acc[c].x += v.x;
                     acc[c].y += v.y;
                 }
             }
         }
         for (int c = 0; c < 3; ++c) {
-            float2 &dst = Lexp[((size_t)cell * 3 + c) * NCP + t];
-            dst.x += sc * acc[c].x;
-            dst.y += sc * acc[c].y;
+            auto &dst = Lexp[((size_t)cell * 3 + c) * NCP + t];
+            dst.x = (S)((R)dst.x + sc * acc[c].x);
+            dst.y = (S)((R)dst.y + sc * acc[c].y);
         }
     }
 }
@@ -364,78 +404,80 @@ __global__ __launch_bounds__(64) void k_l2l(int c0, int c1, const int *parent, c
 // the first and second derivatives of each potential are sums of Lt_n^m
 // against R_{n-1} and R_{n-2}.
 // ---------------------------------------------------------------------------
-template <int P>
+template <int P, class R>
 __global__ __launch_bounds__(64) void k_l2p(const int *leaves, const int *start, const int *count, const float4 *geo,
-                                            const float4 *rec, const float2 *Lexp, int64_t n_all, float *far_u,
-                                            float *far_da, int scheme) {
+                                            const typename VT<R>::V4 *rec, const typename VT<R>::V2 *Lexp,
+                                            int64_t n_all, R *far_u, R *far_da, int scheme) {
+    using V2 = typename VT<R>::V2;
+    using V4 = typename VT<R>::V4;
     constexpr int NCP = NC(P);
     constexpr int NR = NC(P - 1);
-    __shared__ float2 Ls[3][NCP];
+    __shared__ V2 Ls[3][NCP];
     const int cell = leaves[blockIdx.x];
     const int lane = threadIdx.x;
     for (int i = lane; i < 3 * NCP; i += 64) Ls[i / NCP][i % NCP] = Lexp[(size_t)cell * 3 * NCP + i];
     __syncthreads();
     const float4 g = geo[cell];
-    const float inv = 1.0f / g.w;
+    const R inv = R(1) / R(g.w);
     const int s0 = start[cell], cnt = count[cell];
     for (int b = 0; b < cnt; b += 64) {
         if (b + lane >= cnt) continue;
         const int j = s0 + b + lane;
-        const float4 p = rec[2 * j];
-        float2 R[NR];
-        regular_harmonics<P - 1, float, float2>((p.x - g.x) * inv, (p.y - g.y) * inv, (p.z - g.z) * inv, R);
-        float G[3][3], H[3][3][3];
+        const V4 p = rec[2 * j];
+        V2 Rl[NR];
+        regular_harmonics<P - 1, R, V2>((p.x - R(g.x)) * inv, (p.y - R(g.y)) * inv, (p.z - R(g.z)) * inv, Rl);
+        R G[3][3], H[3][3][3];
         for (int c = 0; c < 3; ++c) {
-            float pz = 0.f, pzz = 0.f;
-            float2 pp = make_float2(0.f, 0.f), pzp = make_float2(0.f, 0.f), ppp = make_float2(0.f, 0.f);
+            R pz = R(0), pzz = R(0);
+            V2 pp = V2{R(0), R(0)}, pzp = V2{R(0), R(0)}, ppp = V2{R(0), R(0)};
 #pragma unroll
             for (int n = P; n >= 1; --n) {
 #pragma unroll
                 for (int m = -n; m <= n; ++m) {
-                    const float2 L = getc(Ls[c], n, m);
-                    if (m >= -(n - 1) && m <= n - 1) pz += cmul(L, getc(R, n - 1, m)).x;
+                    const V2 L = getc(Ls[c], n, m);
+                    if (m >= -(n - 1) && m <= n - 1) pz += cmul(L, getc(Rl, n - 1, m)).x;
                     if (m + 1 >= -(n - 1) && m + 1 <= n - 1) {
-                        const float2 v = cmul(L, getc(R, n - 1, m + 1));
+                        const V2 v = cmul(L, getc(Rl, n - 1, m + 1));
                         pp.x += v.x; pp.y += v.y;
                     }
                     if (n >= 2) {
-                        if (m >= -(n - 2) && m <= n - 2) pzz += cmul(L, getc(R, n - 2, m)).x;
+                        if (m >= -(n - 2) && m <= n - 2) pzz += cmul(L, getc(Rl, n - 2, m)).x;
                         if (m + 1 >= -(n - 2) && m + 1 <= n - 2) {
-                            const float2 v = cmul(L, getc(R, n - 2, m + 1));
+                            const V2 v = cmul(L, getc(Rl, n - 2, m + 1));
                             pzp.x += v.x; pzp.y += v.y;
                         }
                         if (m + 2 >= -(n - 2) && m + 2 <= n - 2) {
-                            const float2 v = cmul(L, getc(R, n - 2, m + 2));
+                            const V2 v = cmul(L, getc(Rl, n - 2, m + 2));
                             ppp.x += v.x; ppp.y += v.y;
                         }
                     }
                 }
             }
-            const float i2 = inv * inv, i3 = i2 * inv;
+            const R i2 = inv * inv, i3 = i2 * inv;
             G[c][0] = pp.x * i2;
             G[c][1] = pp.y * i2;
             G[c][2] = pz * i2;
-            const float hzz = pzz * i3;
-            const float hxx = 0.5f * (ppp.x * i3 - hzz);
-            const float hyy = 0.5f * (-ppp.x * i3 - hzz);
-            const float hxy = 0.5f * ppp.y * i3;
-            const float hxz = pzp.x * i3, hyz = pzp.y * i3;
+            const R hzz = pzz * i3;
+            const R hxx = R(0.5) * (ppp.x * i3 - hzz);
+            const R hyy = R(0.5) * (-ppp.x * i3 - hzz);
+            const R hxy = R(0.5) * ppp.y * i3;
+            const R hxz = pzp.x * i3, hyz = pzp.y * i3;
             H[c][0][0] = hxx; H[c][0][1] = hxy; H[c][0][2] = hxz;
             H[c][1][0] = hxy; H[c][1][1] = hyy; H[c][1][2] = hyz;
             H[c][2][0] = hxz; H[c][2][1] = hyz; H[c][2][2] = hzz;
         }
         // u_l = eps_{l k c} d_k psi_c ; J_kl = eps_{l n c} d_k d_n psi_c
-        const float u0 = G[2][1] - G[1][2], u1 = G[0][2] - G[2][0], u2 = G[1][0] - G[0][1];
-        float J[3][3];
+        const R u0 = G[2][1] - G[1][2], u1 = G[0][2] - G[2][0], u2 = G[1][0] - G[0][1];
+        R J[3][3];
         for (int kk = 0; kk < 3; ++kk) {
             J[kk][0] = H[2][kk][1] - H[1][kk][2];
             J[kk][1] = H[0][kk][2] - H[2][kk][0];
             J[kk][2] = H[1][kk][0] - H[0][kk][1];
         }
-        const float4 at = rec[2 * j + 1];
-        const float fp = 12.566370614359172f;  // alpha_i = 4 pi * stored (alpha/4pi)
-        const float a[3] = {at.x * fp, at.y * fp, at.z * fp};
-        float d[3];
+        const V4 at = rec[2 * j + 1];
+        const R fp = R(12.566370614359172);  // alpha_i = 4 pi * stored (alpha/4pi)
+        const R a[3] = {at.x * fp, at.y * fp, at.z * fp};
+        R d[3];
         if (scheme == VFMM_SCHEME_TRANSPOSE) {
             for (int kk = 0; kk < 3; ++kk) d[kk] = J[kk][0] * a[0] + J[kk][1] * a[1] + J[kk][2] * a[2];
         } else {
@@ -452,76 +494,133 @@ __global__ __launch_bounds__(64) void k_l2p(const int *leaves, const int *start,
 
 // ---------------------------------------------------------------------------
 // Periodic lattice: Lt_root += T Mt_root with the precomputed real operator T
-// acting on (Re, Im) of the root coefficients, for each potential.
+// acting on (Re, Im) of the root coefficients, for each potential.  The
+// operator and the arithmetic are in R; the expansions are stored in S.
 // ---------------------------------------------------------------------------
-template <int P>
-__global__ __launch_bounds__(256) void k_lattice(const float *op, const float2 *Mexp, float2 *Lexp) {
+template <int P, class R, class S>
+__global__ __launch_bounds__(256) void k_lattice(const R *op, const typename VT<S>::V2 *Mexp,
+                                                 typename VT<S>::V2 *Lexp) {
     constexpr int NCP = NC(P);
     constexpr int D = 2 * NCP;
-    __shared__ float v[3][D];
+    __shared__ R v[3][D];
     for (int i = threadIdx.x; i < 3 * D; i += 256) {
         const int c = i / D, r = i % D;
-        const float2 mm = Mexp[(size_t)c * NCP + r / 2];
-        v[c][r] = (r & 1) ? mm.y : mm.x;
+        const auto mm = Mexp[(size_t)c * NCP + r / 2];
+        v[c][r] = (r & 1) ? R(mm.y) : R(mm.x);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < 3 * D; i += 256) {
         const int c = i / D, r = i % D;
-        float acc = 0.f;
-        for (int q = D - 1; q >= 0; --q) acc = fmaf(op[(size_t)r * D + q], v[c][q], acc);
-        float *dst = reinterpret_cast<float *>(&Lexp[(size_t)c * NCP + r / 2]) + (r & 1);
-        *dst += acc;
+        R acc = R(0);
+        for (int q = D - 1; q >= 0; --q) acc = fmar(op[(size_t)r * D + q], v[c][q], acc);
+        S *dst = reinterpret_cast<S *>(&Lexp[(size_t)c * NCP + r / 2]) + (r & 1);
+        *dst = (S)((R)*dst + acc);
+    }
+}
+
+// zero nw 32-bit words (any count; whole float4 stores except for the tail)
+__global__ __launch_bounds__(256) void k_zero(float *p, int64_t nw) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t w = 4 * i;
+    if (w + 4 <= nw) {
+        reinterpret_cast<float4 *>(p)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+        for (int64_t q = w; q < nw; ++q) p[q] = 0.f;
+    }
+}
+
+template <int P>
+static void far_prealloc_p(Ctx &c) {
+    constexpr int NCP = NC(P);
+    const size_t rs = c.prm.precision == VFMM_PRECISION_FP64 ? sizeof(double) : sizeof(float);
+    const size_t bytes = 2 * rs * (size_t)c.ncells * 3 * NCP;
+    c.Mexp.ensure(bytes);
+    c.Lexp.ensure(bytes);
+    c.far_u.ensure(rs * 3 * (size_t)c.n);
+    c.far_da.ensure(rs * 3 * (size_t)c.n);
+    if (c.prm.precision == VFMM_PRECISION_FP64) c.rec64.ensure(sizeof(double4) * 2 * (size_t)c.n);
+}
+
+void far_prealloc(Ctx &c) {
+    switch (c.prm.p) {
+        case 4: far_prealloc_p<4>(c); break;
+        case 6: far_prealloc_p<6>(c); break;
+        case 8: far_prealloc_p<8>(c); break;
+        case 10: far_prealloc_p<10>(c); break;
+        case 12: far_prealloc_p<12>(c); break;
+        default: throw Error{VFMM_EINVAL, "unsupported expansion degree p"};
     }
 }
 
 // ---------------------------------------------------------------------------
-template <int P>
-static void far_field_p(Ctx &c) {
+// S: storage and arithmetic type of the expansions, P2M, M2L and L2P;
+// RA: arithmetic type of M2M, L2L and the lattice operator.
+//   plain float32 <float, float>, mixed <float, double>, float64 <double, double>.
+// ---------------------------------------------------------------------------
+template <int P, class S, class RA>
+static void far_field_t(Ctx &c) {
+    using V2 = typename VT<S>::V2;
+    using V4 = typename VT<S>::V4;
     hipStream_t s = c.stream;
     constexpr int NCP = NC(P);
-    const size_t bytes = sizeof(float2) * (size_t)c.ncells * 3 * NCP;
+    const size_t bytes = sizeof(V2) * (size_t)c.ncells * 3 * NCP;
     c.Mexp.ensure(bytes);
     c.Lexp.ensure(bytes);
-    c.far_u.ensure(sizeof(float) * 3 * (size_t)c.n);
-    c.far_da.ensure(sizeof(float) * 3 * (size_t)c.n);
-    if (c.ev_ok) VFMM_HIP(hipEventRecord(c.ev[2 * PH_P2M_M2M], s));
-    VFMM_HIP(hipMemsetAsync(c.Lexp.ptr, 0, bytes, s));
-    k_p2m<P><<<c.nleaves, 64, 0, s>>>(c.leaves.as<int>(), c.c_start.as<int>(), c.c_count.as<int>(),
-                                       c.c_geo.as<float4>(), c.rec.as<float4>(), c.Mexp.as<float2>());
+    c.far_u.ensure(sizeof(S) * 3 * (size_t)c.n);
+    c.far_da.ensure(sizeof(S) * 3 * (size_t)c.n);
+    const V4 *rec = (sizeof(S) == 8) ? reinterpret_cast<const V4 *>(c.rec64.ptr) : reinterpret_cast<const V4 *>(c.rec.ptr);
+    c.record(2 * PH_P2M_M2M);
+    // a fill kernel rather than a memset, so that the evaluation can be captured in a graph
+    k_zero<<<cdiv(cdiv(bytes, 16), 256), 256, 0, s>>>(c.Lexp.as<float>(), (int64_t)(bytes / 4));
+    VFMM_LAUNCH_CHECK();
+    k_p2m<P, S><<<c.nleaves, 64, 0, s>>>(c.leaves.as<int>(), c.c_start.as<int>(), c.c_count.as<int>(),
+                                          c.c_geo.as<float4>(), rec, c.Mexp.as<V2>());
     VFMM_LAUNCH_CHECK();
     for (int l = c.depth - 1; l >= 0; --l) {
         const int c0 = c.lvl_off[l], c1 = c.lvl_off[l + 1];
-        k_m2m<P><<<c1 - c0, 64, 0, s>>>(c0, c1, c.c_child.as<int>(), c.c_nchild.as<int>(), c.c_geo.as<float4>(),
-                                         c.Mexp.as<float2>());
+        k_m2m<P, RA, S><<<c1 - c0, 64, 0, s>>>(c0, c1, c.c_child.as<int>(), c.c_nchild.as<int>(),
+                                                c.c_geo.as<float4>(), c.Mexp.as<V2>());
         VFMM_LAUNCH_CHECK();
     }
-    if (c.ev_ok) VFMM_HIP(hipEventRecord(c.ev[2 * PH_P2M_M2M + 1], s));
-    if (c.ev_ok) VFMM_HIP(hipEventRecord(c.ev[2 * PH_LATTICE], s));
+    c.record(2 * PH_P2M_M2M + 1);
+    c.record(2 * PH_LATTICE);
     if (c.prm.periodic && c.prm.images >= 3) {
-        k_lattice<P><<<1, 256, 0, s>>>(c.lat_op.as<float>(), c.Mexp.as<float2>(), c.Lexp.as<float2>());
+        k_lattice<P, RA, S><<<1, 256, 0, s>>>(c.lat_op.as<RA>(), c.Mexp.as<V2>(), c.Lexp.as<V2>());
         VFMM_LAUNCH_CHECK();
     }
-    if (c.ev_ok) VFMM_HIP(hipEventRecord(c.ev[2 * PH_LATTICE + 1], s));
-    if (c.ev_ok) VFMM_HIP(hipEventRecord(c.ev[2 * PH_M2L], s));
-    if (c.n_m2l > 0) {
-        k_m2l<P><<<c.ncells, M2LCfg<P>::THREADS, 0, s>>>(c.ncells, c.m2l_off.as<int>(), c.m2l_src.as<int2>(),
-                                                          c.c_geo.as<float4>(), c.Mexp.as<float2>(),
-                                                          c.Lexp.as<float2>(), c.img_B,
-                                                          c.prm.periodic ? (float)c.prm.box_len : 0.f);
+    c.record(2 * PH_LATTICE + 1);
+    c.record(2 * PH_M2L);
+    if (c.n_m2l > 0 && c.m2lb_ok && sizeof(S) == 4) {
+        m2lb_run(c);
+    } else if (c.n_m2l > 0) {
+        k_m2l<P, S><<<c.ncells, M2LCfg<P, S>::THREADS, 0, s>>>(c.ncells, c.m2l_off.as<int>(), c.m2l_src.as<int2>(),
+                                                                c.c_geo.as<float4>(), c.Mexp.as<V2>(),
+                                                                c.Lexp.as<V2>(), c.img_B,
+                                                                c.prm.periodic ? (float)c.prm.box_len : 0.f);
         VFMM_LAUNCH_CHECK();
     }
-    if (c.ev_ok) VFMM_HIP(hipEventRecord(c.ev[2 * PH_M2L + 1], s));
-    if (c.ev_ok) VFMM_HIP(hipEventRecord(c.ev[2 * PH_L2L_L2P], s));
+    c.record(2 * PH_M2L + 1);
+    c.record(2 * PH_L2L_L2P);
     for (int l = 1; l <= c.depth; ++l) {
         const int c0 = c.lvl_off[l], c1 = c.lvl_off[l + 1];
-        k_l2l<P><<<c1 - c0, 64, 0, s>>>(c0, c1, c.c_parent.as<int>(), c.c_geo.as<float4>(), c.Lexp.as<float2>());
+        k_l2l<P, RA, S><<<c1 - c0, 64, 0, s>>>(c0, c1, c.c_parent.as<int>(), c.c_geo.as<float4>(),
+                                                c.Lexp.as<V2>());
         VFMM_LAUNCH_CHECK();
     }
-    k_l2p<P><<<c.nleaves, 64, 0, s>>>(c.leaves.as<int>(), c.c_start.as<int>(), c.c_count.as<int>(),
-                                       c.c_geo.as<float4>(), c.rec.as<float4>(), c.Lexp.as<float2>(), c.n,
-                                       c.far_u.as<float>(), c.far_da.as<float>(), c.prm.scheme);
+    k_l2p<P, S><<<c.nleaves, 64, 0, s>>>(c.leaves.as<int>(), c.c_start.as<int>(), c.c_count.as<int>(),
+                                          c.c_geo.as<float4>(), rec, c.Lexp.as<V2>(), c.n, c.far_u.as<S>(),
+                                          c.far_da.as<S>(), c.prm.scheme);
     VFMM_LAUNCH_CHECK();
-    if (c.ev_ok) VFMM_HIP(hipEventRecord(c.ev[2 * PH_L2L_L2P + 1], s));
+    c.record(2 * PH_L2L_L2P + 1);
+}
+
+template <int P>
+static void far_field_p(Ctx &c) {
+    switch (c.prm.precision) {
+        case VFMM_PRECISION_FP64: far_field_t<P, double, double>(c); break;
+        case VFMM_PRECISION_MIXED: far_field_t<P, float, double>(c); break;
+        default: far_field_t<P, float, float>(c); break;
+    }
 }
 
 void far_field(Ctx &c) {

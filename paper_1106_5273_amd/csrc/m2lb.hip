@@ -1,0 +1,575 @@
+// Operator-batched M2L (Sec. 3.1, Sec. 3.6).
+//
+// An M2L translation between a target cell A and a source cell B depends only
+// on the level difference dl = level(B) - level(A) and on the offset
+// c_B + shift - c_A in units of s_A / 2^(max(dl,0)+2) (octree centres lie on
+// that grid), for the size-normalised expansions.  A uniform octree has only a
+// few thousand distinct such keys, so each key's translation is built once as
+// a real (P+1)^2 x (P+1)^2 matrix T acting on (Re, Im) of Mt and producing
+// (Re, Im) rows of Lt:
+//   Lt_k^l = (-1)^{k+l} (s_A/s_B)^{k+1} sum_{n,m} Mt_n^m I_{n+k}^{m-l}((c_A - c_B)/s_B).
+// Target cells are grouped in blocks of 64 consecutive cells of one level and
+// the list entries sorted by (block, key).  A work-group (three waves, one
+// per potential) takes a block and, key by key, builds that key's matrix T in
+// LDS from the key's irregular harmonics (a few per cent of the work), then
+// multiplies it into the 64 targets' accumulators with FP32 matrix-core
+// instructions (v_mfma_f32_16x16x4f32): per wave a [rows x inputs] x
+// [inputs x 64 targets] product with B-fragments gathered from the sources'
+// multipoles.  No operator table leaves the chip.  Work items hold at most
+// ITEM_GROUPS keys of a block; their partial sums are added back per block in
+// a fixed order, so results are bit-reproducible.
+#include <algorithm>
+#include <utility>
+
+#include "ctx.h"
+
+namespace vfmm {
+
+static constexpr int TPB = 256;
+static constexpr int ITEM_GROUPS = 24;
+
+void sort_pairs_u64(Ctx &c, DevBuf &kA, DevBuf &vA, DevBuf &kB, DevBuf &vB, int64_t n, int nbits);
+
+__host__ __device__ constexpr int NR(int P) { return (P + 1) * (P + 1); }      // real rows
+__host__ __device__ constexpr int NRP(int P) { return (NR(P) + 3) / 4 * 4; }   // padded to float4
+__host__ __device__ constexpr int NRT(int P) { return (NR(P) + 15) / 16 * 16; } // rows padded to 16
+__host__ __device__ constexpr int TSTR(int P) {                                   // LDS row stride = 4 mod 64
+    return NRP(P) + ((4 - NRP(P) % 64) + 64) % 64;
+}
+
+// real index r = k^2 + j:  j = 0 -> (l = 0, Re); j odd -> (l = (j+1)/2, Re); j even > 0 -> (l = j/2, Im)
+__host__ __device__ inline void decode_row(int r, int &k, int &l, int &im) {
+    k = 0;
+    while ((k + 1) * (k + 1) <= r) ++k;
+    const int j = r - k * k;
+    l = (j + 1) / 2;
+    im = (j > 0 && (j & 1) == 0) ? 1 : 0;
+}
+
+struct KeyFmt {
+    int bq;       // bits per offset component
+    int bdl;      // bits of the level difference
+    int oq, odl;  // offsets making the packed fields non-negative
+};
+
+struct LvlInfo {
+    int off[23];      // first cell of each level
+    int bbase[23];    // first block of each level
+    int nlev;
+};
+
+__device__ inline int block_of(const LvlInfo &L, int cell, int lvl) {
+    return L.bbase[lvl] + (cell - L.off[lvl]) / 64;
+}
+
+// ---------------------------------------------------------------------------
+// per entry: level difference and quantised offset; track the ranges
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(TPB) void k_m2lb_offsets(int64_t n, const int *tgt, const int2 *src, const float4 *geo,
+                                                      const int *level, int B, float len, int4 *eq, int *range) {
+    const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    int aq = 0, adl = 0;
+    if (e < n) {
+        const int t = tgt[e];
+        const int2 s = src[e];
+        const int W = 2 * B + 1;
+        const float shx = (float)(s.y % W - B) * len;
+        const float shy = (float)((s.y / W) % W - B) * len;
+        const float shz = (float)(s.y / (W * W) - B) * len;
+        const float4 ga = geo[t], gb = geo[s.x];
+        const int dl = level[s.x] - level[t];
+        const float unit = ga.w * exp2f(-(float)(max(dl, 0) + 2));
+        const int qx = (int)rintf((gb.x + shx - ga.x) / unit);
+        const int qy = (int)rintf((gb.y + shy - ga.y) / unit);
+        const int qz = (int)rintf((gb.z + shz - ga.z) / unit);
+        eq[e] = make_int4(qx, qy, qz, dl);
+        aq = max(abs(qx), max(abs(qy), abs(qz)));
+        adl = abs(dl);
+    }
+    // wave max then one atomic per wave
+    for (int o = 32; o > 0; o >>= 1) {
+        aq = max(aq, __shfl_xor(aq, o, 64));
+        adl = max(adl, __shfl_xor(adl, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&range[0], aq);
+        atomicMax(&range[1], adl);
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_m2lb_pack(int64_t n, const int4 *eq, KeyFmt f, uint64_t *key, uint32_t *val) {
+    const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (e >= n) return;
+    const int4 q = eq[e];
+    const uint64_t k = ((uint64_t)(q.w + f.odl) << (3 * f.bq)) | ((uint64_t)(q.x + f.oq) << (2 * f.bq)) |
+                       ((uint64_t)(q.y + f.oq) << f.bq) | (uint64_t)(q.z + f.oq);
+    key[e] = k;
+    val[e] = (uint32_t)e;
+}
+
+__global__ __launch_bounds__(TPB) void k_flag_changes(int64_t n, const uint64_t *key, int *flag) {
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i < n) flag[i] = (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
+}
+
+// unique keys and the key id of every entry
+__global__ __launch_bounds__(TPB) void k_key_ids(int64_t n, const uint64_t *key, const uint32_t *val, const int *flag,
+                                                 const int *pos, int *kid, uint64_t *ukey) {
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i >= n) return;
+    const int id = pos[i] + flag[i] - 1;
+    kid[val[i]] = id;
+    if (flag[i]) ukey[id] = key[i];
+}
+
+__global__ __launch_bounds__(TPB) void k_block_keys(int64_t n, const int *tgt, const int *level, LvlInfo L,
+                                                    const int *kid, int kbits, uint64_t *key, uint32_t *val) {
+    const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (e >= n) return;
+    const int t = tgt[e];
+    key[e] = ((uint64_t)block_of(L, t, level[t]) << kbits) | (uint64_t)kid[e];
+    val[e] = (uint32_t)e;
+}
+
+// sorted entries -> (source cell, target slot); group starts
+__global__ __launch_bounds__(TPB) void k_groups(int64_t n, const uint64_t *ck, const uint32_t *val, const int *flag,
+                                                const int *pos, const int *tgt, const int2 *src, const int *level,
+                                                LvlInfo L, int kbits, int2 *ent, int4 *groups) {
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i >= n) return;
+    const int e = (int)val[i];
+    const int t = tgt[e];
+    const int lv = level[t];
+    const int slot = (t - L.off[lv]) % 64;
+    ent[i] = make_int2(src[e].x, slot);
+    if (flag[i]) {
+        const int g = pos[i];
+        const uint64_t k = ck[i];
+        groups[g] = make_int4((int)(k & ((1ull << kbits) - 1)), (int)i, 0, (int)(k >> kbits));
+    }
+}
+
+// group counts (from the next group's start) and the per-block first group
+__global__ __launch_bounds__(TPB) void k_group_counts(int ng, int64_t n, int4 *groups, int *blk_first) {
+    const int g = blockIdx.x * TPB + threadIdx.x;
+    if (g >= ng) return;
+    int4 gr = groups[g];
+    const int next = (g + 1 < ng) ? groups[g + 1].y : (int)n;
+    gr.z = next - gr.y;
+    groups[g] = gr;
+    if (g == 0 || groups[g - 1].w != gr.w) blk_first[gr.w] = g;
+}
+
+__global__ __launch_bounds__(TPB) void k_item_flags(int ng, const int4 *groups, const int *blk_first, int *flag) {
+    const int g = blockIdx.x * TPB + threadIdx.x;
+    if (g >= ng) return;
+    flag[g] = ((g - blk_first[groups[g].w]) % ITEM_GROUPS) == 0 ? 1 : 0;
+}
+
+// items: (block, first group, end group, 0); per block first item and item count
+__global__ __launch_bounds__(TPB) void k_items(int ng, const int4 *groups, const int *flag, const int *pos,
+                                               int4 *items, int *blk_item0, int *blk_nitem) {
+    const int g = blockIdx.x * TPB + threadIdx.x;
+    if (g >= ng || !flag[g]) return;
+    const int b = groups[g].w;
+    int end = g + 1;
+    while (end < ng && end < g + ITEM_GROUPS && groups[end].w == b) ++end;
+    const int it = pos[g];
+    items[it] = make_int4(b, g, end, 0);
+    if (g == 0 || groups[g - 1].w != b) blk_item0[b] = it;
+    atomicAdd(&blk_nitem[b], 1);
+}
+
+// ---------------------------------------------------------------------------
+// Mt in real row order, padded: Mr[cell][comp][NRP] (extra zero row at the end)
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(TPB) void k_m2lb_mreal(int ncells, const float2 *Mexp, float *Mr) {
+    constexpr int R = NR(P), RP = NRP(P), NCP = NC(P);
+    const int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    const int64_t total = (int64_t)(ncells + 1) * 3 * RP;
+    if (idx >= total) return;
+    const int r = (int)(idx % RP);
+    const int64_t cc = idx / RP;  // cell*3 + comp
+    float v = 0.f;
+    if (r < R && cc < (int64_t)ncells * 3) {
+        int n, m, im;
+        decode_row(r, n, m, im);
+        const float2 z = Mexp[cc * NCP + CIDX(n, m)];
+        v = im ? z.y : z.x;
+    }
+    Mr[idx] = v;
+}
+
+// ---------------------------------------------------------------------------
+// the batched translation
+// ---------------------------------------------------------------------------
+typedef float vf4 __attribute__((ext_vector_type(4)));
+
+template <int P>
+struct MbCfg {
+    static constexpr int R = NR(P), RP = NRP(P), RT = NRT(P), TS = TSTR(P);
+    static constexpr int Q = 2 * P, IW = 4 * P + 1;
+    static constexpr int RTI = RT / 16;   // row tiles
+    static constexpr int KS = RP / 4;     // k steps
+};
+
+template <int P>
+__global__ __launch_bounds__(192) void k_m2lb(const int4 *__restrict__ items, const int4 *__restrict__ groups,
+                                              const int2 *__restrict__ ent, const float *__restrict__ Mr,
+                                              const uint64_t *__restrict__ ukey, KeyFmt f, int zero_cell,
+                                              float *__restrict__ partial) {
+    using C = MbCfg<P>;
+    extern __shared__ float smem[];
+    float *Ts = smem;                                               // [RT][TS]
+    float2 *Is = reinterpret_cast<float2 *>(smem + C::RT * C::TS);  // [(Q+1)][IW], full orders
+    int *src_of = reinterpret_cast<int *>(Is + (C::Q + 1) * C::IW);  // [64]
+    int *rinfo = src_of + 64;                                       // [RP]: k | l << 8 | im << 16
+    const int tid = threadIdx.x;
+    const int comp = tid >> 6;
+    const int lane = tid & 63;
+    const int i16 = lane & 15, kq = lane >> 4;
+    for (int r = tid; r < C::RP; r += 192) {
+        int k = 0, l = 0, im = 0;
+        if (r < C::R) decode_row(r, k, l, im);
+        rinfo[r] = k | (l << 8) | (im << 16) | ((r < C::R) ? 0 : (1 << 24));
+    }
+    for (int i = tid; i < (C::Q + 1) * C::IW; i += 192) Is[i] = make_float2(0.f, 0.f);
+    const int4 it = items[blockIdx.x];
+    const int g0 = __builtin_amdgcn_readfirstlane(it.y);
+    const int g1 = __builtin_amdgcn_readfirstlane(it.z);
+    vf4 acc[C::RTI][4];
+#pragma unroll
+    for (int a = 0; a < C::RTI; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = vf4{0.f, 0.f, 0.f, 0.f};
+    const uint64_t mq = (1ull << f.bq) - 1;
+    for (int g = g0; g < g1; ++g) {
+        const int4 gr = groups[g];
+        const int key = __builtin_amdgcn_readfirstlane(gr.x);
+        const int e0 = __builtin_amdgcn_readfirstlane(gr.y);
+        const int ne = __builtin_amdgcn_readfirstlane(gr.z);
+        const uint64_t kv = ukey[key];
+        const int dl = (int)(kv >> (3 * f.bq)) - f.odl;
+        __syncthreads();
+        if (tid < 64) src_of[tid] = zero_cell;
+        // irregular harmonics I_N^M((c_A - c_B)/s_B), (c_A - c_B)/s_B = -q 2^(min(dl,0) - 2)
+        if (tid >= 64 && tid <= 64 + C::Q) {
+            const int M = tid - 64;
+            const float sc = -ldexpf(1.0f, min(dl, 0) - 2);
+            const float dx = (float)((int)((kv >> (2 * f.bq)) & mq) - f.oq) * sc;
+            const float dy = (float)((int)((kv >> f.bq) & mq) - f.oq) * sc;
+            const float dz = (float)((int)(kv & mq) - f.oq) * sc;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const float ir2 = 1.0f / r2;
+            float cr = rsqrtf(r2), ci = 0.f;
+            for (int mm = 1; mm <= M; ++mm) {
+                const float fc = -(float)(2 * mm - 1) * ir2;
+                const float nr = fc * (dx * cr - dy * ci);
+                const float ni = fc * (dx * ci + dy * cr);
+                cr = nr;
+                ci = ni;
+            }
+            auto put = [&](int N, float vr, float vi) {
+                Is[N * C::IW + C::Q + M] = make_float2(vr, vi);
+                if (M > 0) Is[N * C::IW + C::Q - M] = (M & 1) ? make_float2(-vr, vi) : make_float2(vr, -vi);
+            };
+            put(M, cr, ci);
+            float pr = cr, pi = ci, qr = 0.f, qi = 0.f;
+            if (M + 1 <= C::Q) {
+                const float a0 = (float)(2 * M + 1) * dz * ir2;
+                qr = a0 * cr;
+                qi = a0 * ci;
+                put(M + 1, qr, qi);
+            }
+            for (int N = M + 2; N <= C::Q; ++N) {
+                const float a = (float)(2 * N - 1) * dz;
+                const float b = (float)((N - 1) * (N - 1) - M * M);
+                const float vr = (a * qr - b * pr) * ir2;
+                const float vi = (a * qi - b * pi) * ir2;
+                put(N, vr, vi);
+                pr = qr; pi = qi; qr = vr; qi = vi;
+            }
+        }
+        __syncthreads();
+        if (tid < ne) {
+            const int2 en = ent[e0 + tid];
+            src_of[en.y] = en.x;
+        }
+        // the key's matrix: Ts[r][c], r = output row, c = input row
+        for (int idx = tid; idx < C::RT * C::RP; idx += 192) {
+            const int r = idx / C::RP, c = idx % C::RP;
+            float v = 0.f;
+            if (r < C::R && c < C::R) {
+                const int ri = rinfo[r], ci = rinfo[c];
+                const int k = ri & 255, l = (ri >> 8) & 255, im = (ri >> 16) & 1;
+                const int n = ci & 255, m = (ci >> 8) & 255, imc = (ci >> 16) & 1;
+                const float2 a = Is[(n + k) * C::IW + C::Q + m - l];
+                const float2 b = Is[(n + k) * C::IW + C::Q + m + l];
+                const float sg = (l & 1) ? -1.f : 1.f;
+                if (m == 0) v = im ? a.y : a.x;
+                else if (!im) v = imc ? (-a.y - sg * b.y) : (a.x + sg * b.x);
+                else v = imc ? (a.x - sg * b.x) : (a.y - sg * b.y);
+                v *= (((k + l) & 1) ? -1.f : 1.f) * ldexpf(1.0f, dl * (k + 1));
+            }
+            Ts[r * C::TS + c] = v;
+        }
+        __syncthreads();
+        // B columns of this lane: targets 16 b + i16, input rows 4 ks + kq
+        const float *mrow[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) mrow[b] = Mr + ((size_t)src_of[16 * b + i16] * 3 + comp) * C::RP + kq;
+        float bn[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bn[b] = mrow[b][0];
+        for (int ks = 0; ks < C::KS; ++ks) {
+            float bv[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bv[b] = bn[b];
+            if (ks + 1 < C::KS) {
+#pragma unroll
+                for (int b = 0; b < 4; ++b) bn[b] = mrow[b][4 * (ks + 1)];
+            }
+            float av[C::RTI];
+#pragma unroll
+            for (int a = 0; a < C::RTI; ++a) av[a] = Ts[(16 * a + i16) * C::TS + 4 * ks + kq];
+#pragma unroll
+            for (int a = 0; a < C::RTI; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+        }
+    }
+    // D fragment: lane holds rows 16 a + 4 kq + v of target column 16 b + i16
+    float *out = partial + ((size_t)blockIdx.x * 3 + comp) * C::R * 64;
+#pragma unroll
+    for (int a = 0; a < C::RTI; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * a + 4 * kq + v;
+                if (row < C::R) out[(size_t)row * 64 + 16 * b + i16] = acc[a][b][v];
+            }
+}
+
+template <int P>
+static size_t m2lb_lds_bytes() {
+    using C = MbCfg<P>;
+    return sizeof(float) * C::RT * C::TS + sizeof(float2) * (C::Q + 1) * C::IW + sizeof(int) * (64 + C::RP);
+}
+
+// per block: sum the items' partials in item order and add to Lt
+template <int P, class A>
+__global__ __launch_bounds__(TPB) void k_m2lb_reduce(int nblk, const int *blk_item0, const int *blk_nitem,
+                                                     const int2 *blk_cells, const float *partial, float2 *Lexp) {
+    // A: accumulator type (double in the mixed precision form)
+    constexpr int R = NR(P), NCP = NC(P);
+    const int b = blockIdx.x;
+    if (b >= nblk) return;
+    const int ni = blk_nitem[b];
+    if (ni == 0) return;
+    const int i0 = blk_item0[b];
+    const int2 bc = blk_cells[b];
+    for (int idx = threadIdx.x; idx < 3 * R * 64; idx += TPB) {
+        const int lane = idx & 63;
+        const int cr = idx >> 6;  // comp * R + r
+        if (lane >= bc.y) continue;
+        const int comp = cr / R, r = cr % R;
+        A s = A(0);
+        for (int i = 0; i < ni; ++i) s += (A)partial[((size_t)(i0 + i) * 3 * R + cr) * 64 + lane];
+        int k, l, im;
+        decode_row(r, k, l, im);
+        float *dst = reinterpret_cast<float *>(&Lexp[((size_t)(bc.x + lane) * 3 + comp) * NCP + CIDX(k, l)]) + im;
+        *dst = (float)((A)*dst + s);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static int bits_for_range(int64_t maxabs) {
+    int b = 1;
+    while ((1LL << b) < 2 * maxabs + 1) ++b;
+    return b;
+}
+
+template <int P>
+static void m2lb_plan_p(Ctx &c) {
+    hipStream_t s = c.stream;
+    const int64_t n = c.n_m2l;
+    c.m2lb_ok = false;
+    if (n == 0) return;
+    // ---- offsets and ranges ----
+    c.mb_eq.ensure(sizeof(int4) * n);
+    c.pairs64.ensure(64);
+    VFMM_HIP(hipMemsetAsync(c.pairs64.ptr, 0, 8, s));
+    k_m2lb_offsets<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.m2l_tgt.as<int>(), c.m2l_src.as<int2>(), c.c_geo.as<float4>(),
+                                                 c.c_level.as<int>(), c.img_B,
+                                                 c.prm.periodic ? (float)c.prm.box_len : 0.f, c.mb_eq.as<int4>(),
+                                                 c.pairs64.as<int>());
+    VFMM_LAUNCH_CHECK();
+    int rng[2];
+    VFMM_HIP(hipMemcpyAsync(rng, c.pairs64.ptr, 8, hipMemcpyDeviceToHost, s));
+    VFMM_HIP(hipStreamSynchronize(s));
+    KeyFmt f{};
+    f.bq = bits_for_range(rng[0]);
+    f.bdl = bits_for_range(rng[1]);
+    f.oq = (1 << (f.bq - 1));
+    f.odl = (1 << (f.bdl - 1));
+    const int kb = 3 * f.bq + f.bdl;
+    if (kb > 62) return;  // offsets too spread for packed keys: generic kernel
+    // ---- unique keys ----
+    c.lkey.ensure(sizeof(uint64_t) * n);
+    c.lval.ensure(sizeof(uint32_t) * n);
+    k_m2lb_pack<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.mb_eq.as<int4>(), f, c.lkey.as<uint64_t>(), c.lval.as<uint32_t>());
+    VFMM_LAUNCH_CHECK();
+    sort_pairs_u64(c, c.lkey, c.lval, c.lkey2, c.lval2, n, kb);
+    c.mb_flag.ensure(sizeof(int) * (n + 1));
+    c.mb_pos.ensure(sizeof(int) * (n + 1));
+    int *flag = c.mb_flag.as<int>(), *pos = c.mb_pos.as<int>();
+    k_flag_changes<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.lkey.as<uint64_t>(), flag);
+    VFMM_LAUNCH_CHECK();
+    scan_excl_i32(c, flag, pos, n);
+    int h2[2];
+    VFMM_HIP(hipMemcpyAsync(&h2[0], pos + n - 1, 4, hipMemcpyDeviceToHost, s));
+    VFMM_HIP(hipMemcpyAsync(&h2[1], flag + n - 1, 4, hipMemcpyDeviceToHost, s));
+    VFMM_HIP(hipStreamSynchronize(s));
+    const int nkeys = h2[0] + h2[1];
+    c.mb_kid.ensure(sizeof(int) * n);
+    c.mb_ukey.ensure(sizeof(uint64_t) * nkeys);
+    k_key_ids<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.lkey.as<uint64_t>(), c.lval.as<uint32_t>(), flag, pos,
+                                            c.mb_kid.as<int>(), c.mb_ukey.as<uint64_t>());
+    VFMM_LAUNCH_CHECK();
+    // ---- blocks of 64 target cells per level ----
+    LvlInfo L{};
+    L.nlev = c.depth + 1;
+    int nblk = 0;
+    std::vector<int2> bcells;
+    for (int l = 0; l <= c.depth; ++l) {
+        L.off[l] = c.lvl_off[l];
+        L.bbase[l] = nblk;
+        for (int cell = c.lvl_off[l]; cell < c.lvl_off[l + 1]; cell += 64)
+            bcells.push_back(make_int2(cell, std::min(64, c.lvl_off[l + 1] - cell)));
+        nblk = (int)bcells.size();
+    }
+    c.mb_nblk = nblk;
+    c.mb_bcells.ensure(sizeof(int2) * nblk);
+    VFMM_HIP(hipMemcpyAsync(c.mb_bcells.ptr, bcells.data(), sizeof(int2) * nblk, hipMemcpyHostToDevice, s));
+    const int kbits = bits_for_range(nkeys);
+    const int bbits = bits_for_range(nblk);
+    k_block_keys<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.m2l_tgt.as<int>(), c.c_level.as<int>(), L, c.mb_kid.as<int>(),
+                                               kbits, c.lkey.as<uint64_t>(), c.lval.as<uint32_t>());
+    VFMM_LAUNCH_CHECK();
+    sort_pairs_u64(c, c.lkey, c.lval, c.lkey2, c.lval2, n, kbits + bbits);
+    k_flag_changes<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.lkey.as<uint64_t>(), flag);
+    VFMM_LAUNCH_CHECK();
+    scan_excl_i32(c, flag, pos, n);
+    VFMM_HIP(hipMemcpyAsync(&h2[0], pos + n - 1, 4, hipMemcpyDeviceToHost, s));
+    VFMM_HIP(hipMemcpyAsync(&h2[1], flag + n - 1, 4, hipMemcpyDeviceToHost, s));
+    VFMM_HIP(hipStreamSynchronize(s));
+    const int ng = h2[0] + h2[1];
+    c.mb_ent.ensure(sizeof(int2) * n);
+    c.mb_groups.ensure(sizeof(int4) * ng);
+    k_groups<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.lkey.as<uint64_t>(), c.lval.as<uint32_t>(), flag, pos,
+                                           c.m2l_tgt.as<int>(), c.m2l_src.as<int2>(), c.c_level.as<int>(), L, kbits,
+                                           c.mb_ent.as<int2>(), c.mb_groups.as<int4>());
+    VFMM_LAUNCH_CHECK();
+    c.mb_blk.ensure(sizeof(int) * 3 * (size_t)nblk);
+    int *blk_first = c.mb_blk.as<int>(), *blk_item0 = blk_first + nblk, *blk_nitem = blk_item0 + nblk;
+    VFMM_HIP(hipMemsetAsync(c.mb_blk.ptr, 0, sizeof(int) * 3 * (size_t)nblk, s));
+    k_group_counts<<<cdiv(ng, TPB), TPB, 0, s>>>(ng, n, c.mb_groups.as<int4>(), blk_first);
+    VFMM_LAUNCH_CHECK();
+    k_item_flags<<<cdiv(ng, TPB), TPB, 0, s>>>(ng, c.mb_groups.as<int4>(), blk_first, flag);
+    VFMM_LAUNCH_CHECK();
+    scan_excl_i32(c, flag, pos, ng);
+    VFMM_HIP(hipMemcpyAsync(&h2[0], pos + ng - 1, 4, hipMemcpyDeviceToHost, s));
+    VFMM_HIP(hipMemcpyAsync(&h2[1], flag + ng - 1, 4, hipMemcpyDeviceToHost, s));
+    VFMM_HIP(hipStreamSynchronize(s));
+    const int nitems = h2[0] + h2[1];
+    c.mb_items.ensure(sizeof(int4) * nitems);
+    k_items<<<cdiv(ng, TPB), TPB, 0, s>>>(ng, c.mb_groups.as<int4>(), flag, pos, c.mb_items.as<int4>(), blk_item0,
+                                           blk_nitem);
+    VFMM_LAUNCH_CHECK();
+    c.mb_nkeys = nkeys;
+    c.mb_fmt[0] = f.bq;
+    c.mb_fmt[1] = f.bdl;
+    c.mb_fmt[2] = f.oq;
+    c.mb_fmt[3] = f.odl;
+    c.mb_ngroups = ng;
+    c.mb_nitems = nitems;
+    c.m2lb_ok = true;
+}
+
+void m2lb_plan(Ctx &c) {
+    switch (c.prm.p) {
+        case 4: m2lb_plan_p<4>(c); break;
+        case 6: m2lb_plan_p<6>(c); break;
+        case 8: m2lb_plan_p<8>(c); break;
+        case 10: m2lb_plan_p<10>(c); break;
+        case 12: m2lb_plan_p<12>(c); break;
+        default: throw Error{VFMM_EINVAL, "unsupported expansion degree p"};
+    }
+}
+
+template <int P>
+static void m2lb_prealloc_p(Ctx &c) {
+    constexpr int R = NR(P), RP = NRP(P);
+    c.mb_mr.ensure(sizeof(float) * (size_t)(c.ncells + 1) * 3 * RP);
+    c.mb_partial.ensure(sizeof(float) * (size_t)std::max(c.mb_nitems, 1) * 3 * R * 64);
+}
+
+void m2lb_prealloc(Ctx &c) {
+    if (!c.m2lb_ok) return;
+    switch (c.prm.p) {
+        case 4: m2lb_prealloc_p<4>(c); break;
+        case 6: m2lb_prealloc_p<6>(c); break;
+        case 8: m2lb_prealloc_p<8>(c); break;
+        case 10: m2lb_prealloc_p<10>(c); break;
+        case 12: m2lb_prealloc_p<12>(c); break;
+        default: throw Error{VFMM_EINVAL, "unsupported expansion degree p"};
+    }
+}
+
+template <int P>
+static void m2lb_run_p(Ctx &c) {
+    hipStream_t s = c.stream;
+    constexpr int R = NR(P), RP = NRP(P);
+    const int64_t mr_total = (int64_t)(c.ncells + 1) * 3 * RP;
+    c.mb_mr.ensure(sizeof(float) * mr_total);
+    k_m2lb_mreal<P><<<cdiv(mr_total, TPB), TPB, 0, s>>>(c.ncells, c.Mexp.as<float2>(), c.mb_mr.as<float>());
+    VFMM_LAUNCH_CHECK();
+    c.mb_partial.ensure(sizeof(float) * (size_t)c.mb_nitems * 3 * R * 64);
+    KeyFmt f{c.mb_fmt[0], c.mb_fmt[1], c.mb_fmt[2], c.mb_fmt[3]};
+    const size_t lds = m2lb_lds_bytes<P>();
+    static bool attr_set = false;
+    if (!attr_set) {
+        VFMM_HIP(hipFuncSetAttribute((const void *)k_m2lb<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr_set = true;
+    }
+    k_m2lb<P><<<c.mb_nitems, 192, lds, s>>>(c.mb_items.as<int4>(), c.mb_groups.as<int4>(), c.mb_ent.as<int2>(),
+                                             c.mb_mr.as<float>(), c.mb_ukey.as<uint64_t>(), f, c.ncells,
+                                             c.mb_partial.as<float>());
+    VFMM_LAUNCH_CHECK();
+    const int nblk = c.mb_nblk;
+    int *blk_item0 = c.mb_blk.as<int>() + nblk, *blk_nitem = blk_item0 + nblk;
+    if (c.prm.precision == VFMM_PRECISION_MIXED)
+        k_m2lb_reduce<P, double><<<nblk, TPB, 0, s>>>(nblk, blk_item0, blk_nitem, c.mb_bcells.as<int2>(),
+                                                       c.mb_partial.as<float>(), c.Lexp.as<float2>());
+    else
+        k_m2lb_reduce<P, float><<<nblk, TPB, 0, s>>>(nblk, blk_item0, blk_nitem, c.mb_bcells.as<int2>(),
+                                                      c.mb_partial.as<float>(), c.Lexp.as<float2>());
+    VFMM_LAUNCH_CHECK();
+}
+
+void m2lb_run(Ctx &c) {
+    switch (c.prm.p) {
+        case 4: m2lb_run_p<4>(c); break;
+        case 6: m2lb_run_p<6>(c); break;
+        case 8: m2lb_run_p<8>(c); break;
+        case 10: m2lb_run_p<10>(c); break;
+        case 12: m2lb_run_p<12>(c); break;
+        default: throw Error{VFMM_EINVAL, "unsupported expansion degree p"};
+    }
+}
+
+}  // namespace vfmm

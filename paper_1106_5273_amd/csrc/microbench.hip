@@ -1,0 +1,69 @@
+// VALU rate microbenchmarks for the roofline of the P2P and M2L kernels:
+// independent chains of float32 FMA (with a vector or a scalar operand),
+// v_exp_f32 and v_rsq_f32, timed with HIP events.  Built into its own small
+// library (libvfmm_mb.so); not part of the vfmm C ABI.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace {
+
+constexpr int CH = 8;  // independent chains per lane
+
+template <int KIND>
+__global__ __launch_bounds__(256) void k_rate(float *out, int iters, float a, float b) {
+    float v[CH];
+    for (int i = 0; i < CH; ++i) v[i] = (float)(threadIdx.x + i) * 1e-3f;
+    const float sa = __builtin_amdgcn_readfirstlane(a);
+    const float vb = b + (float)threadIdx.x * 1e-9f;  // per-lane multiplier
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                if (KIND == 0) v[i] = fmaf(v[i], vb, 1e-7f);                         // vector operands
+                if (KIND == 1) v[i] = fmaf(v[i], sa, 1e-7f);                         // scalar operand
+                if (KIND == 2) v[i] = __builtin_amdgcn_exp2f(v[i]);
+                if (KIND == 3) v[i] = __builtin_amdgcn_rsqf(v[i]);
+            }
+        }
+    }
+    float s = 0.f;
+    for (int i = 0; i < CH; ++i) s += v[i];
+    if (s == 12345.678f) out[threadIdx.x] = s;  // keep the chains live
+}
+
+}  // namespace
+
+extern "C" {
+
+// Runs kind (0: FMA vector operands, 1: FMA scalar operand, 2: exp2, 3: rsq)
+// on `blocks` work-groups of 256 threads for `iters` x 16 x 8 operations per
+// lane.  Returns the device time in milliseconds (< 0 on error).
+float vfmm_mb_rate(int kind, int blocks, int iters) {
+    float *out = nullptr;
+    if (hipMalloc(&out, 256 * sizeof(float)) != hipSuccess) return -1.f;
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    auto launch = [&]() {
+        switch (kind) {
+            case 0: k_rate<0><<<blocks, 256>>>(out, iters, 0.999f, 0.9999f); break;
+            case 1: k_rate<1><<<blocks, 256>>>(out, iters, 0.999f, 0.9999f); break;
+            case 2: k_rate<2><<<blocks, 256>>>(out, iters, 0.999f, 0.9999f); break;
+            default: k_rate<3><<<blocks, 256>>>(out, iters, 0.999f, 0.9999f); break;
+        }
+    };
+    launch();
+    (void)hipEventRecord(e0, nullptr);
+    launch();
+    (void)hipEventRecord(e1, nullptr);
+    float ms = -1.f;
+    if (hipEventSynchronize(e1) == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(out);
+    if (hipGetLastError() != hipSuccess) return -1.f;
+    return ms;
+}
+}

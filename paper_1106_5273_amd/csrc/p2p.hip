@@ -226,6 +226,155 @@ __global__ __launch_bounds__(256) void k_p2p(P2PConst k, P2PArgs A) {
     A.daz[o] = d2;
 }
 
+// ---------------------------------------------------------------------------
+// Float64 reference form: the same work blocks and lists, one lane per
+// target, every quantity in double and the cutoff always in its full form:
+//   F = P(3/2, x)/rho^3,  H = P(5/2, x)/rho^5,  x = c^2 rho^2,  c = 1/(sqrt 2 sigma).
+// For x < 2 the power series of the lower incomplete gamma function,
+//   P(a, x) = x^a e^{-x} sum_k x^k / Gamma(a + k + 1),
+// divided by rho^{2a}, gives F and H without cancellation (finite at rho = 0);
+// for x >= 2, 1 - P(3/2, x) = erfc(s) + (2/sqrt pi) s e^{-x}, s = sqrt x, and
+// P(5/2, x) = P(3/2, x) - (4/(3 sqrt pi)) s^3 e^{-x}.
+// ---------------------------------------------------------------------------
+struct P2P64Args {
+    const double4 *__restrict__ rec;
+    const int4 *__restrict__ blocks;
+    const int4 *__restrict__ ent;
+    int nblocks;
+    int B;
+    double len, c, c2;
+    const double *__restrict__ far_u;
+    const double *__restrict__ far_da;
+    int64_t n;
+    const int *__restrict__ perm;
+    const Bounds *__restrict__ bounds;
+    double inv3V;
+    int surface;
+    float *ux, *uy, *uz, *dax, *day, *daz;
+};
+
+__device__ inline void cutoff64(double r2, double c, double c2, double &F, double &H) {
+    const double x = c2 * r2;
+    const double isqpi = 0.56418958354775628695;  // 1/sqrt(pi)
+    const double e = exp(-x);
+    if (x < 2.0) {
+        double t = 4.0 / 3.0 * isqpi, u = 8.0 / 15.0 * isqpi;  // 1/Gamma(5/2), 1/Gamma(7/2)
+        double st = t, su = u;
+        for (int k = 1; k < 60; ++k) {
+            t *= x / (k + 1.5);
+            u *= x / (k + 2.5);
+            st += t;
+            su += u;
+            if (t < 1e-18 * st) break;
+        }
+        F = c * c2 * e * st;
+        H = c2 * c2 * c * e * su;
+    } else {
+        const double sx = sqrt(x);
+        const double rho = sqrt(r2);
+        const double q3 = erfc(sx) + 2.0 * isqpi * sx * e;
+        const double g = 1.0 - q3;
+        const double g5 = g - 4.0 / 3.0 * isqpi * sx * x * e;
+        const double ir = 1.0 / rho, ir2 = ir * ir;
+        F = g * ir * ir2;
+        H = g5 * ir * ir2 * ir2;
+    }
+}
+
+template <int SCHEME>
+__global__ __launch_bounds__(64) void k_p2p64(P2P64Args A) {
+    const int lane = threadIdx.x;
+    const int b = blockIdx.x;
+    if (b >= A.nblocks) return;
+    const int4 blk = A.blocks[b];
+    const bool valid = lane < blk.y;
+    const int i = blk.x + (valid ? lane : 0);
+    const double4 xp = A.rec[2 * (size_t)i];
+    const double4 xa = A.rec[2 * (size_t)i + 1];
+    const double fp = 12.566370614359172954;  // 4 pi
+    const double ai0 = xa.x * fp, ai1 = xa.y * fp, ai2 = xa.z * fp;
+    double S[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int W = 2 * A.B + 1;
+    for (int e = 0; e < blk.w; ++e) {
+        const int4 en = A.ent[blk.z + e];
+        const double xi = xp.x - (double)(en.z % W - A.B) * A.len;
+        const double yi = xp.y - (double)((en.z / W) % W - A.B) * A.len;
+        const double zi = xp.z - (double)(en.z / (W * W) - A.B) * A.len;
+        for (int j = en.x; j < en.x + en.y; ++j) {
+            const double4 sp = A.rec[2 * (size_t)j], sa = A.rec[2 * (size_t)j + 1];
+            const double dx = xi - sp.x, dy = yi - sp.y, dz = zi - sp.z;
+            double F, H;
+            cutoff64(dx * dx + dy * dy + dz * dz, A.c, A.c2, F, H);
+            const double c0 = sa.y * dz - sa.z * dy;
+            const double c1 = sa.z * dx - sa.x * dz;
+            const double c2 = sa.x * dy - sa.y * dx;
+            S[0] += F * c0;
+            S[1] += F * c1;
+            S[2] += F * c2;
+            S[3] += F * sa.x;
+            S[4] += F * sa.y;
+            S[5] += F * sa.z;
+            if (SCHEME == VFMM_SCHEME_TRANSPOSE) {
+                const double hd = H * (ai0 * c0 + ai1 * c1 + ai2 * c2);
+                S[6] += hd * dx;
+                S[7] += hd * dy;
+                S[8] += hd * dz;
+            } else {
+                const double hd = H * (ai0 * dx + ai1 * dy + ai2 * dz);
+                S[6] += hd * c0;
+                S[7] += hd * c1;
+                S[8] += hd * c2;
+            }
+        }
+    }
+    if (!valid) return;
+    double d0, d1, d2;
+    if (SCHEME == VFMM_SCHEME_TRANSPOSE) {
+        d0 = ai1 * S[5] - ai2 * S[4];
+        d1 = ai2 * S[3] - ai0 * S[5];
+        d2 = ai0 * S[4] - ai1 * S[3];
+    } else {
+        d0 = S[4] * ai2 - S[5] * ai1;
+        d1 = S[5] * ai0 - S[3] * ai2;
+        d2 = S[3] * ai1 - S[4] * ai0;
+    }
+    d0 -= 3.0 * S[6];
+    d1 -= 3.0 * S[7];
+    d2 -= 3.0 * S[8];
+    double u0 = S[0], u1 = S[1], u2 = S[2];
+    if (A.far_u) {
+        u0 += A.far_u[i];
+        u1 += A.far_u[A.n + i];
+        u2 += A.far_u[2 * A.n + i];
+        d0 += A.far_da[i];
+        d1 += A.far_da[A.n + i];
+        d2 += A.far_da[2 * A.n + i];
+    }
+    if (A.surface) {
+        u0 -= A.bounds->sum_xa[0] * A.inv3V;
+        u1 -= A.bounds->sum_xa[1] * A.inv3V;
+        u2 -= A.bounds->sum_xa[2] * A.inv3V;
+    }
+    const int o = A.perm[i];
+    A.ux[o] = (float)u0;
+    A.uy[o] = (float)u1;
+    A.uz[o] = (float)u2;
+    A.dax[o] = (float)d0;
+    A.day[o] = (float)d1;
+    A.daz[o] = (float)d2;
+}
+
+static void launch_p2p64(Ctx &c, P2P64Args A) {
+    if (A.nblocks == 0) return;
+    A.c = 1.0 / (std::sqrt(2.0) * (double)c.sigma_uniform);
+    A.c2 = A.c * A.c;
+    if (c.prm.scheme == VFMM_SCHEME_TRANSPOSE)
+        k_p2p64<VFMM_SCHEME_TRANSPOSE><<<A.nblocks, 64, 0, c.stream>>>(A);
+    else
+        k_p2p64<VFMM_SCHEME_CLASSICAL><<<A.nblocks, 64, 0, c.stream>>>(A);
+    VFMM_LAUNCH_CHECK();
+}
+
 static P2PConst make_const(double sigma) {
     P2PConst k{};
     const double c = 1.0 / (std::sqrt(2.0) * sigma);
@@ -254,7 +403,7 @@ static void launch_p2p(Ctx &c, const P2PConst &k, const P2PArgs &A) {
 }
 
 static void dispatch_p2p(Ctx &c, const P2PConst &k, const P2PArgs &A) {
-    const bool kah = c.prm.kahan != 0;
+    const bool kah = c.prm.kahan != 0 || c.prm.precision == VFMM_PRECISION_MIXED;
     if (c.prm.scheme == VFMM_SCHEME_TRANSPOSE) {
         if (kah) launch_p2p<VFMM_SCHEME_TRANSPOSE, true>(c, k, A);
         else launch_p2p<VFMM_SCHEME_TRANSPOSE, false>(c, k, A);
@@ -265,6 +414,27 @@ static void dispatch_p2p(Ctx &c, const P2PConst &k, const P2PArgs &A) {
 }
 
 void p2p_and_finalize(Ctx &c, float *ux, float *uy, float *uz, float *dax, float *day, float *daz) {
+    if (c.prm.precision == VFMM_PRECISION_FP64) {
+        P2P64Args A{};
+        A.rec = c.rec64.as<double4>();
+        A.blocks = c.blocks.as<int4>();
+        A.ent = c.p2p_ent.as<int4>();
+        A.nblocks = c.n_blocks;
+        A.B = c.img_B;
+        A.len = c.prm.periodic ? c.prm.box_len : 0.0;
+        A.far_u = c.far_u.as<double>();
+        A.far_da = c.far_da.as<double>();
+        A.n = c.n;
+        A.perm = c.perm.as<int>();
+        A.bounds = c.bres.as<Bounds>();
+        A.surface = (c.prm.periodic && c.prm.zero_mean) ? 1 : 0;
+        A.inv3V = c.prm.periodic ? 1.0 / (3.0 * c.prm.box_len * c.prm.box_len * c.prm.box_len) : 0.0;
+        A.ux = ux; A.uy = uy; A.uz = uz; A.dax = dax; A.day = day; A.daz = daz;
+        c.record(2 * PH_P2P);
+        launch_p2p64(c, A);
+        c.record(2 * PH_P2P + 1);
+        return;
+    }
     const P2PConst k = make_const(c.sigma_uniform);
     P2PArgs A{};
     A.rec = c.rec.as<float4>();
@@ -281,15 +451,26 @@ void p2p_and_finalize(Ctx &c, float *ux, float *uy, float *uz, float *dax, float
     A.surface = (c.prm.periodic && c.prm.zero_mean) ? 1 : 0;
     A.inv3V = c.prm.periodic ? (float)(1.0 / (3.0 * c.prm.box_len * c.prm.box_len * c.prm.box_len)) : 0.f;
     A.ux = ux; A.uy = uy; A.uz = uz; A.dax = dax; A.day = day; A.daz = daz;
-    if (c.ev_ok) VFMM_HIP(hipEventRecord(c.ev[2 * PH_P2P], c.stream));
+    c.record(2 * PH_P2P);
     dispatch_p2p(c, k, A);
-    if (c.ev_ok) VFMM_HIP(hipEventRecord(c.ev[2 * PH_P2P + 1], c.stream));
+    c.record(2 * PH_P2P + 1);
 }
 
 // ---------------------------------------------------------------------------
 // Direct mode: every target block against all N sources (entries of 64
 // sources, full cutoff form), in the caller's order, no tree, no far field.
 // ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_direct_setup64(int64_t n, const float *x, const float *y, const float *z,
+                                                        const float *ax, const float *ay, const float *az,
+                                                        const float *s, double4 *rec, int *perm) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double k = 0.079577471545947667884;  // 1/(4 pi)
+    rec[2 * i] = make_double4(x[i], y[i], z[i], s[i]);
+    rec[2 * i + 1] = make_double4((double)ax[i] * k, (double)ay[i] * k, (double)az[i] * k, 0.0);
+    perm[i] = (int)i;
+}
+
 __global__ __launch_bounds__(256) void k_direct_setup(int64_t n, const float *x, const float *y, const float *z,
                                                       const float *ax, const float *ay, const float *az,
                                                       const float *s, float4 *rec, int *perm) {
@@ -326,6 +507,27 @@ void direct_all_pairs(Ctx &c, const float *x, const float *y, const float *z, co
     VFMM_LAUNCH_CHECK();
     k_direct_blocks<<<cdiv(nb, 256), 256, 0, c.stream>>>(n, nb, c.blocks.as<int4>(), c.p2p_ent.as<int4>());
     VFMM_LAUNCH_CHECK();
+    c.n_blocks = nb;
+    c.p2p_pairs = n * n;
+    if (c.prm.precision == VFMM_PRECISION_FP64) {
+        c.rec64.ensure(sizeof(double4) * 2 * n);
+        k_direct_setup64<<<cdiv(n, 256), 256, 0, c.stream>>>(n, x, y, z, ax, ay, az, sigma, c.rec64.as<double4>(),
+                                                              c.perm.as<int>());
+        VFMM_LAUNCH_CHECK();
+        P2P64Args A{};
+        A.rec = c.rec64.as<double4>();
+        A.blocks = c.blocks.as<int4>();
+        A.ent = c.p2p_ent.as<int4>();
+        A.nblocks = nb;
+        A.n = n;
+        A.perm = c.perm.as<int>();
+        A.bounds = c.bres.as<Bounds>();
+        A.ux = ux; A.uy = uy; A.uz = uz; A.dax = dax; A.day = day; A.daz = daz;
+        c.record(2 * PH_P2P);
+        launch_p2p64(c, A);
+        c.record(2 * PH_P2P + 1);
+        return;
+    }
     const P2PConst k = make_const(c.sigma_uniform);
     P2PArgs A{};
     A.rec = c.rec.as<float4>();
@@ -343,9 +545,9 @@ void direct_all_pairs(Ctx &c, const float *x, const float *y, const float *z, co
     A.ux = ux; A.uy = uy; A.uz = uz; A.dax = dax; A.day = day; A.daz = daz;
     c.n_blocks = nb;
     c.p2p_pairs = n * n;
-    if (c.ev_ok) VFMM_HIP(hipEventRecord(c.ev[2 * PH_P2P], c.stream));
+    c.record(2 * PH_P2P);
     dispatch_p2p(c, k, A);
-    if (c.ev_ok) VFMM_HIP(hipEventRecord(c.ev[2 * PH_P2P + 1], c.stream));
+    c.record(2 * PH_P2P + 1);
 }
 
 }  // namespace vfmm

@@ -112,9 +112,10 @@ __global__ __launch_bounds__(TPB) void k_trav_write(TravArgs A, const int4 *fr, 
     }
 }
 
-__global__ __launch_bounds__(TPB) void k_trav_init(int4 *fr, int ncode) {
+// one (root, root, image) pair per problem and image code
+__global__ __launch_bounds__(TPB) void k_trav_init(int4 *fr, int nroot, int ncode) {
     const int i = blockIdx.x * TPB + threadIdx.x;
-    if (i < ncode) fr[i] = make_int4(0, 0, i, 0);
+    if (i < nroot * ncode) fr[i] = make_int4(i / ncode, i / ncode, i % ncode, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -133,11 +134,13 @@ __global__ __launch_bounds__(TPB) void k_count_tgt(const int4 *raw, int64_t n, i
     if (i < n) atomicAdd(&cnt[raw[i].x], 1);
 }
 
-__global__ __launch_bounds__(TPB) void k_m2l_gather(const int4 *raw, const uint32_t *order, int64_t n, int2 *out) {
+__global__ __launch_bounds__(TPB) void k_m2l_gather(const int4 *raw, const uint32_t *order, int64_t n, int2 *out,
+                                                    int *tgt) {
     const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (i >= n) return;
     const int4 e = raw[order[i]];
     out[i] = make_int2(e.y, e.z);
+    tgt[i] = e.x;
 }
 
 struct P2PEntryArgs {
@@ -249,9 +252,9 @@ void traverse_and_lists(Ctx &c) {
     const int ncode = c.img_codes;
     c.images_traversed = ncode;
 
-    int nf = ncode;
+    int nf = ncode * c.nprob;
     c.frA.ensure(sizeof(int4) * (size_t)nf);
-    k_trav_init<<<cdiv(nf, TPB), TPB, 0, s>>>(c.frA.as<int4>(), nf);
+    k_trav_init<<<cdiv(nf, TPB), TPB, 0, s>>>(c.frA.as<int4>(), c.nprob, ncode);
     VFMM_LAUNCH_CHECK();
     int64_t n_m2l = 0, n_p2p = 0;
     c.m2l_raw.ensure(sizeof(int4) * 1024);
@@ -292,9 +295,10 @@ void traverse_and_lists(Ctx &c) {
     // ---- M2L CSR ----
     csr_by_target(c, c.m2l_raw.as<int4>(), n_m2l, c.m2l_off);
     c.m2l_src.ensure(sizeof(int2) * (size_t)std::max<int64_t>(n_m2l, 1));
+    c.m2l_tgt.ensure(sizeof(int) * (size_t)std::max<int64_t>(n_m2l, 1));
     if (n_m2l > 0) {
         k_m2l_gather<<<cdiv(n_m2l, TPB), TPB, 0, s>>>(c.m2l_raw.as<int4>(), c.lval.as<uint32_t>(), n_m2l,
-                                                       c.m2l_src.as<int2>());
+                                                       c.m2l_src.as<int2>(), c.m2l_tgt.as<int>());
         VFMM_LAUNCH_CHECK();
     }
     // ---- P2P CSR ----

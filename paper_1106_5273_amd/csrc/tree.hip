@@ -210,20 +210,66 @@ __device__ inline uint64_t spread3(uint32_t v) {
     return x;
 }
 
+// Batched problems: the problem id occupies the bits above 3*KL (KL key
+// levels per axis), so each problem's particles stay contiguous after the
+// sort and every problem gets its own root cube.
 __global__ __launch_bounds__(TPB) void k_morton(const float *x, const float *y, const float *z, int64_t n,
-                                                RootBox box, uint64_t *keys, uint32_t *vals) {
+                                                const RootBox *boxes, const int *pid, int KL, uint64_t *keys,
+                                                uint32_t *vals) {
     const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (i >= n) return;
-    const float sc = 2097152.0f / box.len;
+    const int b = pid ? pid[i] : 0;
+    const RootBox box = boxes[b];
+    const float cells = (float)(1u << KL);
+    const float sc = cells / box.len;
     const float p[3] = {x[i], y[i], z[i]};
     uint32_t q[3];
     for (int d = 0; d < 3; ++d) {
         float t = floorf((p[d] - box.lo[d]) * sc);
-        t = fminf(fmaxf(t, 0.0f), 2097151.0f);
+        t = fminf(fmaxf(t, 0.0f), cells - 1.0f);
         q[d] = (uint32_t)t;
     }
-    keys[i] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+    keys[i] = ((uint64_t)b << (3 * KL)) | (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
     vals[i] = (uint32_t)i;
+}
+
+// problem id of every particle and per-problem bounding cubes
+__global__ __launch_bounds__(TPB) void k_problem_ids(const int64_t *off, int *pid) {
+    const int b = blockIdx.x;
+    for (int64_t i = off[b] + threadIdx.x; i < off[b + 1]; i += TPB) pid[i] = b;
+}
+
+__global__ __launch_bounds__(TPB) void k_problem_boxes(const int64_t *off, const float *x, const float *y,
+                                                       const float *z, RootBox *boxes) {
+    __shared__ float lo[3][TPB], hi[3][TPB];
+    const int b = blockIdx.x;
+    float l[3] = {3.4e38f, 3.4e38f, 3.4e38f}, h[3] = {-3.4e38f, -3.4e38f, -3.4e38f};
+    for (int64_t i = off[b] + threadIdx.x; i < off[b + 1]; i += TPB) {
+        const float p[3] = {x[i], y[i], z[i]};
+        for (int d = 0; d < 3; ++d) { l[d] = fminf(l[d], p[d]); h[d] = fmaxf(h[d], p[d]); }
+    }
+    for (int d = 0; d < 3; ++d) { lo[d][threadIdx.x] = l[d]; hi[d][threadIdx.x] = h[d]; }
+    __syncthreads();
+    for (int o = TPB / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            for (int d = 0; d < 3; ++d) {
+                lo[d][threadIdx.x] = fminf(lo[d][threadIdx.x], lo[d][threadIdx.x + o]);
+                hi[d][threadIdx.x] = fmaxf(hi[d][threadIdx.x], hi[d][threadIdx.x + o]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        float len = 0.f, c[3];
+        for (int d = 0; d < 3; ++d) {
+            len = fmaxf(len, hi[d][0] - lo[d][0]);
+            c[d] = 0.5f * (lo[d][0] + hi[d][0]);
+        }
+        len = len * (1.0f + 1e-5f) + 1e-6f * fmaxf(fabsf(c[0]), fmaxf(fabsf(c[1]), fabsf(c[2]))) + 1e-30f;
+        RootBox r;
+        for (int d = 0; d < 3; ++d) r.lo[d] = c[d] - 0.5f * len;
+        r.len = len;
+        boxes[b] = r;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -340,30 +386,51 @@ void gather_strengths(Ctx &c, const float *ax, const float *ay, const float *az,
     VFMM_LAUNCH_CHECK();
 }
 
+// float64 records for the float64 form: positions and cores from the sorted
+// float32 records (exact), strengths from the caller's arrays scaled in float64
+__global__ __launch_bounds__(TPB) void k_gather_rec64(const int *perm, int64_t n, const float *ax, const float *ay,
+                                                      const float *az, const float4 *rec, double4 *rec64) {
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i >= n) return;
+    const int j = perm[i];
+    const double k = 0.079577471545947667884;  // 1/(4 pi)
+    const float4 p = rec[2 * i];
+    rec64[2 * i] = make_double4(p.x, p.y, p.z, p.w);
+    rec64[2 * i + 1] = make_double4((double)ax[j] * k, (double)ay[j] * k, (double)az[j] * k, 0.0);
+}
+
+void gather_records64(Ctx &c, const float *ax, const float *ay, const float *az) {
+    if (c.n == 0) return;
+    c.rec64.ensure(sizeof(double4) * 2 * (size_t)c.n);
+    k_gather_rec64<<<cdiv(c.n, TPB), TPB, 0, c.stream>>>(c.perm.as<int>(), c.n, ax, ay, az, c.rec.as<float4>(),
+                                                         c.rec64.as<double4>());
+    VFMM_LAUNCH_CHECK();
+}
+
 // ---------------------------------------------------------------------------
 // Octree, level by level.  A cell at level l holds a contiguous range of the
 // sorted keys sharing their top 3l bits; it is split while it holds more than
 // ncrit particles and l < 21.  Children of a cell are contiguous.
 // ---------------------------------------------------------------------------
-__device__ inline int octant_at(uint64_t key, int lchild) { return (int)((key >> (3 * (21 - lchild))) & 7); }
+__device__ inline int octant_at(uint64_t key, int lchild, int KL) { return (int)((key >> (3 * (KL - lchild))) & 7); }
 
-__global__ __launch_bounds__(TPB) void k_count_children(int c0, int c1, int lvl, int ncrit, const int *start,
+__global__ __launch_bounds__(TPB) void k_count_children(int c0, int c1, int lvl, int ncrit, int KL, const int *start,
                                                         const int *count, const uint64_t *keys, int *nchild) {
     const int cell = c0 + blockIdx.x * TPB + threadIdx.x;
     if (cell >= c1) return;
     const int s = start[cell], cnt = count[cell];
     int nc = 0;
-    if (cnt > ncrit && lvl < 21) {
+    if (cnt > ncrit && lvl < KL) {
         // octants are non-decreasing along the range: count distinct values
         int lo = s;
         const int end = s + cnt;
         while (lo < end) {
-            const int o = octant_at(keys[lo], lvl + 1);
+            const int o = octant_at(keys[lo], lvl + 1, KL);
             // first index with octant > o
             int a = lo, b = end;
             while (a < b) {
                 const int mid = (a + b) >> 1;
-                if (octant_at(keys[mid], lvl + 1) <= o) a = mid + 1; else b = mid;
+                if (octant_at(keys[mid], lvl + 1, KL) <= o) a = mid + 1; else b = mid;
             }
             ++nc;
             lo = a;
@@ -372,7 +439,7 @@ __global__ __launch_bounds__(TPB) void k_count_children(int c0, int c1, int lvl,
     nchild[cell - c0] = nc;
 }
 
-__global__ __launch_bounds__(TPB) void k_make_children(int c0, int c1, int lvl, int cnext, const int *start,
+__global__ __launch_bounds__(TPB) void k_make_children(int c0, int c1, int lvl, int cnext, int KL, const int *start,
                                                        const int *count, const uint64_t *keys, const int *choff,
                                                        const int *nchild_l, int *c_start, int *c_count,
                                                        int *c_parent, int *c_child, int *c_nchild, int *c_level) {
@@ -386,11 +453,11 @@ __global__ __launch_bounds__(TPB) void k_make_children(int c0, int c1, int lvl, 
     const int s = start[cell], end = s + count[cell];
     int lo = s, k = 0;
     while (lo < end) {
-        const int o = octant_at(keys[lo], lvl + 1);
+        const int o = octant_at(keys[lo], lvl + 1, KL);
         int a = lo, b = end;
         while (a < b) {
             const int mid = (a + b) >> 1;
-            if (octant_at(keys[mid], lvl + 1) <= o) a = mid + 1; else b = mid;
+            if (octant_at(keys[mid], lvl + 1, KL) <= o) a = mid + 1; else b = mid;
         }
         const int ch = first + k;
         c_start[ch] = lo;
@@ -404,7 +471,8 @@ __global__ __launch_bounds__(TPB) void k_make_children(int c0, int c1, int lvl, 
 
 // Centres from the key prefix of the first particle; leaves get their tight
 // radius (max distance of a particle from the cube centre) and bounding box.
-__global__ __launch_bounds__(TPB) void k_leaf_geometry(int ncell, RootBox box, const int *start, const int *count,
+__global__ __launch_bounds__(TPB) void k_leaf_geometry(int ncell, const RootBox *boxes, int KL, const int *start,
+                                                       const int *count,
                                                        const int *level, const int *nchild, const uint64_t *keys,
                                                        const float4 *rec, float4 *geo, float *rad, float4 *blo,
                                                        float4 *bhi) {
@@ -413,10 +481,11 @@ __global__ __launch_bounds__(TPB) void k_leaf_geometry(int ncell, RootBox box, c
     const int lvl = level[cell];
     const int s = start[cell];
     const uint64_t key = keys[s];
+    const RootBox box = boxes[(int)(key >> (3 * KL))];
     // cell integer coordinates at this level
     uint32_t q[3] = {0, 0, 0};
     for (int b = 0; b < lvl; ++b) {
-        const int o = octant_at(key, b + 1);
+        const int o = octant_at(key, b + 1, KL);
         q[0] = (q[0] << 1) | ((o >> 2) & 1);
         q[1] = (q[1] << 1) | ((o >> 1) & 1);
         q[2] = (q[2] << 1) | (o & 1);
@@ -481,11 +550,14 @@ __global__ __launch_bounds__(TPB) void k_leaf_compact(int ncell, const int *nchi
     if (cell < ncell && nchild[cell] == 0) leaves[pos[cell]] = cell;
 }
 
-__global__ void k_root(int n, int *start, int *count, int *parent, int *level) {
-    start[0] = 0;
-    count[0] = n;
-    parent[0] = -1;
-    level[0] = 0;
+__global__ __launch_bounds__(TPB) void k_roots(int nprob, const int64_t *off, int n, int *start, int *count,
+                                               int *parent, int *level) {
+    const int b = blockIdx.x * TPB + threadIdx.x;
+    if (b >= nprob) return;
+    start[b] = off ? (int)off[b] : 0;
+    count[b] = off ? (int)(off[b + 1] - off[b]) : n;
+    parent[b] = -1;
+    level[b] = 0;
 }
 
 // grow a cell array keeping its first `used` elements
@@ -504,28 +576,47 @@ void build_tree(Ctx &c, int64_t n, const float *x, const float *y, const float *
     // ---- Morton keys and sort ----
     c.keyA.ensure(sizeof(uint64_t) * n);
     c.valA.ensure(sizeof(uint32_t) * n);
-    k_morton<<<cdiv(n, TPB), TPB, 0, s>>>(x, y, z, n, c.box, c.keyA.as<uint64_t>(), c.valA.as<uint32_t>());
+    const int nprob = c.nprob;
+    int pbits = 0;
+    while ((1 << pbits) < nprob) ++pbits;
+    c.key_levels = nprob > 1 ? (63 - pbits) / 3 : 21;
+    const int KL = c.key_levels;
+    c.pbox.ensure(sizeof(RootBox) * (size_t)nprob);
+    int *pid = nullptr;
+    if (nprob > 1) {
+        c.pid.ensure(sizeof(int) * n);
+        pid = c.pid.as<int>();
+        k_problem_ids<<<nprob, TPB, 0, s>>>(c.poff.as<int64_t>(), pid);
+        VFMM_LAUNCH_CHECK();
+        k_problem_boxes<<<nprob, TPB, 0, s>>>(c.poff.as<int64_t>(), x, y, z, c.pbox.as<RootBox>());
+        VFMM_LAUNCH_CHECK();
+    } else {
+        VFMM_HIP(hipMemcpyAsync(c.pbox.ptr, &c.box, sizeof(RootBox), hipMemcpyHostToDevice, s));
+    }
+    k_morton<<<cdiv(n, TPB), TPB, 0, s>>>(x, y, z, n, c.pbox.as<RootBox>(), pid, KL, c.keyA.as<uint64_t>(),
+                                           c.valA.as<uint32_t>());
     VFMM_LAUNCH_CHECK();
-    radix_sort(c, c.keyA, c.valA, c.keyB, c.valB, n, 63);
+    radix_sort(c, c.keyA, c.valA, c.keyB, c.valB, n, 3 * KL + pbits);
     c.rec.ensure(sizeof(float4) * 2 * n);
     c.perm.ensure(sizeof(int) * n);
     k_gather_pos<<<cdiv(n, TPB), TPB, 0, s>>>(c.valA.as<uint32_t>(), n, x, y, z, sigma, c.rec.as<float4>(),
                                                c.perm.as<int>());
     VFMM_LAUNCH_CHECK();
-    if (c.ev_ok) VFMM_HIP(hipEventRecord(c.ev[2 * PH_BOUNDS_SORT + 1], s));
-    if (c.ev_ok) VFMM_HIP(hipEventRecord(c.ev[2 * PH_TREE], s));
+    c.record(2 * PH_BOUNDS_SORT + 1);
+    c.record(2 * PH_TREE);
 
     // ---- levels ----
-    size_t cap = (size_t)std::max<int64_t>(64, 2 * n / std::max(1, c.prm.ncrit) + 64);
+    size_t cap = (size_t)std::max<int64_t>(64, 2 * n / std::max(1, c.prm.ncrit) + 64 + 2 * (int64_t)nprob);
     DevBuf *arrs[] = {&c.c_start, &c.c_count, &c.c_parent, &c.c_child, &c.c_nchild, &c.c_level};
     for (DevBuf *b : arrs) b->ensure(sizeof(int) * cap);
     cap = std::min(c.c_start.cap, std::min(c.c_count.cap, c.c_parent.cap)) / sizeof(int);
     for (DevBuf *b : arrs) cap = std::min(cap, b->cap / sizeof(int));
-    k_root<<<1, 1, 0, s>>>((int)n, c.c_start.as<int>(), c.c_count.as<int>(), c.c_parent.as<int>(),
-                           c.c_level.as<int>());
+    k_roots<<<cdiv(nprob, TPB), TPB, 0, s>>>(nprob, nprob > 1 ? c.poff.as<int64_t>() : nullptr, (int)n,
+                                              c.c_start.as<int>(), c.c_count.as<int>(), c.c_parent.as<int>(),
+                                              c.c_level.as<int>());
     VFMM_LAUNCH_CHECK();
     c.lvl_off.assign(1, 0);
-    c.lvl_off.push_back(1);
+    c.lvl_off.push_back(nprob);
     int lvl = 0;
     const uint64_t *keys = c.keyA.as<uint64_t>();
     int h_tot[2];
@@ -535,7 +626,7 @@ void build_tree(Ctx &c, int64_t n, const float *x, const float *y, const float *
         c.c_tmp.ensure(sizeof(int) * (2 * (size_t)nl + 2));
         int *nch = c.c_tmp.as<int>();
         int *off = nch + nl + 1;
-        k_count_children<<<cdiv(nl, TPB), TPB, 0, s>>>(c0, c1, lvl, c.prm.ncrit, c.c_start.as<int>(),
+        k_count_children<<<cdiv(nl, TPB), TPB, 0, s>>>(c0, c1, lvl, c.prm.ncrit, KL, c.c_start.as<int>(),
                                                         c.c_count.as<int>(), keys, nch);
         VFMM_LAUNCH_CHECK();
         scan_excl_i32(c, nch, off, nl);
@@ -548,7 +639,7 @@ void build_tree(Ctx &c, int64_t n, const float *x, const float *y, const float *
             for (DevBuf *b : arrs) grow_keep(c, *b, sizeof(int) * ncap, sizeof(int) * (size_t)c1);
             cap = ncap;
         }
-        k_make_children<<<cdiv(nl, TPB), TPB, 0, s>>>(c0, c1, lvl, c1, c.c_start.as<int>(), c.c_count.as<int>(),
+        k_make_children<<<cdiv(nl, TPB), TPB, 0, s>>>(c0, c1, lvl, c1, KL, c.c_start.as<int>(), c.c_count.as<int>(),
                                                        keys, off, nch, c.c_start.as<int>(), c.c_count.as<int>(),
                                                        c.c_parent.as<int>(), c.c_child.as<int>(),
                                                        c.c_nchild.as<int>(), c.c_level.as<int>());
@@ -566,7 +657,7 @@ void build_tree(Ctx &c, int64_t n, const float *x, const float *y, const float *
     c.c_rad.ensure(sizeof(float) * nc);
     c.c_lo.ensure(sizeof(float4) * nc);
     c.c_hi.ensure(sizeof(float4) * nc);
-    k_leaf_geometry<<<cdiv(nc, TPB), TPB, 0, s>>>(nc, c.box, c.c_start.as<int>(), c.c_count.as<int>(),
+    k_leaf_geometry<<<cdiv(nc, TPB), TPB, 0, s>>>(nc, c.pbox.as<RootBox>(), KL, c.c_start.as<int>(), c.c_count.as<int>(),
                                                    c.c_level.as<int>(), c.c_nchild.as<int>(), keys,
                                                    c.rec.as<float4>(), c.c_geo.as<float4>(), c.c_rad.as<float>(),
                                                    c.c_lo.as<float4>(), c.c_hi.as<float4>());
@@ -592,7 +683,7 @@ void build_tree(Ctx &c, int64_t n, const float *x, const float *y, const float *
     c.leaves.ensure(sizeof(int) * (size_t)c.nleaves);
     k_leaf_compact<<<cdiv(nc, TPB), TPB, 0, s>>>(nc, c.c_nchild.as<int>(), pos, c.leaves.as<int>());
     VFMM_LAUNCH_CHECK();
-    if (c.ev_ok) VFMM_HIP(hipEventRecord(c.ev[2 * PH_TREE + 1], s));
+    c.record(2 * PH_TREE + 1);
 }
 
 }  // namespace vfmm
