@@ -20,7 +20,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "FMM step time & P2P Gpair-interactions/s at 128^3 particles, p=10, ≤1e-4 err"
-PEAK_FP32_VALU_TFLOPS = 157.3        # 256 CU x 4 SIMD x 16 lanes x 2 (packed) x 2 (FMA) x 2.4 GHz
+PEAK_FP32_VALU_TFLOPS = 157.3        # published FP32 vector peak of MI355X (256 CU, 2.4 GHz); the non-packed
+                                      # v_fmac_f32 rate measured by --microbench reaches 87% of it
 FLOPS_PER_PAIR = 79                   # gfx950 ISA of the P2P pair body (s >= 1 form): 29 FMA + 16 MUL + 3 SUB + 2 TRANS, FMA = 2
 PAPER_FLOPS_PER_PAIR = 174            # Table 1 convention (70 + 104)
 
@@ -40,8 +41,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
-                    help="c2: 128^3 periodic step (default, the headline line); c3: 256^3 plain vs "
-                         "compensated forms; c4: 512 batched ring problems vs sequential; c5: 256^3 "
+                    help="c2: 128^3 periodic step (default, the headline line); c3: 256^3 float32 vs "
+                         "mixed vs float64 forms; c4: 512 batched ring problems vs sequential; c5: 256^3 "
                          "autotuned RK2 step")
     ap.add_argument("--microbench", action="store_true",
                     help="only measure VALU FP32 FMA / exp2 / rsq issue rates and exit")
@@ -71,27 +72,30 @@ def traffic_from_profile(pairs_per_launch):
 
 
 def cpu_baseline(case, seconds):
-    """FP64 direct oracle on a bounded sample: a subset of targets against all
-    sources of the central box, on every host core."""
+    """FP64 direct oracle on a bounded sample: random targets against all
+    sources of the central box, on every host core, in growing chunks until
+    about `seconds` of CPU work have been timed."""
     import numpy as np
 
     import oracle
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     n = case["n"]
-    rng = np.random.default_rng(123)
-    nt = 8
-    t0 = time.perf_counter()
-    oracle.direct(case, targets=rng.choice(n, nt, replace=False))
-    dt = time.perf_counter() - t0
-    nt = int(max(8, min(n, nt * seconds / max(dt, 1e-3))))
-    idx = rng.choice(n, nt, replace=False)
-    t0 = time.perf_counter()
-    oracle.direct(case, targets=idx)
-    dt = time.perf_counter() - t0
-    pairs = nt * n
+    order = np.random.default_rng(123).permutation(n)
+    oracle.direct(case, targets=order[:4])  # load the library, fault in the inputs
+    done, chunk, dt = 0, 16, 0.0
+    while dt < seconds and done < n:
+        idx = order[done:done + chunk]
+        t0 = time.perf_counter()
+        oracle.direct(case, targets=idx)
+        el = time.perf_counter() - t0
+        dt += el
+        done += len(idx)
+        if el < 0.25 * seconds:
+            chunk *= 2
+    pairs = done * n
     return {"value": pairs / dt / 1e9, "unit": "Gpair/s", "cores": cores, "kind": "oracle",
             "sample": "%d random targets x %d sources of the central box (free-space FP64 direct sum), %.1f s"
-                      % (nt, n, dt)}
+                      % (done, n, dt)}
 
 
 def _line(metric, value, unit, ms, args, workload, extra, higher=True):
@@ -189,6 +193,65 @@ def bench_rk(args, vf, wl):
     print(json.dumps(line), flush=True)
 
 
+def bench_precision(args, vf, wl):
+    """256^3 periodic lattice, p = 10: the float32, mixed and float64 forms of
+    the same tree.  Reports each form's step time, its difference from the
+    float64 form (rounding error) and its error against the exact periodic sum
+    on 65,536 random targets."""
+    import numpy as np
+    import torch
+    n1 = args.n if args.n != 128 else 256
+    case = wl.turbulence_case(n1, seed=3)
+    t = vf.case_to_device(case)
+    outs, res = {}, {}
+    for prec, name in ((2, "fp64"), (0, "fp32"), (1, "mixed")):
+        ctx = vf.Context(p=args.p, theta=args.theta, ncrit=args.ncrit, periodic=1, box_len=2 * np.pi,
+                         images=args.images, precision=prec)
+        out = tuple(torch.empty(case["n"], dtype=torch.float32, device="cuda") for _ in range(6))
+        steps = 1 if prec == 2 else args.steps
+        ctx.build(t[0], t[1], t[2], t[6])
+        ctx.evaluate(*t, out=out)
+        torch.cuda.synchronize()
+        ph = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.build(t[0], t[1], t[2], t[6])
+            ctx.evaluate(*t, out=out)
+            ph.append(ctx.timings())
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        st = ctx.stats()
+        ctx.close()
+        outs[name] = (np.stack([o.cpu().numpy() for o in out[:3]], 1).astype(np.float64),
+                      np.stack([o.cpu().numpy() for o in out[3:]], 1).astype(np.float64))
+        res[name] = {"ms_per_step": ms, "steps": steps,
+                     "phases_ms": {k: float(np.mean([p[k] for p in ph])) for k in ph[0]}}
+        print("precision %s: %.1f ms/step" % (name, ms), file=sys.stderr, flush=True)
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    u64, d64 = outs["fp64"]
+    for name in ("fp32", "mixed"):
+        res[name]["rel_l2_vs_fp64_form"] = {"u": rel(outs[name][0], u64), "dalpha": rel(outs[name][1], d64)}
+    if not args.no_check:
+        import oracle
+        rng = np.random.default_rng(33)
+        idx = np.sort(rng.choice(case["n"], size=min(65536, case["n"]), replace=False))
+        us, Js = oracle.spectral_lattice(case)
+        das, _ = oracle.stretching(Js, np.stack([case["ax"], case["ay"], case["az"]], 1).astype(np.float64))
+        for name in ("fp64", "fp32", "mixed"):
+            res[name]["rel_l2_vs_oracle_65536"] = {"u": rel(outs[name][0][idx], us[idx]),
+                                                   "dalpha": rel(outs[name][1][idx], das[idx])}
+    ms = res["fp32"]["ms_per_step"]
+    line = _line("precision forms at %d^3: step time and rounding error" % n1, st["p2p_pairs"] / (ms * 1e-3) / 1e9,
+                 "Gpair/s", ms, args,
+                 "periodic %d^3 turbulence-shaped lattice (seed 3), p=%d, theta=%g, images=%d; float32 / mixed / "
+                 "float64 forms of one tree" % (n1, args.p, args.theta, args.images),
+                 {"p2p_pairs": st["p2p_pairs"], "forms": res})
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -231,8 +294,8 @@ def main():
         return bench_batched(args, vf, wl)
     if args.workload == "c5":
         return bench_rk(args, vf, wl)
-    if args.workload == "c3" and args.n == 128:
-        args.n = 256
+    if args.workload == "c3":
+        return bench_precision(args, vf, wl)
     L = 2 * np.pi
     case = wl.turbulence_case(args.n, seed=2)
     t = vf.case_to_device(case)

@@ -63,6 +63,19 @@ struct DevBuf {
 
 inline unsigned cdiv(size_t a, size_t b) { return unsigned((a + b - 1) / b); }
 
+// Work-groups are dispatched round-robin over the 8 XCDs (work-group i runs on
+// XCD i % 8), and each XCD has its own L2.  Launch 8 * g8 work-groups for g
+// logical ones (g8 = ceil(g / 8)) and map physical i to logical
+// (i % 8) * g8 + i / 8: each XCD then walks one contiguous range of logical
+// work, so neighbouring items (Morton-ordered targets) share its L2.  Logical
+// indices >= g exit at once.
+constexpr int NUM_XCD = 8;
+inline unsigned xcd_grid(unsigned g) { return NUM_XCD * cdiv(g, NUM_XCD); }
+__device__ inline int xcd_logical(int i, int grid) {
+    const int g8 = grid / NUM_XCD;
+    return (i % NUM_XCD) * g8 + i / NUM_XCD;
+}
+
 // Global reduction result of the bounds pass (device, float64 accumulators).
 struct Bounds {
     double lo[3], hi[3];

@@ -113,69 +113,90 @@ __global__ __launch_bounds__(64) void k_p2m(const int *leaves, const int *start,
 }
 
 // ---------------------------------------------------------------------------
-// M2M: one wave per parent cell of one level.
-//   Mt_n^m(P) = sum_children sum_{k,l} conj(R_k^l(d)) Mt_{n-k}^{m-l}(c) (s_c/s_P)^{n-k},
+// M2M: one work-group per parent cell of one level, one thread per
+// (potential, coefficient n >= m >= 0) of the parent.
+//   Mt_n^m(P) = sum_children sum_{k,l} conj(R_k^l(d)) (s_c/s_P)^{n-k} Mt_{n-k}^{m-l}(c),
 //   d = (c - P)/s_P.
+// Children are staged one at a time in LDS as full-order tables (m from -n
+// to n, negative orders expanded once) with the size ratio folded into the
+// child's coefficients, so the inner loop is a plain complex multiply-add.
 // S is the storage type of the expansions, R the arithmetic type (the mixed
 // precision form keeps float storage and accumulates in double).
 // ---------------------------------------------------------------------------
+template <int P>
+struct XferCfg {
+    static constexpr int NCP = NC(P);
+    static constexpr int W = 2 * P + 1;                       // full-order row width
+    static constexpr int THREADS = ((3 * NCP + 63) / 64) * 64;
+};
+
 template <int P, class R, class S>
-__global__ __launch_bounds__(64) void k_m2m(int c0, int c1, const int *child, const int *nchild, const float4 *geo,
-                                            typename VT<S>::V2 *Mexp) {
+__global__ __launch_bounds__((XferCfg<P>::THREADS)) void k_m2m(int c0, int c1, const int *child, const int *nchild,
+                                                               const float4 *geo, typename VT<S>::V2 *Mexp) {
     using V2 = typename VT<R>::V2;
-    constexpr int NCP = NC(P);
-    __shared__ V2 Mc[8][3][NCP];
-    __shared__ V2 Rd[8][NCP];
-    __shared__ R ratio[8];
+    using C = XferCfg<P>;
+    constexpr int NCP = C::NCP, W = C::W;
+    __shared__ V2 Mf[3][P + 1][W];   // child multipole, scaled by (s_c/s_P)^n, full orders
+    __shared__ V2 Rf[P + 1][W];      // conj R_k^l(d), full orders
     const int cell = c0 + blockIdx.x;
     if (cell >= c1) return;
     const int nc = nchild[cell];
     if (nc == 0) return;
     const int f = child[cell];
     const float4 gp = geo[cell];
-    const int lane = threadIdx.x;
-    if (lane < nc) {
-        const float4 gc = geo[f + lane];
-        const R inv = R(1) / R(gp.w);
-        V2 Rl[NCP];
-        regular_harmonics<P, R, V2>((R(gc.x) - R(gp.x)) * inv, (R(gc.y) - R(gp.y)) * inv, (R(gc.z) - R(gp.z)) * inv,
-                                    Rl);
-        for (int t = 0; t < NCP; ++t) Rd[lane][t] = Rl[t];
-        ratio[lane] = R(gc.w) * inv;
-    }
-    for (int i = lane; i < nc * 3 * NCP; i += 64) {
-        const int k = i / (3 * NCP), r = i % (3 * NCP);
-        const auto v = Mexp[((size_t)(f + k) * 3) * NCP + r];
-        Mc[k][r / NCP][r % NCP] = V2{R(v.x), R(v.y)};
-    }
-    __syncthreads();
-    for (int t = lane; t < NCP; t += 64) {
-        int n, m;
-        decode_nm(t, n, m);
-        V2 acc[3] = {V2{R(0), R(0)}, V2{R(0), R(0)}, V2{R(0), R(0)}};
-        for (int k = 0; k < nc; ++k) {
-            const R rt = ratio[k];
-            // sum from high source degree nm = n - kk to low: kk from 0 up
+    const int tid = threadIdx.x;
+    const bool active = tid < 3 * NCP;
+    const int comp = active ? tid / NCP : 0;
+    int n = 0, m = 0;
+    decode_nm(active ? tid % NCP : 0, n, m);
+    const R inv = R(1) / R(gp.w);
+    V2 acc = V2{R(0), R(0)};
+    for (int k = 0; k < nc; ++k) {
+        const float4 gc = geo[f + k];
+        __syncthreads();
+        if (tid == 0) {
+            V2 Rl[NCP];
+            regular_harmonics<P, R, V2>((R(gc.x) - R(gp.x)) * inv, (R(gc.y) - R(gp.y)) * inv,
+                                        (R(gc.z) - R(gp.z)) * inv, Rl);
+#pragma unroll
+            for (int q = 0; q < NCP; ++q) {
+                int a, b;
+                decode_nm(q, a, b);
+                const V2 v = Rl[q];
+                Rf[a][P + b] = V2{v.x, -v.y};                                   // conj R^b
+                if (b > 0) Rf[a][P - b] = (b & 1) ? V2{-v.x, -v.y} : V2{v.x, v.y};  // conj R^{-b}
+            }
+        }
+        const R rt = R(gc.w) * inv;
+        for (int i = tid; i < 3 * NCP; i += C::THREADS) {
+            const int cc = i / NCP;
+            int a, b;
+            decode_nm(i % NCP, a, b);
+            const auto v = Mexp[((size_t)(f + k) * 3 + cc) * NCP + i % NCP];
+            const R sc = powr(rt, a);
+            const R vr = sc * R(v.x), vi = sc * R(v.y);
+            Mf[cc][a][P + b] = V2{vr, vi};
+            if (b > 0) Mf[cc][a][P - b] = (b & 1) ? V2{-vr, vi} : V2{vr, -vi};
+        }
+        __syncthreads();
+        if (active) {
+            // sum from high source degree n - kk to low: kk from 0 up
             for (int kk = 0; kk <= n; ++kk) {
                 const int nm = n - kk;
-                const R sc = powr(rt, nm);
-                for (int l = -kk; l <= kk; ++l) {
-                    const int mm = m - l;
-                    if (mm < -nm || mm > nm) continue;
-                    const V2 r = cconj(getc(Rd[k], kk, l));
-                    for (int c = 0; c < 3; ++c) {
-                        const V2 v = cmul(r, getc(Mc[k][c], nm, mm));
-                        acc[c].x += sc * v.x;
-                        acc[c].y += sc * v.y;
-                    }
+                const int lo = max(-kk, m - nm), hi = min(kk, m + nm);
+                for (int l = lo; l <= hi; ++l) {
+                    const V2 r = Rf[kk][P + l];
+                    const V2 v = Mf[comp][nm][P + m - l];
+                    acc.x = fmar(r.x, v.x, fmar(-r.y, v.y, acc.x));
+                    acc.y = fmar(r.x, v.y, fmar(r.y, v.x, acc.y));
                 }
             }
         }
-        for (int c = 0; c < 3; ++c) {
-            auto &dst = Mexp[((size_t)cell * 3 + c) * NCP + t];
-            dst.x = (S)acc[c].x;
-            dst.y = (S)acc[c].y;
-        }
+    }
+    if (active) {
+        auto &dst = Mexp[((size_t)cell * 3 + comp) * NCP + CIDX(n, m)];
+        dst.x = (S)acc.x;
+        dst.y = (S)acc.y;
     }
 }
 
@@ -343,58 +364,67 @@ __global__ __launch_bounds__((M2LCfg<P, R>::THREADS)) void k_m2l(int ncells, con
 }
 
 // ---------------------------------------------------------------------------
-// L2L: one wave per child cell of one level (storage S, arithmetic R as in M2M).
-//   Lt_k^l(c) = sum_{n >= k, m} Lt_n^m(P) R_{n-k}^{m-l}(d) (s_c/s_P)^{k+1},  d = (c - P)/s_P.
+// L2L: one work-group per child cell of one level, one thread per
+// (potential, coefficient k >= l >= 0) of the child (storage S, arithmetic R
+// as in M2M); parent expansion and R(d) staged as full-order tables.
+//   Lt_k^l(c) = (s_c/s_P)^{k+1} sum_{n >= k, m} Lt_n^m(P) R_{n-k}^{m-l}(d),  d = (c - P)/s_P.
 // ---------------------------------------------------------------------------
 template <int P, class R, class S>
-__global__ __launch_bounds__(64) void k_l2l(int c0, int c1, const int *parent, const float4 *geo,
-                                            typename VT<S>::V2 *Lexp) {
+__global__ __launch_bounds__((XferCfg<P>::THREADS)) void k_l2l(int c0, int c1, const int *parent, const float4 *geo,
+                                                               typename VT<S>::V2 *Lexp) {
     using V2 = typename VT<R>::V2;
-    constexpr int NCP = NC(P);
-    __shared__ V2 Lp[3][NCP];
-    __shared__ V2 Rd[NCP];
+    using C = XferCfg<P>;
+    constexpr int NCP = C::NCP, W = C::W;
+    __shared__ V2 Lf[3][P + 1][W];
+    __shared__ V2 Rf[P + 1][W];
     const int cell = c0 + blockIdx.x;
     if (cell >= c1) return;
     const int par = parent[cell];
     const float4 gp = geo[par], gc = geo[cell];
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
     const R inv = R(1) / R(gp.w);
-    if (lane == 0) {
+    if (tid == 0) {
         V2 Rl[NCP];
         regular_harmonics<P, R, V2>((R(gc.x) - R(gp.x)) * inv, (R(gc.y) - R(gp.y)) * inv, (R(gc.z) - R(gp.z)) * inv,
                                     Rl);
-        for (int t = 0; t < NCP; ++t) Rd[t] = Rl[t];
+#pragma unroll
+        for (int q = 0; q < NCP; ++q) {
+            int a, b;
+            decode_nm(q, a, b);
+            const V2 v = Rl[q];
+            Rf[a][P + b] = v;
+            if (b > 0) Rf[a][P - b] = (b & 1) ? V2{-v.x, v.y} : V2{v.x, -v.y};
+        }
     }
-    for (int i = lane; i < 3 * NCP; i += 64) {
-        const auto v = Lexp[(size_t)par * 3 * NCP + i];
-        Lp[i / NCP][i % NCP] = V2{R(v.x), R(v.y)};
+    for (int i = tid; i < 3 * NCP; i += C::THREADS) {
+        const int cc = i / NCP;
+        int a, b;
+        decode_nm(i % NCP, a, b);
+        const auto v = Lexp[((size_t)par * 3 + cc) * NCP + i % NCP];
+        const R vr = R(v.x), vi = R(v.y);
+        Lf[cc][a][P + b] = V2{vr, vi};
+        if (b > 0) Lf[cc][a][P - b] = (b & 1) ? V2{-vr, vi} : V2{vr, -vi};
     }
     __syncthreads();
-    const R rt = R(gc.w) * inv;
-    for (int t = lane; t < NCP; t += 64) {
-        int k, l;
-        decode_nm(t, k, l);
-        const R sc = powr(rt, k + 1);
-        V2 acc[3] = {V2{R(0), R(0)}, V2{R(0), R(0)}, V2{R(0), R(0)}};
-        for (int n = P; n >= k; --n) {
-            const int dn = n - k;
-            for (int m = -n; m <= n; ++m) {
-                const int dm = m - l;
-                if (dm < -dn || dm > dn) continue;
-                const V2 r = getc(Rd, dn, dm);
-                for (int c = 0; c < 3; ++c) {
-                    const V2 v = cmul(getc(Lp[c], n, m), r);
-                    acc[c].x += v.x;
-                    acc[c].y += v.y;
-                }
-            }
-        }
-        for (int c = 0; c < 3; ++c) {
-            auto &dst = Lexp[((size_t)cell * 3 + c) * NCP + t];
-            dst.x = (S)((R)dst.x + sc * acc[c].x);
-            dst.y = (S)((R)dst.y + sc * acc[c].y);
+    if (tid >= 3 * NCP) return;
+    const int comp = tid / NCP;
+    int k, l;
+    decode_nm(tid % NCP, k, l);
+    V2 acc = V2{R(0), R(0)};
+    for (int n = P; n >= k; --n) {
+        const int dn = n - k;
+        const int lo = max(-n, l - dn), hi = min(n, l + dn);
+        for (int m = lo; m <= hi; ++m) {
+            const V2 L = Lf[comp][n][P + m];
+            const V2 r = Rf[dn][P + m - l];
+            acc.x = fmar(L.x, r.x, fmar(-L.y, r.y, acc.x));
+            acc.y = fmar(L.x, r.y, fmar(L.y, r.x, acc.y));
         }
     }
+    const R sc = powr(R(gc.w) * inv, k + 1);
+    auto &dst = Lexp[((size_t)cell * 3 + comp) * NCP + tid % NCP];
+    dst.x = (S)((R)dst.x + sc * acc.x);
+    dst.y = (S)((R)dst.y + sc * acc.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -578,7 +608,7 @@ static void far_field_t(Ctx &c) {
     VFMM_LAUNCH_CHECK();
     for (int l = c.depth - 1; l >= 0; --l) {
         const int c0 = c.lvl_off[l], c1 = c.lvl_off[l + 1];
-        k_m2m<P, RA, S><<<c1 - c0, 64, 0, s>>>(c0, c1, c.c_child.as<int>(), c.c_nchild.as<int>(),
+        k_m2m<P, RA, S><<<c1 - c0, XferCfg<P>::THREADS, 0, s>>>(c0, c1, c.c_child.as<int>(), c.c_nchild.as<int>(),
                                                 c.c_geo.as<float4>(), c.Mexp.as<V2>());
         VFMM_LAUNCH_CHECK();
     }
@@ -603,7 +633,7 @@ static void far_field_t(Ctx &c) {
     c.record(2 * PH_L2L_L2P);
     for (int l = 1; l <= c.depth; ++l) {
         const int c0 = c.lvl_off[l], c1 = c.lvl_off[l + 1];
-        k_l2l<P, RA, S><<<c1 - c0, 64, 0, s>>>(c0, c1, c.c_parent.as<int>(), c.c_geo.as<float4>(),
+        k_l2l<P, RA, S><<<c1 - c0, XferCfg<P>::THREADS, 0, s>>>(c0, c1, c.c_parent.as<int>(), c.c_geo.as<float4>(),
                                                 c.Lexp.as<V2>());
         VFMM_LAUNCH_CHECK();
     }

@@ -27,15 +27,19 @@ namespace vfmm {
 
 static constexpr int TPB = 256;
 static constexpr int ITEM_GROUPS = 24;
+static constexpr int TABLE_KEY_BITS = 24;  // offset keys up to this width are numbered through a direct table
+static constexpr size_t MAX_TABLE_BYTES = size_t(8) << 30;  // operator table cap (else the per-pair kernel)
 
 void sort_pairs_u64(Ctx &c, DevBuf &kA, DevBuf &vA, DevBuf &kB, DevBuf &vB, int64_t n, int nbits);
 
 __host__ __device__ constexpr int NR(int P) { return (P + 1) * (P + 1); }      // real rows
-__host__ __device__ constexpr int NRP(int P) { return (NR(P) + 3) / 4 * 4; }   // padded to float4
+__host__ __device__ constexpr int NRP(int P) { return (NR(P) + 15) / 16 * 16; } // inputs padded to 16
 __host__ __device__ constexpr int NRT(int P) { return (NR(P) + 15) / 16 * 16; } // rows padded to 16
-__host__ __device__ constexpr int TSTR(int P) {                                   // LDS row stride = 4 mod 64
-    return NRP(P) + ((4 - NRP(P) % 64) + 64) % 64;
-}
+
+// Within each chunk of 16 input rows the (e, kq) digits of a row r = 16 c + 4 e + kq
+// are swapped, so that the four rows one MFMA lane needs for k steps 4c..4c+3
+// are contiguous: position 16 c + 4 kq + e.  The map is its own inverse.
+__host__ __device__ constexpr int kperm(int r) { return (r & ~15) | ((r & 3) << 2) | ((r >> 2) & 3); }
 
 // real index r = k^2 + j:  j = 0 -> (l = 0, Re); j odd -> (l = (j+1)/2, Re); j even > 0 -> (l = j/2, Im)
 __host__ __device__ inline void decode_row(int r, int &k, int &l, int &im) {
@@ -67,12 +71,12 @@ __device__ inline int block_of(const LvlInfo &L, int cell, int lvl) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(TPB) void k_m2lb_offsets(int64_t n, const int *tgt, const int2 *src, const float4 *geo,
                                                       const int *level, int B, float len, int4 *eq, int *range) {
-    const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    __shared__ int red[2][TPB / 64];
     int aq = 0, adl = 0;
-    if (e < n) {
+    const int W = 2 * B + 1;
+    for (int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x; e < n; e += (int64_t)gridDim.x * TPB) {
         const int t = tgt[e];
         const int2 s = src[e];
-        const int W = 2 * B + 1;
         const float shx = (float)(s.y % W - B) * len;
         const float shy = (float)((s.y / W) % W - B) * len;
         const float shz = (float)(s.y / (W * W) - B) * len;
@@ -83,28 +87,56 @@ __global__ __launch_bounds__(TPB) void k_m2lb_offsets(int64_t n, const int *tgt,
         const int qy = (int)rintf((gb.y + shy - ga.y) / unit);
         const int qz = (int)rintf((gb.z + shz - ga.z) / unit);
         eq[e] = make_int4(qx, qy, qz, dl);
-        aq = max(abs(qx), max(abs(qy), abs(qz)));
-        adl = abs(dl);
+        aq = max(aq, max(abs(qx), max(abs(qy), abs(qz))));
+        adl = max(adl, abs(dl));
     }
-    // wave max then one atomic per wave
+    // block max, then one atomic per block (the grid is capped, so few atomics)
     for (int o = 32; o > 0; o >>= 1) {
         aq = max(aq, __shfl_xor(aq, o, 64));
         adl = max(adl, __shfl_xor(adl, o, 64));
     }
     if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = aq;
+        red[1][threadIdx.x >> 6] = adl;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < TPB / 64; ++w) {
+            aq = max(aq, red[0][w]);
+            adl = max(adl, red[1][w]);
+        }
         atomicMax(&range[0], aq);
         atomicMax(&range[1], adl);
     }
 }
 
+__device__ inline uint64_t pack_key(int4 q, const KeyFmt &f) {
+    return ((uint64_t)(q.w + f.odl) << (3 * f.bq)) | ((uint64_t)(q.x + f.oq) << (2 * f.bq)) |
+           ((uint64_t)(q.y + f.oq) << f.bq) | (uint64_t)(q.z + f.oq);
+}
+
 __global__ __launch_bounds__(TPB) void k_m2lb_pack(int64_t n, const int4 *eq, KeyFmt f, uint64_t *key, uint32_t *val) {
     const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (e >= n) return;
-    const int4 q = eq[e];
-    const uint64_t k = ((uint64_t)(q.w + f.odl) << (3 * f.bq)) | ((uint64_t)(q.x + f.oq) << (2 * f.bq)) |
-                       ((uint64_t)(q.y + f.oq) << f.bq) | (uint64_t)(q.z + f.oq);
-    key[e] = k;
+    key[e] = pack_key(eq[e], f);
     val[e] = (uint32_t)e;
+}
+
+// compact key spaces: mark the keys in use in a direct table (every writer
+// stores the same value), number them by a scan, look the numbers up
+__global__ __launch_bounds__(TPB) void k_key_mark(int64_t n, const int4 *eq, KeyFmt f, int *tab) {
+    const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (e < n) tab[pack_key(eq[e], f)] = 1;
+}
+
+__global__ __launch_bounds__(TPB) void k_key_lookup(int64_t n, const int4 *eq, KeyFmt f, const int *pos, int *kid,
+                                                    uint64_t *ukey) {
+    const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (e >= n) return;
+    const uint64_t k = pack_key(eq[e], f);
+    const int id = pos[k];
+    kid[e] = id;
+    ukey[id] = k;
 }
 
 __global__ __launch_bounds__(TPB) void k_flag_changes(int64_t n, const uint64_t *key, int *flag) {
@@ -181,7 +213,7 @@ __global__ __launch_bounds__(TPB) void k_items(int ng, const int4 *groups, const
 }
 
 // ---------------------------------------------------------------------------
-// Mt in real row order, padded: Mr[cell][comp][NRP] (extra zero row at the end)
+// Mt in real row order, padded, k-permuted: Mr[cell][comp][NRP] (extra zero cell at the end)
 // ---------------------------------------------------------------------------
 template <int P>
 __global__ __launch_bounds__(TPB) void k_m2lb_mreal(int ncells, const float2 *Mexp, float *Mr) {
@@ -189,8 +221,8 @@ __global__ __launch_bounds__(TPB) void k_m2lb_mreal(int ncells, const float2 *Me
     const int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
     const int64_t total = (int64_t)(ncells + 1) * 3 * RP;
     if (idx >= total) return;
-    const int r = (int)(idx % RP);
-    const int64_t cc = idx / RP;  // cell*3 + comp
+    const int r = kperm((int)(idx % RP));  // row held at this position
+    const int64_t cc = idx / RP;           // cell*3 + comp
     float v = 0.f;
     if (r < R && cc < (int64_t)ncells * 3) {
         int n, m, im;
@@ -208,177 +240,266 @@ typedef float vf4 __attribute__((ext_vector_type(4)));
 
 template <int P>
 struct MbCfg {
-    static constexpr int R = NR(P), RP = NRP(P), RT = NRT(P), TS = TSTR(P);
+    static constexpr int R = NR(P), RP = NRP(P), RT = NRT(P);
     static constexpr int Q = 2 * P, IW = 4 * P + 1;
-    static constexpr int RTI = RT / 16;   // row tiles
-    static constexpr int KS = RP / 4;     // k steps
+    static constexpr int RTI = RT / 16;            // row tiles
+    static constexpr int KC = RP / 16;             // chunks of four k steps
+    static constexpr int RW = (RTI + 3) / 4;       // row tiles per wave (4 waves)
+    static constexpr int BS = RP + 4;              // LDS column stride of the staged multipoles
+    static constexpr size_t OP = (size_t)RT * RP;  // floats per operator
 };
 
+// One operator per key, built once per tree.  T[r][c] (r output row
+// (k, l, Re/Im), c input row (n, m, Re/Im)):
+//   Lt_k^l = (-1)^{k+l} 2^{dl (k+1)} sum_{n,m} Mt_n^m I_{n+k}^{m-l}(-q 2^{min(dl,0)-2}).
+// Stored in MFMA A-fragment order [key][row tile a][chunk][lane][e] =
+// T[16 a + lane % 16][16 chunk + 4 e + lane / 16], zero outside R x R, so a
+// lane reads the operands of four k steps as one float4.
 template <int P>
-__global__ __launch_bounds__(192) void k_m2lb(const int4 *__restrict__ items, const int4 *__restrict__ groups,
-                                              const int2 *__restrict__ ent, const float *__restrict__ Mr,
-                                              const uint64_t *__restrict__ ukey, KeyFmt f, int zero_cell,
-                                              float *__restrict__ partial) {
+__global__ __launch_bounds__(256) void k_m2lb_optab(int nkeys, const uint64_t *__restrict__ ukey, KeyFmt f,
+                                                    float *__restrict__ tab) {
     using C = MbCfg<P>;
-    extern __shared__ float smem[];
-    float *Ts = smem;                                               // [RT][TS]
-    float2 *Is = reinterpret_cast<float2 *>(smem + C::RT * C::TS);  // [(Q+1)][IW], full orders
-    int *src_of = reinterpret_cast<int *>(Is + (C::Q + 1) * C::IW);  // [64]
-    int *rinfo = src_of + 64;                                       // [RP]: k | l << 8 | im << 16
+    __shared__ float2 Is[(C::Q + 1) * C::IW];  // full orders M in [-Q, Q]
+    __shared__ int rinfo[C::RP];
+    const int key = blockIdx.x;
+    if (key >= nkeys) return;
     const int tid = threadIdx.x;
-    const int comp = tid >> 6;
-    const int lane = tid & 63;
-    const int i16 = lane & 15, kq = lane >> 4;
-    for (int r = tid; r < C::RP; r += 192) {
+    for (int r = tid; r < C::RP; r += 256) {
         int k = 0, l = 0, im = 0;
         if (r < C::R) decode_row(r, k, l, im);
-        rinfo[r] = k | (l << 8) | (im << 16) | ((r < C::R) ? 0 : (1 << 24));
+        rinfo[r] = k | (l << 8) | (im << 16);
     }
-    for (int i = tid; i < (C::Q + 1) * C::IW; i += 192) Is[i] = make_float2(0.f, 0.f);
-    const int4 it = items[blockIdx.x];
+    for (int i = tid; i < (C::Q + 1) * C::IW; i += 256) Is[i] = make_float2(0.f, 0.f);
+    const uint64_t kv = ukey[key];
+    const uint64_t mq = (1ull << f.bq) - 1;
+    const int dl = (int)(kv >> (3 * f.bq)) - f.odl;
+    __syncthreads();
+    if (tid <= C::Q) {
+        // irregular harmonics I_N^M((c_A - c_B)/s_B), (c_A - c_B)/s_B = -q 2^(min(dl,0) - 2)
+        const int M = tid;
+        const float sc = -ldexpf(1.0f, min(dl, 0) - 2);
+        const float dx = (float)((int)((kv >> (2 * f.bq)) & mq) - f.oq) * sc;
+        const float dy = (float)((int)((kv >> f.bq) & mq) - f.oq) * sc;
+        const float dz = (float)((int)(kv & mq) - f.oq) * sc;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float ir2 = 1.0f / r2;
+        float cr = rsqrtf(r2), ci = 0.f;
+        for (int mm = 1; mm <= M; ++mm) {
+            const float fc = -(float)(2 * mm - 1) * ir2;
+            const float nr = fc * (dx * cr - dy * ci);
+            const float ni = fc * (dx * ci + dy * cr);
+            cr = nr;
+            ci = ni;
+        }
+        auto put = [&](int N, float vr, float vi) {
+            Is[N * C::IW + C::Q + M] = make_float2(vr, vi);
+            if (M > 0) Is[N * C::IW + C::Q - M] = (M & 1) ? make_float2(-vr, vi) : make_float2(vr, -vi);
+        };
+        put(M, cr, ci);
+        float pr = cr, pi = ci, qr = 0.f, qi = 0.f;
+        if (M + 1 <= C::Q) {
+            const float a0 = (float)(2 * M + 1) * dz * ir2;
+            qr = a0 * cr;
+            qi = a0 * ci;
+            put(M + 1, qr, qi);
+        }
+        for (int N = M + 2; N <= C::Q; ++N) {
+            const float a = (float)(2 * N - 1) * dz;
+            const float b = (float)((N - 1) * (N - 1) - M * M);
+            const float vr = (a * qr - b * pr) * ir2;
+            const float vi = (a * qi - b * pi) * ir2;
+            put(N, vr, vi);
+            pr = qr; pi = qi; qr = vr; qi = vi;
+        }
+    }
+    __syncthreads();
+    float *T = tab + (size_t)key * C::OP;
+    for (int idx = tid; idx < (int)C::OP; idx += 256) {
+        const int e = idx & 3, lane = (idx >> 2) & 63;
+        const int chunk = (idx >> 8) % C::KC, a = (idx >> 8) / C::KC;
+        const int r = 16 * a + (lane & 15), c = 16 * chunk + 4 * e + (lane >> 4);
+        float v = 0.f;
+        if (r < C::R && c < C::R) {
+            const int ri = rinfo[r], ci = rinfo[c];
+            const int k = ri & 255, l = (ri >> 8) & 255, im = (ri >> 16) & 1;
+            const int n = ci & 255, m = (ci >> 8) & 255, imc = (ci >> 16) & 1;
+            const float2 x = Is[(n + k) * C::IW + C::Q + m - l];
+            const float2 y = Is[(n + k) * C::IW + C::Q + m + l];
+            const float sg = (l & 1) ? -1.f : 1.f;
+            if (m == 0) v = im ? x.y : x.x;
+            else if (!im) v = imc ? (-x.y - sg * y.y) : (x.x + sg * y.x);
+            else v = imc ? (x.x - sg * y.x) : (x.y - sg * y.y);
+            v *= (((k + l) & 1) ? -1.f : 1.f) * ldexpf(1.0f, dl * (k + 1));
+        }
+        T[idx] = v;
+    }
+}
+
+// A work-group of four waves takes one work item: up to ITEM_GROUPS keys of
+// one block of 64 target cells.  Wave w owns row tiles w, w + 4, ... of the
+// output for the three potentials; per key it loads its operator rows into
+// registers, and the group stages the 64 target slots' source multipoles
+// (absent slots read the zero cell) in LDS one potential at a time, double
+// buffered, while the previous potential's products
+// [16 rows x 4 inputs] x [4 inputs x 16 targets] run on v_mfma_f32_16x16x4f32.
+template <int P>
+__global__ __launch_bounds__(256) void k_m2lb(const int4 *__restrict__ items, const int4 *__restrict__ groups,
+                                              const int2 *__restrict__ ent, const float *__restrict__ Mr,
+                                              const float *__restrict__ tab, int zero_cell, int nitems,
+                                              float *__restrict__ partial) {
+    using C = MbCfg<P>;
+    const int item = xcd_logical(blockIdx.x, gridDim.x);
+    if (item >= nitems) return;
+    static_assert(64 * C::RP / 4 == 256 * C::KC, "one float4 per thread and chunk");
+    extern __shared__ float smem[];
+    float *Bs = smem;                                                // [2][64][BS]
+    int *src_of = reinterpret_cast<int *>(smem + 2 * 64 * C::BS);    // [64]
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int i16 = lane & 15, kq = lane >> 4;
+    const int4 it = items[item];
     const int g0 = __builtin_amdgcn_readfirstlane(it.y);
     const int g1 = __builtin_amdgcn_readfirstlane(it.z);
-    vf4 acc[C::RTI][4];
+    vf4 acc[3][C::RW][4];
 #pragma unroll
-    for (int a = 0; a < C::RTI; ++a)
+    for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = vf4{0.f, 0.f, 0.f, 0.f};
-    const uint64_t mq = (1ull << f.bq) - 1;
+        for (int j = 0; j < C::RW; ++j)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[c][j][b] = vf4{0.f, 0.f, 0.f, 0.f};
     for (int g = g0; g < g1; ++g) {
         const int4 gr = groups[g];
         const int key = __builtin_amdgcn_readfirstlane(gr.x);
         const int e0 = __builtin_amdgcn_readfirstlane(gr.y);
         const int ne = __builtin_amdgcn_readfirstlane(gr.z);
-        const uint64_t kv = ukey[key];
-        const int dl = (int)(kv >> (3 * f.bq)) - f.odl;
-        __syncthreads();
+        __syncthreads();  // the previous key's tiles and slots are no longer read
         if (tid < 64) src_of[tid] = zero_cell;
-        // irregular harmonics I_N^M((c_A - c_B)/s_B), (c_A - c_B)/s_B = -q 2^(min(dl,0) - 2)
-        if (tid >= 64 && tid <= 64 + C::Q) {
-            const int M = tid - 64;
-            const float sc = -ldexpf(1.0f, min(dl, 0) - 2);
-            const float dx = (float)((int)((kv >> (2 * f.bq)) & mq) - f.oq) * sc;
-            const float dy = (float)((int)((kv >> f.bq) & mq) - f.oq) * sc;
-            const float dz = (float)((int)(kv & mq) - f.oq) * sc;
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            const float ir2 = 1.0f / r2;
-            float cr = rsqrtf(r2), ci = 0.f;
-            for (int mm = 1; mm <= M; ++mm) {
-                const float fc = -(float)(2 * mm - 1) * ir2;
-                const float nr = fc * (dx * cr - dy * ci);
-                const float ni = fc * (dx * ci + dy * cr);
-                cr = nr;
-                ci = ni;
-            }
-            auto put = [&](int N, float vr, float vi) {
-                Is[N * C::IW + C::Q + M] = make_float2(vr, vi);
-                if (M > 0) Is[N * C::IW + C::Q - M] = (M & 1) ? make_float2(-vr, vi) : make_float2(vr, -vi);
-            };
-            put(M, cr, ci);
-            float pr = cr, pi = ci, qr = 0.f, qi = 0.f;
-            if (M + 1 <= C::Q) {
-                const float a0 = (float)(2 * M + 1) * dz * ir2;
-                qr = a0 * cr;
-                qi = a0 * ci;
-                put(M + 1, qr, qi);
-            }
-            for (int N = M + 2; N <= C::Q; ++N) {
-                const float a = (float)(2 * N - 1) * dz;
-                const float b = (float)((N - 1) * (N - 1) - M * M);
-                const float vr = (a * qr - b * pr) * ir2;
-                const float vi = (a * qi - b * pi) * ir2;
-                put(N, vr, vi);
-                pr = qr; pi = qi; qr = vr; qi = vi;
-            }
-        }
         __syncthreads();
         if (tid < ne) {
             const int2 en = ent[e0 + tid];
             src_of[en.y] = en.x;
         }
-        // the key's matrix: Ts[r][c], r = output row, c = input row
-        for (int idx = tid; idx < C::RT * C::RP; idx += 192) {
-            const int r = idx / C::RP, c = idx % C::RP;
-            float v = 0.f;
-            if (r < C::R && c < C::R) {
-                const int ri = rinfo[r], ci = rinfo[c];
-                const int k = ri & 255, l = (ri >> 8) & 255, im = (ri >> 16) & 1;
-                const int n = ci & 255, m = (ci >> 8) & 255, imc = (ci >> 16) & 1;
-                const float2 a = Is[(n + k) * C::IW + C::Q + m - l];
-                const float2 b = Is[(n + k) * C::IW + C::Q + m + l];
-                const float sg = (l & 1) ? -1.f : 1.f;
-                if (m == 0) v = im ? a.y : a.x;
-                else if (!im) v = imc ? (-a.y - sg * b.y) : (a.x + sg * b.x);
-                else v = imc ? (a.x - sg * b.x) : (a.y - sg * b.y);
-                v *= (((k + l) & 1) ? -1.f : 1.f) * ldexpf(1.0f, dl * (k + 1));
-            }
-            Ts[r * C::TS + c] = v;
+        // operator rows of this wave: A[j][chunk] holds k steps 4 chunk .. 4 chunk + 3
+        vf4 A[C::RW][C::KC];
+        const vf4 *T4 = reinterpret_cast<const vf4 *>(tab + (size_t)key * C::OP);
+#pragma unroll
+        for (int j = 0; j < C::RW; ++j) {
+            const int a = wave + 4 * j;
+#pragma unroll
+            for (int ch = 0; ch < C::KC; ++ch)
+                A[j][ch] = (a < C::RTI) ? T4[((size_t)a * C::KC + ch) * 64 + lane] : vf4{0.f, 0.f, 0.f, 0.f};
         }
         __syncthreads();
-        // B columns of this lane: targets 16 b + i16, input rows 4 ks + kq
-        const float *mrow[4];
+        // column and offset of this thread's float4 number i of a staged tile
+        int scol[C::KC];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) mrow[b] = Mr + ((size_t)src_of[16 * b + i16] * 3 + comp) * C::RP + kq;
-        float bn[4];
+        for (int i = 0; i < C::KC; ++i) scol[i] = src_of[(tid + 256 * i) / (C::RP / 4)];
+        auto src4 = [&](int i, int c) {
+            return reinterpret_cast<const vf4 *>(Mr + ((size_t)scol[i] * 3 + c) * C::RP +
+                                                 4 * ((tid + 256 * i) % (C::RP / 4)));
+        };
+        auto dst4 = [&](float *B, int i) {
+            const int q = tid + 256 * i;
+            return reinterpret_cast<vf4 *>(&B[(q / (C::RP / 4)) * C::BS + 4 * (q % (C::RP / 4))]);
+        };
+        {
+            vf4 pre[C::KC];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) bn[b] = mrow[b][0];
-        for (int ks = 0; ks < C::KS; ++ks) {
-            float bv[4];
+            for (int i = 0; i < C::KC; ++i) pre[i] = *src4(i, 0);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) bv[b] = bn[b];
-            if (ks + 1 < C::KS) {
+            for (int i = 0; i < C::KC; ++i) *dst4(Bs, i) = pre[i];
+        }
+        __syncthreads();
 #pragma unroll
-                for (int b = 0; b < 4; ++b) bn[b] = mrow[b][4 * (ks + 1)];
+        for (int c = 0; c < 3; ++c) {
+            const float *Bc = Bs + (c & 1) * 64 * C::BS;
+            float *Bn = Bs + ((c + 1) & 1) * 64 * C::BS;
+            // the next potential's tile streams in one float4 per chunk, stored a chunk later
+            vf4 inflight = vf4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ch = 0; ch < C::KC; ++ch) {
+                if (c < 2) {
+                    if (ch > 0) *dst4(Bn, ch - 1) = inflight;
+                    inflight = *src4(ch, c + 1);
+                }
+                vf4 Bv[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    Bv[b] = *reinterpret_cast<const vf4 *>(&Bc[(16 * b + i16) * C::BS + 16 * ch + 4 * kq]);
+#pragma unroll
+                for (int j = 0; j < C::RW; ++j) {
+                    if (wave + 4 * j >= C::RTI) continue;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+#pragma unroll
+                        for (int b = 0; b < 4; ++b)
+                            acc[c][j][b] =
+                                __builtin_amdgcn_mfma_f32_16x16x4f32(A[j][ch][e], Bv[b][e], acc[c][j][b], 0, 0, 0);
+                }
             }
-            float av[C::RTI];
-#pragma unroll
-            for (int a = 0; a < C::RTI; ++a) av[a] = Ts[(16 * a + i16) * C::TS + 4 * ks + kq];
-#pragma unroll
-            for (int a = 0; a < C::RTI; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+            if (c < 2) {
+                *dst4(Bn, C::KC - 1) = inflight;
+                __syncthreads();
+            }
         }
     }
     // D fragment: lane holds rows 16 a + 4 kq + v of target column 16 b + i16
-    float *out = partial + ((size_t)blockIdx.x * 3 + comp) * C::R * 64;
 #pragma unroll
-    for (int a = 0; a < C::RTI; ++a)
+    for (int c = 0; c < 3; ++c) {
+        float *out = partial + ((size_t)item * 3 + c) * C::R * 64;
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+        for (int j = 0; j < C::RW; ++j) {
+            const int a = wave + 4 * j;
+            if (a >= C::RTI) continue;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = 16 * a + 4 * kq + v;
-                if (row < C::R) out[(size_t)row * 64 + 16 * b + i16] = acc[a][b][v];
-            }
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * a + 4 * kq + v;
+                    if (row < C::R) out[(size_t)row * 64 + 16 * b + i16] = acc[c][j][b][v];
+                }
+        }
+    }
 }
 
 template <int P>
 static size_t m2lb_lds_bytes() {
     using C = MbCfg<P>;
-    return sizeof(float) * C::RT * C::TS + sizeof(float2) * (C::Q + 1) * C::IW + sizeof(int) * (64 + C::RP);
+    return sizeof(float) * 2 * 64 * C::BS + sizeof(int) * 64;
 }
 
-// per block: sum the items' partials in item order and add to Lt
+// per block: sum the items' partials in item order and add to Lt.  One thread
+// per (potential, row, target slot) of a block; blockIdx.y strides over blocks.
 template <int P, class A>
 __global__ __launch_bounds__(TPB) void k_m2lb_reduce(int nblk, const int *blk_item0, const int *blk_nitem,
                                                      const int2 *blk_cells, const float *partial, float2 *Lexp) {
     // A: accumulator type (double in the mixed precision form)
     constexpr int R = NR(P), NCP = NC(P);
-    const int b = blockIdx.x;
-    if (b >= nblk) return;
-    const int ni = blk_nitem[b];
-    if (ni == 0) return;
-    const int i0 = blk_item0[b];
-    const int2 bc = blk_cells[b];
-    for (int idx = threadIdx.x; idx < 3 * R * 64; idx += TPB) {
-        const int lane = idx & 63;
-        const int cr = idx >> 6;  // comp * R + r
-        if (lane >= bc.y) continue;
-        const int comp = cr / R, r = cr % R;
+    const int idx = blockIdx.x * TPB + threadIdx.x;
+    if (idx >= 3 * R * 64) return;
+    const int lane = idx & 63;
+    const int cr = idx >> 6;  // comp * R + r
+    const int comp = cr / R, r = cr % R;
+    int k, l, im;
+    decode_row(r, k, l, im);
+    const size_t stride = (size_t)3 * R * 64;
+    for (int b = blockIdx.y; b < nblk; b += gridDim.y) {
+        const int ni = blk_nitem[b];
+        const int2 bc = blk_cells[b];
+        if (ni == 0 || lane >= bc.y) continue;
+        const float *p = partial + ((size_t)blk_item0[b] * 3 * R + cr) * 64 + lane;
         A s = A(0);
-        for (int i = 0; i < ni; ++i) s += (A)partial[((size_t)(i0 + i) * 3 * R + cr) * 64 + lane];
-        int k, l, im;
-        decode_row(r, k, l, im);
+        int i = 0;
+        for (; i + 4 <= ni; i += 4) {
+            const float v0 = p[(size_t)i * stride], v1 = p[(size_t)(i + 1) * stride];
+            const float v2 = p[(size_t)(i + 2) * stride], v3 = p[(size_t)(i + 3) * stride];
+            s += (A)v0;
+            s += (A)v1;
+            s += (A)v2;
+            s += (A)v3;
+        }
+        for (; i < ni; ++i) s += (A)p[(size_t)i * stride];
         float *dst = reinterpret_cast<float *>(&Lexp[((size_t)(bc.x + lane) * 3 + comp) * NCP + CIDX(k, l)]) + im;
         *dst = (float)((A)*dst + s);
     }
@@ -403,7 +524,7 @@ static void m2lb_plan_p(Ctx &c) {
     c.mb_eq.ensure(sizeof(int4) * n);
     c.pairs64.ensure(64);
     VFMM_HIP(hipMemsetAsync(c.pairs64.ptr, 0, 8, s));
-    k_m2lb_offsets<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.m2l_tgt.as<int>(), c.m2l_src.as<int2>(), c.c_geo.as<float4>(),
+    k_m2lb_offsets<<<std::min<unsigned>(cdiv(n, TPB), 1024), TPB, 0, s>>>(n, c.m2l_tgt.as<int>(), c.m2l_src.as<int2>(), c.c_geo.as<float4>(),
                                                  c.c_level.as<int>(), c.img_B,
                                                  c.prm.periodic ? (float)c.prm.box_len : 0.f, c.mb_eq.as<int4>(),
                                                  c.pairs64.as<int>());
@@ -418,28 +539,53 @@ static void m2lb_plan_p(Ctx &c) {
     f.odl = (1 << (f.bdl - 1));
     const int kb = 3 * f.bq + f.bdl;
     if (kb > 62) return;  // offsets too spread for packed keys: generic kernel
-    // ---- unique keys ----
+    // ---- unique keys, numbered in increasing key order ----
+    int nkeys = 0;
+    int h2[2];
+    if (kb <= TABLE_KEY_BITS) {
+        const int64_t tsz = (int64_t)1 << kb;
+        c.mb_flag.ensure(sizeof(int) * (std::max<int64_t>(n, tsz) + 1));
+        c.mb_pos.ensure(sizeof(int) * (std::max<int64_t>(n, tsz) + 1));
+        int *tab = c.mb_flag.as<int>(), *tpos = c.mb_pos.as<int>();
+        VFMM_HIP(hipMemsetAsync(tab, 0, sizeof(int) * tsz, s));
+        k_key_mark<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.mb_eq.as<int4>(), f, tab);
+        VFMM_LAUNCH_CHECK();
+        scan_excl_i32(c, tab, tpos, tsz);
+        VFMM_HIP(hipMemcpyAsync(&h2[0], tpos + tsz - 1, 4, hipMemcpyDeviceToHost, s));
+        VFMM_HIP(hipMemcpyAsync(&h2[1], tab + tsz - 1, 4, hipMemcpyDeviceToHost, s));
+        VFMM_HIP(hipStreamSynchronize(s));
+        nkeys = h2[0] + h2[1];
+        c.mb_kid.ensure(sizeof(int) * n);
+        c.mb_ukey.ensure(sizeof(uint64_t) * nkeys);
+        k_key_lookup<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.mb_eq.as<int4>(), f, tpos, c.mb_kid.as<int>(),
+                                                   c.mb_ukey.as<uint64_t>());
+        VFMM_LAUNCH_CHECK();
+    } else {
+        c.lkey.ensure(sizeof(uint64_t) * n);
+        c.lval.ensure(sizeof(uint32_t) * n);
+        k_m2lb_pack<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.mb_eq.as<int4>(), f, c.lkey.as<uint64_t>(),
+                                                  c.lval.as<uint32_t>());
+        VFMM_LAUNCH_CHECK();
+        sort_pairs_u64(c, c.lkey, c.lval, c.lkey2, c.lval2, n, kb);
+        c.mb_flag.ensure(sizeof(int) * (n + 1));
+        c.mb_pos.ensure(sizeof(int) * (n + 1));
+        int *flag = c.mb_flag.as<int>(), *pos = c.mb_pos.as<int>();
+        k_flag_changes<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.lkey.as<uint64_t>(), flag);
+        VFMM_LAUNCH_CHECK();
+        scan_excl_i32(c, flag, pos, n);
+        VFMM_HIP(hipMemcpyAsync(&h2[0], pos + n - 1, 4, hipMemcpyDeviceToHost, s));
+        VFMM_HIP(hipMemcpyAsync(&h2[1], flag + n - 1, 4, hipMemcpyDeviceToHost, s));
+        VFMM_HIP(hipStreamSynchronize(s));
+        nkeys = h2[0] + h2[1];
+        c.mb_kid.ensure(sizeof(int) * n);
+        c.mb_ukey.ensure(sizeof(uint64_t) * nkeys);
+        k_key_ids<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.lkey.as<uint64_t>(), c.lval.as<uint32_t>(), flag, pos,
+                                                c.mb_kid.as<int>(), c.mb_ukey.as<uint64_t>());
+        VFMM_LAUNCH_CHECK();
+    }
     c.lkey.ensure(sizeof(uint64_t) * n);
     c.lval.ensure(sizeof(uint32_t) * n);
-    k_m2lb_pack<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.mb_eq.as<int4>(), f, c.lkey.as<uint64_t>(), c.lval.as<uint32_t>());
-    VFMM_LAUNCH_CHECK();
-    sort_pairs_u64(c, c.lkey, c.lval, c.lkey2, c.lval2, n, kb);
-    c.mb_flag.ensure(sizeof(int) * (n + 1));
-    c.mb_pos.ensure(sizeof(int) * (n + 1));
     int *flag = c.mb_flag.as<int>(), *pos = c.mb_pos.as<int>();
-    k_flag_changes<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.lkey.as<uint64_t>(), flag);
-    VFMM_LAUNCH_CHECK();
-    scan_excl_i32(c, flag, pos, n);
-    int h2[2];
-    VFMM_HIP(hipMemcpyAsync(&h2[0], pos + n - 1, 4, hipMemcpyDeviceToHost, s));
-    VFMM_HIP(hipMemcpyAsync(&h2[1], flag + n - 1, 4, hipMemcpyDeviceToHost, s));
-    VFMM_HIP(hipStreamSynchronize(s));
-    const int nkeys = h2[0] + h2[1];
-    c.mb_kid.ensure(sizeof(int) * n);
-    c.mb_ukey.ensure(sizeof(uint64_t) * nkeys);
-    k_key_ids<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.lkey.as<uint64_t>(), c.lval.as<uint32_t>(), flag, pos,
-                                            c.mb_kid.as<int>(), c.mb_ukey.as<uint64_t>());
-    VFMM_LAUNCH_CHECK();
     // ---- blocks of 64 target cells per level ----
     LvlInfo L{};
     L.nlev = c.depth + 1;
@@ -490,6 +636,13 @@ static void m2lb_plan_p(Ctx &c) {
     k_items<<<cdiv(ng, TPB), TPB, 0, s>>>(ng, c.mb_groups.as<int4>(), flag, pos, c.mb_items.as<int4>(), blk_item0,
                                            blk_nitem);
     VFMM_LAUNCH_CHECK();
+    // ---- one operator per key ----
+    using C = MbCfg<P>;
+    const size_t tab_bytes = sizeof(float) * C::OP * (size_t)nkeys;
+    if (tab_bytes > MAX_TABLE_BYTES) return;  // too many distinct offsets: generic kernel
+    c.mb_tab.ensure(tab_bytes);
+    k_m2lb_optab<P><<<nkeys, 256, 0, s>>>(nkeys, c.mb_ukey.as<uint64_t>(), f, c.mb_tab.as<float>());
+    VFMM_LAUNCH_CHECK();
     c.mb_nkeys = nkeys;
     c.mb_fmt[0] = f.bq;
     c.mb_fmt[1] = f.bdl;
@@ -539,25 +692,26 @@ static void m2lb_run_p(Ctx &c) {
     k_m2lb_mreal<P><<<cdiv(mr_total, TPB), TPB, 0, s>>>(c.ncells, c.Mexp.as<float2>(), c.mb_mr.as<float>());
     VFMM_LAUNCH_CHECK();
     c.mb_partial.ensure(sizeof(float) * (size_t)c.mb_nitems * 3 * R * 64);
-    KeyFmt f{c.mb_fmt[0], c.mb_fmt[1], c.mb_fmt[2], c.mb_fmt[3]};
     const size_t lds = m2lb_lds_bytes<P>();
     static bool attr_set = false;
     if (!attr_set) {
         VFMM_HIP(hipFuncSetAttribute((const void *)k_m2lb<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr_set = true;
     }
-    k_m2lb<P><<<c.mb_nitems, 192, lds, s>>>(c.mb_items.as<int4>(), c.mb_groups.as<int4>(), c.mb_ent.as<int2>(),
-                                             c.mb_mr.as<float>(), c.mb_ukey.as<uint64_t>(), f, c.ncells,
-                                             c.mb_partial.as<float>());
+    k_m2lb<P><<<xcd_grid(c.mb_nitems), 256, lds, s>>>(c.mb_items.as<int4>(), c.mb_groups.as<int4>(),
+                                                       c.mb_ent.as<int2>(), c.mb_mr.as<float>(),
+                                                       c.mb_tab.as<float>(), c.ncells, c.mb_nitems,
+                                                       c.mb_partial.as<float>());
     VFMM_LAUNCH_CHECK();
     const int nblk = c.mb_nblk;
     int *blk_item0 = c.mb_blk.as<int>() + nblk, *blk_nitem = blk_item0 + nblk;
+    const dim3 rgrid(cdiv(3 * R * 64, TPB), std::min(nblk, 65535));
     if (c.prm.precision == VFMM_PRECISION_MIXED)
-        k_m2lb_reduce<P, double><<<nblk, TPB, 0, s>>>(nblk, blk_item0, blk_nitem, c.mb_bcells.as<int2>(),
-                                                       c.mb_partial.as<float>(), c.Lexp.as<float2>());
+        k_m2lb_reduce<P, double><<<rgrid, TPB, 0, s>>>(nblk, blk_item0, blk_nitem, c.mb_bcells.as<int2>(),
+                                                        c.mb_partial.as<float>(), c.Lexp.as<float2>());
     else
-        k_m2lb_reduce<P, float><<<nblk, TPB, 0, s>>>(nblk, blk_item0, blk_nitem, c.mb_bcells.as<int2>(),
-                                                      c.mb_partial.as<float>(), c.Lexp.as<float2>());
+        k_m2lb_reduce<P, float><<<rgrid, TPB, 0, s>>>(nblk, blk_item0, blk_nitem, c.mb_bcells.as<int2>(),
+                                                       c.mb_partial.as<float>(), c.Lexp.as<float2>());
     VFMM_LAUNCH_CHECK();
 }
 

@@ -146,7 +146,7 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
 template <int SCHEME, bool KAHAN>
 __global__ __launch_bounds__(256) void k_p2p(P2PConst k, P2PArgs A) {
     const int lane = threadIdx.x & 63;
-    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int b = xcd_logical(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     if (b >= A.nblocks) return;
     const int4 blk = A.blocks[b];
     const int t0 = __builtin_amdgcn_readfirstlane(blk.x);
@@ -398,7 +398,7 @@ static P2PConst make_const(double sigma) {
 template <int SCHEME, bool KAHAN>
 static void launch_p2p(Ctx &c, const P2PConst &k, const P2PArgs &A) {
     if (A.nblocks == 0) return;
-    k_p2p<SCHEME, KAHAN><<<cdiv(A.nblocks, 4), 256, 0, c.stream>>>(k, A);
+    k_p2p<SCHEME, KAHAN><<<xcd_grid(cdiv(A.nblocks, 4)), 256, 0, c.stream>>>(k, A);
     VFMM_LAUNCH_CHECK();
 }
 
