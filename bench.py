@@ -22,7 +22,7 @@ sys.path.insert(0, ROOT)
 METRIC = "FMM step time & P2P Gpair-interactions/s at 128^3 particles, p=10, ≤1e-4 err"
 PEAK_FP32_VALU_TFLOPS = 157.3        # published FP32 vector peak of MI355X (256 CU, 2.4 GHz); the non-packed
                                       # v_fmac_f32 rate measured by --microbench reaches 87% of it
-FLOPS_PER_PAIR = 79                   # gfx950 ISA of the P2P pair body (s >= 1 form): 29 FMA + 16 MUL + 3 SUB + 2 TRANS, FMA = 2
+FLOPS_PER_PAIR = 71                   # gfx950 ISA of the P2P pair body (s >= 1 form): 25 FMA + 16 MUL + 3 SUB + 2 TRANS, FMA = 2
 PAPER_FLOPS_PER_PAIR = 174            # Table 1 convention (70 + 104)
 
 
@@ -52,9 +52,11 @@ def parse():
 
 
 def kernel_hash():
+    """Hash of the sources the P2P kernel is compiled from."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1106_5273_amd", "csrc", "p2p.hip"), "rb") as f:
-        h.update(f.read())
+    for name in ("p2p.hip", "cutoff_fits.h", "common.h"):
+        with open(os.path.join(ROOT, "paper_1106_5273_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 

@@ -41,7 +41,7 @@ class Timings(ctypes.Structure):
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("theta", ctypes.c_float), ("ncrit", ctypes.c_int32),
-                ("err_u", ctypes.c_float), ("err_dalpha", ctypes.c_float), ("ms", ctypes.c_float),
+                ("sigma_gap", ctypes.c_float), ("err_u", ctypes.c_float), ("err_dalpha", ctypes.c_float), ("ms", ctypes.c_float),
                 ("tried", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
 
 
@@ -179,6 +179,7 @@ class Context:
         self._raise(_lib.vfmm_autotune(self._h, n, *[_ptr(t) for t in (x, y, z, ax, ay, az, sigma)],
                                        float(max_rel_l2), cp, ctypes.byref(r)))
         self.params.p, self.params.theta, self.params.ncrit = r.p, r.theta, r.ncrit
+        self.params.sigma_gap = r.sigma_gap
         return {f: getattr(r, f) for f, _ in TuneResult._fields_}
 
     def timings(self):

@@ -1,9 +1,10 @@
-// Autotuner: chooses the expansion degree p, the acceptance parameter theta
-// and the leaf size ncrit that minimise the time of one build + evaluate on
-// the caller's particles while keeping the relative L2 error of u and of
-// dalpha/dt below a bound.  The error of each candidate is measured against
-// the library's own high-accuracy configuration (p = 12, theta = 0.35) on
-// the same input.  The paper fixes p and does not tune (Sec. 4.2); this is a
+// Autotuner: chooses the expansion degree p, the acceptance parameter theta,
+// the leaf size ncrit and the core-overlap gap of the M2L test (sigma_gap)
+// that minimise the time of one build + evaluate on the caller's particles
+// while keeping the relative L2 error of u and of dalpha/dt below a bound.
+// The error of each candidate is measured against the library's own
+// high-accuracy configuration (p = 12, theta = 0.35, sigma_gap >= 6) on the
+// same input.  The paper fixes p and does not tune (Sec. 4.2); this is a
 // library feature for choosing the accuracy/time operating point.
 #include <cmath>
 #include <cstdio>
@@ -59,15 +60,21 @@ static void rel_errors(Ctx &c, int64_t n, const float *a, const float *b, double
 }
 
 static std::string cache_key(const Ctx &c, int64_t n, float tol) {
+    std::string arch = "unknown";
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    for (char &ch : arch)
+        if (ch == ' ' || ch == '|') ch = '_';
     std::ostringstream k;
-    k << "n=" << n << " periodic=" << c.prm.periodic << " images=" << c.prm.images << " scheme=" << c.prm.scheme
-      << " sigma_gap=" << c.prm.sigma_gap << " tol=" << tol;
+    k << "arch=" << arch << " n=" << n << " periodic=" << c.prm.periodic << " images=" << c.prm.images
+      << " scheme=" << c.prm.scheme << " precision=" << c.prm.precision << " tol=" << tol;
     return k.str();
 }
 
 struct Trial {
     int p, ncrit;
-    float theta;
+    float theta, gap;
     double eu, ed, ms;
     bool ok;
 };
@@ -98,7 +105,7 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
                 if (bar == std::string::npos || line.substr(0, bar) != key) continue;
                 std::istringstream v(line.substr(bar + 3));
                 vfmm_tune_result r{};
-                if (v >> r.p >> r.theta >> r.ncrit >> r.err_u >> r.err_dalpha >> r.ms) {
+                if (v >> r.p >> r.theta >> r.ncrit >> r.sigma_gap >> r.err_u >> r.err_dalpha >> r.ms) {
                     r.from_cache = 1;
                     *out = r;
                 }
@@ -108,6 +115,7 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
                 p.p = out->p;
                 p.theta = out->theta;
                 p.ncrit = out->ncrit;
+                p.sigma_gap = out->sigma_gap;
                 vfmm::set_params_public(c, p);
                 return VFMM_OK;
             }
@@ -115,11 +123,12 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
         c.tune_ref.ensure(sizeof(float) * 6 * (size_t)n);
         c.tune_out.ensure(sizeof(float) * 6 * (size_t)n);
         float *R = c.tune_ref.as<float>(), *O = c.tune_out.as<float>();
-        auto run = [&](int p, float theta, int ncrit, float *dst, double &ms) {
+        auto run = [&](int p, float theta, int ncrit, float gap, float *dst, double &ms) {
             vfmm_params q = base;
             q.p = p;
             q.theta = theta;
             q.ncrit = ncrit;
+            q.sigma_gap = gap;
             q.use_graph = 0;
             vfmm::set_params_public(c, q);
             // first pass warms the buffers; the second is timed
@@ -135,13 +144,14 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
             ms = (double)b + (double)e;
         };
         double ref_ms = 0;
-        run(12, 0.35f, base.ncrit, R, ref_ms);
+        run(12, 0.35f, base.ncrit, std::max(base.sigma_gap, 6.0f), R, ref_ms);
         std::vector<vfmm::Trial> trials;
-        auto trial = [&](int p, float theta, int ncrit) {
+        auto trial = [&](int p, float theta, int ncrit, float gap) {
             for (const auto &t : trials)
-                if (t.p == p && t.ncrit == ncrit && std::fabs(t.theta - theta) < 1e-6f) return t;
-            vfmm::Trial t{p, ncrit, theta, 0, 0, 0, false};
-            run(p, theta, ncrit, O, t.ms);
+                if (t.p == p && t.ncrit == ncrit && std::fabs(t.theta - theta) < 1e-6f && std::fabs(t.gap - gap) < 1e-6f)
+                    return t;
+            vfmm::Trial t{p, ncrit, theta, gap, 0, 0, 0, false};
+            run(p, theta, ncrit, gap, O, t.ms);
             vfmm::rel_errors(c, n, O, R, t.eu, t.ed);
             t.ok = t.eu <= max_rel_l2 && t.ed <= max_rel_l2;
             trials.push_back(t);
@@ -150,10 +160,11 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
         const int ps[] = {6, 8, 10, 12};
         const float thetas[] = {0.3f, 0.4f, 0.5f, 0.6f, 0.7f};
         const int ncrits[] = {32, 64, 128, 256, 512};
-        // (theta, p) at the caller's ncrit: smallest feasible p per theta
+        const float gaps[] = {4.0f, 5.0f, 6.0f};
+        // (theta, p) at the caller's ncrit and sigma_gap: smallest feasible p per theta
         for (float th : thetas)
             for (int p : ps)
-                if (trial(p, th, base.ncrit).ok) break;
+                if (trial(p, th, base.ncrit, base.sigma_gap).ok) break;
         auto best_of = [&]() {
             const vfmm::Trial *b = nullptr;
             for (const auto &t : trials)
@@ -167,12 +178,20 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
         // leaf size at the best (theta, p), raising p once if accuracy drops
         for (int nc : ncrits) {
             if (nc == base.ncrit) continue;
-            if (!trial(bp, bth, nc).ok && bp + 2 <= 12) trial(bp + 2, bth, nc);
+            if (!trial(bp, bth, nc, base.sigma_gap).ok && bp + 2 <= 12) trial(bp + 2, bth, nc, base.sigma_gap);
+        }
+        // gap of the M2L core-overlap test at the best (theta, p, ncrit)
+        b = best_of();
+        {
+            const vfmm::Trial bb = *b;
+            for (float gp : gaps)
+                if (std::fabs(gp - bb.gap) > 1e-6f) trial(bb.p, bb.theta, bb.ncrit, gp);
         }
         b = best_of();
         out->p = b->p;
         out->theta = b->theta;
         out->ncrit = b->ncrit;
+        out->sigma_gap = b->gap;
         out->err_u = (float)b->eu;
         out->err_dalpha = (float)b->ed;
         out->ms = (float)b->ms;
@@ -182,11 +201,12 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
         p.p = b->p;
         p.theta = b->theta;
         p.ncrit = b->ncrit;
+        p.sigma_gap = b->gap;
         vfmm::set_params_public(c, p);
         if (cache_path) {
             std::ofstream o(cache_path, std::ios::app);
-            o << key << " | " << out->p << " " << out->theta << " " << out->ncrit << " " << out->err_u << " "
-              << out->err_dalpha << " " << out->ms << "\n";
+            o << key << " | " << out->p << " " << out->theta << " " << out->ncrit << " " << out->sigma_gap << " "
+              << out->err_u << " " << out->err_dalpha << " " << out->ms << "\n";
         }
         return VFMM_OK;
     } catch (const Error &e) {

@@ -56,14 +56,27 @@ struct KeyFmt {
     int oq, odl;  // offsets making the packed fields non-negative
 };
 
-struct LvlInfo {
-    int off[23];      // first cell of each level
-    int bbase[23];    // first block of each level
-    int nlev;
+// Blocking of target cells: the M2L list of a cell in a uniform region is
+// fixed by its position in its parent (and, more weakly, the parent's in the
+// grandparent), so the 64 targets of a block are taken from one such class:
+// cells of one level with equal octant digits, in Morton order.  Per level the
+// mode is 0 (no class), 1 (own octant) or 2 (own and parent's octant), chosen
+// from the number of cells in the level so that classes still fill blocks.
+struct ClassModes {
+    int m[23];
 };
 
-__device__ inline int block_of(const LvlInfo &L, int cell, int lvl) {
-    return L.bbase[lvl] + (cell - L.off[lvl]) / 64;
+__global__ __launch_bounds__(TPB) void k_cell_class(int ncells, const int *level, const int *start,
+                                                    const uint64_t *keys, int KL, ClassModes M, int *cls) {
+    const int c = blockIdx.x * TPB + threadIdx.x;
+    if (c >= ncells) return;
+    const int lv = level[c];
+    const int mode = M.m[lv];
+    const uint64_t k = keys[start[c]];
+    int v = 0;
+    if (mode >= 1) v = (int)((k >> (3 * (KL - lv))) & 7);
+    if (mode >= 2) v = v * 8 + (int)((k >> (3 * (KL - lv + 1))) & 7);
+    cls[c] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -154,26 +167,22 @@ __global__ __launch_bounds__(TPB) void k_key_ids(int64_t n, const uint64_t *key,
     if (flag[i]) ukey[id] = key[i];
 }
 
-__global__ __launch_bounds__(TPB) void k_block_keys(int64_t n, const int *tgt, const int *level, LvlInfo L,
-                                                    const int *kid, int kbits, uint64_t *key, uint32_t *val) {
+__global__ __launch_bounds__(TPB) void k_block_keys(int64_t n, const int *tgt, const int2 *cell_bs, const int *kid,
+                                                    int kbits, uint64_t *key, uint32_t *val) {
     const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (e >= n) return;
-    const int t = tgt[e];
-    key[e] = ((uint64_t)block_of(L, t, level[t]) << kbits) | (uint64_t)kid[e];
+    key[e] = ((uint64_t)cell_bs[tgt[e]].x << kbits) | (uint64_t)kid[e];
     val[e] = (uint32_t)e;
 }
 
 // sorted entries -> (source cell, target slot); group starts
 __global__ __launch_bounds__(TPB) void k_groups(int64_t n, const uint64_t *ck, const uint32_t *val, const int *flag,
-                                                const int *pos, const int *tgt, const int2 *src, const int *level,
-                                                LvlInfo L, int kbits, int2 *ent, int4 *groups) {
+                                                const int *pos, const int *tgt, const int2 *src, const int2 *cell_bs,
+                                                int kbits, int2 *ent, int4 *groups) {
     const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (i >= n) return;
     const int e = (int)val[i];
-    const int t = tgt[e];
-    const int lv = level[t];
-    const int slot = (t - L.off[lv]) % 64;
-    ent[i] = make_int2(src[e].x, slot);
+    ent[i] = make_int2(src[e].x, cell_bs[tgt[e]].y);
     if (flag[i]) {
         const int g = pos[i];
         const uint64_t k = ck[i];
@@ -473,7 +482,7 @@ static size_t m2lb_lds_bytes() {
 // per (potential, row, target slot) of a block; blockIdx.y strides over blocks.
 template <int P, class A>
 __global__ __launch_bounds__(TPB) void k_m2lb_reduce(int nblk, const int *blk_item0, const int *blk_nitem,
-                                                     const int2 *blk_cells, const float *partial, float2 *Lexp) {
+                                                     const int *blk_cells, const float *partial, float2 *Lexp) {
     // A: accumulator type (double in the mixed precision form)
     constexpr int R = NR(P), NCP = NC(P);
     const int idx = blockIdx.x * TPB + threadIdx.x;
@@ -486,8 +495,8 @@ __global__ __launch_bounds__(TPB) void k_m2lb_reduce(int nblk, const int *blk_it
     const size_t stride = (size_t)3 * R * 64;
     for (int b = blockIdx.y; b < nblk; b += gridDim.y) {
         const int ni = blk_nitem[b];
-        const int2 bc = blk_cells[b];
-        if (ni == 0 || lane >= bc.y) continue;
+        const int cell = blk_cells[(size_t)b * 64 + lane];
+        if (ni == 0 || cell < 0) continue;
         const float *p = partial + ((size_t)blk_item0[b] * 3 * R + cr) * 64 + lane;
         A s = A(0);
         int i = 0;
@@ -500,7 +509,7 @@ __global__ __launch_bounds__(TPB) void k_m2lb_reduce(int nblk, const int *blk_it
             s += (A)v3;
         }
         for (; i < ni; ++i) s += (A)p[(size_t)i * stride];
-        float *dst = reinterpret_cast<float *>(&Lexp[((size_t)(bc.x + lane) * 3 + comp) * NCP + CIDX(k, l)]) + im;
+        float *dst = reinterpret_cast<float *>(&Lexp[((size_t)cell * 3 + comp) * NCP + CIDX(k, l)]) + im;
         *dst = (float)((A)*dst + s);
     }
 }
@@ -586,24 +595,49 @@ static void m2lb_plan_p(Ctx &c) {
     c.lkey.ensure(sizeof(uint64_t) * n);
     c.lval.ensure(sizeof(uint32_t) * n);
     int *flag = c.mb_flag.as<int>(), *pos = c.mb_pos.as<int>();
-    // ---- blocks of 64 target cells per level ----
-    LvlInfo L{};
-    L.nlev = c.depth + 1;
+    // ---- blocks of 64 target cells: one level, one octant class, Morton order ----
+    ClassModes cm{};
+    for (int l = 0; l <= c.depth && l < 23; ++l) {
+        const int cnt = c.lvl_off[l + 1] - c.lvl_off[l];
+        cm.m[l] = (l >= 2 && cnt >= 64 * 64) ? 2 : (l >= 1 && cnt >= 64 * 8) ? 1 : 0;
+    }
+    const int nc = c.ncells;
+    c.mb_cls.ensure(sizeof(int) * (size_t)nc);
+    k_cell_class<<<cdiv(nc, TPB), TPB, 0, s>>>(nc, c.c_level.as<int>(), c.c_start.as<int>(), c.keyA.as<uint64_t>(),
+                                               c.key_levels, cm, c.mb_cls.as<int>());
+    VFMM_LAUNCH_CHECK();
+    std::vector<int> cls(nc);
+    VFMM_HIP(hipMemcpyAsync(cls.data(), c.mb_cls.ptr, sizeof(int) * nc, hipMemcpyDeviceToHost, s));
+    VFMM_HIP(hipStreamSynchronize(s));
+    std::vector<int2> cell_bs(nc);
+    std::vector<int> bcells;
     int nblk = 0;
-    std::vector<int2> bcells;
-    for (int l = 0; l <= c.depth; ++l) {
-        L.off[l] = c.lvl_off[l];
-        L.bbase[l] = nblk;
-        for (int cell = c.lvl_off[l]; cell < c.lvl_off[l + 1]; cell += 64)
-            bcells.push_back(make_int2(cell, std::min(64, c.lvl_off[l + 1] - cell)));
-        nblk = (int)bcells.size();
+    {
+        std::vector<std::vector<int>> bucket(64);
+        for (int l = 0; l <= c.depth; ++l) {
+            const int ncl = cm.m[l] == 2 ? 64 : cm.m[l] == 1 ? 8 : 1;
+            for (int q = 0; q < ncl; ++q) bucket[q].clear();
+            for (int cell = c.lvl_off[l]; cell < c.lvl_off[l + 1]; ++cell) bucket[cls[cell]].push_back(cell);
+            for (int q = 0; q < ncl; ++q)
+                for (size_t i = 0; i < bucket[q].size(); ++i) {
+                    if (i % 64 == 0) {
+                        bcells.resize(bcells.size() + 64, -1);
+                        ++nblk;
+                    }
+                    const int cell = bucket[q][i];
+                    bcells[(size_t)(nblk - 1) * 64 + i % 64] = cell;
+                    cell_bs[cell] = make_int2(nblk - 1, (int)(i % 64));
+                }
+        }
     }
     c.mb_nblk = nblk;
-    c.mb_bcells.ensure(sizeof(int2) * nblk);
-    VFMM_HIP(hipMemcpyAsync(c.mb_bcells.ptr, bcells.data(), sizeof(int2) * nblk, hipMemcpyHostToDevice, s));
+    c.mb_bcells.ensure(sizeof(int) * bcells.size());
+    c.mb_cellbs.ensure(sizeof(int2) * (size_t)nc);
+    VFMM_HIP(hipMemcpyAsync(c.mb_bcells.ptr, bcells.data(), sizeof(int) * bcells.size(), hipMemcpyHostToDevice, s));
+    VFMM_HIP(hipMemcpyAsync(c.mb_cellbs.ptr, cell_bs.data(), sizeof(int2) * nc, hipMemcpyHostToDevice, s));
     const int kbits = bits_for_range(nkeys);
     const int bbits = bits_for_range(nblk);
-    k_block_keys<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.m2l_tgt.as<int>(), c.c_level.as<int>(), L, c.mb_kid.as<int>(),
+    k_block_keys<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.m2l_tgt.as<int>(), c.mb_cellbs.as<int2>(), c.mb_kid.as<int>(),
                                                kbits, c.lkey.as<uint64_t>(), c.lval.as<uint32_t>());
     VFMM_LAUNCH_CHECK();
     sort_pairs_u64(c, c.lkey, c.lval, c.lkey2, c.lval2, n, kbits + bbits);
@@ -617,7 +651,7 @@ static void m2lb_plan_p(Ctx &c) {
     c.mb_ent.ensure(sizeof(int2) * n);
     c.mb_groups.ensure(sizeof(int4) * ng);
     k_groups<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.lkey.as<uint64_t>(), c.lval.as<uint32_t>(), flag, pos,
-                                           c.m2l_tgt.as<int>(), c.m2l_src.as<int2>(), c.c_level.as<int>(), L, kbits,
+                                           c.m2l_tgt.as<int>(), c.m2l_src.as<int2>(), c.mb_cellbs.as<int2>(), kbits,
                                            c.mb_ent.as<int2>(), c.mb_groups.as<int4>());
     VFMM_LAUNCH_CHECK();
     c.mb_blk.ensure(sizeof(int) * 3 * (size_t)nblk);
@@ -707,10 +741,10 @@ static void m2lb_run_p(Ctx &c) {
     int *blk_item0 = c.mb_blk.as<int>() + nblk, *blk_nitem = blk_item0 + nblk;
     const dim3 rgrid(cdiv(3 * R * 64, TPB), std::min(nblk, 65535));
     if (c.prm.precision == VFMM_PRECISION_MIXED)
-        k_m2lb_reduce<P, double><<<rgrid, TPB, 0, s>>>(nblk, blk_item0, blk_nitem, c.mb_bcells.as<int2>(),
+        k_m2lb_reduce<P, double><<<rgrid, TPB, 0, s>>>(nblk, blk_item0, blk_nitem, c.mb_bcells.as<int>(),
                                                         c.mb_partial.as<float>(), c.Lexp.as<float2>());
     else
-        k_m2lb_reduce<P, float><<<rgrid, TPB, 0, s>>>(nblk, blk_item0, blk_nitem, c.mb_bcells.as<int2>(),
+        k_m2lb_reduce<P, float><<<rgrid, TPB, 0, s>>>(nblk, blk_item0, blk_nitem, c.mb_bcells.as<int>(),
                                                        c.mb_partial.as<float>(), c.Lexp.as<float2>());
     VFMM_LAUNCH_CHECK();
 }

@@ -129,9 +129,13 @@ __global__ __launch_bounds__(TPB) void k_list_keys(const int4 *raw, int64_t n, u
     val[i] = (uint32_t)i;
 }
 
-__global__ __launch_bounds__(TPB) void k_count_tgt(const int4 *raw, int64_t n, int *cnt) {
+// CSR offsets from the sorted targets: off[t] = first position with target >= t
+__global__ __launch_bounds__(TPB) void k_csr_bounds(const uint64_t *key, int64_t n, int nc, int *off) {
     const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
-    if (i < n) atomicAdd(&cnt[raw[i].x], 1);
+    if (i > n) return;
+    const int lo = (i == 0) ? 0 : (int)key[i - 1] + 1;  // targets in (key[i-1], key[i]] start at i
+    const int hi = (i == n) ? nc : (int)key[i];
+    for (int t = lo; t <= hi; ++t) off[t] = (int)i;
 }
 
 __global__ __launch_bounds__(TPB) void k_m2l_gather(const int4 *raw, const uint32_t *order, int64_t n, int2 *out,
@@ -224,18 +228,17 @@ static void csr_by_target(Ctx &c, const int4 *raw, int64_t n, DevBuf &off) {
     hipStream_t s = c.stream;
     const int nc = c.ncells;
     off.ensure(sizeof(int) * ((size_t)nc + 1));
-    VFMM_HIP(hipMemsetAsync(off.ptr, 0, sizeof(int) * ((size_t)nc + 1), s));
-    if (n > 0) {
-        k_count_tgt<<<cdiv(n, TPB), TPB, 0, s>>>(raw, n, off.as<int>());
-        VFMM_LAUNCH_CHECK();
+    if (n == 0) {
+        VFMM_HIP(hipMemsetAsync(off.ptr, 0, sizeof(int) * ((size_t)nc + 1), s));
+        return;
     }
-    scan_excl_i32(c, off.as<int>(), off.as<int>(), (int64_t)nc + 1);
-    if (n == 0) return;
     c.lkey.ensure(sizeof(uint64_t) * n);
     c.lval.ensure(sizeof(uint32_t) * n);
     k_list_keys<<<cdiv(n, TPB), TPB, 0, s>>>(raw, n, c.lkey.as<uint64_t>(), c.lval.as<uint32_t>());
     VFMM_LAUNCH_CHECK();
     sort_pairs_u64(c, c.lkey, c.lval, c.lkey2, c.lval2, n, bits_for(nc));
+    k_csr_bounds<<<cdiv(n + 1, TPB), TPB, 0, s>>>(c.lkey.as<uint64_t>(), n, nc, off.as<int>());
+    VFMM_LAUNCH_CHECK();
 }
 
 void traverse_and_lists(Ctx &c) {

@@ -480,4 +480,5 @@ def test_autotune_meets_bound_and_reuses_cache(tmp_path):
         r2 = ctx.autotune(*t, max_rel_l2=1e-4, cache_path=cache)
         assert r2["from_cache"] == 1
         assert (r2["p"], r2["ncrit"]) == (r["p"], r["ncrit"]) and abs(r2["theta"] - r["theta"]) < 1e-6
+        assert abs(r2["sigma_gap"] - r["sigma_gap"]) < 1e-6 and r["sigma_gap"] in (4.0, 5.0, 6.0)
         assert (ctx.params.p, ctx.params.ncrit) == (r["p"], r["ncrit"])
