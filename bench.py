@@ -362,7 +362,8 @@ def main():
         "paper_convention_gflops": pairs * PAPER_FLOPS_PER_PAIR / (p2p_ms * 1e-3) / 1e9,
         "phases_ms": mean_ph,
         "tree": {"ncells": st["ncells"], "nleaves": st["nleaves"], "depth": st["depth"],
-                 "m2l": st["m2l_entries"], "p2p_entries": st["p2p_entries"]},
+                 "m2l": st["m2l_entries"], "p2p_entries": st["p2p_entries"], "m2l_keys": st["m2l_keys"],
+                 "m2l_groups": st["m2l_groups"], "m2l_items": st["m2l_items"]},
         "accuracy": acc,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": traffic,

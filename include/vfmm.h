@@ -122,6 +122,9 @@ typedef struct vfmm_stats {
     int32_t images_traversed; /* periodic image cells started in the traversal    */
     double sum_alpha[3];    /* float64 sum of alpha (set by fmm_evaluate)         */
     double sigma_min, sigma_max;
+    int32_t m2l_keys;       /* batched M2L: distinct translation operators (0 if per pair) */
+    int32_t m2l_groups;     /* batched M2L: (target block, operator) groups        */
+    int32_t m2l_items;      /* batched M2L: work items (<= 24 groups of one block) */
 } vfmm_stats;
 
 /* Fill *p with the defaults listed above (free space). */

@@ -549,6 +549,11 @@ vfmm_status vfmm_get_stats(vfmm_ctx *ctx, vfmm_stats *out) {
     out->images_traversed = c.prm.periodic ? c.img_codes : 0;
     out->sigma_min = c.hb.sig_min;
     out->sigma_max = c.hb.sig_max;
+    if (c.m2lb_ok) {
+        out->m2l_keys = c.mb_nkeys;
+        out->m2l_groups = c.mb_ngroups;
+        out->m2l_items = c.mb_nitems;
+    }
     if (c.bres.ptr && c.n > 0) {
         vfmm::Bounds b;
         if (hipMemcpy(&b, c.bres.ptr, sizeof(b), hipMemcpyDeviceToHost) == hipSuccess)

@@ -39,6 +39,12 @@ __device__ inline void img_shift(int code, int B, float len, float &sx, float &s
     sz = iz * len;
 }
 
+// Decisions on distances and radii use a relative margin TIE_TOL: quantities
+// that agree to within float32 rounding of the cell coordinates (exact ties
+// are common in regular particle layouts) are decided the same way for every
+// cell pair, so pairs related by a translation of the tree get equal lists.
+static constexpr float TIE_TOL = 1.0f / 65536.0f;
+
 // 0 = M2L, 1 = P2P, 2 = push
 __device__ inline int interact(const TravArgs &A, int a, int b, int img) {
     float sx, sy, sz;
@@ -47,17 +53,19 @@ __device__ inline int interact(const TravArgs &A, int a, int b, int img) {
     const float dx = ga.x - gb.x - sx, dy = ga.y - gb.y - sy, dz = ga.z - gb.z - sz;
     const float D = sqrtf(dx * dx + dy * dy + dz * dz);
     const float ra = A.rad[a], rb = A.rad[b];
-    if (ra + rb < A.theta * D && D - ra - rb >= A.gap) return 0;
+    // the MAC and the core gap, both failing on (near-)ties
+    if (ra + rb < A.theta * D * (1.0f - TIE_TOL) && D - ra - rb >= A.gap + TIE_TOL * D) return 0;
     if (A.nchild[a] == 0 && A.nchild[b] == 0) return 1;
     return 2;
 }
 
 // Children pairs of a frontier pair (Algorithm 1): split A when its radius is
-// larger (ties split B), unless the chosen cell is a leaf.
+// larger (radii equal to within TIE_TOL split B), unless the chosen cell is a
+// leaf.
 __device__ inline void split_pair(const TravArgs &A, int a, int b, bool &splitA, int &first, int &cnt) {
     const float ra = A.rad[a], rb = A.rad[b];
     const bool la = A.nchild[a] == 0, lb = A.nchild[b] == 0;
-    splitA = (ra > rb && !la) || lb;
+    splitA = (ra > rb * (1.0f + TIE_TOL) && !la) || lb;
     const int s = splitA ? a : b;
     first = A.child[s];
     cnt = A.nchild[s];
