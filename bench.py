@@ -35,6 +35,9 @@ def parse():
     ap.add_argument("--p", type=int, default=10)
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--ncrit", type=int, default=64)
+    ap.add_argument("--ncrit-c4", type=int, default=256,
+                    help="leaf size of the ring batch: a ring's leaves hold a short arc, so larger leaves are "
+                         "needed to fill the 64-lane P2P waves")
     ap.add_argument("--images", type=int, default=6)
     ap.add_argument("--kahan", type=int, default=0)
     ap.add_argument("--no-check", action="store_true", help="skip the accuracy check against the oracle")
@@ -123,7 +126,7 @@ def bench_batched(args, vf, wl):
     res = {}
     with torch.cuda.stream(st):
         out = tuple(torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(6))
-        ctx = vf.Context(p=8, use_graph=1, stream=st)
+        ctx = vf.Context(p=8, ncrit=args.ncrit_c4, use_graph=1, stream=st)
         ctx.build_batched(off, t[0], t[1], t[2], t[6])
         for _ in range(args.warmup):
             ctx.evaluate(*t, out=out)
@@ -141,7 +144,7 @@ def bench_batched(args, vf, wl):
         stats = ctx.stats()
         ctx.close()
         # sequential: one context, 512 build+evaluate calls on slices
-        ctx = vf.Context(p=8, stream=st)
+        ctx = vf.Context(p=8, ncrit=args.ncrit_c4, stream=st)
         views = [tuple(x[off[b]:off[b + 1]] for x in t) for b in range(len(probs))]
         outs = [tuple(o[off[b]:off[b + 1]] for o in out) for b in range(len(probs))]
         for v, o in zip(views[:8], outs[:8]):
@@ -157,8 +160,10 @@ def bench_batched(args, vf, wl):
         ctx.close()
     total = res["batched_build_ms"] + res["batched_evaluate_graph_ms"]
     line = _line("512 ring problems, build+evaluate throughput", n / (total * 1e-3) / 1e6, "Mparticles/s", total, args,
-                 "512 free-space Gaussian vortex rings, N log-uniform in [1024, 65536], p=8, batched forest",
-                 {"p2p_pairs": stats["p2p_pairs"], "n": n, "speedup_vs_sequential":
+                 "512 free-space Gaussian vortex rings, N log-uniform in [1024, 65536], p=8, ncrit=%d, "
+                 "batched forest" % args.ncrit_c4,
+                 {"p2p_pairs": stats["p2p_pairs"], "n": n, "m2l_entries": stats["m2l_entries"],
+                  "m2l_groups": stats["m2l_groups"], "p2p_blocks": stats["p2p_blocks"], "speedup_vs_sequential":
                   res["sequential_build_evaluate_ms"] / total, **res})
     print(json.dumps(line), flush=True)
 

@@ -78,8 +78,10 @@ typedef struct vfmm_params {
     int32_t kahan;       /* 1: compensated per-target sums in P2P (default 0: blocked sums)    */
     int32_t zero_mean;   /* periodic: subtract (1/3V) sum x_j x alpha_j (default 1)           */
     int32_t direct;      /* 1: all-pairs P2P without a tree (test mode; free space only)      */
-    int32_t m2l_mode;    /* 0: operator-batched M2L (default; falls back to 1 when the offsets of
-                            a tree are too spread to key), 1: per-pair M2L                     */
+    int32_t m2l_mode;    /* 0 (default): operator-batched M2L when the tree's translations group
+                            densely (at least 8 per (64-target block, offset) group), else per
+                            pair; 1: per-pair M2L; 2: operator-batched whenever the offsets can be
+                            keyed (falls back to per pair only when they cannot)                 */
     int32_t use_graph;   /* 1: fmm_evaluate runs as a hipGraph, captured on the first call after
                             a build (or when its pointers change) and replayed afterwards; needs
                             a non-default stream and the tree path (default 0)                */

@@ -14,7 +14,7 @@ void Ctx::release_all() {
                       &c_tmp, &leaves, &frA, &frB, &tcnt, &m2l_raw, &p2p_raw, &lkey, &lkey2, &lval, &lval2,
                       &m2l_off, &m2l_src, &p2p_off, &p2p_ent, &blocks, &pairs64, &Mexp, &Lexp, &lat_op, &far_u,
                       &far_da, &dsurf, &rk, &m2l_tgt, &mb_eq, &mb_flag, &mb_pos, &mb_kid, &mb_ukey,
-                      &mb_tab, &mb_bcells, &mb_ent, &mb_groups, &mb_blk, &mb_items, &mb_mr, &mb_partial, &mb_cls, &mb_cellbs, &pid, &pbox, &poff, &tune_ref, &tune_out, &tune_part};
+                      &mb_tab, &mb_bcells, &mb_ent, &mb_groups, &mb_blk, &mb_items, &mb_mr, &mb_partial, &mb_cls, &mb_cellbs, &mb_gcnt, &mb_gid, &mb_goff, &mb_gcur, &pid, &pbox, &poff, &tune_ref, &tune_out, &tune_part};
     for (DevBuf *b : bufs) b->release();
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -34,7 +34,7 @@ static void validate(const vfmm_params &p) {
     if (!(p.sigma_gap >= 0.f)) throw Error{VFMM_EINVAL, "sigma_gap must be >= 0"};
     if (p.scheme != VFMM_SCHEME_TRANSPOSE && p.scheme != VFMM_SCHEME_CLASSICAL)
         throw Error{VFMM_EINVAL, "scheme must be VFMM_SCHEME_TRANSPOSE or VFMM_SCHEME_CLASSICAL"};
-    if (p.m2l_mode != 0 && p.m2l_mode != 1) throw Error{VFMM_EINVAL, "m2l_mode must be 0 or 1"};
+    if (p.m2l_mode < 0 || p.m2l_mode > 2) throw Error{VFMM_EINVAL, "m2l_mode must be 0, 1 or 2"};
     if (p.use_graph != 0 && p.use_graph != 1) throw Error{VFMM_EINVAL, "use_graph must be 0 or 1"};
     if (p.use_graph && p.direct) throw Error{VFMM_EINVAL, "use_graph needs the tree path (direct = 0)"};
     if (p.precision < VFMM_PRECISION_FP32 || p.precision > VFMM_PRECISION_FP64)
@@ -149,7 +149,8 @@ static void do_build(Ctx &c, int64_t n, const float *x, const float *y, const fl
     c.record(2 * PH_TRAVERSE);
     traverse_and_lists(c);
     c.m2lb_ok = false;
-    if (c.prm.m2l_mode == 0 && c.prm.precision != VFMM_PRECISION_FP64) m2lb_plan(c);
+    if (c.prm.m2l_mode != 1 && c.prm.precision != VFMM_PRECISION_FP64) m2lb_plan(c);
+    if (!c.m2lb_ok && !c.m2l_csr) build_m2l_csr(c);  // the per-pair M2L runs instead
     far_prealloc(c);
     m2lb_prealloc(c);
     ++c.build_id;
@@ -601,6 +602,10 @@ vfmm_status vfmm_copy_lists(vfmm_ctx *ctx, int32_t *p2p_tgt, int32_t *p2p_src, i
                 }
         }
         if (c.n_m2l > 0 && (m2l_tgt || m2l_src || m2l_img)) {
+            if (!c.m2l_csr) {  // the batched M2L works from the raw list; order it on request
+                vfmm::build_m2l_csr(c);
+                VFMM_HIP(hipStreamSynchronize(c.stream));
+            }
             VFMM_HIP(hipMemcpy(off.data(), c.m2l_off.ptr, sizeof(int) * (nc + 1), hipMemcpyDeviceToHost));
             std::vector<int2> src(c.n_m2l);
             VFMM_HIP(hipMemcpy(src.data(), c.m2l_src.ptr, sizeof(int2) * c.n_m2l, hipMemcpyDeviceToHost));

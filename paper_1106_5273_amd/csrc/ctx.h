@@ -64,10 +64,11 @@ struct Ctx {
     double lat_len = 0.0;
     // operator-batched M2L plan
     bool m2lb_ok = false;
+    bool m2l_csr = false;                // M2L CSR by target (m2l_off/src/tgt) built for this tree
     int mb_nblk = 0, mb_nkeys = 0, mb_ngroups = 0, mb_nitems = 0;
     int mb_fmt[4] = {0, 0, 0, 0};
     DevBuf mb_eq, mb_flag, mb_pos, mb_kid, mb_ukey, mb_tab, mb_bcells, mb_ent, mb_groups, mb_blk, mb_items,
-        mb_mr, mb_partial, mb_cls, mb_cellbs;
+        mb_mr, mb_partial, mb_cls, mb_cellbs, mb_gcnt, mb_gid, mb_goff, mb_gcur;
     // outputs of the far field, sorted order: float [3n] each
     DevBuf far_u, far_da;
     DevBuf dsurf;                        // float[4] surface velocity term
@@ -106,6 +107,7 @@ void compute_bounds(Ctx &c, int64_t n, const float *x, const float *y, const flo
 void build_tree(Ctx &c, int64_t n, const float *x, const float *y, const float *z, const float *sigma);
 void gather_strengths(Ctx &c, const float *ax, const float *ay, const float *az, const float *sigma);
 void gather_records64(Ctx &c, const float *ax, const float *ay, const float *az);
+void build_m2l_csr(Ctx &c);
 void scan_excl_i32(Ctx &c, const int *in, int *out, int64_t n);  // out may alias in
 // traverse.hip
 void traverse_and_lists(Ctx &c);

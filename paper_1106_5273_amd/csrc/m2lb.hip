@@ -29,6 +29,7 @@ static constexpr int TPB = 256;
 static constexpr int ITEM_GROUPS = 24;
 static constexpr int TABLE_KEY_BITS = 24;  // offset keys up to this width are numbered through a direct table
 static constexpr size_t MAX_TABLE_BYTES = size_t(8) << 30;  // operator table cap (else the per-pair kernel)
+static constexpr int MIN_GROUP_FILL = 8;  // translations per (block, key) group below which per-pair M2L runs
 
 void sort_pairs_u64(Ctx &c, DevBuf &kA, DevBuf &vA, DevBuf &kB, DevBuf &vB, int64_t n, int nbits);
 
@@ -82,14 +83,15 @@ __global__ __launch_bounds__(TPB) void k_cell_class(int ncells, const int *level
 // ---------------------------------------------------------------------------
 // per entry: level difference and quantised offset; track the ranges
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(TPB) void k_m2lb_offsets(int64_t n, const int *tgt, const int2 *src, const float4 *geo,
-                                                      const int *level, int B, float len, int4 *eq, int *range) {
+__global__ __launch_bounds__(TPB) void k_m2lb_offsets(int64_t n, const int4 *raw, const float4 *geo, const int *level,
+                                                      int B, float len, int4 *eq, int *range) {
     __shared__ int red[2][TPB / 64];
     int aq = 0, adl = 0;
     const int W = 2 * B + 1;
     for (int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x; e < n; e += (int64_t)gridDim.x * TPB) {
-        const int t = tgt[e];
-        const int2 s = src[e];
+        const int4 r = raw[e];  // (target, source, image code, -)
+        const int t = r.x;
+        const int2 s = make_int2(r.y, r.z);
         const float shx = (float)(s.y % W - B) * len;
         const float shy = (float)((s.y / W) % W - B) * len;
         const float shz = (float)(s.y / (W * W) - B) * len;
@@ -167,27 +169,39 @@ __global__ __launch_bounds__(TPB) void k_key_ids(int64_t n, const uint64_t *key,
     if (flag[i]) ukey[id] = key[i];
 }
 
-__global__ __launch_bounds__(TPB) void k_block_keys(int64_t n, const int *tgt, const int2 *cell_bs, const int *kid,
-                                                    int kbits, uint64_t *key, uint32_t *val) {
+// (block, key) groups by counting: gk = block * nkeys + key indexes a dense
+// table; entries are scattered to their group with an atomic cursor.  Within
+// a group every entry fills a different target slot, so the order in which
+// the entries land does not change any result.
+__global__ __launch_bounds__(TPB) void k_gk_count(int64_t n, const int4 *raw, const int2 *cell_bs, const int *kid,
+                                                  int nkeys, int *cnt) {
     const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (e >= n) return;
-    key[e] = ((uint64_t)cell_bs[tgt[e]].x << kbits) | (uint64_t)kid[e];
-    val[e] = (uint32_t)e;
+    atomicAdd(&cnt[(int64_t)cell_bs[raw[e].x].x * nkeys + kid[e]], 1);
 }
 
-// sorted entries -> (source cell, target slot); group starts
-__global__ __launch_bounds__(TPB) void k_groups(int64_t n, const uint64_t *ck, const uint32_t *val, const int *flag,
-                                                const int *pos, const int *tgt, const int2 *src, const int2 *cell_bs,
-                                                int kbits, int2 *ent, int4 *groups) {
+__global__ __launch_bounds__(TPB) void k_gk_flags(int64_t T, const int *cnt, int *flag) {
     const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
-    if (i >= n) return;
-    const int e = (int)val[i];
-    ent[i] = make_int2(src[e].x, cell_bs[tgt[e]].y);
-    if (flag[i]) {
-        const int g = pos[i];
-        const uint64_t k = ck[i];
-        groups[g] = make_int4((int)(k & ((1ull << kbits) - 1)), (int)i, 0, (int)(k >> kbits));
-    }
+    if (i < T) flag[i] = cnt[i] > 0 ? 1 : 0;
+}
+
+__global__ __launch_bounds__(TPB) void k_gk_groups(int64_t T, const int *cnt, const int *gid, const int *eoff, int nkeys,
+                                                   int4 *groups, int *cursor) {
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i >= T) return;
+    cursor[i] = 0;
+    if (cnt[i] > 0) groups[gid[i]] = make_int4((int)(i % nkeys), eoff[i], cnt[i], (int)(i / nkeys));
+}
+
+__global__ __launch_bounds__(TPB) void k_gk_scatter(int64_t n, const int4 *raw, const int2 *cell_bs, const int *kid,
+                                                    int nkeys, const int *eoff, int *cursor, int2 *ent) {
+    const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (e >= n) return;
+    const int4 r = raw[e];
+    const int2 bs = cell_bs[r.x];
+    const int64_t gk = (int64_t)bs.x * nkeys + kid[e];
+    const int pos = eoff[gk] + atomicAdd(&cursor[gk], 1);
+    ent[pos] = make_int2(r.y, bs.y);
 }
 
 // group counts (from the next group's start) and the per-block first group
@@ -533,7 +547,7 @@ static void m2lb_plan_p(Ctx &c) {
     c.mb_eq.ensure(sizeof(int4) * n);
     c.pairs64.ensure(64);
     VFMM_HIP(hipMemsetAsync(c.pairs64.ptr, 0, 8, s));
-    k_m2lb_offsets<<<std::min<unsigned>(cdiv(n, TPB), 1024), TPB, 0, s>>>(n, c.m2l_tgt.as<int>(), c.m2l_src.as<int2>(), c.c_geo.as<float4>(),
+    k_m2lb_offsets<<<std::min<unsigned>(cdiv(n, TPB), 1024), TPB, 0, s>>>(n, c.m2l_raw.as<int4>(), c.c_geo.as<float4>(),
                                                  c.c_level.as<int>(), c.img_B,
                                                  c.prm.periodic ? (float)c.prm.box_len : 0.f, c.mb_eq.as<int4>(),
                                                  c.pairs64.as<int>());
@@ -635,24 +649,38 @@ static void m2lb_plan_p(Ctx &c) {
     c.mb_cellbs.ensure(sizeof(int2) * (size_t)nc);
     VFMM_HIP(hipMemcpyAsync(c.mb_bcells.ptr, bcells.data(), sizeof(int) * bcells.size(), hipMemcpyHostToDevice, s));
     VFMM_HIP(hipMemcpyAsync(c.mb_cellbs.ptr, cell_bs.data(), sizeof(int2) * nc, hipMemcpyHostToDevice, s));
-    const int kbits = bits_for_range(nkeys);
-    const int bbits = bits_for_range(nblk);
-    k_block_keys<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.m2l_tgt.as<int>(), c.mb_cellbs.as<int2>(), c.mb_kid.as<int>(),
-                                               kbits, c.lkey.as<uint64_t>(), c.lval.as<uint32_t>());
+    // ---- groups (block, key) in (block, key) order ----
+    const int64_t T = (int64_t)nblk * nkeys;
+    if (T > ((int64_t)1 << 28)) return;  // table too large: per-pair M2L
+    c.mb_gcnt.ensure(sizeof(int) * (size_t)(T + 1));
+    c.mb_gid.ensure(sizeof(int) * (size_t)(T + 1));
+    c.mb_goff.ensure(sizeof(int) * (size_t)(T + 1));
+    c.mb_gcur.ensure(sizeof(int) * (size_t)(T + 1));
+    int *gcnt = c.mb_gcnt.as<int>(), *gid = c.mb_gid.as<int>(), *goff = c.mb_goff.as<int>(),
+        *gcur = c.mb_gcur.as<int>();
+    VFMM_HIP(hipMemsetAsync(gcnt, 0, sizeof(int) * (size_t)T, s));
+    k_gk_count<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.m2l_raw.as<int4>(), c.mb_cellbs.as<int2>(), c.mb_kid.as<int>(), nkeys,
+                                             gcnt);
     VFMM_LAUNCH_CHECK();
-    sort_pairs_u64(c, c.lkey, c.lval, c.lkey2, c.lval2, n, kbits + bbits);
-    k_flag_changes<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.lkey.as<uint64_t>(), flag);
+    scan_excl_i32(c, gcnt, goff, T);
+    k_gk_flags<<<cdiv(T, TPB), TPB, 0, s>>>(T, gcnt, gcur);  // flags, then reused as cursors
     VFMM_LAUNCH_CHECK();
-    scan_excl_i32(c, flag, pos, n);
-    VFMM_HIP(hipMemcpyAsync(&h2[0], pos + n - 1, 4, hipMemcpyDeviceToHost, s));
-    VFMM_HIP(hipMemcpyAsync(&h2[1], flag + n - 1, 4, hipMemcpyDeviceToHost, s));
+    scan_excl_i32(c, gcur, gid, T);
+    VFMM_HIP(hipMemcpyAsync(&h2[0], gid + T - 1, 4, hipMemcpyDeviceToHost, s));
+    VFMM_HIP(hipMemcpyAsync(&h2[1], gcur + T - 1, 4, hipMemcpyDeviceToHost, s));
     VFMM_HIP(hipStreamSynchronize(s));
     const int ng = h2[0] + h2[1];
+    // A group costs a full 64-target operator product whether its targets are
+    // all present or not; measured on gfx950 a group costs about as much as
+    // 6-7 translations of the per-pair kernel, so sparse groups (irregular
+    // trees: many offsets, few targets sharing each) go to the per-pair M2L.
+    if (c.prm.m2l_mode == 0 && n < (int64_t)MIN_GROUP_FILL * ng) return;
     c.mb_ent.ensure(sizeof(int2) * n);
     c.mb_groups.ensure(sizeof(int4) * ng);
-    k_groups<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.lkey.as<uint64_t>(), c.lval.as<uint32_t>(), flag, pos,
-                                           c.m2l_tgt.as<int>(), c.m2l_src.as<int2>(), c.mb_cellbs.as<int2>(), kbits,
-                                           c.mb_ent.as<int2>(), c.mb_groups.as<int4>());
+    k_gk_groups<<<cdiv(T, TPB), TPB, 0, s>>>(T, gcnt, gid, goff, nkeys, c.mb_groups.as<int4>(), gcur);
+    VFMM_LAUNCH_CHECK();
+    k_gk_scatter<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.m2l_raw.as<int4>(), c.mb_cellbs.as<int2>(), c.mb_kid.as<int>(),
+                                               nkeys, goff, gcur, c.mb_ent.as<int2>());
     VFMM_LAUNCH_CHECK();
     c.mb_blk.ensure(sizeof(int) * 3 * (size_t)nblk);
     int *blk_first = c.mb_blk.as<int>(), *blk_item0 = blk_first + nblk, *blk_nitem = blk_item0 + nblk;

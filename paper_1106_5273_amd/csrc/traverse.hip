@@ -249,6 +249,22 @@ static void csr_by_target(Ctx &c, const int4 *raw, int64_t n, DevBuf &off) {
     VFMM_LAUNCH_CHECK();
 }
 
+// M2L list in CSR order by target cell (stable: traversal order within a
+// target), for the per-pair M2L kernel and for vfmm_copy_lists.
+void build_m2l_csr(Ctx &c) {
+    hipStream_t s = c.stream;
+    const int64_t n_m2l = c.n_m2l;
+    csr_by_target(c, c.m2l_raw.as<int4>(), n_m2l, c.m2l_off);
+    c.m2l_src.ensure(sizeof(int2) * (size_t)std::max<int64_t>(n_m2l, 1));
+    c.m2l_tgt.ensure(sizeof(int) * (size_t)std::max<int64_t>(n_m2l, 1));
+    if (n_m2l > 0) {
+        k_m2l_gather<<<cdiv(n_m2l, TPB), TPB, 0, s>>>(c.m2l_raw.as<int4>(), c.lval.as<uint32_t>(), n_m2l,
+                                                       c.m2l_src.as<int2>(), c.m2l_tgt.as<int>());
+        VFMM_LAUNCH_CHECK();
+    }
+    c.m2l_csr = true;
+}
+
 void traverse_and_lists(Ctx &c) {
     hipStream_t s = c.stream;
     TravArgs A{};
@@ -303,15 +319,9 @@ void traverse_and_lists(Ctx &c) {
     c.n_m2l = n_m2l;
     c.n_p2p = (int)n_p2p;
 
-    // ---- M2L CSR ----
-    csr_by_target(c, c.m2l_raw.as<int4>(), n_m2l, c.m2l_off);
-    c.m2l_src.ensure(sizeof(int2) * (size_t)std::max<int64_t>(n_m2l, 1));
-    c.m2l_tgt.ensure(sizeof(int) * (size_t)std::max<int64_t>(n_m2l, 1));
-    if (n_m2l > 0) {
-        k_m2l_gather<<<cdiv(n_m2l, TPB), TPB, 0, s>>>(c.m2l_raw.as<int4>(), c.lval.as<uint32_t>(), n_m2l,
-                                                       c.m2l_src.as<int2>(), c.m2l_tgt.as<int>());
-        VFMM_LAUNCH_CHECK();
-    }
+    // ---- M2L CSR: only for the per-pair M2L (the batched plan reads the raw list) ----
+    c.m2l_csr = false;
+    if (!(c.prm.m2l_mode != 1 && c.prm.precision != VFMM_PRECISION_FP64)) build_m2l_csr(c);
     // ---- P2P CSR ----
     csr_by_target(c, c.p2p_raw.as<int4>(), n_p2p, c.p2p_off);
     c.p2p_ent.ensure(sizeof(int4) * (size_t)std::max<int64_t>(n_p2p, 1));

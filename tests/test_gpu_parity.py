@@ -205,7 +205,10 @@ def test_m2l_batched_matches_per_pair(name):
                     ax=a[:, 0].astype(np.float32), ay=a[:, 1].astype(np.float32), az=a[:, 2].astype(np.float32),
                     sigma=np.full(n, 0.005, np.float32), n=n)
         kw = dict(p=8, ncrit=32)
-    u0, d0 = run(case, m2l_mode=0, **kw)
+    u0, d0, ctx = run(case, ret_ctx=True, m2l_mode=2, **kw)
+    st = ctx.stats()
+    ctx.close()
+    assert st["m2l_groups"] > 0  # the batched kernel ran
     u1, d1 = run(case, m2l_mode=1, **kw)
     assert rel(u0, u1) <= 2e-6 and rel(d0, d1) <= 2e-6
 
