@@ -189,6 +189,41 @@ def test_ring_cloud(p, tol):
     assert eu <= tol and ed <= tol
 
 
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 129, 1000])
+def test_fmm_small_and_ragged_sizes(n):
+    """Sizes around the 64-target block and leaf boundaries, down to one
+    particle (whose velocity is exactly zero and whose stretching, the
+    rho = 0 self term alpha x q(0) alpha / (4 pi), vanishes up to float32
+    rounding of the parallel vectors)."""
+    case = wl.random_cloud(n, seed=30 + n, L=0.5, core=0.04)
+    ref = oracle.direct(case)
+    u, da = run(case, p=8, ncrit=16)
+    if n == 1:
+        a2 = float(np.sum(alpha_of(case) ** 2))
+        q0 = 4.0 / (3.0 * np.sqrt(np.pi)) / (2.0 * np.sqrt(2.0) * 0.04 ** 3)  # q(0) of Eq. (2)
+        assert np.all(u == 0)
+        assert np.abs(da).max() <= 1e-6 * a2 * q0 / (4 * np.pi)
+        return
+    assert rel(u, ref["u"]) <= 1e-4 and rel(da, ref["da_t"]) <= 1e-4
+
+
+def test_fmm_all_particles_coincide():
+    """Degenerate input: every particle at one point.  The tree stops at its
+    depth limit with one overfull leaf; u vanishes and dalpha is the
+    rho = 0 limit of Eq. (3), alpha_i x sum_j q(0) alpha_j / (4 pi)."""
+    n = 200
+    rng = np.random.default_rng(31)
+    a = rng.standard_normal((n, 3)) * 0.01
+    case = dict(x=np.full(n, 0.3, np.float32), y=np.full(n, -0.2, np.float32), z=np.full(n, 0.7, np.float32),
+                ax=a[:, 0].astype(np.float32), ay=a[:, 1].astype(np.float32), az=a[:, 2].astype(np.float32),
+                sigma=np.full(n, 0.05, np.float32), n=n)
+    ref = oracle.direct(case)
+    u, da = run(case, p=8, ncrit=32)
+    assert np.all(np.isfinite(u)) and np.all(np.isfinite(da))
+    assert np.abs(u).max() <= 1e-6 * np.abs(da).max()
+    assert rel(da, ref["da_t"]) <= 1e-5
+
+
 @pytest.mark.parametrize("name", ["turb32_periodic", "cluster_free"])
 def test_m2l_batched_matches_per_pair(name):
     """The operator-batched M2L and the per-pair M2L compute the same
