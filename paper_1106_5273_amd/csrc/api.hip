@@ -13,7 +13,7 @@ void Ctx::release_all() {
                       &c_start, &c_count, &c_parent, &c_child, &c_nchild, &c_level, &c_geo, &c_rad, &c_lo, &c_hi,
                       &c_tmp, &leaves, &frA, &frB, &tcnt, &m2l_raw, &p2p_raw, &lkey, &lkey2, &lval, &lval2,
                       &m2l_off, &m2l_src, &p2p_off, &p2p_ent, &blocks, &pairs64, &Mexp, &Lexp, &lat_op, &far_u,
-                      &far_da, &dsurf, &rk, &m2l_tgt, &mb_eq, &mb_flag, &mb_pos, &mb_kid, &mb_ukey,
+                      &far_da, &near, &dsurf, &rk, &m2l_tgt, &mb_eq, &mb_flag, &mb_pos, &mb_kid, &mb_ukey,
                       &mb_tab, &mb_bcells, &mb_ent, &mb_groups, &mb_blk, &mb_items, &mb_mr, &mb_partial, &mb_cls, &mb_cellbs, &mb_gcnt, &mb_gid, &mb_goff, &mb_gcur, &pid, &pbox, &poff, &tune_ref, &tune_out, &tune_part};
     for (DevBuf *b : bufs) b->release();
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
@@ -23,6 +23,14 @@ void Ctx::release_all() {
     if (ev_ok)
         for (auto &e : ev) (void)hipEventDestroy(e);
     ev_ok = false;
+    if (side) {
+        (void)hipStreamSynchronize(side);
+        (void)hipStreamDestroy(side);
+        side = nullptr;
+    }
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    ev_fork = ev_join = nullptr;
 }
 
 static bool supported_p(int p) { return p == 4 || p == 6 || p == 8 || p == 10 || p == 12; }
@@ -101,6 +109,15 @@ static void upload_lattice(Ctx &c) {
     c.lat_dbl = dbl;
 }
 
+static void ensure_side(Ctx &c) {
+    if (c.side) return;
+    // non-blocking so that it overlaps the library stream even when that is the
+    // legacy default stream; ordering comes from the fork/join events alone
+    VFMM_HIP(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
+    VFMM_HIP(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming));
+    VFMM_HIP(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
+}
+
 static void do_build(Ctx &c, int64_t n, const float *x, const float *y, const float *z, const float *sigma) {
     ensure_events(c);
     c.built = false;
@@ -153,6 +170,7 @@ static void do_build(Ctx &c, int64_t n, const float *x, const float *y, const fl
     if (!c.m2lb_ok && !c.m2l_csr) build_m2l_csr(c);  // the per-pair M2L runs instead
     far_prealloc(c);
     m2lb_prealloc(c);
+    if (c.prm.precision != VFMM_PRECISION_FP64) ensure_side(c);
     ++c.build_id;
     c.record(2 * PH_TRAVERSE + 1);
     c.record(2 * PH_NUM + 1);
@@ -175,9 +193,22 @@ static void do_evaluate(Ctx &c, int64_t n, const float *x, const float *y, const
         direct_all_pairs(c, x, y, z, ax, ay, az, sigma, ux, uy, uz, dax, day, daz);
     } else {
         gather_strengths(c, ax, ay, az, sigma);
-        if (c.prm.precision == VFMM_PRECISION_FP64) gather_records64(c, ax, ay, az);
-        far_field(c);
-        p2p_and_finalize(c, ux, uy, uz, dax, day, daz);
+        if (c.prm.precision == VFMM_PRECISION_FP64) {
+            gather_records64(c, ax, ay, az);
+            far_field(c);
+            p2p_and_finalize(c, ux, uy, uz, dax, day, daz);
+        } else {
+            // near field (VALU) on the side stream concurrently with the far
+            // field (M2L on the matrix cores) on the library stream
+            ensure_side(c);
+            VFMM_HIP(hipEventRecord(c.ev_fork, s));
+            VFMM_HIP(hipStreamWaitEvent(c.side, c.ev_fork, 0));
+            p2p_near(c, c.side);
+            far_field(c);
+            VFMM_HIP(hipEventRecord(c.ev_join, c.side));
+            VFMM_HIP(hipStreamWaitEvent(s, c.ev_join, 0));
+            finalize_near_far(c, ux, uy, uz, dax, day, daz);
+        }
     }
     c.record(2 * PH_NUM + 3);
     c.eval_timed = true;

@@ -84,6 +84,11 @@ struct Ctx {
     bool capturing = false;
     uint64_t build_id = 0, graph_build_id = 0;
 
+    // near field on a second stream, concurrent with the far field
+    hipStream_t side = nullptr;          // non-blocking, default priority; created on first use
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    DevBuf near;                         // float[6][n]: P2P u and dalpha in sorted order
+
     // timing
     hipEvent_t ev[2 * PH_NUM + 4] = {};
     bool ev_ok = false;
@@ -92,13 +97,15 @@ struct Ctx {
     bool build_timed = false, eval_timed = false;
 
     void release_all();
-    // records timing event i unless the stream is being captured into a graph
-    void record(int i) {
+    // records timing event i (on stream s, default the library stream) unless
+    // the stream is being captured into a graph
+    void record(int i, hipStream_t s) {
         if (ev_ok && !capturing) {
-            hipError_t e = hipEventRecord(ev[i], stream);
+            hipError_t e = hipEventRecord(ev[i], s);
             if (e != hipSuccess) throw Error{VFMM_EHIP, std::string("hipEventRecord: ") + hipGetErrorString(e)};
         }
     }
+    void record(int i) { record(i, stream); }
 };
 
 // tree.hip
@@ -108,6 +115,8 @@ void build_tree(Ctx &c, int64_t n, const float *x, const float *y, const float *
 void gather_strengths(Ctx &c, const float *ax, const float *ay, const float *az, const float *sigma);
 void gather_records64(Ctx &c, const float *ax, const float *ay, const float *az);
 void build_m2l_csr(Ctx &c);
+void p2p_near(Ctx &c, hipStream_t s);
+void finalize_near_far(Ctx &c, float *ux, float *uy, float *uz, float *dax, float *day, float *daz);
 void scan_excl_i32(Ctx &c, const int *in, int *out, int64_t n);  // out may alias in
 // traverse.hip
 void traverse_and_lists(Ctx &c);

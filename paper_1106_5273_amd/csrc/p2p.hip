@@ -54,6 +54,7 @@ struct P2PArgs {
     float inv3V;
     int surface;
     float *ux, *uy, *uz, *dax, *day, *daz;
+    float *near;  // non-null: write u and dalpha in sorted order to near[6][n] instead of finishing
 };
 
 struct Acc9 {
@@ -204,6 +205,15 @@ __global__ __launch_bounds__(256) void k_p2p(P2PConst k, P2PArgs A) {
     d1 = fmaf(-3.0f, S[7], d1);
     d2 = fmaf(-3.0f, S[8], d2);
     float u0 = S[0], u1 = S[1], u2 = S[2];
+    if (A.near) {
+        A.near[i] = u0;
+        A.near[A.n + i] = u1;
+        A.near[2 * A.n + i] = u2;
+        A.near[3 * A.n + i] = d0;
+        A.near[4 * A.n + i] = d1;
+        A.near[5 * A.n + i] = d2;
+        return;
+    }
     if (A.far_u) {
         u0 += A.far_u[i];
         u1 += A.far_u[A.n + i];
@@ -396,21 +406,81 @@ static P2PConst make_const(double sigma) {
 }
 
 template <int SCHEME, bool KAHAN>
-static void launch_p2p(Ctx &c, const P2PConst &k, const P2PArgs &A) {
+static void launch_p2p(const P2PConst &k, const P2PArgs &A, hipStream_t s) {
     if (A.nblocks == 0) return;
-    k_p2p<SCHEME, KAHAN><<<xcd_grid(cdiv(A.nblocks, 4)), 256, 0, c.stream>>>(k, A);
+    k_p2p<SCHEME, KAHAN><<<xcd_grid(cdiv(A.nblocks, 4)), 256, 0, s>>>(k, A);
     VFMM_LAUNCH_CHECK();
 }
 
-static void dispatch_p2p(Ctx &c, const P2PConst &k, const P2PArgs &A) {
+static void dispatch_p2p(Ctx &c, const P2PConst &k, const P2PArgs &A, hipStream_t s) {
     const bool kah = c.prm.kahan != 0 || c.prm.precision == VFMM_PRECISION_MIXED;
     if (c.prm.scheme == VFMM_SCHEME_TRANSPOSE) {
-        if (kah) launch_p2p<VFMM_SCHEME_TRANSPOSE, true>(c, k, A);
-        else launch_p2p<VFMM_SCHEME_TRANSPOSE, false>(c, k, A);
+        if (kah) launch_p2p<VFMM_SCHEME_TRANSPOSE, true>(k, A, s);
+        else launch_p2p<VFMM_SCHEME_TRANSPOSE, false>(k, A, s);
     } else {
-        if (kah) launch_p2p<VFMM_SCHEME_CLASSICAL, true>(c, k, A);
-        else launch_p2p<VFMM_SCHEME_CLASSICAL, false>(c, k, A);
+        if (kah) launch_p2p<VFMM_SCHEME_CLASSICAL, true>(k, A, s);
+        else launch_p2p<VFMM_SCHEME_CLASSICAL, false>(k, A, s);
     }
+}
+
+static P2PArgs tree_args(Ctx &c) {
+    P2PArgs A{};
+    A.rec = c.rec.as<float4>();
+    A.blocks = c.blocks.as<int4>();
+    A.ent = c.p2p_ent.as<int4>();
+    A.nblocks = c.n_blocks;
+    A.B = c.img_B;
+    A.len = c.prm.periodic ? (float)c.prm.box_len : 0.f;
+    A.n = c.n;
+    A.perm = c.perm.as<int>();
+    A.bounds = c.bres.as<Bounds>();
+    A.surface = (c.prm.periodic && c.prm.zero_mean) ? 1 : 0;
+    A.inv3V = c.prm.periodic ? (float)(1.0 / (3.0 * c.prm.box_len * c.prm.box_len * c.prm.box_len)) : 0.f;
+    return A;
+}
+
+// Near field alone, on stream s, into c.near (sorted order); the far field
+// runs meanwhile on the library stream and finalize_near_far adds the two.
+void p2p_near(Ctx &c, hipStream_t s) {
+    const P2PConst k = make_const(c.sigma_uniform);
+    c.near.ensure(sizeof(float) * 6 * (size_t)c.n);
+    P2PArgs A = tree_args(c);
+    A.near = c.near.as<float>();
+    c.record(2 * PH_P2P, s);
+    dispatch_p2p(c, k, A, s);
+    c.record(2 * PH_P2P + 1, s);
+}
+
+// out[perm[i]] = near[i] + far[i] (- the zero-mean surface term for u)
+__global__ __launch_bounds__(256) void k_finalize(P2PArgs A, const float *__restrict__ near) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= A.n) return;
+    const int64_t n = A.n;
+    float u0 = near[i] + A.far_u[i], u1 = near[n + i] + A.far_u[n + i], u2 = near[2 * n + i] + A.far_u[2 * n + i];
+    const float d0 = near[3 * n + i] + A.far_da[i], d1 = near[4 * n + i] + A.far_da[n + i],
+                d2 = near[5 * n + i] + A.far_da[2 * n + i];
+    if (A.surface) {
+        u0 -= (float)(A.bounds->sum_xa[0]) * A.inv3V;
+        u1 -= (float)(A.bounds->sum_xa[1]) * A.inv3V;
+        u2 -= (float)(A.bounds->sum_xa[2]) * A.inv3V;
+    }
+    const int o = A.perm[i];
+    A.ux[o] = u0;
+    A.uy[o] = u1;
+    A.uz[o] = u2;
+    A.dax[o] = d0;
+    A.day[o] = d1;
+    A.daz[o] = d2;
+}
+
+void finalize_near_far(Ctx &c, float *ux, float *uy, float *uz, float *dax, float *day, float *daz) {
+    P2PArgs A = tree_args(c);
+    A.far_u = c.far_u.as<float>();
+    A.far_da = c.far_da.as<float>();
+    A.ux = ux; A.uy = uy; A.uz = uz; A.dax = dax; A.day = day; A.daz = daz;
+    if (c.n == 0) return;
+    k_finalize<<<cdiv(c.n, 256), 256, 0, c.stream>>>(A, c.near.as<float>());
+    VFMM_LAUNCH_CHECK();
 }
 
 void p2p_and_finalize(Ctx &c, float *ux, float *uy, float *uz, float *dax, float *day, float *daz) {
@@ -452,7 +522,7 @@ void p2p_and_finalize(Ctx &c, float *ux, float *uy, float *uz, float *dax, float
     A.inv3V = c.prm.periodic ? (float)(1.0 / (3.0 * c.prm.box_len * c.prm.box_len * c.prm.box_len)) : 0.f;
     A.ux = ux; A.uy = uy; A.uz = uz; A.dax = dax; A.day = day; A.daz = daz;
     c.record(2 * PH_P2P);
-    dispatch_p2p(c, k, A);
+    dispatch_p2p(c, k, A, c.stream);
     c.record(2 * PH_P2P + 1);
 }
 
@@ -546,7 +616,7 @@ void direct_all_pairs(Ctx &c, const float *x, const float *y, const float *z, co
     c.n_blocks = nb;
     c.p2p_pairs = n * n;
     c.record(2 * PH_P2P);
-    dispatch_p2p(c, k, A);
+    dispatch_p2p(c, k, A, c.stream);
     c.record(2 * PH_P2P + 1);
 }
 
