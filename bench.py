@@ -344,6 +344,19 @@ def main():
 
     achieved = pairs * FLOPS_PER_PAIR / (p2p_ms * 1e-3) / 1e12
     traffic = traffic_from_profile(pairs)
+    # the same step on one stream: the P2P kernel alone on the GPU (informational;
+    # in the timed steps it shares the GPU with the far field's small kernels)
+    iso = {}
+    ctx1 = vf.Context(overlap=0, **params)
+    out1 = tuple(torch.empty(case["n"], dtype=torch.float32, device="cuda") for _ in range(6))
+    for _ in range(2):
+        ctx1.build(t[0], t[1], t[2], t[6])
+        ctx1.evaluate(*t, out=out1)
+    iso_ph = ctx1.timings()
+    ctx1.close()
+    iso_tf = pairs * FLOPS_PER_PAIR / (iso_ph["p2p_ms"] * 1e-3) / 1e12
+    iso = {"p2p_kernel_ms": iso_ph["p2p_ms"], "tflops": iso_tf, "frac": iso_tf / PEAK_FP32_VALU_TFLOPS,
+           "evaluate_ms": iso_ph["evaluate_ms"]}
     line = {
         "metric": METRIC,
         "value": pairs / (ms * 1e-3) / 1e9,
@@ -373,6 +386,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": traffic,
                      "kernel": "k_p2p", "flops_per_pair": FLOPS_PER_PAIR},
+        "p2p_single_stream": iso,
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)

@@ -30,7 +30,8 @@ class Params(ctypes.Structure):
                 ("sigma_gap", ctypes.c_float), ("periodic", ctypes.c_int32), ("images", ctypes.c_int32),
                 ("box_lo", ctypes.c_double * 3), ("box_len", ctypes.c_double), ("scheme", ctypes.c_int32),
                 ("kahan", ctypes.c_int32), ("zero_mean", ctypes.c_int32), ("direct", ctypes.c_int32),
-                ("m2l_mode", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("m2l_mode", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("overlap", ctypes.c_int32)]
 
 
 class Timings(ctypes.Structure):
@@ -92,7 +93,10 @@ class VfmmError(RuntimeError):
 def default_params(**kw):
     p = Params()
     _lib.vfmm_default_params(ctypes.byref(p))
+    names = {f for f, _ in Params._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError("unknown vfmm parameter %r" % k)
         if k == "box_lo":
             for d in range(3):
                 p.box_lo[d] = float(v[d])

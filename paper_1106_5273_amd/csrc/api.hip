@@ -45,6 +45,7 @@ static void validate(const vfmm_params &p) {
     if (p.m2l_mode < 0 || p.m2l_mode > 2) throw Error{VFMM_EINVAL, "m2l_mode must be 0, 1 or 2"};
     if (p.use_graph != 0 && p.use_graph != 1) throw Error{VFMM_EINVAL, "use_graph must be 0 or 1"};
     if (p.use_graph && p.direct) throw Error{VFMM_EINVAL, "use_graph needs the tree path (direct = 0)"};
+    if (p.overlap != 0 && p.overlap != 1) throw Error{VFMM_EINVAL, "overlap must be 0 or 1"};
     if (p.precision < VFMM_PRECISION_FP32 || p.precision > VFMM_PRECISION_FP64)
         throw Error{VFMM_EINVAL, "precision must be VFMM_PRECISION_FP32, _MIXED or _FP64"};
     if (p.periodic) {
@@ -170,7 +171,7 @@ static void do_build(Ctx &c, int64_t n, const float *x, const float *y, const fl
     if (!c.m2lb_ok && !c.m2l_csr) build_m2l_csr(c);  // the per-pair M2L runs instead
     far_prealloc(c);
     m2lb_prealloc(c);
-    if (c.prm.precision != VFMM_PRECISION_FP64) ensure_side(c);
+    if (c.prm.precision != VFMM_PRECISION_FP64 && c.prm.overlap) ensure_side(c);
     ++c.build_id;
     c.record(2 * PH_TRAVERSE + 1);
     c.record(2 * PH_NUM + 1);
@@ -193,8 +194,8 @@ static void do_evaluate(Ctx &c, int64_t n, const float *x, const float *y, const
         direct_all_pairs(c, x, y, z, ax, ay, az, sigma, ux, uy, uz, dax, day, daz);
     } else {
         gather_strengths(c, ax, ay, az, sigma);
-        if (c.prm.precision == VFMM_PRECISION_FP64) {
-            gather_records64(c, ax, ay, az);
+        if (c.prm.precision == VFMM_PRECISION_FP64 || !c.prm.overlap) {
+            if (c.prm.precision == VFMM_PRECISION_FP64) gather_records64(c, ax, ay, az);
             far_field(c);
             p2p_and_finalize(c, ux, uy, uz, dax, day, daz);
         } else {
@@ -395,6 +396,7 @@ void vfmm_default_params(vfmm_params *p) {
     p->direct = 0;
     p->m2l_mode = 0;
     p->use_graph = 0;
+    p->overlap = 1;
 }
 
 vfmm_status vfmm_create(const vfmm_params *params, void *hip_stream, vfmm_ctx **out) {

@@ -8,16 +8,19 @@
 // a real (P+1)^2 x (P+1)^2 matrix T acting on (Re, Im) of Mt and producing
 // (Re, Im) rows of Lt:
 //   Lt_k^l = (-1)^{k+l} (s_A/s_B)^{k+1} sum_{n,m} Mt_n^m I_{n+k}^{m-l}((c_A - c_B)/s_B).
-// Target cells are grouped in blocks of 64 consecutive cells of one level and
-// the list entries sorted by (block, key).  A work-group (three waves, one
-// per potential) takes a block and, key by key, builds that key's matrix T in
-// LDS from the key's irregular harmonics (a few per cent of the work), then
-// multiplies it into the 64 targets' accumulators with FP32 matrix-core
-// instructions (v_mfma_f32_16x16x4f32): per wave a [rows x inputs] x
-// [inputs x 64 targets] product with B-fragments gathered from the sources'
-// multipoles.  No operator table leaves the chip.  Work items hold at most
-// ITEM_GROUPS keys of a block; their partial sums are added back per block in
-// a fixed order, so results are bit-reproducible.
+// Plan (once per tree): the distinct keys are numbered and each key's matrix
+// is built into an HBM table in MFMA operand order (k_m2lb_optab).  Target
+// cells are cut into blocks of 64 cells of one level and one octant class
+// (cells whose position in their parent, and in their grandparent where the
+// level is large enough, agree), so that the 64 targets of a block share
+// almost all of their keys; the translations are grouped by (block, key) by
+// counting.  Evaluation: a work-group of four waves takes up to ITEM_GROUPS
+// keys of one block; each wave holds its operator rows in registers, the
+// group stages the source multipoles of the 64 target slots in LDS, and the
+// products [rows x inputs] x [inputs x 64 targets] run on FP32 matrix-core
+// instructions (v_mfma_f32_16x16x4f32).  Partial sums of the work items are
+// added per block in item order, so results are bit-reproducible.  Trees
+// whose groups stay sparse (irregular particle sets) use the per-pair M2L.
 #include <algorithm>
 #include <utility>
 
@@ -755,10 +758,9 @@ static void m2lb_run_p(Ctx &c) {
     VFMM_LAUNCH_CHECK();
     c.mb_partial.ensure(sizeof(float) * (size_t)c.mb_nitems * 3 * R * 64);
     const size_t lds = m2lb_lds_bytes<P>();
-    static bool attr_set = false;
-    if (!attr_set) {
+    if (c.m2lb_lds_set < (int)lds) {  // once per context (a context lives on one device)
         VFMM_HIP(hipFuncSetAttribute((const void *)k_m2lb<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        attr_set = true;
+        c.m2lb_lds_set = (int)lds;
     }
     k_m2lb<P><<<xcd_grid(c.mb_nitems), 256, lds, s>>>(c.mb_items.as<int4>(), c.mb_groups.as<int4>(),
                                                        c.mb_ent.as<int2>(), c.mb_mr.as<float>(),

@@ -1,6 +1,9 @@
 // Near field P2P (Sec. 3.1, Sec. 3.6) of the regularised Biot-Savart law and
-// the stretching term, Eqs. (1)-(3), fused with the far-field sum and the
-// scatter back to the caller's order.
+// the stretching term, Eqs. (1)-(3).  The tree path writes the near-field
+// results in sorted order and a finalize kernel adds the far field and
+// scatters to the caller's order (the near field runs concurrently with the
+// far field on a second stream); the float64 form and the direct mode finish
+// in the P2P kernel itself.
 //
 // Work item: one wave64 per block of <= 64 targets (one target per lane) of a
 // leaf; the wave walks the leaf's P2P list.  Source particles are the same
@@ -144,18 +147,40 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
     s = t;
 }
 
-template <int SCHEME, bool KAHAN>
-__global__ __launch_bounds__(256) void k_p2p(P2PConst k, P2PArgs A) {
+// Blocks of few targets split the wave into SPLIT lane groups of 64/SPLIT
+// lanes that each hold every target of the block and take every SPLIT-th
+// source (the group's source is selected per lane from the SPLIT records
+// fetched together); the groups' sums are added at the end.  A missing last
+// source gets zero strength, which contributes exactly zero.
+template <int V, int SCHEME, int SPLIT>
+__device__ __forceinline__ void leaf_loop_split(const P2PConst &k, const float4 *__restrict__ rec, int s0, int cnt,
+                                                int grp, float xi, float yi, float zi, float ai0, float ai1,
+                                                float ai2, Acc9 &p) {
+    const float4 *src = rec + 2 * (size_t)s0;
+    for (int j = 0; j < cnt; j += SPLIT) {
+        float4 mp = src[2 * j], ma = src[2 * j + 1];
+#pragma unroll
+        for (int t = 1; t < SPLIT; ++t) {
+            const int jj = min(j + t, cnt - 1);
+            const float4 sp = src[2 * jj];
+            float4 sa = src[2 * jj + 1];
+            if (j + t >= cnt) sa = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (grp == t) {
+                mp = sp;
+                ma = sa;
+            }
+        }
+        pair<V, SCHEME>(k, xi, yi, zi, ai0, ai1, ai2, mp, ma, p);
+    }
+}
+
+template <int SCHEME, bool KAHAN, int SPLIT>
+__device__ __forceinline__ void p2p_block(const P2PConst &k, const P2PArgs &A, int t0, int tc, int l0, int lc) {
     const int lane = threadIdx.x & 63;
-    const int b = xcd_logical(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
-    if (b >= A.nblocks) return;
-    const int4 blk = A.blocks[b];
-    const int t0 = __builtin_amdgcn_readfirstlane(blk.x);
-    const int tc = __builtin_amdgcn_readfirstlane(blk.y);
-    const int l0 = __builtin_amdgcn_readfirstlane(blk.z);
-    const int lc = __builtin_amdgcn_readfirstlane(blk.w);
-    const bool valid = lane < tc;
-    const int i = t0 + (valid ? lane : 0);
+    constexpr int GL = 64 / SPLIT;  // lanes per group
+    const int tl = lane % GL, grp = lane / GL;
+    const bool valid = tl < tc;
+    const int i = t0 + (valid ? tl : 0);
     const float4 xp = A.rec[2 * (size_t)i];
     const float4 xa = A.rec[2 * (size_t)i + 1];
     const float fp = 12.566370614359172f;  // 4 pi: stored strengths are alpha/(4 pi)
@@ -174,12 +199,21 @@ __global__ __launch_bounds__(256) void k_p2p(P2PConst k, P2PArgs A) {
         const float shz = (float)(img / (W * W) - A.B) * A.len;
         const float xi = xp.x - shx, yi = xp.y - shy, zi = xp.z - shz;
         Acc9 p = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-        if (var == 1)
-            leaf_loop<1, SCHEME>(k, A.rec, s0, sc, xi, yi, zi, ai0, ai1, ai2, p);
-        else if (var == 0)
-            leaf_loop<0, SCHEME>(k, A.rec, s0, sc, xi, yi, zi, ai0, ai1, ai2, p);
-        else
-            leaf_loop<2, SCHEME>(k, A.rec, s0, sc, xi, yi, zi, ai0, ai1, ai2, p);
+        if (SPLIT == 1) {
+            if (var == 1)
+                leaf_loop<1, SCHEME>(k, A.rec, s0, sc, xi, yi, zi, ai0, ai1, ai2, p);
+            else if (var == 0)
+                leaf_loop<0, SCHEME>(k, A.rec, s0, sc, xi, yi, zi, ai0, ai1, ai2, p);
+            else
+                leaf_loop<2, SCHEME>(k, A.rec, s0, sc, xi, yi, zi, ai0, ai1, ai2, p);
+        } else {
+            if (var == 1)
+                leaf_loop_split<1, SCHEME, SPLIT>(k, A.rec, s0, sc, grp, xi, yi, zi, ai0, ai1, ai2, p);
+            else if (var == 0)
+                leaf_loop_split<0, SCHEME, SPLIT>(k, A.rec, s0, sc, grp, xi, yi, zi, ai0, ai1, ai2, p);
+            else
+                leaf_loop_split<2, SCHEME, SPLIT>(k, A.rec, s0, sc, grp, xi, yi, zi, ai0, ai1, ai2, p);
+        }
         const float pv[9] = {p.u0, p.u1, p.u2, p.a0, p.a1, p.a2, p.t0, p.t1, p.t2};
         if (KAHAN) {
 #pragma unroll
@@ -189,7 +223,15 @@ __global__ __launch_bounds__(256) void k_p2p(P2PConst k, P2PArgs A) {
             for (int q = 0; q < 9; ++q) S[q] += pv[q];
         }
     }
-    if (!valid) return;
+    if (SPLIT > 1) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            if (KAHAN) S[q] -= Cc[q];
+            S[q] += __shfl_xor(S[q], 32, 64);
+            if (SPLIT > 2) S[q] += __shfl_xor(S[q], 16, 64);
+        }
+    }
+    if (!valid || grp != 0) return;
     // dalpha = alpha_i x A - 3 T (transpose) or A x alpha_i - 3 T (classical)
     float d0, d1, d2;
     if (SCHEME == VFMM_SCHEME_TRANSPOSE) {
@@ -234,6 +276,23 @@ __global__ __launch_bounds__(256) void k_p2p(P2PConst k, P2PArgs A) {
     A.dax[o] = d0;
     A.day[o] = d1;
     A.daz[o] = d2;
+}
+
+template <int SCHEME, bool KAHAN>
+__global__ __launch_bounds__(256) void k_p2p(P2PConst k, P2PArgs A) {
+    const int b = xcd_logical(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    if (b >= A.nblocks) return;
+    const int4 blk = A.blocks[b];
+    const int t0 = __builtin_amdgcn_readfirstlane(blk.x);
+    const int tc = __builtin_amdgcn_readfirstlane(blk.y);
+    const int l0 = __builtin_amdgcn_readfirstlane(blk.z);
+    const int lc = __builtin_amdgcn_readfirstlane(blk.w);
+    if (tc <= 16)
+        p2p_block<SCHEME, KAHAN, 4>(k, A, t0, tc, l0, lc);
+    else if (tc <= 32)
+        p2p_block<SCHEME, KAHAN, 2>(k, A, t0, tc, l0, lc);
+    else
+        p2p_block<SCHEME, KAHAN, 1>(k, A, t0, tc, l0, lc);
 }
 
 // ---------------------------------------------------------------------------

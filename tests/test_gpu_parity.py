@@ -305,6 +305,35 @@ def test_periodic_taylor_green_closed_form():
     assert rel(u, us) <= 1e-4 and rel(da, das) <= 1e-4
 
 
+def test_periodic_off_lattice_matches_fourier_series():
+    """Periodic sum for particles off the lattice: a random zero-mean cloud in
+    the cube against the exact zero-mean Fourier series evaluated at every
+    particle (sigma = 0.5 makes the series converge by |m| <= 18)."""
+    case = wl.random_cloud(300, seed=41, L=2 * np.pi, core=0.5, zero_mean=True, periodic=True)
+    us, Js = oracle.fourier_points(case, 2 * np.pi, kmax=18)
+    das, _ = oracle.stretching(Js, alpha_of(case))
+    u, da = run(case, p=10, ncrit=16, periodic=1, box_len=2 * np.pi, images=6)
+    eu, ed = rel(u, us), rel(da, das)
+    print("off-lattice periodic cloud: rel-L2 u %.3e dalpha %.3e" % (eu, ed))
+    assert eu <= 1e-4 and ed <= 1e-4
+
+
+def test_sigma_gap_controls_far_field_error(tg32_ref):
+    """The M2L test's core gap (D - R_A - R_B >= c sigma): the far field uses
+    the singular kernel, so accepting cells whose cores overlap leaves an
+    error of the size of the missing cutoff, which falls as c grows.  (At
+    theta = 0.5 the MAC alone already keeps leaf pairs about 4.6 sigma apart
+    for this lattice; theta = 0.8 lets them come within about 1.2 sigma.)"""
+    case, ref = tg32_ref
+    errs = {}
+    for gap in (0.0, 2.0, 5.0):
+        u, da = run(case, p=10, theta=0.8, sigma_gap=gap)
+        errs[gap] = (rel(u, ref["u"]), rel(da, ref["da_t"]))
+        print("C1 sigma_gap %.0f: rel-L2 u %.3e dalpha %.3e" % (gap, *errs[gap]))
+    assert errs[0.0][1] > errs[2.0][1] > errs[5.0][1]
+    assert errs[5.0][0] <= 1e-4 and errs[5.0][1] <= 1e-4
+
+
 def test_periodic_turbulence_images_sweep():
     case = wl.turbulence_case(32, seed=21)
     us, Js = oracle.spectral_lattice(case)
@@ -347,6 +376,16 @@ def test_bitwise_deterministic():
         torch.cuda.synchronize()
     for x, y in zip(a, b):
         assert torch.equal(x, y)
+
+
+def test_overlap_off_gives_identical_results():
+    """The near field on its own stream (overlap = 1) and the single-stream
+    evaluation (overlap = 0) produce bitwise the same outputs."""
+    case = wl.turbulence_case(32, seed=6)
+    kw = dict(p=8, periodic=1, box_len=2 * np.pi, images=3)
+    u1, d1 = run(case, overlap=1, **kw)
+    u0, d0 = run(case, overlap=0, **kw)
+    assert np.array_equal(u1, u0) and np.array_equal(d1, d0)
 
 
 def test_outputs_follow_input_order():
