@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--kahan", type=int, default=0)
     ap.add_argument("--no-check", action="store_true", help="skip the accuracy check against the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-overlap-pass", action="store_true",
+                    help="skip the extra timing of the two-stream (overlap = 1) step (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
                     help="c2: 128^3 periodic step (default, the headline line); c3: 256^3 float32 vs "
@@ -259,6 +261,26 @@ def bench_precision(args, vf, wl):
     print(json.dumps(line), flush=True)
 
 
+def _time_overlap(ctx1, t, case, args, pairs):
+    """Time the same steps with the near field on its own stream beside the far field."""
+    import torch
+    out1 = tuple(torch.empty(case["n"], dtype=torch.float32, device="cuda") for _ in range(6))
+    for _ in range(max(1, args.warmup)):
+        ctx1.build(t[0], t[1], t[2], t[6])
+        ctx1.evaluate(*t, out=out1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx1.build(t[0], t[1], t[2], t[6])
+        ctx1.evaluate(*t, out=out1)
+    torch.cuda.synchronize()
+    ms1 = (time.perf_counter() - t1) * 1e3 / args.steps
+    ph = ctx1.timings()
+    ctx1.close()
+    return {"ms_per_step": ms1, "gpair_s": pairs / (ms1 * 1e-3) / 1e9, "p2p_interval_ms": ph["p2p_ms"],
+            "evaluate_ms": ph["evaluate_ms"]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -346,22 +368,10 @@ def main():
     traffic = traffic_from_profile(pairs)
     # the same steps with the near field on a second stream beside the far field
     # (overlap = 1, informational: the P2P kernel then shares the GPU)
-    ctx1 = vf.Context(overlap=1, **params)
-    out1 = tuple(torch.empty(case["n"], dtype=torch.float32, device="cuda") for _ in range(6))
-    for _ in range(max(1, args.warmup)):
-        ctx1.build(t[0], t[1], t[2], t[6])
-        ctx1.evaluate(*t, out=out1)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        ctx1.build(t[0], t[1], t[2], t[6])
-        ctx1.evaluate(*t, out=out1)
-    torch.cuda.synchronize()
-    ms1 = (time.perf_counter() - t1) * 1e3 / args.steps
-    ov_ph = ctx1.timings()
-    ctx1.close()
-    ov = {"ms_per_step": ms1, "gpair_s": pairs / (ms1 * 1e-3) / 1e9, "p2p_interval_ms": ov_ph["p2p_ms"],
-          "evaluate_ms": ov_ph["evaluate_ms"]}
+    ov = None
+    ctx1 = None if args.no_overlap_pass else vf.Context(overlap=1, **params)
+    if ctx1 is not None:
+        ov = _time_overlap(ctx1, t, case, args, pairs)
     line = {
         "metric": METRIC,
         "value": pairs / (ms * 1e-3) / 1e9,
