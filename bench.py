@@ -20,9 +20,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "FMM step time & P2P Gpair-interactions/s at 128^3 particles, p=10, ≤1e-4 err"
-PEAK_FP32_VALU_TFLOPS = 157.3        # published FP32 vector peak of MI355X (256 CU, 2.4 GHz); the non-packed
-                                      # v_fmac_f32 rate measured by --microbench reaches 87% of it
-FLOPS_PER_PAIR = 71                   # gfx950 ISA of the P2P pair body (s >= 1 form): 25 FMA + 16 MUL + 3 SUB + 2 TRANS, FMA = 2
+PEAK_FP32_VALU_TFLOPS = 157.3        # published FP32 vector peak of MI355X (256 CU, 2.4 GHz); non-packed FMA with
+                                      # vector-register operands reaches 84-94% of it, with a scalar operand half that
+FLOPS_PER_PAIR = 65                   # gfx950 ISA of the P2P pair body (s >= 1 form): 25 FMA + 10 MUL + 3 SUB + 2 TRANS, FMA = 2
 PAPER_FLOPS_PER_PAIR = 174            # Table 1 convention (70 + 104)
 
 

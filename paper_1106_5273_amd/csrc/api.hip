@@ -12,7 +12,7 @@ void Ctx::release_all() {
     DevBuf *bufs[] = {&bpart, &bres, &keyA, &keyB, &valA, &valB, &hist, &scanA, &scanB, &scanC, &perm, &rec, &rec64,
                       &c_start, &c_count, &c_parent, &c_child, &c_nchild, &c_level, &c_geo, &c_rad, &c_lo, &c_hi,
                       &c_tmp, &leaves, &frA, &frB, &tcnt, &m2l_raw, &p2p_raw, &lkey, &lkey2, &lval, &lval2,
-                      &m2l_off, &m2l_src, &p2p_off, &p2p_ent, &blocks, &pairs64, &Mexp, &Lexp, &lat_op, &far_u,
+                      &m2l_off, &m2l_src, &p2p_off, &p2p_ent, &p2p_sh, &recp, &blocks, &pairs64, &Mexp, &Lexp, &lat_op, &far_u,
                       &far_da, &near, &dsurf, &rk, &m2l_tgt, &mb_eq, &mb_flag, &mb_pos, &mb_kid, &mb_ukey,
                       &mb_tab, &mb_bcells, &mb_ent, &mb_groups, &mb_blk, &mb_items, &mb_mr, &mb_partial, &mb_cls, &mb_cellbs, &mb_gcnt, &mb_gid, &mb_goff, &mb_gcur, &pid, &pbox, &poff, &tune_ref, &tune_out, &tune_part};
     for (DevBuf *b : bufs) b->release();
@@ -194,6 +194,7 @@ static void do_evaluate(Ctx &c, int64_t n, const float *x, const float *y, const
         direct_all_pairs(c, x, y, z, ax, ay, az, sigma, ux, uy, uz, dax, day, daz);
     } else {
         gather_strengths(c, ax, ay, az, sigma);
+        if (c.prm.precision != VFMM_PRECISION_FP64) p2p_prepare(c);
         if (c.prm.precision == VFMM_PRECISION_FP64 || !c.prm.overlap) {
             if (c.prm.precision == VFMM_PRECISION_FP64) gather_records64(c, ax, ay, az);
             far_field(c);

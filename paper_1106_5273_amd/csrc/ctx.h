@@ -40,6 +40,7 @@ struct Ctx {
     DevBuf pid, pbox, poff;              // batched problems: id per particle, root cubes, offsets
     DevBuf rec;                          // float4[2n]: (x,y,z,sigma) (ax,ay,az,0)/(4 pi)
     DevBuf rec64;                        // double4[2n]: the same records, float64 form only
+    DevBuf recp;                         // float4[3n]: float32 near-field records (scaled, leaf-local)
     // cells
     DevBuf c_start, c_count, c_parent, c_child, c_nchild, c_level;  // int
     DevBuf c_geo;                        // float4 (cx, cy, cz, size)
@@ -55,6 +56,7 @@ struct Ctx {
     DevBuf m2l_off, m2l_src;             // CSR by target cell: int offsets[ncells+1], int2 (src, img)
     DevBuf m2l_tgt;                      // target cell of each CSR entry
     DevBuf p2p_off, p2p_ent;             // CSR by target cell: int offsets, int4 (start, count, img, variant)
+    DevBuf p2p_sh;                       // float4 per P2P entry: scaled offset between the two leaf centres
     DevBuf blocks;                       // int4 (tgt start, tgt count, list off, list count)
     DevBuf pairs64;                      // int64 reduction scratch
     // expansions
@@ -116,6 +118,7 @@ void build_tree(Ctx &c, int64_t n, const float *x, const float *y, const float *
 void gather_strengths(Ctx &c, const float *ax, const float *ay, const float *az, const float *sigma);
 void gather_records64(Ctx &c, const float *ax, const float *ay, const float *az);
 void build_m2l_csr(Ctx &c);
+void p2p_prepare(Ctx &c);
 void p2p_near(Ctx &c, hipStream_t s);
 void finalize_near_far(Ctx &c, float *ux, float *uy, float *uz, float *dax, float *day, float *daz);
 void scan_excl_i32(Ctx &c, const int *in, int *out, int64_t n);  // out may alias in
@@ -133,6 +136,10 @@ void p2p_and_finalize(Ctx &c, float *ux, float *uy, float *uz, float *dax, float
 void direct_all_pairs(Ctx &c, const float *x, const float *y, const float *z, const float *ax,
                       const float *ay, const float *az, const float *sigma, float *ux, float *uy,
                       float *uz, float *dax, float *day, float *daz);
+// Scale of the float32 near field: lengths times kappa = log2(e)^(1/2) / (sqrt 2 sigma)
+// turn the Gaussian e^{-rho^2/(2 sigma^2)} into 2^{-rho'^2}; a = (2/sqrt pi) ln(2)^(1/2).
+inline double p2p_kappa(double sigma) { return std::sqrt(1.0 / std::log(2.0)) / (std::sqrt(2.0) * sigma); }
+inline double p2p_cutoff_a() { return 2.0 / std::sqrt(M_PI) * std::sqrt(std::log(2.0)); }
 // lattice_host.cpp
 void lattice_operator_host(int p, int K, std::vector<double> &op);
 

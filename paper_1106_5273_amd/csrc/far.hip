@@ -569,7 +569,10 @@ static void far_prealloc_p(Ctx &c) {
     c.far_u.ensure(rs * 3 * (size_t)c.n);
     c.far_da.ensure(rs * 3 * (size_t)c.n);
     if (c.prm.precision == VFMM_PRECISION_FP64) c.rec64.ensure(sizeof(double4) * 2 * (size_t)c.n);
-    else c.near.ensure(sizeof(float) * 6 * (size_t)c.n);
+    else {
+        c.near.ensure(sizeof(float) * 6 * (size_t)c.n);
+        c.recp.ensure(sizeof(float4) * 3 * (size_t)c.n);
+    }
 }
 
 void far_prealloc(Ctx &c) {

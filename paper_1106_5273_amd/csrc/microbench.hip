@@ -1,7 +1,9 @@
 // VALU rate microbenchmarks for the roofline of the P2P and M2L kernels:
-// independent chains of float32 FMA (with a vector or a scalar operand),
-// v_exp_f32 and v_rsq_f32, timed with HIP events.  Built into its own small
-// library (libvfmm_mb.so); not part of the vfmm C ABI.
+// independent chains of float32 FMA (v_fmac_f32 with vector-register
+// operands only, or with one scalar-register operand; the instruction is
+// written out so that the compiler cannot pick another form), v_exp_f32 and
+// v_rsq_f32, timed with HIP events.  Built into its own small library
+// (libvfmm_mb.so); not part of the vfmm C ABI.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -14,15 +16,16 @@ template <int KIND>
 __global__ __launch_bounds__(256) void k_rate(float *out, int iters, float a, float b) {
     float v[CH];
     for (int i = 0; i < CH; ++i) v[i] = (float)(threadIdx.x + i) * 1e-3f;
-    const float sa = __builtin_amdgcn_readfirstlane(a);
-    const float vb = b + (float)threadIdx.x * 1e-9f;  // per-lane multiplier
+    const float sa = a;                                // kernel argument: a scalar register
+    const float va = a + (float)threadIdx.x * 1e-9f;  // per-lane values
+    const float vb = b + (float)threadIdx.x * 1e-9f;
     for (int it = 0; it < iters; ++it) {
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
 #pragma unroll
             for (int i = 0; i < CH; ++i) {
-                if (KIND == 0) v[i] = fmaf(v[i], vb, 1e-7f);                         // vector operands
-                if (KIND == 1) v[i] = fmaf(v[i], sa, 1e-7f);                         // scalar operand
+                if (KIND == 0) asm volatile("v_fmac_f32_e32 %0, %1, %2" : "+v"(v[i]) : "v"(va), "v"(vb));
+                if (KIND == 1) asm volatile("v_fmac_f32_e32 %0, %1, %2" : "+v"(v[i]) : "s"(sa), "v"(vb));
                 if (KIND == 2) v[i] = __builtin_amdgcn_exp2f(v[i]);
                 if (KIND == 3) v[i] = __builtin_amdgcn_rsqf(v[i]);
             }

@@ -1,9 +1,9 @@
 // Near field P2P (Sec. 3.1, Sec. 3.6) of the regularised Biot-Savart law and
 // the stretching term, Eqs. (1)-(3).  The tree path writes the near-field
 // results in sorted order and a finalize kernel adds the far field and
-// scatters to the caller's order (the near field runs concurrently with the
-// far field on a second stream); the float64 form and the direct mode finish
-// in the P2P kernel itself.
+// scatters to the caller's order (or, with the near field on a second
+// stream, into a buffer that the finalize kernel adds); the float64 form and
+// the direct mode finish in the P2P kernel itself.
 //
 // Work item: one wave64 per block of <= 64 targets (one target per lane) of a
 // leaf; the wave walks the leaf's P2P list.  Source particles are the same
@@ -13,42 +13,56 @@
 // source leaf and then added to the running total (blocked summation, with an
 // optional compensated add).
 //
-// Per pair, with r = x_i - x_j, s = |r| / (sqrt 2 sigma), x = s^2, and
-// alpha~ = alpha/(4 pi) stored in the records:
-//   q alpha_j       = F alpha~_j,        F = P(3/2, x) / rho^3
-//   (q'/rho) alpha_j = -3 H alpha~_j,    H = P(5/2, x) / rho^5
-// where P(a, x) is the regularised lower incomplete gamma function: P(3/2, x)
-// is the cutoff g of Eq. (2), and P(5/2, x) = g - 4 s^3 e^{-x} / (3 sqrt pi).
-//   u_i       += F (alpha~_j x r)
-//   A_i       += F alpha~_j                     (alpha_i x A_i = sum q alpha_i x alpha_j)
-//   T_i       += H (alpha_i . (alpha~_j x r)) r  (transpose reading of Eq. (3))
-//   dalpha_i   = alpha_i x A_i - 3 T_i
+// Scaled, leaf-local coordinates.  With c = 1/(sqrt 2 sigma) and
+// lambda = log2 e, lengths are multiplied by kappa = c sqrt(lambda), so that
+// e^{-x} = 2^{-r'^2} for x = (rho/(sqrt 2 sigma))^2 and the Gaussian needs no
+// argument scaling.  Each particle's record holds its offset from the centre
+// of its own leaf, delta' = kappa (x - c_leaf), and each list entry holds the
+// offset between the two leaves, D' = kappa (c_t - c_s - image shift), so
+// that r' = (delta'_i + D') - delta'_j = y_i - delta'_j is formed from small
+// numbers.  Strengths are stored as ah = kappa^3 a alpha/(4 pi) with
+// a = (2/sqrt pi)/sqrt(lambda), together with bh = ah x delta'.
+//
+// Per pair, with E = 2^{-r2'} and rho' = |r'|:
+//   G3 = 1/a - E (rho' + (1/rho') pe(1/rho'))      = P(3/2, x) / a
+//   G5 = G3 - E b rho'^3,  b = 2/(3 lambda)         = P(5/2, x) / a
+//   Fh = G3 / rho'^3,  Hh = G5 / rho'^5
+// where pe is the erfcx fit rescaled to 1/rho' and P(a, x) is the regularised
+// lower incomplete gamma function (P(3/2, x) is the cutoff g of Eq. (2)).
+// Then, in physical units, q alpha_j x r = Fh (ah_j x r') / kappa and
+// (q'/rho)(alpha_i . (alpha_j x r)) r = -3 Hh (alpha_i . (ah_j x r')) r', and
+//   transpose reading of Eq. (3):
+//     Ah += Fh ah_j,  Bh += Fh bh_j,  T += Hh d r',
+//     d = alpha_i . (ah_j x r') = ah_j . (y_i x alpha_i) - alpha_i . bh_j,
+//     and per source leaf  U += Ah x y_i - Bh  (= sum Fh ah_j x r');
+//   classical reading: U += Fh (ah_j x r'), Ah += Fh ah_j,
+//     T += Hh (alpha_i . r') (ah_j x r');
+//   u_i = U / kappa,  dalpha_i = alpha_i x Ah - 3 T  (or Ah x alpha_i - 3 T).
 // Three forms of the cutoff, chosen per source leaf from the leaf boxes:
-//   full : some pair may have s < 1: Kummer series for s < 1, erfc form else;
-//   mid  : every pair has s >= 1: 1 - P = e^{-x} (erfcx(s) + ...), no branch;
-//   sing : the float32 cutoff is 1 for every pair (s >= 5.1): F = rho^-3.
+//   full : some pair may have s < 1: Kummer series for s < 1, the erfcx form else;
+//   mid  : every pair has s >= 1: the erfcx form, no branch;
+//   sing : the float32 cutoff is 1 for every pair (s >= 5.1): G3 = G5 = 1/a.
 #include "ctx.h"
 #include "cutoff_fits.h"
 
 namespace vfmm {
 
 struct P2PConst {
-    float kE;        // -log2(e) / (2 sigma^2): e^{-x} = exp2(r2 kE)
-    float kS;        // 2 c / sqrt(pi), c = 1/(sqrt 2 sigma): (2/sqrt pi) s = rho kS
-    float kU;        // 1/c: 1/s = rinv kU
-    float t5;        // 2 c^2 / 3: (4/(3 sqrt pi)) s^3 = r2 t5 * rho kS
-    float K3;        // c^3 4/(3 sqrt pi): P(3/2,x)/rho^3 -> K3 at rho = 0
-    float r2_small;  // 2 sigma^2 (s < 1 <=> r2 < r2_small)
-    float q[VFMM_M2_DEG + 1];  // c^5 8/(15 sqrt pi) * M2 coefficients, in powers of r2
+    float inv_a;     // 1/a
+    float b;         // 2/(3 lambda)
+    float K3;        // series form: Fh at r = 0 is K3 (times E)
+    float r2_small;  // s < 1  <=>  r2' < r2_small
+    float inv_kappa; // u = U / kappa
+    float pe[VFMM_ERFCX_DEG + 1];  // erfcx fit in powers of 1/rho', divided by a
+    float q[VFMM_M2_DEG + 1];      // series: Hh = E sum q_k r2'^k,  Fh = E (K3 + r2' sum q_k r2'^k)
 };
 
 struct P2PArgs {
-    const float4 *__restrict__ rec;
+    const float4 *__restrict__ rec;  // float4[3n]: (delta', alpha_x) (ah, alpha_y) (bh, alpha_z)
     const int4 *__restrict__ blocks;
     const int4 *__restrict__ ent;
+    const float4 *__restrict__ sh;   // per entry: (D', 0)
     int nblocks;
-    int B;
-    float len;
     const float *__restrict__ far_u;
     const float *__restrict__ far_da;
     int64_t n;
@@ -64,61 +78,86 @@ struct Acc9 {
     float u0, u1, u2, a0, a1, a2, t0, t1, t2;
 };
 
-template <int V, int SCHEME>
-__device__ __forceinline__ void pair(const P2PConst &k, float xi, float yi, float zi, float ai0, float ai1, float ai2,
-                                     float4 sp, float4 sa, Acc9 &p) {
-    const float dx = xi - sp.x, dy = yi - sp.y, dz = zi - sp.z;
+// Target-side quantities for one list entry.
+struct Tgt {
+    float y0, y1, y2;     // y_i = delta'_i + D'
+    float w0, w1, w2;     // y_i x alpha_i (transpose reading)
+    float ai0, ai1, ai2;  // alpha_i
+};
+
+// On gfx950 an FP32 VALU operation that reads a scalar register issues at
+// half the rate of one whose operands are all vector registers (measured:
+// 38.7e12 against 66-74e12 lane operations/s).  The loop-invariant constants
+// of the cutoff are therefore held in vector registers.  The source records
+// stay scalar operands: copying them into vector registers every step costs
+// more issue slots than it saves.
+__device__ __forceinline__ void to_vgpr(float &a) { asm("" : "+v"(a)); }
+
+template <int V, int SCHEME, bool MASK>
+__device__ __forceinline__ void pair(const P2PConst &k, const Tgt &t, float4 sp, float4 sa, float4 sb, bool ok,
+                                     Acc9 &p) {
+    const float dx = t.y0 - sp.x, dy = t.y1 - sp.y, dz = t.y2 - sp.z;
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     const float rinv = __builtin_amdgcn_rsqf(r2);
     const float rinv2 = rinv * rinv;
     const float rinv3 = rinv2 * rinv;
-    const float h5 = rinv3 * rinv2;
-    float F = rinv3, H = h5;
-    if (V <= 1) {
-        const float E = __builtin_amdgcn_exp2f(r2 * k.kE);
+    float F, H;
+    if (V == 2) {
+        F = k.inv_a * rinv3;
+        H = F * rinv2;
+    } else {
+        const float E = __builtin_amdgcn_exp2f(-r2);
         const float rho = r2 * rinv;
-        const float ks = rho * k.kS;
-        const float u = rinv * k.kU;
-        float pe = VFMM_ERFCX_C[VFMM_ERFCX_DEG];
+        float pe = k.pe[VFMM_ERFCX_DEG];
 #pragma unroll
-        for (int i = VFMM_ERFCX_DEG - 1; i >= 0; --i) pe = fmaf(pe, u, VFMM_ERFCX_C[i]);
-        const float w3 = fmaf(u, pe, ks);                // erfcx(s) + (2/sqrt pi) s
-        const float g = fmaf(-E, w3, 1.0f);              // P(3/2, x)
-        const float w5 = fmaf(r2 * k.t5, ks, w3);        // + (4/(3 sqrt pi)) s^3
-        const float g5 = fmaf(-E, w5, 1.0f);             // P(5/2, x)
-        F = g * rinv3;
-        H = g5 * h5;
+        for (int i = VFMM_ERFCX_DEG - 1; i >= 0; --i) pe = fmaf(pe, rinv, k.pe[i]);
+        const float w3 = fmaf(rinv, pe, rho);
+        const float g3 = fmaf(-E, w3, k.inv_a);
+        const float w5 = fmaf(r2 * rho, k.b, w3);
+        const float g5 = fmaf(-E, w5, k.inv_a);
+        F = g3 * rinv3;
+        H = (g5 * rinv3) * rinv2;
         if (V == 0) {
             if (__any(r2 < k.r2_small)) {
                 float q2 = k.q[VFMM_M2_DEG];
 #pragma unroll
                 for (int i = VFMM_M2_DEG - 1; i >= 0; --i) q2 = fmaf(q2, r2, k.q[i]);
-                const float Fs = E * fmaf(r2, q2, k.K3);  // e^{-x} K3 1F1(1;5/2;x)
-                const float Hs = E * q2;                  // e^{-x} K5 1F1(1;7/2;x)
+                const float Fs = E * fmaf(r2, q2, k.K3);  // 2^{-r2'} K3 1F1(1; 5/2; x)
+                const float Hs = E * q2;                  // 2^{-r2'} K5 1F1(1; 7/2; x)
                 const bool sm = r2 < k.r2_small;
                 F = sm ? Fs : F;
                 H = sm ? Hs : H;
             }
         }
     }
-    // alpha~_j x r
-    const float c0 = sa.y * dz - sa.z * dy;
-    const float c1 = sa.z * dx - sa.x * dz;
-    const float c2 = sa.x * dy - sa.y * dx;
-    p.u0 = fmaf(F, c0, p.u0);
-    p.u1 = fmaf(F, c1, p.u1);
-    p.u2 = fmaf(F, c2, p.u2);
-    p.a0 = fmaf(F, sa.x, p.a0);
-    p.a1 = fmaf(F, sa.y, p.a1);
-    p.a2 = fmaf(F, sa.z, p.a2);
+    if (MASK) {  // a padding source contributes exactly zero
+        F = ok ? F : 0.f;
+        H = ok ? H : 0.f;
+    }
     if (SCHEME == VFMM_SCHEME_TRANSPOSE) {
-        const float d = fmaf(ai0, c0, fmaf(ai1, c1, ai2 * c2));
+        float d = fmaf(sa.x, t.w0, fmaf(sa.y, t.w1, sa.z * t.w2));
+        d = fmaf(-t.ai0, sb.x, fmaf(-t.ai1, sb.y, fmaf(-t.ai2, sb.z, d)));
+        p.u0 = fmaf(F, sb.x, p.u0);
+        p.u1 = fmaf(F, sb.y, p.u1);
+        p.u2 = fmaf(F, sb.z, p.u2);
+        p.a0 = fmaf(F, sa.x, p.a0);
+        p.a1 = fmaf(F, sa.y, p.a1);
+        p.a2 = fmaf(F, sa.z, p.a2);
         const float hd = H * d;
         p.t0 = fmaf(hd, dx, p.t0);
         p.t1 = fmaf(hd, dy, p.t1);
         p.t2 = fmaf(hd, dz, p.t2);
     } else {
-        const float d = fmaf(ai0, dx, fmaf(ai1, dy, ai2 * dz));
+        const float c0 = sa.y * dz - sa.z * dy;
+        const float c1 = sa.z * dx - sa.x * dz;
+        const float c2 = sa.x * dy - sa.y * dx;
+        p.u0 = fmaf(F, c0, p.u0);
+        p.u1 = fmaf(F, c1, p.u1);
+        p.u2 = fmaf(F, c2, p.u2);
+        p.a0 = fmaf(F, sa.x, p.a0);
+        p.a1 = fmaf(F, sa.y, p.a1);
+        p.a2 = fmaf(F, sa.z, p.a2);
+        const float d = fmaf(t.ai0, dx, fmaf(t.ai1, dy, t.ai2 * dz));
         const float hd = H * d;
         p.t0 = fmaf(hd, c0, p.t0);
         p.t1 = fmaf(hd, c1, p.t1);
@@ -128,16 +167,16 @@ __device__ __forceinline__ void pair(const P2PConst &k, float xi, float yi, floa
 
 template <int V, int SCHEME>
 __device__ __forceinline__ void leaf_loop(const P2PConst &k, const float4 *__restrict__ rec, int s0, int cnt,
-                                          float xi, float yi, float zi, float ai0, float ai1, float ai2, Acc9 &p) {
-    const float4 *src = rec + 2 * (size_t)s0;
+                                          const Tgt &t, Acc9 &p) {
+    const float4 *src = rec + 3 * (size_t)s0;
     int j = 0;
     for (; j + 2 <= cnt; j += 2) {
-        const float4 sp0 = src[2 * j], sa0 = src[2 * j + 1];
-        const float4 sp1 = src[2 * j + 2], sa1 = src[2 * j + 3];
-        pair<V, SCHEME>(k, xi, yi, zi, ai0, ai1, ai2, sp0, sa0, p);
-        pair<V, SCHEME>(k, xi, yi, zi, ai0, ai1, ai2, sp1, sa1, p);
+        const float4 sp0 = src[3 * j], sa0 = src[3 * j + 1], sb0 = src[3 * j + 2];
+        const float4 sp1 = src[3 * j + 3], sa1 = src[3 * j + 4], sb1 = src[3 * j + 5];
+        pair<V, SCHEME, false>(k, t, sp0, sa0, sb0, true, p);
+        pair<V, SCHEME, false>(k, t, sp1, sa1, sb1, true, p);
     }
-    if (j < cnt) pair<V, SCHEME>(k, xi, yi, zi, ai0, ai1, ai2, src[2 * j], src[2 * j + 1], p);
+    if (j < cnt) pair<V, SCHEME, false>(k, t, src[3 * j], src[3 * j + 1], src[3 * j + 2], true, p);
 }
 
 __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
@@ -149,28 +188,17 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
 
 // Blocks of few targets split the wave into SPLIT lane groups of 64/SPLIT
 // lanes that each hold every target of the block and take every SPLIT-th
-// source (the group's source is selected per lane from the SPLIT records
-// fetched together); the groups' sums are added at the end.  A missing last
-// source gets zero strength, which contributes exactly zero.
+// source of the leaf (vector loads, one address per group); the groups' sums
+// are added at the end.  A group past the last source re-reads the last one
+// with its cutoff factors forced to zero, which contributes exactly zero.
 template <int V, int SCHEME, int SPLIT>
 __device__ __forceinline__ void leaf_loop_split(const P2PConst &k, const float4 *__restrict__ rec, int s0, int cnt,
-                                                int grp, float xi, float yi, float zi, float ai0, float ai1,
-                                                float ai2, Acc9 &p) {
-    const float4 *src = rec + 2 * (size_t)s0;
+                                                int grp, const Tgt &t, Acc9 &p) {
+    const float4 *src = rec + 3 * (size_t)s0;
     for (int j = 0; j < cnt; j += SPLIT) {
-        float4 mp = src[2 * j], ma = src[2 * j + 1];
-#pragma unroll
-        for (int t = 1; t < SPLIT; ++t) {
-            const int jj = min(j + t, cnt - 1);
-            const float4 sp = src[2 * jj];
-            float4 sa = src[2 * jj + 1];
-            if (j + t >= cnt) sa = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (grp == t) {
-                mp = sp;
-                ma = sa;
-            }
-        }
-        pair<V, SCHEME>(k, xi, yi, zi, ai0, ai1, ai2, mp, ma, p);
+        const bool ok = j + grp < cnt;
+        const int jj = ok ? j + grp : cnt - 1;
+        pair<V, SCHEME, true>(k, t, src[3 * jj], src[3 * jj + 1], src[3 * jj + 2], ok, p);
     }
 }
 
@@ -181,40 +209,55 @@ __device__ __forceinline__ void p2p_block(const P2PConst &k, const P2PArgs &A, i
     const int tl = lane % GL, grp = lane / GL;
     const bool valid = tl < tc;
     const int i = t0 + (valid ? tl : 0);
-    const float4 xp = A.rec[2 * (size_t)i];
-    const float4 xa = A.rec[2 * (size_t)i + 1];
-    const float fp = 12.566370614359172f;  // 4 pi: stored strengths are alpha/(4 pi)
-    const float ai0 = xa.x * fp, ai1 = xa.y * fp, ai2 = xa.z * fp;
+    const float4 r0 = A.rec[3 * (size_t)i], r1 = A.rec[3 * (size_t)i + 1], r2 = A.rec[3 * (size_t)i + 2];
+    Tgt t;
+    t.ai0 = r0.w;
+    t.ai1 = r1.w;
+    t.ai2 = r2.w;
     float S[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     float Cc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    const int W = 2 * A.B + 1;
+    P2PConst kv = k;  // the constants of the erfcx form, in vector registers
+#pragma unroll
+    for (int q = 0; q <= VFMM_ERFCX_DEG; ++q) to_vgpr(kv.pe[q]);
+    to_vgpr(kv.inv_a);
+    to_vgpr(kv.b);
     for (int e = 0; e < lc; ++e) {
         const int4 en = A.ent[l0 + e];
+        const float4 D = A.sh[l0 + e];
         const int s0 = __builtin_amdgcn_readfirstlane(en.x);
         const int sc = __builtin_amdgcn_readfirstlane(en.y);
-        const int img = __builtin_amdgcn_readfirstlane(en.z);
         const int var = __builtin_amdgcn_readfirstlane(en.w);
-        const float shx = (float)(img % W - A.B) * A.len;
-        const float shy = (float)((img / W) % W - A.B) * A.len;
-        const float shz = (float)(img / (W * W) - A.B) * A.len;
-        const float xi = xp.x - shx, yi = xp.y - shy, zi = xp.z - shz;
+        t.y0 = r0.x + D.x;
+        t.y1 = r0.y + D.y;
+        t.y2 = r0.z + D.z;
+        if (SCHEME == VFMM_SCHEME_TRANSPOSE) {
+            t.w0 = t.y1 * t.ai2 - t.y2 * t.ai1;
+            t.w1 = t.y2 * t.ai0 - t.y0 * t.ai2;
+            t.w2 = t.y0 * t.ai1 - t.y1 * t.ai0;
+        }
         Acc9 p = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         if (SPLIT == 1) {
             if (var == 1)
-                leaf_loop<1, SCHEME>(k, A.rec, s0, sc, xi, yi, zi, ai0, ai1, ai2, p);
+                leaf_loop<1, SCHEME>(kv, A.rec, s0, sc, t, p);
             else if (var == 0)
-                leaf_loop<0, SCHEME>(k, A.rec, s0, sc, xi, yi, zi, ai0, ai1, ai2, p);
+                leaf_loop<0, SCHEME>(kv, A.rec, s0, sc, t, p);
             else
-                leaf_loop<2, SCHEME>(k, A.rec, s0, sc, xi, yi, zi, ai0, ai1, ai2, p);
+                leaf_loop<2, SCHEME>(kv, A.rec, s0, sc, t, p);
         } else {
             if (var == 1)
-                leaf_loop_split<1, SCHEME, SPLIT>(k, A.rec, s0, sc, grp, xi, yi, zi, ai0, ai1, ai2, p);
+                leaf_loop_split<1, SCHEME, SPLIT>(kv, A.rec, s0, sc, grp, t, p);
             else if (var == 0)
-                leaf_loop_split<0, SCHEME, SPLIT>(k, A.rec, s0, sc, grp, xi, yi, zi, ai0, ai1, ai2, p);
+                leaf_loop_split<0, SCHEME, SPLIT>(kv, A.rec, s0, sc, grp, t, p);
             else
-                leaf_loop_split<2, SCHEME, SPLIT>(k, A.rec, s0, sc, grp, xi, yi, zi, ai0, ai1, ai2, p);
+                leaf_loop_split<2, SCHEME, SPLIT>(kv, A.rec, s0, sc, grp, t, p);
         }
-        const float pv[9] = {p.u0, p.u1, p.u2, p.a0, p.a1, p.a2, p.t0, p.t1, p.t2};
+        float u0 = p.u0, u1 = p.u1, u2 = p.u2;
+        if (SCHEME == VFMM_SCHEME_TRANSPOSE) {  // Ah x y_i - Bh
+            u0 = fmaf(p.a1, t.y2, fmaf(-p.a2, t.y1, -p.u0));
+            u1 = fmaf(p.a2, t.y0, fmaf(-p.a0, t.y2, -p.u1));
+            u2 = fmaf(p.a0, t.y1, fmaf(-p.a1, t.y0, -p.u2));
+        }
+        const float pv[9] = {u0, u1, u2, p.a0, p.a1, p.a2, p.t0, p.t1, p.t2};
         if (KAHAN) {
 #pragma unroll
             for (int q = 0; q < 9; ++q) kahan_add(S[q], Cc[q], pv[q]);
@@ -232,6 +275,7 @@ __device__ __forceinline__ void p2p_block(const P2PConst &k, const P2PArgs &A, i
         }
     }
     if (!valid || grp != 0) return;
+    const float ai0 = t.ai0, ai1 = t.ai1, ai2 = t.ai2;
     // dalpha = alpha_i x A - 3 T (transpose) or A x alpha_i - 3 T (classical)
     float d0, d1, d2;
     if (SCHEME == VFMM_SCHEME_TRANSPOSE) {
@@ -246,7 +290,7 @@ __device__ __forceinline__ void p2p_block(const P2PConst &k, const P2PArgs &A, i
     d0 = fmaf(-3.0f, S[6], d0);
     d1 = fmaf(-3.0f, S[7], d1);
     d2 = fmaf(-3.0f, S[8], d2);
-    float u0 = S[0], u1 = S[1], u2 = S[2];
+    float u0 = S[0] * k.inv_kappa, u1 = S[1] * k.inv_kappa, u2 = S[2] * k.inv_kappa;
     if (A.near) {
         A.near[i] = u0;
         A.near[A.n + i] = u1;
@@ -293,6 +337,45 @@ __global__ __launch_bounds__(256) void k_p2p(P2PConst k, P2PArgs A) {
         p2p_block<SCHEME, KAHAN, 2>(k, A, t0, tc, l0, lc);
     else
         p2p_block<SCHEME, KAHAN, 1>(k, A, t0, tc, l0, lc);
+}
+
+// Records of the float32 near field (sorted order), one wave per leaf:
+//   rec[3i] = (kappa (x_i - c_leaf), alpha_x), rec[3i+1] = (ah_i, alpha_y),
+//   rec[3i+2] = (ah_i x delta'_i, alpha_z),   ah = kappa^3 a alpha/(4 pi).
+// Computed in float64 and rounded once.  A null cell list means one common
+// origin for every particle (direct mode).
+__global__ __launch_bounds__(256) void k_p2p_records(const int *__restrict__ leaves, int nleaves,
+                                                     const int *__restrict__ start, const int *__restrict__ count,
+                                                     const float4 *__restrict__ geo, int64_t n, double ox, double oy,
+                                                     double oz, double kappa, double sa,
+                                                     const float4 *__restrict__ rec_in, float4 *__restrict__ out) {
+    int64_t i0, i1;
+    double cx = ox, cy = oy, cz = oz;
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (leaves) {
+        if (w >= nleaves) return;
+        const int cell = leaves[w];
+        i0 = start[cell];
+        i1 = i0 + count[cell];
+        const float4 g = geo[cell];
+        cx = g.x;
+        cy = g.y;
+        cz = g.z;
+    } else {
+        i0 = (int64_t)w * 64;
+        i1 = min<int64_t>(i0 + 64, n);
+        if (i0 >= n) return;
+    }
+    const double fp = 12.566370614359172954;  // 4 pi: rec_in holds alpha/(4 pi)
+    for (int64_t i = i0 + (threadIdx.x & 63); i < i1; i += 64) {
+        const float4 p = rec_in[2 * i], a = rec_in[2 * i + 1];
+        const double d0 = kappa * ((double)p.x - cx), d1 = kappa * ((double)p.y - cy), d2 = kappa * ((double)p.z - cz);
+        const double h0 = sa * a.x, h1 = sa * a.y, h2 = sa * a.z;
+        out[3 * i] = make_float4((float)d0, (float)d1, (float)d2, (float)(fp * a.x));
+        out[3 * i + 1] = make_float4((float)h0, (float)h1, (float)h2, (float)(fp * a.y));
+        out[3 * i + 2] = make_float4((float)(h1 * d2 - h2 * d1), (float)(h2 * d0 - h0 * d2),
+                                     (float)(h0 * d1 - h1 * d0), (float)(fp * a.z));
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -444,25 +527,45 @@ static void launch_p2p64(Ctx &c, P2P64Args A) {
     VFMM_LAUNCH_CHECK();
 }
 
+// Constants of the scaled form; every one but kappa is independent of sigma.
 static P2PConst make_const(double sigma) {
     P2PConst k{};
-    const double c = 1.0 / (std::sqrt(2.0) * sigma);
-    const double c2 = c * c;
+    const double lam = 1.0 / std::log(2.0);  // log2 e
     const double sqpi = std::sqrt(M_PI);
-    k.kE = (float)(-c2 / std::log(2.0));
-    k.kS = (float)(2.0 * c / sqpi);
-    k.kU = (float)(1.0 / c);
-    k.t5 = (float)(2.0 * c2 / 3.0);
-    k.K3 = (float)(c * c2 * 4.0 / (3.0 * sqpi));
-    k.r2_small = (float)(VFMM_CUTOFF_XSPLIT / c2);
-    const double K5 = c2 * c2 * c * 8.0 / (15.0 * sqpi);
-    double pw = 1.0;
-    for (int i = 0; i <= VFMM_M2_DEG; ++i) {
-        k.q[i] = (float)(K5 * (double)VFMM_M2_C[i] * pw);
-        pw *= c2;
-    }
+    const double a = p2p_cutoff_a();
+    k.inv_a = (float)(1.0 / a);
+    k.b = (float)(2.0 / (3.0 * lam));
+    k.K3 = (float)(4.0 / (3.0 * sqpi) / (a * std::pow(lam, 1.5)));
+    k.r2_small = (float)((double)VFMM_CUTOFF_XSPLIT * lam);
+    k.inv_kappa = (float)(1.0 / p2p_kappa(sigma));
+    for (int i = 0; i <= VFMM_ERFCX_DEG; ++i)
+        k.pe[i] = (float)((double)VFMM_ERFCX_C[i] * std::pow(lam, 0.5 * (i + 1)) / a);
+    for (int i = 0; i <= VFMM_M2_DEG; ++i)
+        k.q[i] = (float)(8.0 / (15.0 * sqpi) * (double)VFMM_M2_C[i] / (a * std::pow(lam, 2.5 + i)));
     return k;
 }
+
+// Builds the float32 near-field records from the sorted records (tree: per
+// leaf, offsets from the leaf centre; direct: from one common origin).
+static void p2p_records(Ctx &c, bool tree, const double *origin) {
+    if (c.n == 0) return;
+    const double kap = p2p_kappa(c.sigma_uniform);
+    const double sa = kap * kap * kap * p2p_cutoff_a();
+    c.recp.ensure(sizeof(float4) * 3 * (size_t)c.n);
+    const double o0 = origin ? origin[0] : 0.0, o1 = origin ? origin[1] : 0.0, o2 = origin ? origin[2] : 0.0;
+    if (tree) {
+        k_p2p_records<<<cdiv(c.nleaves, 4), 256, 0, c.stream>>>(
+            c.leaves.as<int>(), c.nleaves, c.c_start.as<int>(), c.c_count.as<int>(), c.c_geo.as<float4>(), c.n, 0.0,
+            0.0, 0.0, kap, sa, c.rec.as<float4>(), c.recp.as<float4>());
+    } else {
+        k_p2p_records<<<cdiv(cdiv(c.n, 64), 4), 256, 0, c.stream>>>(nullptr, 0, nullptr, nullptr, nullptr, c.n, o0,
+                                                                     o1, o2, kap, sa, c.rec.as<float4>(),
+                                                                     c.recp.as<float4>());
+    }
+    VFMM_LAUNCH_CHECK();
+}
+
+void p2p_prepare(Ctx &c) { p2p_records(c, true, nullptr); }
 
 template <int SCHEME, bool KAHAN>
 static void launch_p2p(const P2PConst &k, const P2PArgs &A, hipStream_t s) {
@@ -484,12 +587,11 @@ static void dispatch_p2p(Ctx &c, const P2PConst &k, const P2PArgs &A, hipStream_
 
 static P2PArgs tree_args(Ctx &c) {
     P2PArgs A{};
-    A.rec = c.rec.as<float4>();
+    A.rec = c.recp.as<float4>();
     A.blocks = c.blocks.as<int4>();
     A.ent = c.p2p_ent.as<int4>();
+    A.sh = c.p2p_sh.as<float4>();
     A.nblocks = c.n_blocks;
-    A.B = c.img_B;
-    A.len = c.prm.periodic ? (float)c.prm.box_len : 0.f;
     A.n = c.n;
     A.perm = c.perm.as<int>();
     A.bounds = c.bres.as<Bounds>();
@@ -565,20 +667,9 @@ void p2p_and_finalize(Ctx &c, float *ux, float *uy, float *uz, float *dax, float
         return;
     }
     const P2PConst k = make_const(c.sigma_uniform);
-    P2PArgs A{};
-    A.rec = c.rec.as<float4>();
-    A.blocks = c.blocks.as<int4>();
-    A.ent = c.p2p_ent.as<int4>();
-    A.nblocks = c.n_blocks;
-    A.B = c.img_B;
-    A.len = c.prm.periodic ? (float)c.prm.box_len : 0.f;
+    P2PArgs A = tree_args(c);
     A.far_u = c.far_u.as<float>();
     A.far_da = c.far_da.as<float>();
-    A.n = c.n;
-    A.perm = c.perm.as<int>();
-    A.bounds = c.bres.as<Bounds>();
-    A.surface = (c.prm.periodic && c.prm.zero_mean) ? 1 : 0;
-    A.inv3V = c.prm.periodic ? (float)(1.0 / (3.0 * c.prm.box_len * c.prm.box_len * c.prm.box_len)) : 0.f;
     A.ux = ux; A.uy = uy; A.uz = uz; A.dax = dax; A.day = day; A.daz = daz;
     c.record(2 * PH_P2P);
     dispatch_p2p(c, k, A, c.stream);
@@ -613,12 +704,13 @@ __global__ __launch_bounds__(256) void k_direct_setup(int64_t n, const float *x,
 
 // Sources split into entries of 64 so that per-entry partial sums are blocked
 // exactly as in tree mode.
-__global__ __launch_bounds__(256) void k_direct_blocks(int64_t n, int nb, int4 *blocks, int4 *ent) {
+__global__ __launch_bounds__(256) void k_direct_blocks(int64_t n, int nb, int4 *blocks, int4 *ent, float4 *sh) {
     const int b = blockIdx.x * 256 + threadIdx.x;
     if (b < nb) {
         const int cnt = (int)min<int64_t>(64, n - (int64_t)b * 64);
         blocks[b] = make_int4(b * 64, cnt, 0, nb);
         ent[b] = make_int4(b * 64, cnt, 0, 0);
+        if (sh) sh[b] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
 }
 
@@ -631,10 +723,13 @@ void direct_all_pairs(Ctx &c, const float *x, const float *y, const float *z, co
     const int nb = (int)cdiv(n, 64);
     c.blocks.ensure(sizeof(int4) * nb);
     c.p2p_ent.ensure(sizeof(int4) * nb);
+    const bool f32 = c.prm.precision != VFMM_PRECISION_FP64;
+    if (f32) c.p2p_sh.ensure(sizeof(float4) * nb);
     k_direct_setup<<<cdiv(n, 256), 256, 0, c.stream>>>(n, x, y, z, ax, ay, az, sigma, c.rec.as<float4>(),
                                                         c.perm.as<int>());
     VFMM_LAUNCH_CHECK();
-    k_direct_blocks<<<cdiv(nb, 256), 256, 0, c.stream>>>(n, nb, c.blocks.as<int4>(), c.p2p_ent.as<int4>());
+    k_direct_blocks<<<cdiv(nb, 256), 256, 0, c.stream>>>(n, nb, c.blocks.as<int4>(), c.p2p_ent.as<int4>(),
+                                                          f32 ? c.p2p_sh.as<float4>() : nullptr);
     VFMM_LAUNCH_CHECK();
     c.n_blocks = nb;
     c.p2p_pairs = n * n;
@@ -657,14 +752,17 @@ void direct_all_pairs(Ctx &c, const float *x, const float *y, const float *z, co
         c.record(2 * PH_P2P + 1);
         return;
     }
+    // one origin for every record: the centre of the bounding box
+    const double org[3] = {0.5 * (c.hb.lo[0] + c.hb.hi[0]), 0.5 * (c.hb.lo[1] + c.hb.hi[1]),
+                           0.5 * (c.hb.lo[2] + c.hb.hi[2])};
+    p2p_records(c, false, org);
     const P2PConst k = make_const(c.sigma_uniform);
     P2PArgs A{};
-    A.rec = c.rec.as<float4>();
+    A.rec = c.recp.as<float4>();
     A.blocks = c.blocks.as<int4>();
     A.ent = c.p2p_ent.as<int4>();
+    A.sh = c.p2p_sh.as<float4>();
     A.nblocks = nb;
-    A.B = 0;
-    A.len = 0.f;
     A.far_u = nullptr;
     A.far_da = nullptr;
     A.n = n;

@@ -158,14 +158,19 @@ __global__ __launch_bounds__(TPB) void k_m2l_gather(const int4 *raw, const uint3
 struct P2PEntryArgs {
     const int *start, *count;
     const float4 *lo, *hi;
+    const float4 *geo;        // cell centres
     float len;
     int B;
     float r2_small, r2_sing;  // thresholds on squared distance for the cutoff branches
+    double kappa;             // length scale of the float32 near field
+    double len64;             // period (0: free space)
+    float4 *sh;               // out: kappa (c_t - c_s - image shift) per entry (null: not needed)
 };
 
 // entry = (source start, source count, image code, variant) with variant
 // 0 = full cutoff (some pair may have s < 1), 1 = s >= 1 for every pair,
-// 2 = cutoff equal to 1 in float32 for every pair (singular kernel).
+// 2 = cutoff equal to 1 in float32 for every pair (singular kernel).  The
+// float32 near field also gets the scaled offset between the leaf centres.
 __global__ __launch_bounds__(TPB) void k_p2p_gather(P2PEntryArgs A, const int4 *raw, const uint32_t *order,
                                                     int64_t n, int4 *out, unsigned long long *pairs) {
     const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
@@ -185,6 +190,14 @@ __global__ __launch_bounds__(TPB) void k_p2p_gather(P2PEntryArgs A, const int4 *
         const float d2 = gx * gx + gy * gy + gz * gz;
         const int variant = d2 >= A.r2_sing ? 2 : (d2 >= A.r2_small ? 1 : 0);
         out[i] = make_int4(A.start[s], A.count[s], e.z, variant);
+        if (A.sh) {
+            const float4 ct = A.geo[t], cs = A.geo[s];
+            const double L = A.len64;
+            const double Dx = ((double)ct.x - (double)cs.x - (double)(e.z % W - A.B) * L) * A.kappa;
+            const double Dy = ((double)ct.y - (double)cs.y - (double)((e.z / W) % W - A.B) * L) * A.kappa;
+            const double Dz = ((double)ct.z - (double)cs.z - (double)(e.z / (W * W) - A.B) * L) * A.kappa;
+            A.sh[i] = make_float4((float)Dx, (float)Dy, (float)Dz, 0.f);
+        }
         np = (unsigned long long)A.count[t] * (unsigned long long)A.count[s];
     }
     // block reduction of the pair count
@@ -325,6 +338,8 @@ void traverse_and_lists(Ctx &c) {
     // ---- P2P CSR ----
     csr_by_target(c, c.p2p_raw.as<int4>(), n_p2p, c.p2p_off);
     c.p2p_ent.ensure(sizeof(int4) * (size_t)std::max<int64_t>(n_p2p, 1));
+    const bool f32 = c.prm.precision != VFMM_PRECISION_FP64;
+    if (f32) c.p2p_sh.ensure(sizeof(float4) * (size_t)std::max<int64_t>(n_p2p, 1));
     c.pairs64.ensure(64);
     VFMM_HIP(hipMemsetAsync(c.pairs64.ptr, 0, 8, s));
     if (n_p2p > 0) {
@@ -338,6 +353,10 @@ void traverse_and_lists(Ctx &c) {
         const float s2 = 2.0f * (float)(c.hb.sig_max * c.hb.sig_max);
         E.r2_small = s2 * VFMM_CUTOFF_XSPLIT * 1.0001f;
         E.r2_sing = s2 * 26.0f;
+        E.geo = c.c_geo.as<float4>();
+        E.kappa = p2p_kappa(c.sigma_uniform);
+        E.len64 = c.prm.periodic ? c.prm.box_len : 0.0;
+        E.sh = f32 ? c.p2p_sh.as<float4>() : nullptr;
         k_p2p_gather<<<cdiv(n_p2p, TPB), TPB, 0, s>>>(E, c.p2p_raw.as<int4>(), c.lval.as<uint32_t>(), n_p2p,
                                                        c.p2p_ent.as<int4>(),
                                                        c.pairs64.as<unsigned long long>());
