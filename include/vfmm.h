@@ -100,6 +100,15 @@ typedef struct vfmm_params {
                             kernels then fill the GPU beside the P2P: about 2.5% shorter steps at
                             128^3; the P2P and far-field phase timings overlap).  Results are
                             bitwise the same.                                                    */
+    int32_t m2l_form;    /* products of the operator-batched M2L.  0 (default) or 1: float32
+                            matrix-core products.  2 (p <= 10; p = 12 uses 1): split products:
+                            operator and multipole values are each split into three bfloat16
+                            parts (24 significant bits) and the six leading partial products
+                            run on the bfloat16 matrix cores with float32 accumulation; the
+                            translations agree with form 1 to float32 rounding and the M2L
+                            kernel is about 1.2x faster at 128^3, p = 10 (but the P2P kernel
+                            that follows it then measured slower, leaving the step nearly
+                            unchanged).                                                          */
 } vfmm_params;
 
 /* Per-phase device times of the last fmm_build / fmm_evaluate, in milliseconds,
@@ -135,6 +144,7 @@ typedef struct vfmm_stats {
     int32_t m2l_keys;       /* batched M2L: distinct translation operators (0 if per pair) */
     int32_t m2l_groups;     /* batched M2L: (target block, operator) groups        */
     int32_t m2l_items;      /* batched M2L: work items (<= 24 groups of one block) */
+    int32_t m2l_split;      /* batched M2L: 1 when it runs the split bf16 products */
 } vfmm_stats;
 
 /* Fill *p with the defaults listed above (free space). */

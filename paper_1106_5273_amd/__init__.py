@@ -31,7 +31,7 @@ class Params(ctypes.Structure):
                 ("box_lo", ctypes.c_double * 3), ("box_len", ctypes.c_double), ("scheme", ctypes.c_int32),
                 ("kahan", ctypes.c_int32), ("zero_mean", ctypes.c_int32), ("direct", ctypes.c_int32),
                 ("m2l_mode", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("overlap", ctypes.c_int32)]
+                ("overlap", ctypes.c_int32), ("m2l_form", ctypes.c_int32)]
 
 
 class Timings(ctypes.Structure):
@@ -52,7 +52,7 @@ class Stats(ctypes.Structure):
                 ("m2l_entries", ctypes.c_int64), ("p2p_blocks", ctypes.c_int32),
                 ("images_traversed", ctypes.c_int32), ("sum_alpha", ctypes.c_double * 3),
                 ("sigma_min", ctypes.c_double), ("sigma_max", ctypes.c_double), ("m2l_keys", ctypes.c_int32),
-                ("m2l_groups", ctypes.c_int32), ("m2l_items", ctypes.c_int32)]
+                ("m2l_groups", ctypes.c_int32), ("m2l_items", ctypes.c_int32), ("m2l_split", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p

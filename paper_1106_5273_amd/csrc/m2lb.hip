@@ -273,15 +273,28 @@ struct MbCfg {
     static constexpr int RW = (RTI + 3) / 4;       // row tiles per wave (4 waves)
     static constexpr int BS = RP + 4;              // LDS column stride of the staged multipoles
     static constexpr size_t OP = (size_t)RT * RP;  // floats per operator
+    static constexpr bool X6 = RP % 32 == 0;       // bf16 k blocks of 32 fit the padded inputs
+    static constexpr size_t OPX = (size_t)RT * RP * 3 / 2;  // 32-bit words per operator, split form
 };
 
 // One operator per key, built once per tree.  T[r][c] (r output row
 // (k, l, Re/Im), c input row (n, m, Re/Im)):
 //   Lt_k^l = (-1)^{k+l} 2^{dl (k+1)} sum_{n,m} Mt_n^m I_{n+k}^{m-l}(-q 2^{min(dl,0)-2}).
-// Stored in MFMA A-fragment order [key][row tile a][chunk][lane][e] =
-// T[16 a + lane % 16][16 chunk + 4 e + lane / 16], zero outside R x R, so a
-// lane reads the operands of four k steps as one float4.
-template <int P>
+// FORM 0 (float32 products): MFMA A-fragment order [key][row tile a][chunk]
+// [lane][e] = T[16 a + lane % 16][16 chunk + 4 e + lane / 16], zero outside
+// R x R, so a lane reads the operands of four k steps as one float4.
+// FORM 1 (three-way bfloat16 split): T = T0 + T1 + T2 with T0 = bf16(T),
+// T1 = bf16(T - T0), T2 = bf16(T - T0 - T1) (24 significant bits), stored
+// [key][row tile a][k block kb][split s][lane][e] = Ts[16 a + lane % 16]
+// [kperm(32 kb + 8 (lane / 16) + e)], e = 0..7: the input positions of a
+// bf16 MFMA k block are eight consecutive positions of the k-permuted
+// multipole rows.
+__device__ inline uint32_t bf16_bits_rne(float x) {
+    const uint32_t u = __float_as_uint(x);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;  // finite inputs only
+}
+
+template <int P, int FORM>
 __global__ __launch_bounds__(256) void k_m2lb_optab(int nkeys, const uint64_t *__restrict__ ukey, KeyFmt f,
                                                     float *__restrict__ tab) {
     using C = MbCfg<P>;
@@ -339,11 +352,7 @@ __global__ __launch_bounds__(256) void k_m2lb_optab(int nkeys, const uint64_t *_
         }
     }
     __syncthreads();
-    float *T = tab + (size_t)key * C::OP;
-    for (int idx = tid; idx < (int)C::OP; idx += 256) {
-        const int e = idx & 3, lane = (idx >> 2) & 63;
-        const int chunk = (idx >> 8) % C::KC, a = (idx >> 8) / C::KC;
-        const int r = 16 * a + (lane & 15), c = 16 * chunk + 4 * e + (lane >> 4);
+    auto value = [&](int r, int c) -> float {
         float v = 0.f;
         if (r < C::R && c < C::R) {
             const int ri = rinfo[r], ci = rinfo[c];
@@ -357,7 +366,39 @@ __global__ __launch_bounds__(256) void k_m2lb_optab(int nkeys, const uint64_t *_
             else v = imc ? (x.x - sg * y.x) : (x.y - sg * y.y);
             v *= (((k + l) & 1) ? -1.f : 1.f) * ldexpf(1.0f, dl * (k + 1));
         }
-        T[idx] = v;
+        return v;
+    };
+    if (FORM == 0) {
+        float *T = tab + (size_t)key * C::OP;
+        for (int idx = tid; idx < (int)C::OP; idx += 256) {
+            const int e = idx & 3, lane = (idx >> 2) & 63;
+            const int chunk = (idx >> 8) % C::KC, a = (idx >> 8) / C::KC;
+            T[idx] = value(16 * a + (lane & 15), 16 * chunk + 4 * e + (lane >> 4));
+        }
+    } else {
+        // one thread per (a, kb, lane, pair of e): two values packed per 32-bit word and split
+        uint32_t *T = reinterpret_cast<uint32_t *>(tab) + (size_t)key * C::OPX;
+        constexpr int KB = C::RP / 32;
+        for (int idx = tid; idx < C::RTI * KB * 64 * 4; idx += 256) {
+            const int ep = idx & 3, lane = (idx >> 2) & 63;
+            const int kb = (idx >> 8) % KB, a = (idx >> 8) / KB;
+            const int r = 16 * a + (lane & 15);
+            const int p0 = 32 * kb + 8 * (lane >> 4) + 2 * ep;
+            float v[2] = {value(r, kperm(p0)), value(r, kperm(p0 + 1))};
+            uint32_t w[3][2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                float rem = v[h];
+#pragma unroll
+                for (int sp = 0; sp < 3; ++sp) {
+                    w[sp][h] = bf16_bits_rne(rem);
+                    rem -= __uint_as_float(w[sp][h] << 16);
+                }
+            }
+#pragma unroll
+            for (int sp = 0; sp < 3; ++sp)
+                T[((((size_t)a * KB + kb) * 3 + sp) * 64 + lane) * 4 + ep] = w[sp][0] | (w[sp][1] << 16);
+        }
     }
 }
 
@@ -489,6 +530,195 @@ __global__ __launch_bounds__(256) void k_m2lb(const int4 *__restrict__ items, co
     }
 }
 
+// Split-product form of the batched translation (float32-accurate products
+// on the bfloat16 matrix cores).  The operator comes from the table in three
+// bf16 parts (T = T0 + T1 + T2, 24 significant bits); each staged multipole
+// value is split the same way (M = M0 + M1 + M2) as it is written to LDS.
+// T M is then the sum of the six products Ti Mj with i + j <= 2, each on
+// v_mfma_f32_16x16x32_bf16 (exact bf16 products, float32 accumulation); the
+// three dropped products and the splitting residuals are each of order
+// 2^-26 |T| |M|.  A work-group of RTI waves (eight at p = 10) takes one work
+// item; a wave owns two row tiles (32 output rows) of 32 of the 64 targets,
+// for the three potentials.
+template <int P>
+struct MbxCfg {
+    using C = MbCfg<P>;
+    static constexpr int KB = C::RP / 32;     // k blocks of 32 inputs
+    static constexpr int WAVES = C::RTI;      // (RTI / 2 row-tile pairs) x (2 column halves)
+    static constexpr int BSX = C::RP + 8;     // LDS column stride (bf16) of a split plane
+    static constexpr int PLANE = 64 * BSX;    // bf16 per plane
+    static constexpr int F4 = 64 * C::RP / 4 / (64 * WAVES);  // staged float4 per thread and potential
+    static_assert(!C::X6 || ((64 * C::RP / 4) % (64 * WAVES) == 0 && C::RTI % 2 == 0), "tile split");
+};
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// x = h + m + l with h, m, l in bf16 (v_cvt_pk_bf16_f32, round to nearest
+// even; each residual is exact in float32); two values per word
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ inline void split4(vf4 x, u32x2 &h, u32x2 &m, u32x2 &l) {
+    float r[4] = {x[0], x[1], x[2], x[3]};
+    uint32_t w[3][2];
+#pragma unroll
+    for (int sp = 0; sp < 3; ++sp)
+#pragma unroll
+        for (int pr = 0; pr < 2; ++pr) {
+            const bf16x2 v = {(__bf16)r[2 * pr], (__bf16)r[2 * pr + 1]};
+            const uint32_t u = __builtin_bit_cast(uint32_t, v);
+            w[sp][pr] = u;
+            if (sp < 2) {
+                r[2 * pr] -= __uint_as_float(u << 16);
+                r[2 * pr + 1] -= __uint_as_float(u & 0xffff0000u);
+            }
+        }
+    h = u32x2{w[0][0], w[0][1]};
+    m = u32x2{w[1][0], w[1][1]};
+    l = u32x2{w[2][0], w[2][1]};
+}
+
+__device__ __forceinline__ vf4 mfma_bf16(u32x4 a, u32x4 b, vf4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                  0, 0, 0);
+}
+
+template <int P>
+__global__ __launch_bounds__(MbxCfg<P>::WAVES * 64) void k_m2lb_x6(const int4 *__restrict__ items,
+                                                                  const int4 *__restrict__ groups,
+                                                                  const int2 *__restrict__ ent,
+                                                                  const float *__restrict__ Mr,
+                                                                  const uint32_t *__restrict__ tab, int zero_cell,
+                                                                  int nitems, float *__restrict__ partial) {
+    using C = MbCfg<P>;
+    using X = MbxCfg<P>;
+    constexpr int NT = X::WAVES * 64;
+    const int item = xcd_logical(blockIdx.x, gridDim.x);
+    if (item >= nitems) return;
+    extern __shared__ float smem[];
+    uint16_t *Bs = reinterpret_cast<uint16_t *>(smem);                     // [2][3][64][BSX]
+    int *src_of = reinterpret_cast<int *>(smem) + 2 * 3 * X::PLANE / 2;      // [64]
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    const int i16 = lane & 15, kq = lane >> 4;
+    constexpr int RH = C::RTI / 2;              // row-tile pairs
+    const int ra0 = 2 * (wave % RH), cb0 = 2 * (wave / RH);  // this wave: row tiles ra0, ra0+1; columns cb0, cb0+1
+    const int4 it = items[item];
+    const int g0 = __builtin_amdgcn_readfirstlane(it.y);
+    const int g1 = __builtin_amdgcn_readfirstlane(it.z);
+    vf4 acc[3][2][2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[c][j][b] = vf4{0.f, 0.f, 0.f, 0.f};
+    for (int g = g0; g < g1; ++g) {
+        const int4 gr = groups[g];
+        const int key = __builtin_amdgcn_readfirstlane(gr.x);
+        const int e0 = __builtin_amdgcn_readfirstlane(gr.y);
+        const int ne = __builtin_amdgcn_readfirstlane(gr.z);
+        __syncthreads();  // the previous key's tiles and slots are no longer read
+        if (tid < 64) src_of[tid] = zero_cell;
+        __syncthreads();
+        if (tid < ne) {
+            const int2 en = ent[e0 + tid];
+            src_of[en.y] = en.x;
+        }
+        // this wave's two row tiles of the operator: A[j][kb][split]
+        u32x4 A[2][X::KB][3];
+        const u32x4 *T4 = reinterpret_cast<const u32x4 *>(tab + (size_t)key * C::OPX);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int kb = 0; kb < X::KB; ++kb)
+#pragma unroll
+                for (int sp = 0; sp < 3; ++sp)
+                    A[j][kb][sp] = T4[(((size_t)(ra0 + j) * X::KB + kb) * 3 + sp) * 64 + lane];
+        __syncthreads();
+        // float4 number q = tid + NT i of a staged tile: column q / (RP/4), inputs 4 (q % (RP/4)) ..
+        int scol[X::F4];
+#pragma unroll
+        for (int i = 0; i < X::F4; ++i) scol[i] = src_of[(tid + NT * i) / (C::RP / 4)];
+        auto src4 = [&](int i, int c) {
+            return reinterpret_cast<const vf4 *>(Mr + ((size_t)scol[i] * 3 + c) * C::RP +
+                                                 4 * ((tid + NT * i) % (C::RP / 4)));
+        };
+        auto put = [&](int buf, int i, vf4 x) {
+            const int q = tid + NT * i;
+            const int off = (q / (C::RP / 4)) * X::BSX + 4 * (q % (C::RP / 4));
+            u32x2 h, m, l;
+            split4(x, h, m, l);
+            uint16_t *base = Bs + (size_t)buf * 3 * X::PLANE + off;
+            *reinterpret_cast<u32x2 *>(base) = h;
+            *reinterpret_cast<u32x2 *>(base + X::PLANE) = m;
+            *reinterpret_cast<u32x2 *>(base + 2 * X::PLANE) = l;
+        };
+        {
+            vf4 pre[X::F4];
+#pragma unroll
+            for (int i = 0; i < X::F4; ++i) pre[i] = *src4(i, 0);
+#pragma unroll
+            for (int i = 0; i < X::F4; ++i) put(0, i, pre[i]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const uint16_t *Bc = Bs + (size_t)(c & 1) * 3 * X::PLANE;
+            vf4 nxt[X::F4];
+            if (c < 2) {
+#pragma unroll
+                for (int i = 0; i < X::F4; ++i) nxt[i] = *src4(i, c + 1);
+            }
+#pragma unroll
+            for (int kb = 0; kb < X::KB; ++kb) {
+                u32x4 Bv[2][3];
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int sp = 0; sp < 3; ++sp)
+                        Bv[b][sp] = *reinterpret_cast<const u32x4 *>(
+                            Bc + sp * X::PLANE + (16 * (cb0 + b) + i16) * X::BSX + 32 * kb + 8 * kq);
+                // smallest products first: (2,0) (1,1) (0,2) (1,0) (0,1) (0,0)
+                constexpr int TA[6] = {2, 1, 0, 1, 0, 0}, TB[6] = {0, 1, 2, 0, 1, 0};
+#pragma unroll
+                for (int t = 0; t < 6; ++t)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+#pragma unroll
+                        for (int b = 0; b < 2; ++b)
+                            acc[c][j][b] = mfma_bf16(A[j][kb][TA[t]], Bv[b][TB[t]], acc[c][j][b]);
+            }
+            if (c < 2) {
+#pragma unroll
+                for (int i = 0; i < X::F4; ++i) put((c + 1) & 1, i, nxt[i]);
+                __syncthreads();
+            }
+        }
+    }
+    // D fragment: lane holds rows 16 a + 4 kq + v of target column 16 b + i16
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float *out = partial + ((size_t)item * 3 + c) * C::R * 64;
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * (ra0 + j) + 4 * kq + v;
+                    if (row < C::R) out[(size_t)row * 64 + 16 * (cb0 + b) + i16] = acc[c][j][b][v];
+                }
+    }
+}
+
+template <int P>
+static size_t m2lb_x6_lds_bytes() {
+    using X = MbxCfg<P>;
+    return sizeof(uint16_t) * 2 * 3 * X::PLANE + sizeof(int) * 64;
+}
+
 template <int P>
 static size_t m2lb_lds_bytes() {
     using C = MbCfg<P>;
@@ -534,6 +764,10 @@ __global__ __launch_bounds__(TPB) void k_m2lb_reduce(int nblk, const int *blk_it
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+// Product form of the batched M2L: split bf16 products when asked for
+// (m2l_form 2) and the padded inputs make whole k blocks of 32.
+static bool m2lb_split_form(const Ctx &c, bool fits) { return fits && c.prm.m2l_form == 2; }
+
 static int bits_for_range(int64_t maxabs) {
     int b = 1;
     while ((1LL << b) < 2 * maxabs + 1) ++b;
@@ -703,11 +937,16 @@ static void m2lb_plan_p(Ctx &c) {
     VFMM_LAUNCH_CHECK();
     // ---- one operator per key ----
     using C = MbCfg<P>;
-    const size_t tab_bytes = sizeof(float) * C::OP * (size_t)nkeys;
+    const bool x6 = m2lb_split_form(c, C::X6);
+    const size_t tab_bytes = (x6 ? sizeof(uint32_t) * C::OPX : sizeof(float) * C::OP) * (size_t)nkeys;
     if (tab_bytes > MAX_TABLE_BYTES) return;  // too many distinct offsets: generic kernel
     c.mb_tab.ensure(tab_bytes);
-    k_m2lb_optab<P><<<nkeys, 256, 0, s>>>(nkeys, c.mb_ukey.as<uint64_t>(), f, c.mb_tab.as<float>());
+    if (x6)
+        k_m2lb_optab<P, 1><<<nkeys, 256, 0, s>>>(nkeys, c.mb_ukey.as<uint64_t>(), f, c.mb_tab.as<float>());
+    else
+        k_m2lb_optab<P, 0><<<nkeys, 256, 0, s>>>(nkeys, c.mb_ukey.as<uint64_t>(), f, c.mb_tab.as<float>());
     VFMM_LAUNCH_CHECK();
+    c.mb_x6 = x6;
     c.mb_nkeys = nkeys;
     c.mb_fmt[0] = f.bq;
     c.mb_fmt[1] = f.bdl;
@@ -757,15 +996,29 @@ static void m2lb_run_p(Ctx &c) {
     k_m2lb_mreal<P><<<cdiv(mr_total, TPB), TPB, 0, s>>>(c.ncells, c.Mexp.as<float2>(), c.mb_mr.as<float>());
     VFMM_LAUNCH_CHECK();
     c.mb_partial.ensure(sizeof(float) * (size_t)c.mb_nitems * 3 * R * 64);
-    const size_t lds = m2lb_lds_bytes<P>();
-    if (c.m2lb_lds_set < (int)lds) {  // once per context (a context lives on one device)
-        VFMM_HIP(hipFuncSetAttribute((const void *)k_m2lb<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        c.m2lb_lds_set = (int)lds;
+    if (c.mb_x6) {
+        using X = MbxCfg<P>;
+        const size_t lds = m2lb_x6_lds_bytes<P>();
+        if (c.m2lbx_lds_set < (int)lds) {  // once per context (a context lives on one device)
+            VFMM_HIP(hipFuncSetAttribute((const void *)k_m2lb_x6<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)lds));
+            c.m2lbx_lds_set = (int)lds;
+        }
+        k_m2lb_x6<P><<<xcd_grid(c.mb_nitems), X::WAVES * 64, lds, s>>>(
+            c.mb_items.as<int4>(), c.mb_groups.as<int4>(), c.mb_ent.as<int2>(), c.mb_mr.as<float>(),
+            c.mb_tab.as<uint32_t>(), c.ncells, c.mb_nitems, c.mb_partial.as<float>());
+    } else {
+        const size_t lds = m2lb_lds_bytes<P>();
+        if (c.m2lb_lds_set < (int)lds) {  // once per context (a context lives on one device)
+            VFMM_HIP(hipFuncSetAttribute((const void *)k_m2lb<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)lds));
+            c.m2lb_lds_set = (int)lds;
+        }
+        k_m2lb<P><<<xcd_grid(c.mb_nitems), 256, lds, s>>>(c.mb_items.as<int4>(), c.mb_groups.as<int4>(),
+                                                           c.mb_ent.as<int2>(), c.mb_mr.as<float>(),
+                                                           c.mb_tab.as<float>(), c.ncells, c.mb_nitems,
+                                                           c.mb_partial.as<float>());
     }
-    k_m2lb<P><<<xcd_grid(c.mb_nitems), 256, lds, s>>>(c.mb_items.as<int4>(), c.mb_groups.as<int4>(),
-                                                       c.mb_ent.as<int2>(), c.mb_mr.as<float>(),
-                                                       c.mb_tab.as<float>(), c.ncells, c.mb_nitems,
-                                                       c.mb_partial.as<float>());
     VFMM_LAUNCH_CHECK();
     const int nblk = c.mb_nblk;
     int *blk_item0 = c.mb_blk.as<int>() + nblk, *blk_nitem = blk_item0 + nblk;

@@ -248,6 +248,25 @@ def test_m2l_batched_matches_per_pair(name):
     assert rel(u0, u1) <= 2e-6 and rel(d0, d1) <= 2e-6
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("p", [4, 6, 8, 10])
+def test_m2l_split_products_match_float32_products(p):
+    """The split bf16 products (three parts of each operand, six leading
+    products) give the float32 products' translations to float32 rounding."""
+    case = wl.turbulence_case(32, seed=19)
+    kw = dict(p=p, periodic=1, box_len=2 * np.pi, images=3, m2l_mode=2)
+    u2, d2, ctx = run(case, ret_ctx=True, m2l_form=2, **kw)
+    st = ctx.stats()
+    ctx.close()
+    assert st["m2l_groups"] > 0 and st["m2l_split"] == 1
+    u1, d1, ctx = run(case, ret_ctx=True, m2l_form=1, **kw)
+    st1 = ctx.stats()
+    ctx.close()
+    assert st1["m2l_split"] == 0
+    print("p=%d split vs float32 products: u %.2e dalpha %.2e" % (p, rel(u2, u1), rel(d2, d1)))
+    assert rel(u2, u1) <= 1e-6 and rel(d2, d1) <= 1e-6
+
+
 # ----------------------------------------------------------------------------
 # traversal coverage: every (target, source, image) particle pair exactly once
 # ----------------------------------------------------------------------------
