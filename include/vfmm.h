@@ -165,7 +165,9 @@ vfmm_status vfmm_set_params(vfmm_ctx *ctx, const vfmm_params *params);
  * x, y, z, sigma: device float32[n].  The tree depends on positions only; the
  * cores enter the separation test (sigma_gap * max sigma).  n = 0 is allowed
  * (evaluate then writes nothing).  Errors: VFMM_EINVAL (null pointer, n < 0,
- * n >= 2^31), VFMM_EDOMAIN (non-finite input; periodic position outside the
+ * n >= 2^31, cores not uniform, or - float32 and mixed forms, whose near field
+ * works in lengths scaled by 1/sigma - cores below 1/(2e7) of the domain
+ * extent), VFMM_EDOMAIN (non-finite input; periodic position outside the
  * cube), VFMM_ENOMEM, VFMM_EHIP. */
 vfmm_status fmm_build(vfmm_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
                       const float *sigma);

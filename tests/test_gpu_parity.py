@@ -249,6 +249,21 @@ def test_m2l_batched_matches_per_pair(name):
 
 
 @pytest.mark.gpu
+def test_cores_too_small_for_the_domain_are_rejected():
+    """The float32 near field scales lengths by 1/sigma; a core below 1/(2e7)
+    of the extent is refused at build time (the float64 form accepts it)."""
+    vf = _vf()
+    case = _ring(200, seed=5)
+    case = dict(case, sigma=np.full(case["n"], 1e-8, np.float32))
+    t = vf.case_to_device(case)
+    with vf.Context() as ctx:
+        with pytest.raises(vf.VfmmError, match="cores too small"):
+            ctx.build(t[0], t[1], t[2], t[6])
+    with vf.Context(precision=2) as ctx:
+        ctx.build(t[0], t[1], t[2], t[6])
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("p", [4, 6, 8, 10])
 def test_m2l_split_products_match_float32_products(p):
     """The split bf16 products (three parts of each operand, six leading
