@@ -45,10 +45,10 @@ def parse():
     ap.add_argument("--no-overlap-pass", action="store_true",
                     help="skip the extra timing of the two-stream (overlap = 1) step (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "var"],
                     help="c2: 128^3 periodic step (default, the headline line); c3: 256^3 float32 vs "
                          "mixed vs float64 forms; c4: 512 batched ring problems vs sequential; c5: 256^3 "
-                         "autotuned RK2 step")
+                         "autotuned RK2 step; var: 128^3 free space with per-particle cores vs uniform")
     ap.add_argument("--microbench", action="store_true",
                     help="only measure VALU FP32 FMA / exp2 / rsq issue rates and exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -261,6 +261,62 @@ def bench_precision(args, vf, wl):
     print(json.dumps(line), flush=True)
 
 
+def bench_varcore(args, vf, wl):
+    """Per-particle cores (Eq. 2 with each source's own sigma_j): the 128^3
+    turbulence-shaped lattice in free space with sigma_j = 1.5 h U(0.75, 1.25),
+    against the same particles with the uniform core.  Reports both step
+    times and the error of the per-particle run on 1,024 random targets
+    against the float64 direct sum."""
+    import numpy as np
+    import torch
+    case = wl.turbulence_case(args.n, seed=2)
+    rng = np.random.default_rng(7)
+    var = dict(case)
+    var["sigma"] = (np.asarray(case["sigma"], np.float64) * rng.uniform(0.75, 1.25, case["n"])).astype(np.float32)
+    res, outs = {}, {}
+    for name, c in (("uniform", case), ("per_particle", var)):
+        t = vf.case_to_device(c)
+        ctx = vf.Context(p=args.p, theta=args.theta, ncrit=args.ncrit, periodic=0)
+        out = tuple(torch.empty(c["n"], dtype=torch.float32, device="cuda") for _ in range(6))
+        for _ in range(max(args.warmup, 1)):
+            ctx.build(t[0], t[1], t[2], t[6])
+            ctx.evaluate(*t, out=out)
+        torch.cuda.synchronize()
+        ph = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.build(t[0], t[1], t[2], t[6])
+            ctx.evaluate(*t, out=out)
+            ph.append(ctx.timings())
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        st = ctx.stats()
+        ctx.close()
+        outs[name] = (np.stack([o.cpu().numpy() for o in out[:3]], 1).astype(np.float64),
+                      np.stack([o.cpu().numpy() for o in out[3:]], 1).astype(np.float64))
+        res[name] = {"ms_per_step": ms, "p2p_pairs": st["p2p_pairs"], "sigma_min": st["sigma_min"],
+                     "sigma_max": st["sigma_max"],
+                     "phases_ms": {k: float(np.mean([p[k] for p in ph])) for k in ph[0]}}
+        print("%s cores: %.1f ms/step" % (name, ms), file=sys.stderr, flush=True)
+    if not args.no_check:
+        import oracle
+        idx = np.sort(np.random.default_rng(71).choice(var["n"], size=1024, replace=False))
+        ref = oracle.direct(var, targets=idx)
+
+        def rel(a, b):
+            return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+        res["per_particle"]["rel_l2_vs_oracle_1024"] = {"u": rel(outs["per_particle"][0][idx], ref["u"]),
+                                                        "dalpha": rel(outs["per_particle"][1][idx], ref["da_t"])}
+    r = res["per_particle"]
+    line = _line("per-particle cores at %d^3: step time" % args.n, r["p2p_pairs"] / (r["ms_per_step"] * 1e-3) / 1e9,
+                 "Gpair/s", r["ms_per_step"], args,
+                 "free-space %d^3 turbulence-shaped lattice, sigma_j = 1.5 h U(0.75, 1.25) (seed 7), p=%d, "
+                 "theta=%g; the same particles with the uniform core beside it" % (args.n, args.p, args.theta),
+                 {"forms": res, "slowdown_vs_uniform": r["ms_per_step"] / res["uniform"]["ms_per_step"]})
+    print(json.dumps(line), flush=True)
+
+
 def _time_overlap(ctx1, t, case, args, pairs):
     """Time the same steps with the near field on its own stream beside the far field."""
     import torch
@@ -284,8 +340,8 @@ def _time_overlap(ctx1, t, case, args, pairs):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU sharding is described in DESIGN.md, "
-              "not implemented (got --gpus %d)" % args.gpus, file=sys.stderr)
+        print("bench.py: runs on one GPU only; sharding over several GPUs is not implemented "
+              "(got --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -323,6 +379,8 @@ def main():
         return bench_batched(args, vf, wl)
     if args.workload == "c5":
         return bench_rk(args, vf, wl)
+    if args.workload == "var":
+        return bench_varcore(args, vf, wl)
     if args.workload == "c3":
         return bench_precision(args, vf, wl)
     L = 2 * np.pi

@@ -140,15 +140,16 @@ static void do_build(Ctx &c, int64_t n, const float *x, const float *y, const fl
     if (c.prm.periodic && c.hb.outside) throw Error{VFMM_EDOMAIN, "position outside the periodic cube"};
     if (c.nprob > 1 && (c.prm.periodic || c.prm.direct))
         throw Error{VFMM_EINVAL, "batched problems are free space and use the tree (periodic = 0, direct = 0)"};
-    if (c.hb.sig_max > c.hb.sig_min * (1.0 + 1e-6))
-        throw Error{VFMM_EINVAL, "cores must be uniform (variable sigma is not supported by this build)"};
+    // per-source cores: the separation test and the cutoff-form thresholds use
+    // the largest core; the near field evaluates each pair with its source's core
+    c.var_sigma = c.hb.sig_max > c.hb.sig_min * (1.0 + 1e-6);
     c.sigma_uniform = (float)c.hb.sig_max;
     {
         // the float32 near field works in lengths scaled by kappa ~ 1/sigma: keep
         // kappa x (domain extent) below 2^24 so that rho'^-5 stays a normal float
         double ext = c.prm.periodic ? c.prm.box_len : 0.0;
         for (int d = 0; d < 3; ++d) ext = std::max(ext, c.hb.hi[d] - c.hb.lo[d]);
-        if (c.prm.precision != VFMM_PRECISION_FP64 && ext * p2p_kappa(c.sigma_uniform) >= 16777216.0)
+        if (c.prm.precision != VFMM_PRECISION_FP64 && ext * p2p_kappa(c.hb.sig_min) >= 16777216.0)
             throw Error{VFMM_EINVAL, "cores too small for the domain: extent / sigma must stay below about 2e7"};
     }
     if (c.prm.direct) {

@@ -93,7 +93,11 @@ struct Tgt {
 // more issue slots than it saves.
 __device__ __forceinline__ void to_vgpr(float &a) { asm("" : "+v"(a)); }
 
-template <int V, int SCHEME, bool MASK>
+// VAR (per-source cores): records hold unscaled leaf-local offsets and
+// kappa_j^2, 1/kappa_j, kappa_j^3 of the source in their fourth components;
+// the cutoff is evaluated at r' = kappa_j r and the powers of 1/rho are
+// unscaled, with ah = a alpha/(4 pi) (the same sums, kappa folded per pair).
+template <int V, int SCHEME, bool MASK, bool VAR>
 __device__ __forceinline__ void pair(const P2PConst &k, const Tgt &t, float4 sp, float4 sa, float4 sb, bool ok,
                                      Acc9 &p) {
     const float dx = t.y0 - sp.x, dy = t.y1 - sp.y, dz = t.y2 - sp.z;
@@ -106,25 +110,31 @@ __device__ __forceinline__ void pair(const P2PConst &k, const Tgt &t, float4 sp,
         F = k.inv_a * rinv3;
         H = F * rinv2;
     } else {
-        const float E = __builtin_amdgcn_exp2f(-r2);
-        const float rho = r2 * rinv;
+        const float r2s = VAR ? r2 * sp.w : r2;      // (kappa_j rho)^2
+        const float rinvs = VAR ? rinv * sa.w : rinv;  // 1 / (kappa_j rho)
+        const float E = __builtin_amdgcn_exp2f(-r2s);
+        const float rho = r2s * rinvs;
         float pe = k.pe[VFMM_ERFCX_DEG];
 #pragma unroll
-        for (int i = VFMM_ERFCX_DEG - 1; i >= 0; --i) pe = fmaf(pe, rinv, k.pe[i]);
-        const float w3 = fmaf(rinv, pe, rho);
+        for (int i = VFMM_ERFCX_DEG - 1; i >= 0; --i) pe = fmaf(pe, rinvs, k.pe[i]);
+        const float w3 = fmaf(rinvs, pe, rho);
         const float g3 = fmaf(-E, w3, k.inv_a);
-        const float w5 = fmaf(r2 * rho, k.b, w3);
+        const float w5 = fmaf(r2s * rho, k.b, w3);
         const float g5 = fmaf(-E, w5, k.inv_a);
         F = g3 * rinv3;
         H = (g5 * rinv3) * rinv2;
         if (V == 0) {
-            if (__any(r2 < k.r2_small)) {
+            if (__any(r2s < k.r2_small)) {
                 float q2 = k.q[VFMM_M2_DEG];
 #pragma unroll
-                for (int i = VFMM_M2_DEG - 1; i >= 0; --i) q2 = fmaf(q2, r2, k.q[i]);
-                const float Fs = E * fmaf(r2, q2, k.K3);  // 2^{-r2'} K3 1F1(1; 5/2; x)
-                const float Hs = E * q2;                  // 2^{-r2'} K5 1F1(1; 7/2; x)
-                const bool sm = r2 < k.r2_small;
+                for (int i = VFMM_M2_DEG - 1; i >= 0; --i) q2 = fmaf(q2, r2s, k.q[i]);
+                float Fs = E * fmaf(r2s, q2, k.K3);  // 2^{-r2'} K3 1F1(1; 5/2; x)
+                float Hs = E * q2;                   // 2^{-r2'} K5 1F1(1; 7/2; x)
+                if (VAR) {
+                    Fs *= sb.w;         // kappa_j^3
+                    Hs *= sb.w * sp.w;  // kappa_j^5
+                }
+                const bool sm = r2s < k.r2_small;
                 F = sm ? Fs : F;
                 H = sm ? Hs : H;
             }
@@ -165,18 +175,19 @@ __device__ __forceinline__ void pair(const P2PConst &k, const Tgt &t, float4 sp,
     }
 }
 
-template <int V, int SCHEME>
+template <int V, int SCHEME, bool VAR>
 __device__ __forceinline__ void leaf_loop(const P2PConst &k, const float4 *__restrict__ rec, int s0, int cnt,
                                           const Tgt &t, Acc9 &p) {
-    const float4 *src = rec + 3 * (size_t)s0;
+    constexpr int RS = VAR ? 4 : 3;  // float4 per record
+    const float4 *src = rec + RS * (size_t)s0;
     int j = 0;
     for (; j + 2 <= cnt; j += 2) {
-        const float4 sp0 = src[3 * j], sa0 = src[3 * j + 1], sb0 = src[3 * j + 2];
-        const float4 sp1 = src[3 * j + 3], sa1 = src[3 * j + 4], sb1 = src[3 * j + 5];
-        pair<V, SCHEME, false>(k, t, sp0, sa0, sb0, true, p);
-        pair<V, SCHEME, false>(k, t, sp1, sa1, sb1, true, p);
+        const float4 sp0 = src[RS * j], sa0 = src[RS * j + 1], sb0 = src[RS * j + 2];
+        const float4 sp1 = src[RS * j + RS], sa1 = src[RS * j + RS + 1], sb1 = src[RS * j + RS + 2];
+        pair<V, SCHEME, false, VAR>(k, t, sp0, sa0, sb0, true, p);
+        pair<V, SCHEME, false, VAR>(k, t, sp1, sa1, sb1, true, p);
     }
-    if (j < cnt) pair<V, SCHEME, false>(k, t, src[3 * j], src[3 * j + 1], src[3 * j + 2], true, p);
+    if (j < cnt) pair<V, SCHEME, false, VAR>(k, t, src[RS * j], src[RS * j + 1], src[RS * j + 2], true, p);
 }
 
 __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
@@ -191,29 +202,39 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
 // source of the leaf (vector loads, one address per group); the groups' sums
 // are added at the end.  A group past the last source re-reads the last one
 // with its cutoff factors forced to zero, which contributes exactly zero.
-template <int V, int SCHEME, int SPLIT>
+template <int V, int SCHEME, int SPLIT, bool VAR>
 __device__ __forceinline__ void leaf_loop_split(const P2PConst &k, const float4 *__restrict__ rec, int s0, int cnt,
                                                 int grp, const Tgt &t, Acc9 &p) {
-    const float4 *src = rec + 3 * (size_t)s0;
+    constexpr int RS = VAR ? 4 : 3;
+    const float4 *src = rec + RS * (size_t)s0;
     for (int j = 0; j < cnt; j += SPLIT) {
         const bool ok = j + grp < cnt;
         const int jj = ok ? j + grp : cnt - 1;
-        pair<V, SCHEME, true>(k, t, src[3 * jj], src[3 * jj + 1], src[3 * jj + 2], ok, p);
+        pair<V, SCHEME, true, VAR>(k, t, src[RS * jj], src[RS * jj + 1], src[RS * jj + 2], ok, p);
     }
 }
 
-template <int SCHEME, bool KAHAN, int SPLIT>
+template <int SCHEME, bool KAHAN, int SPLIT, bool VAR>
 __device__ __forceinline__ void p2p_block(const P2PConst &k, const P2PArgs &A, int t0, int tc, int l0, int lc) {
     const int lane = threadIdx.x & 63;
     constexpr int GL = 64 / SPLIT;  // lanes per group
     const int tl = lane % GL, grp = lane / GL;
     const bool valid = tl < tc;
     const int i = t0 + (valid ? tl : 0);
-    const float4 r0 = A.rec[3 * (size_t)i], r1 = A.rec[3 * (size_t)i + 1], r2 = A.rec[3 * (size_t)i + 2];
     Tgt t;
-    t.ai0 = r0.w;
-    t.ai1 = r1.w;
-    t.ai2 = r2.w;
+    float4 r0;
+    if (VAR) {
+        r0 = A.rec[4 * (size_t)i];
+        const float4 r3 = A.rec[4 * (size_t)i + 3];
+        t.ai0 = r3.x;
+        t.ai1 = r3.y;
+        t.ai2 = r3.z;
+    } else {
+        r0 = A.rec[3 * (size_t)i];
+        t.ai0 = r0.w;
+        t.ai1 = A.rec[3 * (size_t)i + 1].w;
+        t.ai2 = A.rec[3 * (size_t)i + 2].w;
+    }
     float S[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     float Cc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     P2PConst kv = k;  // the constants of the erfcx form, in vector registers
@@ -238,18 +259,18 @@ __device__ __forceinline__ void p2p_block(const P2PConst &k, const P2PArgs &A, i
         Acc9 p = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         if (SPLIT == 1) {
             if (var == 1)
-                leaf_loop<1, SCHEME>(kv, A.rec, s0, sc, t, p);
+                leaf_loop<1, SCHEME, VAR>(kv, A.rec, s0, sc, t, p);
             else if (var == 0)
-                leaf_loop<0, SCHEME>(kv, A.rec, s0, sc, t, p);
+                leaf_loop<0, SCHEME, VAR>(kv, A.rec, s0, sc, t, p);
             else
-                leaf_loop<2, SCHEME>(kv, A.rec, s0, sc, t, p);
+                leaf_loop<2, SCHEME, VAR>(kv, A.rec, s0, sc, t, p);
         } else {
             if (var == 1)
-                leaf_loop_split<1, SCHEME, SPLIT>(kv, A.rec, s0, sc, grp, t, p);
+                leaf_loop_split<1, SCHEME, SPLIT, VAR>(kv, A.rec, s0, sc, grp, t, p);
             else if (var == 0)
-                leaf_loop_split<0, SCHEME, SPLIT>(kv, A.rec, s0, sc, grp, t, p);
+                leaf_loop_split<0, SCHEME, SPLIT, VAR>(kv, A.rec, s0, sc, grp, t, p);
             else
-                leaf_loop_split<2, SCHEME, SPLIT>(kv, A.rec, s0, sc, grp, t, p);
+                leaf_loop_split<2, SCHEME, SPLIT, VAR>(kv, A.rec, s0, sc, grp, t, p);
         }
         float u0 = p.u0, u1 = p.u1, u2 = p.u2;
         if (SCHEME == VFMM_SCHEME_TRANSPOSE) {  // Ah x y_i - Bh
@@ -322,7 +343,7 @@ __device__ __forceinline__ void p2p_block(const P2PConst &k, const P2PArgs &A, i
     A.daz[o] = d2;
 }
 
-template <int SCHEME, bool KAHAN>
+template <int SCHEME, bool KAHAN, bool VAR>
 __global__ __launch_bounds__(256) void k_p2p(P2PConst k, P2PArgs A) {
     const int b = xcd_logical(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     if (b >= A.nblocks) return;
@@ -332,18 +353,23 @@ __global__ __launch_bounds__(256) void k_p2p(P2PConst k, P2PArgs A) {
     const int l0 = __builtin_amdgcn_readfirstlane(blk.z);
     const int lc = __builtin_amdgcn_readfirstlane(blk.w);
     if (tc <= 16)
-        p2p_block<SCHEME, KAHAN, 4>(k, A, t0, tc, l0, lc);
+        p2p_block<SCHEME, KAHAN, 4, VAR>(k, A, t0, tc, l0, lc);
     else if (tc <= 32)
-        p2p_block<SCHEME, KAHAN, 2>(k, A, t0, tc, l0, lc);
+        p2p_block<SCHEME, KAHAN, 2, VAR>(k, A, t0, tc, l0, lc);
     else
-        p2p_block<SCHEME, KAHAN, 1>(k, A, t0, tc, l0, lc);
+        p2p_block<SCHEME, KAHAN, 1, VAR>(k, A, t0, tc, l0, lc);
 }
 
-// Records of the float32 near field (sorted order), one wave per leaf:
+// Records of the float32 near field (sorted order), one wave per leaf.
+// Uniform cores (kappa the scale of the shared core):
 //   rec[3i] = (kappa (x_i - c_leaf), alpha_x), rec[3i+1] = (ah_i, alpha_y),
 //   rec[3i+2] = (ah_i x delta'_i, alpha_z),   ah = kappa^3 a alpha/(4 pi).
+// Per-source cores (kappa_j of each particle's own core):
+//   rec[4i] = (x_i - c_leaf, kappa_i^2), rec[4i+1] = (ah_i, 1/kappa_i),
+//   rec[4i+2] = (ah_i x delta_i, kappa_i^3), rec[4i+3] = (alpha_i, 0),  ah = a alpha/(4 pi).
 // Computed in float64 and rounded once.  A null cell list means one common
 // origin for every particle (direct mode).
+template <bool VAR>
 __global__ __launch_bounds__(256) void k_p2p_records(const int *__restrict__ leaves, int nleaves,
                                                      const int *__restrict__ start, const int *__restrict__ count,
                                                      const float4 *__restrict__ geo, int64_t n, double ox, double oy,
@@ -369,19 +395,30 @@ __global__ __launch_bounds__(256) void k_p2p_records(const int *__restrict__ lea
     const double fp = 12.566370614359172954;  // 4 pi: rec_in holds alpha/(4 pi)
     for (int64_t i = i0 + (threadIdx.x & 63); i < i1; i += 64) {
         const float4 p = rec_in[2 * i], a = rec_in[2 * i + 1];
-        const double d0 = kappa * ((double)p.x - cx), d1 = kappa * ((double)p.y - cy), d2 = kappa * ((double)p.z - cz);
+        // VAR: kappa argument = sqrt(log2 e)/sqrt(2), divided by each core
+        const double kap = VAR ? kappa / (double)p.w : kappa;
+        const double sc = VAR ? 1.0 : kappa;
+        const double d0 = sc * ((double)p.x - cx), d1 = sc * ((double)p.y - cy), d2 = sc * ((double)p.z - cz);
         const double h0 = sa * a.x, h1 = sa * a.y, h2 = sa * a.z;
-        out[3 * i] = make_float4((float)d0, (float)d1, (float)d2, (float)(fp * a.x));
-        out[3 * i + 1] = make_float4((float)h0, (float)h1, (float)h2, (float)(fp * a.y));
-        out[3 * i + 2] = make_float4((float)(h1 * d2 - h2 * d1), (float)(h2 * d0 - h0 * d2),
-                                     (float)(h0 * d1 - h1 * d0), (float)(fp * a.z));
+        const double b0 = h1 * d2 - h2 * d1, b1 = h2 * d0 - h0 * d2, b2 = h0 * d1 - h1 * d0;
+        if (VAR) {
+            out[4 * i] = make_float4((float)d0, (float)d1, (float)d2, (float)(kap * kap));
+            out[4 * i + 1] = make_float4((float)h0, (float)h1, (float)h2, (float)(1.0 / kap));
+            out[4 * i + 2] = make_float4((float)b0, (float)b1, (float)b2, (float)(kap * kap * kap));
+            out[4 * i + 3] = make_float4((float)(fp * a.x), (float)(fp * a.y), (float)(fp * a.z), 0.f);
+        } else {
+            out[3 * i] = make_float4((float)d0, (float)d1, (float)d2, (float)(fp * a.x));
+            out[3 * i + 1] = make_float4((float)h0, (float)h1, (float)h2, (float)(fp * a.y));
+            out[3 * i + 2] = make_float4((float)b0, (float)b1, (float)b2, (float)(fp * a.z));
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
 // Float64 reference form: the same work blocks and lists, one lane per
 // target, every quantity in double and the cutoff always in its full form:
-//   F = P(3/2, x)/rho^3,  H = P(5/2, x)/rho^5,  x = c^2 rho^2,  c = 1/(sqrt 2 sigma).
+//   F = P(3/2, x)/rho^3,  H = P(5/2, x)/rho^5,  x = c^2 rho^2,  c = 1/(sqrt 2 sigma_j)
+// of the source's own core (stored in the fourth component of its record).
 // For x < 2 the power series of the lower incomplete gamma function,
 //   P(a, x) = x^a e^{-x} sum_k x^k / Gamma(a + k + 1),
 // divided by rho^{2a}, gives F and H without cancellation (finite at rho = 0);
@@ -394,7 +431,7 @@ struct P2P64Args {
     const int4 *__restrict__ ent;
     int nblocks;
     int B;
-    double len, c, c2;
+    double len;
     const double *__restrict__ far_u;
     const double *__restrict__ far_da;
     int64_t n;
@@ -456,7 +493,8 @@ __global__ __launch_bounds__(64) void k_p2p64(P2P64Args A) {
             const double4 sp = A.rec[2 * (size_t)j], sa = A.rec[2 * (size_t)j + 1];
             const double dx = xi - sp.x, dy = yi - sp.y, dz = zi - sp.z;
             double F, H;
-            cutoff64(dx * dx + dy * dy + dz * dz, A.c, A.c2, F, H);
+            const double cj = sp.w;  // 1/(sqrt 2 sigma_j), stored in the float64 records
+            cutoff64(dx * dx + dy * dy + dz * dz, cj, cj * cj, F, H);
             const double c0 = sa.y * dz - sa.z * dy;
             const double c1 = sa.z * dx - sa.x * dz;
             const double c2 = sa.x * dy - sa.y * dx;
@@ -518,8 +556,6 @@ __global__ __launch_bounds__(64) void k_p2p64(P2P64Args A) {
 
 static void launch_p2p64(Ctx &c, P2P64Args A) {
     if (A.nblocks == 0) return;
-    A.c = 1.0 / (std::sqrt(2.0) * (double)c.sigma_uniform);
-    A.c2 = A.c * A.c;
     if (c.prm.scheme == VFMM_SCHEME_TRANSPOSE)
         k_p2p64<VFMM_SCHEME_TRANSPOSE><<<A.nblocks, 64, 0, c.stream>>>(A);
     else
@@ -528,7 +564,7 @@ static void launch_p2p64(Ctx &c, P2P64Args A) {
 }
 
 // Constants of the scaled form; every one but kappa is independent of sigma.
-static P2PConst make_const(double sigma) {
+static P2PConst make_const(double sigma, bool var) {
     P2PConst k{};
     const double lam = 1.0 / std::log(2.0);  // log2 e
     const double sqpi = std::sqrt(M_PI);
@@ -537,7 +573,7 @@ static P2PConst make_const(double sigma) {
     k.b = (float)(2.0 / (3.0 * lam));
     k.K3 = (float)(4.0 / (3.0 * sqpi) / (a * std::pow(lam, 1.5)));
     k.r2_small = (float)((double)VFMM_CUTOFF_XSPLIT * lam);
-    k.inv_kappa = (float)(1.0 / p2p_kappa(sigma));
+    k.inv_kappa = var ? 1.0f : (float)(1.0 / p2p_kappa(sigma));
     for (int i = 0; i <= VFMM_ERFCX_DEG; ++i)
         k.pe[i] = (float)((double)VFMM_ERFCX_C[i] * std::pow(lam, 0.5 * (i + 1)) / a);
     for (int i = 0; i <= VFMM_M2_DEG; ++i)
@@ -549,39 +585,48 @@ static P2PConst make_const(double sigma) {
 // leaf, offsets from the leaf centre; direct: from one common origin).
 static void p2p_records(Ctx &c, bool tree, const double *origin) {
     if (c.n == 0) return;
-    const double kap = p2p_kappa(c.sigma_uniform);
-    const double sa = kap * kap * kap * p2p_cutoff_a();
-    c.recp.ensure(sizeof(float4) * 3 * (size_t)c.n);
+    const bool var = c.var_sigma;
+    // uniform: kappa of the shared core and ah = kappa^3 a alpha/(4 pi); per source: the
+    // numerator of kappa_j and ah = a alpha/(4 pi)
+    const double kap = var ? p2p_kappa(1.0) : p2p_kappa(c.sigma_uniform);
+    const double sa = (var ? 1.0 : kap * kap * kap) * p2p_cutoff_a();
+    const int rs = var ? 4 : 3;
+    c.recp.ensure(sizeof(float4) * rs * (size_t)c.n);
     const double o0 = origin ? origin[0] : 0.0, o1 = origin ? origin[1] : 0.0, o2 = origin ? origin[2] : 0.0;
-    if (tree) {
-        k_p2p_records<<<cdiv(c.nleaves, 4), 256, 0, c.stream>>>(
-            c.leaves.as<int>(), c.nleaves, c.c_start.as<int>(), c.c_count.as<int>(), c.c_geo.as<float4>(), c.n, 0.0,
-            0.0, 0.0, kap, sa, c.rec.as<float4>(), c.recp.as<float4>());
-    } else {
-        k_p2p_records<<<cdiv(cdiv(c.n, 64), 4), 256, 0, c.stream>>>(nullptr, 0, nullptr, nullptr, nullptr, c.n, o0,
-                                                                     o1, o2, kap, sa, c.rec.as<float4>(),
-                                                                     c.recp.as<float4>());
-    }
+    const int *lv = tree ? c.leaves.as<int>() : nullptr;
+    const int nl = tree ? c.nleaves : 0;
+    const unsigned grid = tree ? cdiv(c.nleaves, 4) : cdiv(cdiv(c.n, 64), 4);
+    if (var)
+        k_p2p_records<true><<<grid, 256, 0, c.stream>>>(lv, nl, c.c_start.as<int>(), c.c_count.as<int>(),
+                                                        c.c_geo.as<float4>(), c.n, o0, o1, o2, kap, sa,
+                                                        c.rec.as<float4>(), c.recp.as<float4>());
+    else
+        k_p2p_records<false><<<grid, 256, 0, c.stream>>>(lv, nl, c.c_start.as<int>(), c.c_count.as<int>(),
+                                                         c.c_geo.as<float4>(), c.n, o0, o1, o2, kap, sa,
+                                                         c.rec.as<float4>(), c.recp.as<float4>());
     VFMM_LAUNCH_CHECK();
 }
 
 void p2p_prepare(Ctx &c) { p2p_records(c, true, nullptr); }
 
 template <int SCHEME, bool KAHAN>
-static void launch_p2p(const P2PConst &k, const P2PArgs &A, hipStream_t s) {
+static void launch_p2p(const P2PConst &k, const P2PArgs &A, bool var, hipStream_t s) {
     if (A.nblocks == 0) return;
-    k_p2p<SCHEME, KAHAN><<<xcd_grid(cdiv(A.nblocks, 4)), 256, 0, s>>>(k, A);
+    if (var)
+        k_p2p<SCHEME, KAHAN, true><<<xcd_grid(cdiv(A.nblocks, 4)), 256, 0, s>>>(k, A);
+    else
+        k_p2p<SCHEME, KAHAN, false><<<xcd_grid(cdiv(A.nblocks, 4)), 256, 0, s>>>(k, A);
     VFMM_LAUNCH_CHECK();
 }
 
 static void dispatch_p2p(Ctx &c, const P2PConst &k, const P2PArgs &A, hipStream_t s) {
     const bool kah = c.prm.kahan != 0 || c.prm.precision == VFMM_PRECISION_MIXED;
     if (c.prm.scheme == VFMM_SCHEME_TRANSPOSE) {
-        if (kah) launch_p2p<VFMM_SCHEME_TRANSPOSE, true>(k, A, s);
-        else launch_p2p<VFMM_SCHEME_TRANSPOSE, false>(k, A, s);
+        if (kah) launch_p2p<VFMM_SCHEME_TRANSPOSE, true>(k, A, c.var_sigma, s);
+        else launch_p2p<VFMM_SCHEME_TRANSPOSE, false>(k, A, c.var_sigma, s);
     } else {
-        if (kah) launch_p2p<VFMM_SCHEME_CLASSICAL, true>(k, A, s);
-        else launch_p2p<VFMM_SCHEME_CLASSICAL, false>(k, A, s);
+        if (kah) launch_p2p<VFMM_SCHEME_CLASSICAL, true>(k, A, c.var_sigma, s);
+        else launch_p2p<VFMM_SCHEME_CLASSICAL, false>(k, A, c.var_sigma, s);
     }
 }
 
@@ -603,7 +648,7 @@ static P2PArgs tree_args(Ctx &c) {
 // Near field alone, on stream s, into c.near (sorted order); the far field
 // runs meanwhile on the library stream and finalize_near_far adds the two.
 void p2p_near(Ctx &c, hipStream_t s) {
-    const P2PConst k = make_const(c.sigma_uniform);
+    const P2PConst k = make_const(c.sigma_uniform, c.var_sigma);
     c.near.ensure(sizeof(float) * 6 * (size_t)c.n);
     P2PArgs A = tree_args(c);
     A.near = c.near.as<float>();
@@ -666,7 +711,7 @@ void p2p_and_finalize(Ctx &c, float *ux, float *uy, float *uz, float *dax, float
         c.record(2 * PH_P2P + 1);
         return;
     }
-    const P2PConst k = make_const(c.sigma_uniform);
+    const P2PConst k = make_const(c.sigma_uniform, c.var_sigma);
     P2PArgs A = tree_args(c);
     A.far_u = c.far_u.as<float>();
     A.far_da = c.far_da.as<float>();
@@ -686,7 +731,7 @@ __global__ __launch_bounds__(256) void k_direct_setup64(int64_t n, const float *
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const double k = 0.079577471545947667884;  // 1/(4 pi)
-    rec[2 * i] = make_double4(x[i], y[i], z[i], s[i]);
+    rec[2 * i] = make_double4(x[i], y[i], z[i], 0.70710678118654752440 / (double)s[i]);  // 1/(sqrt 2 sigma)
     rec[2 * i + 1] = make_double4((double)ax[i] * k, (double)ay[i] * k, (double)az[i] * k, 0.0);
     perm[i] = (int)i;
 }
@@ -756,7 +801,7 @@ void direct_all_pairs(Ctx &c, const float *x, const float *y, const float *z, co
     const double org[3] = {0.5 * (c.hb.lo[0] + c.hb.hi[0]), 0.5 * (c.hb.lo[1] + c.hb.hi[1]),
                            0.5 * (c.hb.lo[2] + c.hb.hi[2])};
     p2p_records(c, false, org);
-    const P2PConst k = make_const(c.sigma_uniform);
+    const P2PConst k = make_const(c.sigma_uniform, c.var_sigma);
     P2PArgs A{};
     A.rec = c.recp.as<float4>();
     A.blocks = c.blocks.as<int4>();

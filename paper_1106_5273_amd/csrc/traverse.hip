@@ -354,7 +354,7 @@ void traverse_and_lists(Ctx &c) {
         E.r2_small = s2 * VFMM_CUTOFF_XSPLIT * 1.0001f;
         E.r2_sing = s2 * 26.0f;
         E.geo = c.c_geo.as<float4>();
-        E.kappa = p2p_kappa(c.sigma_uniform);
+        E.kappa = c.var_sigma ? 1.0 : p2p_kappa(c.sigma_uniform);  // per-source cores: unscaled offsets
         E.len64 = c.prm.periodic ? c.prm.box_len : 0.0;
         E.sh = f32 ? c.p2p_sh.as<float4>() : nullptr;
         k_p2p_gather<<<cdiv(n_p2p, TPB), TPB, 0, s>>>(E, c.p2p_raw.as<int4>(), c.lval.as<uint32_t>(), n_p2p,

@@ -386,8 +386,9 @@ void gather_strengths(Ctx &c, const float *ax, const float *ay, const float *az,
     VFMM_LAUNCH_CHECK();
 }
 
-// float64 records for the float64 form: positions and cores from the sorted
-// float32 records (exact), strengths from the caller's arrays scaled in float64
+// float64 records for the float64 form: positions from the sorted float32
+// records (exact), c = 1/(sqrt 2 sigma) of each core, strengths from the
+// caller's arrays scaled in float64
 __global__ __launch_bounds__(TPB) void k_gather_rec64(const int *perm, int64_t n, const float *ax, const float *ay,
                                                       const float *az, const float4 *rec, double4 *rec64) {
     const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
@@ -395,7 +396,7 @@ __global__ __launch_bounds__(TPB) void k_gather_rec64(const int *perm, int64_t n
     const int j = perm[i];
     const double k = 0.079577471545947667884;  // 1/(4 pi)
     const float4 p = rec[2 * i];
-    rec64[2 * i] = make_double4(p.x, p.y, p.z, p.w);
+    rec64[2 * i] = make_double4(p.x, p.y, p.z, 0.70710678118654752440 / (double)p.w);  // 1/(sqrt 2 sigma)
     rec64[2 * i + 1] = make_double4((double)ax[j] * k, (double)ay[j] * k, (double)az[j] * k, 0.0);
 }
 

@@ -91,6 +91,64 @@ def test_direct_p2p_fp64_form_matches_fp64_oracle(name, make, scheme):
     assert rel(da, ref["da_t" if scheme == 0 else "da_c"]) <= 1e-7
 
 
+def _varcore(case, seed, lo=0.6, hi=1.6):
+    """The same particles with per-particle cores sigma_j = sigma U(lo, hi)."""
+    rng = np.random.default_rng(seed)
+    c = dict(case)
+    c["sigma"] = (np.asarray(case["sigma"], np.float64) * rng.uniform(lo, hi, case["n"])).astype(np.float32)
+    return c
+
+
+@pytest.mark.parametrize("name,make", [
+    ("ring777", _ring),
+    ("cloud1000", lambda: wl.random_cloud(1000, seed=1, L=1.0, core=0.05)),
+    ("coincident", _dup),
+])
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_variable_cores_direct_matches_fp64(name, make, scheme):
+    """Per-source cores (Eq. 2 with sigma_j of each source): the float32 P2P
+    (cutoff evaluated at kappa_j r) and the float64 P2P against the oracle."""
+    case = _varcore(make(), 11)
+    ref = oracle.direct(case)
+    key = "da_t" if scheme == 0 else "da_c"
+    u, da = run(case, direct=1, scheme=scheme)
+    assert np.all(np.isfinite(u)) and np.all(np.isfinite(da))
+    assert rel(u, ref["u"]) <= 1e-5 and rel(da, ref[key]) <= 1e-5
+    u, da = run(case, direct=1, scheme=scheme, precision=2)
+    assert rel(u, ref["u"]) <= 1e-7 and rel(da, ref[key]) <= 1e-7
+
+
+def test_variable_cores_fmm_matches_fp64():
+    """The tree path with cores varying by a factor 3 against the direct
+    float64 sum: the separation test and the cutoff forms take the largest
+    core, each pair its source's core."""
+    case = _varcore(wl.random_cloud(12000, seed=12, L=1.0, core=0.02), 13, 0.5, 1.5)
+    ref = oracle.direct(case)
+    for prec in (0, 1, 2):
+        u, da = run(case, p=10, precision=prec)
+        e = (rel(u, ref["u"]), rel(da, ref["da_t"]))
+        print("variable cores, cloud 12000, p=10, precision=%d: u %.2e dalpha %.2e" % (prec, *e))
+        assert e[0] <= 1e-4 and e[1] <= 1e-4
+
+
+def test_variable_cores_path_agrees_with_uniform_path():
+    """Cores that differ by 1e-5 take the per-source path; its result equals
+    the uniform-core path's up to that perturbation (periodic 32^3 lattice)."""
+    case = wl.turbulence_case(32, seed=23)
+    kw = dict(p=10, periodic=1, box_len=2 * np.pi, images=3)
+    u0, d0 = run(case, **kw)
+    c1 = dict(case)
+    j = np.arange(case["n"])
+    c1["sigma"] = (np.asarray(case["sigma"], np.float64) * (1.0 + 1e-5 * (j % 3 == 0))).astype(np.float32)
+    u1, d1, ctx = run(c1, ret_ctx=True, **kw)
+    st = ctx.stats()
+    ctx.close()
+    assert st["sigma_max"] > st["sigma_min"]
+    e = (rel(u1, u0), rel(d1, d0))
+    print("per-source path vs uniform path: u %.2e dalpha %.2e" % e)
+    assert e[0] <= 2e-5 and e[1] <= 2e-5
+
+
 def test_direct_p2p_compensated_sum():
     case = wl.random_cloud(2000, seed=9, L=1.0, core=0.05)
     u, da = run(case, direct=1, kahan=1)
@@ -450,9 +508,11 @@ def test_abi_errors():
         with pytest.raises(vf.VfmmError, match="EDOMAIN"):
             ctx.build(bad, t[1], t[2], t[6])
         sig = t[6].clone()
-        sig[0] *= 2
-        with pytest.raises(vf.VfmmError, match="EINVAL"):
+        sig[0] = 0.0
+        with pytest.raises(vf.VfmmError, match="EDOMAIN"):
             ctx.build(t[0], t[1], t[2], sig)
+        sig[0] = 2 * t[6][0]
+        ctx.build(t[0], t[1], t[2], sig)  # per-particle cores are accepted
         e = torch.empty(0, device="cuda")
         ctx.build(e, e, e, e)
         ctx.evaluate(e, e, e, e, e, e, e)
