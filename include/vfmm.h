@@ -163,18 +163,20 @@ vfmm_status vfmm_set_params(vfmm_ctx *ctx, const vfmm_params *params);
 
 /* Build the octree and interaction lists for n particles (Sec. 3.2-3.3).
  * x, y, z, sigma: device float32[n].  The tree depends on positions only; the
- * cores enter the separation test (sigma_gap * max sigma).  n = 0 is allowed
+ * cores enter the separation test (sigma_gap * largest core) and the near
+ * field, where every pair uses its source's own core (Eq. 2); cores may differ
+ * per particle (equal cores take a faster near-field path).  n = 0 is allowed
  * (evaluate then writes nothing).  Errors: VFMM_EINVAL (null pointer, n < 0,
- * n >= 2^31, cores not uniform, or - float32 and mixed forms, whose near field
- * works in lengths scaled by 1/sigma - cores below 1/(2e7) of the domain
- * extent), VFMM_EDOMAIN (non-finite input; periodic position outside the
+ * n >= 2^31, or - float32 and mixed forms, whose near field works in lengths
+ * scaled by 1/sigma - cores below 1/(2e7) of the domain extent), VFMM_EDOMAIN
+ * (non-finite input or non-positive core; periodic position outside the
  * cube), VFMM_ENOMEM, VFMM_EHIP. */
 vfmm_status fmm_build(vfmm_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
                       const float *sigma);
 
 /* Evaluate u (Eq. 1) and dalpha/dt (Eq. 3, reading ctx scheme) at every
  * particle, using the tree of the last fmm_build, which must have been made
- * from the same n and positions (the library checks n only).  Inputs and
+ * from the same n, positions and cores (the library checks n only).  Inputs and
  * outputs are device float32[n].  Periodic with zero_mean: u is the zero-mean
  * periodic field (the cube-ordered image sum minus (1/3V) sum x_j x alpha_j).
  * Errors: VFMM_ESTATE (no build, or n differs), VFMM_EINVAL (null pointer,
