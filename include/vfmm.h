@@ -185,6 +185,24 @@ vfmm_status fmm_evaluate(vfmm_ctx *ctx, int64_t n, const float *x, const float *
                          const float *ax, const float *ay, const float *az, const float *sigma,
                          float *ux, float *uy, float *uz, float *dax, float *day, float *daz);
 
+/* Velocity at target points that are not particles (Eq. 1 holds at any point
+ * x; e.g. a probe lattice for spectra).  fmm_build_targets builds one tree
+ * over the n particles and the m target points (targets carry no strength
+ * and no core); fmm_evaluate_targets then evaluates, from the strengths of
+ * the n particles, u and dalpha/dt at the particles (as fmm_evaluate) and u
+ * at the targets.  Particle inputs are those of fmm_build / fmm_evaluate;
+ * tx, ty, tz: device float32[m]; outputs: device float32[n] (ux .. daz) and
+ * float32[m] (tux, tuy, tuz), all in the caller's order; m = 0 is allowed.
+ * The library keeps float32[13 (n + m)] of combined inputs and outputs.  A
+ * later fmm_build (or rk_step) ends the target set.  Errors: as fmm_build /
+ * fmm_evaluate; VFMM_EINVAL also for n < 1; VFMM_ESTATE when the last build
+ * was not fmm_build_targets with the same n and m. */
+vfmm_status fmm_build_targets(vfmm_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
+                              const float *sigma, int64_t m, const float *tx, const float *ty, const float *tz);
+vfmm_status fmm_evaluate_targets(vfmm_ctx *ctx, int64_t n, const float *ax, const float *ay, const float *az,
+                                 int64_t m, float *ux, float *uy, float *uz, float *dax, float *day, float *daz,
+                                 float *tux, float *tuy, float *tuz);
+
 /* Batched form: nprob independent free-space problems stored back to back in
  * the same arrays; problem b owns particles [offsets[b], offsets[b+1]).
  * offsets is a HOST int64 array of nprob+1 entries with offsets[0] = 0 and

@@ -119,6 +119,28 @@ def direct(case, targets=None, shifts=None):
     return dict(u=u, J=J, da_t=da_t, da_c=da_c)
 
 
+def direct_points(case, points, shifts=None):
+    """FP64 direct sum of Eq. (1) at arbitrary points (velocity and gradient;
+    the points carry no strength and are not sources).  ``points``: (m, 3).
+    Returns dict(u=(m,3), J=(m,3,3))."""
+    pts = _d(np.asarray(points, dtype=np.float64).reshape(-1, 3))
+    sx, sy, sz = _d(case["x"]), _d(case["y"]), _d(case["z"])
+    sax, say, saz = _d(case["ax"]), _d(case["ay"]), _d(case["az"])
+    ssig = _d(case["sigma"])
+    tx, ty, tz = _d(pts[:, 0]), _d(pts[:, 1]), _d(pts[:, 2])
+    if shifts is None:
+        nsh, sh = 0, np.zeros(3)
+    else:
+        sh = _d(np.asarray(shifts).reshape(-1, 3))
+        nsh = sh.shape[0]
+    nt = tx.size
+    u = np.empty((nt, 3))
+    J = np.empty((nt, 3, 3))
+    _lib().oracle_direct(nt, _p(tx), _p(ty), _p(tz), sx.size, _p(sx), _p(sy), _p(sz),
+                         _p(sax), _p(say), _p(saz), _p(ssig), nsh, _p(sh), _p(u), _p(J))
+    return dict(u=u, J=J)
+
+
 def image_shifts(M, L):
     """All lattice shifts n*L with |n|_inf <= M, ordered by shell."""
     r = np.arange(-M, M + 1)
@@ -141,7 +163,7 @@ def surface_term(case, L):
     return np.cross(x, a).sum(axis=0) / (3.0 * L ** 3)
 
 
-def fourier_points(case, L, kmax, targets=None):
+def fourier_points(case, L, kmax, targets=None, points=None):
     """Zero-mean periodic velocity and gradient by the Fourier series summed
     over wavevectors k = 2 pi m / L, 0 < |m|_inf <= kmax (tiny N; uniform sigma).
 
@@ -151,6 +173,8 @@ def fourier_points(case, L, kmax, targets=None):
     x = np.stack([_d(case["x"]), _d(case["y"]), _d(case["z"])], axis=1)
     a = np.stack([_d(case["ax"]), _d(case["ay"]), _d(case["az"])], axis=1)
     xt = x if targets is None else x[np.asarray(targets)]
+    if points is not None:  # arbitrary evaluation points (m, 3)
+        xt = np.asarray(points, dtype=np.float64).reshape(-1, 3)
     r = np.arange(-kmax, kmax + 1)
     m = np.stack(np.meshgrid(r, r, r, indexing="ij"), axis=-1).reshape(-1, 3)
     m = m[np.any(m != 0, axis=1)]

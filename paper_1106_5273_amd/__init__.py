@@ -68,6 +68,8 @@ _lib.rk_step.argtypes = [_vp, _i64, ctypes.c_float, ctypes.c_float] + [_vp] * 7
 _lib.vfmm_autotune.argtypes = [_vp, _i64] + [_vp] * 7 + [ctypes.c_float, ctypes.c_char_p, ctypes.POINTER(TuneResult)]
 _lib.fmm_build_batched.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)] + [_vp] * 4
 _lib.fmm_evaluate_batched.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)] + [_vp] * 13
+_lib.fmm_build_targets.argtypes = [_vp, _i64] + [_vp] * 4 + [_i64] + [_vp] * 3
+_lib.fmm_evaluate_targets.argtypes = [_vp, _i64] + [_vp] * 3 + [_i64] + [_vp] * 9
 _lib.vfmm_get_timings.argtypes = [_vp, ctypes.POINTER(Timings)]
 _lib.vfmm_get_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
 _lib.vfmm_copy_lists.argtypes = [_vp] + [_i32p] * 9
@@ -76,12 +78,14 @@ _lib.vfmm_last_error.restype = ctypes.c_char_p
 _lib.vfmm_destroy.argtypes = [_vp]
 _lib.vfmm_destroy.restype = None
 for _f in ("vfmm_create", "vfmm_set_params", "fmm_build", "fmm_evaluate", "rk_step", "vfmm_get_timings",
-           "vfmm_get_stats", "vfmm_copy_lists", "fmm_build_batched", "fmm_evaluate_batched", "vfmm_autotune"):
+           "vfmm_get_stats", "vfmm_copy_lists", "fmm_build_batched", "fmm_evaluate_batched", "vfmm_autotune",
+           "fmm_build_targets", "fmm_evaluate_targets"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("vfmm_default_params", "vfmm_create", "vfmm_set_params", "fmm_build", "fmm_evaluate", "rk_step",
             "vfmm_get_timings", "vfmm_get_stats", "vfmm_copy_lists", "vfmm_last_error", "vfmm_destroy",
-            "fmm_build_batched", "fmm_evaluate_batched", "vfmm_autotune")
+            "fmm_build_batched", "fmm_evaluate_batched", "vfmm_autotune", "fmm_build_targets",
+            "fmm_evaluate_targets")
 
 
 class VfmmError(RuntimeError):
@@ -129,6 +133,7 @@ class Context:
             raise VfmmError(st, _lib.vfmm_last_error(None).decode())
         self._h = h
         self.params = params
+        self._targets = (0, 0)
 
     def _raise(self, st):
         if st != VFMM_OK:
@@ -166,6 +171,29 @@ class Context:
             out = tuple(torch.empty(n, dtype=torch.float32, device=x.device) for _ in range(6))
         args = [_ptr(t) for t in (x, y, z, ax, ay, az, sigma)] + [_ptr(t) for t in out]
         self._raise(_lib.fmm_evaluate(self._h, n, *args))
+        return out
+
+    def build_targets(self, x, y, z, sigma, tx, ty, tz):
+        """One tree over the particles and the target points (which carry no strength)."""
+        n, m = x.numel(), tx.numel()
+        for t, nm in ((x, "x"), (y, "y"), (z, "z"), (sigma, "sigma")):
+            _check_tensor(t, n, nm)
+        for t, nm in ((tx, "tx"), (ty, "ty"), (tz, "tz")):
+            _check_tensor(t, m, nm)
+        self._raise(_lib.fmm_build_targets(self._h, n, _ptr(x), _ptr(y), _ptr(z), _ptr(sigma), m, _ptr(tx),
+                                           _ptr(ty), _ptr(tz)))
+        self._targets = (n, m)
+
+    def evaluate_targets(self, ax, ay, az, out=None):
+        """Returns (ux, uy, uz, dax, day, daz) at the particles and (tux, tuy, tuz) at the targets."""
+        import torch
+        n, m = self._targets
+        for t, nm in ((ax, "ax"), (ay, "ay"), (az, "az")):
+            _check_tensor(t, n, nm)
+        if out is None:
+            out = tuple(torch.empty(n if k < 6 else m, dtype=torch.float32, device=ax.device) for k in range(9))
+        self._raise(_lib.fmm_evaluate_targets(self._h, n, _ptr(ax), _ptr(ay), _ptr(az), m,
+                                              *[_ptr(t) for t in out]))
         return out
 
     def rk_step(self, dt, nu, x, y, z, ax, ay, az, sigma):

@@ -12,7 +12,7 @@ void Ctx::release_all() {
     DevBuf *bufs[] = {&bpart, &bres, &keyA, &keyB, &valA, &valB, &hist, &scanA, &scanB, &scanC, &perm, &rec, &rec64,
                       &c_start, &c_count, &c_parent, &c_child, &c_nchild, &c_level, &c_geo, &c_rad, &c_lo, &c_hi,
                       &c_tmp, &leaves, &frA, &frB, &tcnt, &m2l_raw, &p2p_raw, &lkey, &lkey2, &lval, &lval2,
-                      &m2l_off, &m2l_src, &p2p_off, &p2p_ent, &p2p_sh, &recp, &blocks, &pairs64, &Mexp, &Lexp, &lat_op, &far_u,
+                      &m2l_off, &m2l_src, &p2p_off, &p2p_ent, &p2p_sh, &recp, &tgt, &blocks, &pairs64, &Mexp, &Lexp, &lat_op, &far_u,
                       &far_da, &near, &dsurf, &rk, &m2l_tgt, &mb_eq, &mb_flag, &mb_pos, &mb_kid, &mb_ukey,
                       &mb_tab, &mb_bcells, &mb_ent, &mb_groups, &mb_blk, &mb_items, &mb_mr, &mb_partial, &mb_cls, &mb_cellbs, &mb_gcnt, &mb_gid, &mb_goff, &mb_gcur, &pid, &pbox, &poff, &tune_ref, &tune_out, &tune_part};
     for (DevBuf *b : bufs) b->release();
@@ -446,6 +446,12 @@ vfmm_status vfmm_set_params(vfmm_ctx *ctx, const vfmm_params *params) {
     }
 }
 
+// [a, a + na floats) and [b, b + nb floats) intersect
+static bool overlaps_ab(const void *a, int64_t na, const void *b, int64_t nb) {
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    return pa < pb + 4 * nb && pb < pa + 4 * na;
+}
+
 static bool overlaps(const void *a, const void *b, int64_t n) {
     const char *pa = (const char *)a, *pb = (const char *)b;
     const int64_t bytes = n * (int64_t)sizeof(float);
@@ -461,10 +467,112 @@ vfmm_status fmm_build(vfmm_ctx *ctx, int64_t n, const float *x, const float *y, 
         c.err.clear();
         c.nprob = 1;
         c.last_was_rk = false;
+        c.tg_n = -1;
         vfmm::do_build(c, n, x, y, z, sigma);
         return VFMM_OK;
     } catch (const Error &e) {
         c.built = false;
+        return vfmm::fail(&c, e);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Separate target points: the particles and the m target points share one
+// tree (the targets carry zero strength, so they add nothing to any sum) and
+// one evaluation; the caller's outputs are copied out of the combined ones.
+// ---------------------------------------------------------------------------
+namespace vfmm {
+__global__ __launch_bounds__(256) void k_fill_first(int64_t m, const float *src, float *dst) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < m) dst[i] = src[0];
+}
+
+static void copy_d2d(Ctx &c, float *dst, const float *src, int64_t n) {
+    if (n > 0) VFMM_HIP(hipMemcpyAsync(dst, src, sizeof(float) * n, hipMemcpyDeviceToDevice, c.stream));
+}
+}  // namespace vfmm
+
+vfmm_status fmm_build_targets(vfmm_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
+                              const float *sigma, int64_t m, const float *tx, const float *ty, const float *tz) {
+    if (!ctx) return VFMM_EINVAL;
+    Ctx &c = ctx->c;
+    try {
+        if (n < 1 || m < 0 || n + m >= (1LL << 31)) throw Error{VFMM_EINVAL, "need n >= 1, m >= 0, n + m < 2^31"};
+        if (!x || !y || !z || !sigma || (m > 0 && (!tx || !ty || !tz))) throw Error{VFMM_EINVAL, "null input pointer"};
+        c.err.clear();
+        c.nprob = 1;
+        c.last_was_rk = false;
+        c.tg_n = -1;
+        const int64_t N = n + m;
+        c.tgt.ensure(sizeof(float) * 13 * (size_t)N);
+        float *X = c.tgt.as<float>(), *Y = X + N, *Z = Y + N, *S = Z + N;
+        copy_d2d(c, X, x, n);
+        copy_d2d(c, Y, y, n);
+        copy_d2d(c, Z, z, n);
+        copy_d2d(c, S, sigma, n);
+        copy_d2d(c, X + n, tx, m);
+        copy_d2d(c, Y + n, ty, m);
+        copy_d2d(c, Z + n, tz, m);
+        if (m > 0) {
+            vfmm::k_fill_first<<<vfmm::cdiv(m, 256), 256, 0, c.stream>>>(m, sigma, S + n);  // any particle's core
+            VFMM_LAUNCH_CHECK();
+        }
+        vfmm::do_build(c, N, X, Y, Z, S);
+        c.tg_n = n;
+        c.tg_m = m;
+        return VFMM_OK;
+    } catch (const Error &e) {
+        c.built = false;
+        c.tg_n = -1;
+        return vfmm::fail(&c, e);
+    }
+}
+
+vfmm_status fmm_evaluate_targets(vfmm_ctx *ctx, int64_t n, const float *ax, const float *ay, const float *az,
+                                 int64_t m, float *ux, float *uy, float *uz, float *dax, float *day, float *daz,
+                                 float *tux, float *tuy, float *tuz) {
+    if (!ctx) return VFMM_EINVAL;
+    Ctx &c = ctx->c;
+    try {
+        if (!c.built || c.tg_n < 0 || n != c.tg_n || m != c.tg_m)
+            throw Error{VFMM_ESTATE, "fmm_evaluate_targets needs a prior fmm_build_targets with the same n and m"};
+        if (!ax || !ay || !az) throw Error{VFMM_EINVAL, "null input pointer"};
+        float *op[6] = {ux, uy, uz, dax, day, daz};
+        float *tp[3] = {tux, tuy, tuz};
+        for (float *p : op)
+            if (!p) throw Error{VFMM_EINVAL, "null output pointer"};
+        for (float *p : tp)
+            if (m > 0 && !p) throw Error{VFMM_EINVAL, "null output pointer"};
+        const void *in[3] = {ax, ay, az};
+        for (int a = 0; a < 9; ++a) {
+            void *pa = a < 6 ? (void *)op[a] : (void *)tp[a - 6];
+            const int64_t la = a < 6 ? n : m;
+            if (la == 0) continue;
+            for (int b = a + 1; b < 9; ++b) {
+                void *pb = b < 6 ? (void *)op[b] : (void *)tp[b - 6];
+                const int64_t lb = b < 6 ? n : m;
+                if (lb > 0 && overlaps_ab(pa, la, pb, lb)) throw Error{VFMM_EINVAL, "output arrays overlap"};
+            }
+            for (const void *p : in)
+                if (overlaps_ab(pa, la, p, n)) throw Error{VFMM_EINVAL, "an output aliases an input"};
+        }
+        c.err.clear();
+        const int64_t N = n + m;
+        float *X = c.tgt.as<float>(), *Y = X + N, *Z = Y + N, *S = Z + N;
+        float *AX = S + N, *AY = AX + N, *AZ = AY + N, *O = AZ + N;
+        copy_d2d(c, AX, ax, n);
+        copy_d2d(c, AY, ay, n);
+        copy_d2d(c, AZ, az, n);
+        if (m > 0) {
+            VFMM_HIP(hipMemsetAsync(AX + n, 0, sizeof(float) * m, c.stream));
+            VFMM_HIP(hipMemsetAsync(AY + n, 0, sizeof(float) * m, c.stream));
+            VFMM_HIP(hipMemsetAsync(AZ + n, 0, sizeof(float) * m, c.stream));
+        }
+        vfmm::do_evaluate(c, N, X, Y, Z, AX, AY, AZ, S, O, O + N, O + 2 * N, O + 3 * N, O + 4 * N, O + 5 * N);
+        for (int k = 0; k < 6; ++k) copy_d2d(c, op[k], O + k * N, n);
+        for (int k = 0; k < 3; ++k) copy_d2d(c, tp[k], O + k * N + n, m);
+        return VFMM_OK;
+    } catch (const Error &e) {
         return vfmm::fail(&c, e);
     }
 }

@@ -79,6 +79,9 @@ struct Ctx {
     DevBuf dsurf;                        // float[4] surface velocity term
     // rk_step stage storage
     DevBuf rk;                           // float [19 n]
+    // separate target points: combined inputs/outputs x y z sigma ax ay az + 6 outputs, float[13 (n + m)]
+    DevBuf tgt;
+    int64_t tg_n = -1, tg_m = 0;         // particles and targets of the last fmm_build_targets (-1: none)
     // autotuner scratch
     DevBuf tune_ref, tune_out, tune_part;
 

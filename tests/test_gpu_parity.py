@@ -653,3 +653,67 @@ def test_autotune_meets_bound_and_reuses_cache(tmp_path):
         assert (r2["p"], r2["ncrit"]) == (r["p"], r["ncrit"]) and abs(r2["theta"] - r["theta"]) < 1e-6
         assert abs(r2["sigma_gap"] - r["sigma_gap"]) < 1e-6 and r["sigma_gap"] in (4.0, 5.0, 6.0)
         assert (ctx.params.p, ctx.params.ncrit) == (r["p"], r["ncrit"])
+
+
+# ----------------------------------------------------------------------------
+# separate target points (velocity at points that are not particles)
+# ----------------------------------------------------------------------------
+def _run_targets(case, pts, **kw):
+    import torch
+    vf = _vf()
+    t = vf.case_to_device(case)
+    T = [torch.tensor(np.ascontiguousarray(pts[:, k], dtype=np.float32), device="cuda") for k in range(3)]
+    with vf.Context(**kw) as ctx:
+        ctx.build_targets(t[0], t[1], t[2], t[6], *T)
+        out = ctx.evaluate_targets(t[3], t[4], t[5])
+        torch.cuda.synchronize()
+    st = lambda o: np.stack([x.cpu().numpy() for x in o], 1).astype(np.float64)
+    return st(out[:3]), st(out[3:6]), st(out[6:9])
+
+
+def test_targets_free_space_match_oracle():
+    """u at 3,000 points in, on and far around a cloud (p = 10) against the
+    float64 direct sum at those points; the particles' own outputs as from
+    fmm_evaluate."""
+    rng = np.random.default_rng(42)
+    case = wl.random_cloud(6000, seed=40, L=1.0, core=0.03)
+    on = np.stack([case["x"], case["y"], case["z"]], 1)[:100]
+    pts = np.concatenate([rng.uniform(-0.1, 1.1, (2800, 3)), on, rng.uniform(-5.0, 5.0, (100, 3))])
+    pts = pts.astype(np.float32).astype(np.float64)
+    u, da, tu = _run_targets(case, pts, p=10)
+    ref = oracle.direct_points(case, pts)
+    refp = oracle.direct(case)
+    e = (rel(tu, ref["u"]), rel(u, refp["u"]), rel(da, refp["da_t"]))
+    print("targets free space: u(targets) %.2e u %.2e dalpha %.2e" % e)
+    assert e[0] <= 1e-5 and e[1] <= 1e-5 and e[2] <= 1e-5
+
+
+def test_targets_periodic_match_fourier_series():
+    """Periodic: u at random points of the cube against the zero-mean Fourier series."""
+    rng = np.random.default_rng(43)
+    case = wl.random_cloud(300, seed=41, L=2 * np.pi, core=0.5, zero_mean=True, periodic=True)
+    pts = rng.uniform(0.0, 2 * np.pi, (400, 3)).astype(np.float32).astype(np.float64)
+    u, da, tu = _run_targets(case, pts, p=10, ncrit=16, periodic=1, box_len=2 * np.pi, images=6)
+    us, _ = oracle.fourier_points(case, 2 * np.pi, kmax=18, points=pts)
+    e = rel(tu, us)
+    print("targets periodic: rel-L2 u %.3e" % e)
+    assert e <= 1e-4
+
+
+def test_targets_state_and_empty_target_set():
+    import torch
+    vf = _vf()
+    case = _ring(500, seed=6)
+    t = vf.case_to_device(case)
+    e = torch.empty(0, device="cuda")
+    with vf.Context() as ctx:
+        ctx.build(t[0], t[1], t[2], t[6])
+        ctx._targets = (case["n"], 0)
+        with pytest.raises(vf.VfmmError, match="ESTATE"):
+            ctx.evaluate_targets(t[3], t[4], t[5])
+        ctx.build_targets(t[0], t[1], t[2], t[6], e, e, e)
+        u0 = ctx.evaluate_targets(t[3], t[4], t[5])
+        u1 = ctx.evaluate(*t)
+        torch.cuda.synchronize()
+        for a, b in zip(u0[:6], u1):
+            assert torch.equal(a, b)  # m = 0: the same tree and sums as fmm_evaluate

@@ -271,3 +271,35 @@ def test_paper_table1_flop_convention():
     assert sum(st.values()) == t["total_stretching"] == 104
     pf = 4096 * 256 ** 3 * 19 * 512 * (70 + 104) / 108.0
     assert abs(pf / 1e15 - t["sustained_pflops"]) < 0.01
+
+
+# ----------------------------------------------------------------------------
+# Eq. (1) at points that are not particles (separate target sets)
+# ----------------------------------------------------------------------------
+def test_points_far_field_is_singular_biot_savart_of_total_strength():
+    """Far from a compact cloud every cutoff is 1 and u -> (sum alpha) x x / (4 pi |x|^3),
+    with a relative correction of order (cloud size / distance)."""
+    case = _cloud(60, seed=8)
+    A = np.array([np.sum(case["ax"]), np.sum(case["ay"]), np.sum(case["az"])], dtype=np.float64)
+    c0 = np.array([np.mean(case["x"]), np.mean(case["y"]), np.mean(case["z"])], dtype=np.float64)
+    d = np.array([[1.0, 0.3, -0.2], [-0.4, 1.0, 0.7], [0.2, -0.6, -1.0]])
+    for R in (1e3, 1e4):
+        pts = c0 + R * d
+        u = oracle.direct_points(case, pts)["u"]
+        r = pts - c0
+        ref = np.cross(A, r) / (4 * np.pi * np.linalg.norm(r, axis=1)[:, None] ** 3)
+        err = np.abs(u - ref).max() / np.abs(ref).max()
+        assert err <= 10.0 / R, (R, err)
+
+
+def test_points_match_particle_sums_and_are_divergence_free():
+    """At the particles' own positions the point sum equals the particle sum
+    (the self pair contributes nothing), and off the particles tr J = 0."""
+    case = _cloud(70, seed=9)
+    pts = np.stack([case["x"], case["y"], case["z"]], axis=1).astype(np.float64)
+    a = oracle.direct_points(case, pts)
+    b = oracle.direct(case)
+    assert np.allclose(a["u"], b["u"], rtol=0, atol=1e-14 * np.abs(b["u"]).max())
+    off = np.random.default_rng(3).uniform(-0.2, 1.2, size=(50, 3))
+    J = oracle.direct_points(case, off)["J"]
+    assert np.abs(J[:, 0, 0] + J[:, 1, 1] + J[:, 2, 2]).max() <= 1e-12 * np.abs(J).max()
