@@ -45,10 +45,11 @@ def parse():
     ap.add_argument("--no-overlap-pass", action="store_true",
                     help="skip the extra timing of the two-stream (overlap = 1) step (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "var"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "var", "targets"],
                     help="c2: 128^3 periodic step (default, the headline line); c3: 256^3 float32 vs "
                          "mixed vs float64 forms; c4: 512 batched ring problems vs sequential; c5: 256^3 "
-                         "autotuned RK2 step; var: 128^3 free space with per-particle cores vs uniform")
+                         "autotuned RK2 step; var: 128^3 free space with per-particle cores vs uniform; targets: "
+                         "128^3 particles and a 128^3 probe lattice")
     ap.add_argument("--microbench", action="store_true",
                     help="only measure VALU FP32 FMA / exp2 / rsq issue rates and exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -317,6 +318,67 @@ def bench_varcore(args, vf, wl):
     print(json.dumps(line), flush=True)
 
 
+def bench_targets(args, vf, wl):
+    """Velocity on a probe lattice that is not the particle lattice: the
+    128^3 turbulence-shaped particles in free space and 128^3 probe points at
+    the cell corners (offset h/2), one tree over both; against the particles
+    alone.  Error on 1,024 random probes against the float64 direct sum."""
+    import numpy as np
+    import torch
+    case = wl.turbulence_case(args.n, seed=2)
+    h = 2 * np.pi / args.n
+    g = np.arange(args.n) * h
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    pts = [np.ascontiguousarray(a.ravel(), dtype=np.float32) for a in (X, Y, Z)]
+    t = vf.case_to_device(case)
+    T = [torch.tensor(p, device="cuda") for p in pts]
+    res = {}
+
+    def timed(fn):
+        for _ in range(max(args.warmup, 1)):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / args.steps
+
+    ctx = vf.Context(p=args.p, theta=args.theta, ncrit=args.ncrit, periodic=0)
+    out = tuple(torch.empty(case["n"], dtype=torch.float32, device="cuda") for _ in range(6))
+    res["particles_only_ms_per_step"] = timed(lambda: (ctx.build(t[0], t[1], t[2], t[6]), ctx.evaluate(*t, out=out)))
+    ctx.close()
+    # the tree holds two points (a particle and a probe) per lattice cell: leaves of 2 ncrit points
+    ctx = vf.Context(p=args.p, theta=args.theta, ncrit=2 * args.ncrit, periodic=0)
+    outt = tuple(torch.empty(case["n"] if k < 6 else pts[0].size, dtype=torch.float32, device="cuda")
+                 for k in range(9))
+
+    def step():
+        ctx.build_targets(t[0], t[1], t[2], t[6], *T)
+        ctx.evaluate_targets(t[3], t[4], t[5], out=outt)
+
+    ms = timed(step)
+    st = ctx.stats()
+    res["with_targets_ms_per_step"] = ms
+    res["p2p_pairs"] = st["p2p_pairs"]
+    res["phases_ms"] = ctx.timings()
+    ctx.close()
+    if not args.no_check:
+        import oracle
+        idx = np.sort(np.random.default_rng(72).choice(pts[0].size, size=1024, replace=False))
+        P = np.stack([p[idx] for p in pts], 1).astype(np.float64)
+        ref = oracle.direct_points(case, P)
+        tu = np.stack([o.cpu().numpy() for o in outt[6:9]], 1).astype(np.float64)[idx]
+        res["rel_l2_u_targets_vs_oracle_1024"] = float(np.linalg.norm(tu - ref["u"]) / np.linalg.norm(ref["u"]))
+    m = pts[0].size
+    line = _line("velocity at %d^3 probe points beside %d^3 particles: step time" % (args.n, args.n),
+                 m / (ms * 1e-3) / 1e6, "Mtargets/s", ms, args,
+                 "free-space %d^3 turbulence-shaped lattice with a %d^3 probe lattice at the cell corners, p=%d, "
+                 "theta=%g, ncrit=%d (particles and probes); one tree over both, against the particles alone"
+                 % (args.n, args.n, args.p, args.theta, 2 * args.ncrit), res)
+    print(json.dumps(line), flush=True)
+
+
 def _time_overlap(ctx1, t, case, args, pairs):
     """Time the same steps with the near field on its own stream beside the far field."""
     import torch
@@ -379,6 +441,8 @@ def main():
         return bench_batched(args, vf, wl)
     if args.workload == "c5":
         return bench_rk(args, vf, wl)
+    if args.workload == "targets":
+        return bench_targets(args, vf, wl)
     if args.workload == "var":
         return bench_varcore(args, vf, wl)
     if args.workload == "c3":

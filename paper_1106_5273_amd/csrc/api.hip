@@ -12,7 +12,7 @@ void Ctx::release_all() {
     DevBuf *bufs[] = {&bpart, &bres, &keyA, &keyB, &valA, &valB, &hist, &scanA, &scanB, &scanC, &perm, &rec, &rec64,
                       &c_start, &c_count, &c_parent, &c_child, &c_nchild, &c_level, &c_geo, &c_rad, &c_lo, &c_hi,
                       &c_tmp, &leaves, &frA, &frB, &tcnt, &m2l_raw, &p2p_raw, &lkey, &lkey2, &lval, &lval2,
-                      &m2l_off, &m2l_src, &p2p_off, &p2p_ent, &p2p_sh, &recp, &tgt, &blocks, &pairs64, &Mexp, &Lexp, &lat_op, &far_u,
+                      &m2l_off, &m2l_src, &p2p_off, &p2p_ent, &p2p_sh, &recp, &tgt, &c_nsrc, &part, &blocks, &pairs64, &Mexp, &Lexp, &lat_op, &far_u,
                       &far_da, &near, &dsurf, &rk, &m2l_tgt, &mb_eq, &mb_flag, &mb_pos, &mb_kid, &mb_ukey,
                       &mb_tab, &mb_bcells, &mb_ent, &mb_groups, &mb_blk, &mb_items, &mb_mr, &mb_partial, &mb_cls, &mb_cellbs, &mb_gcnt, &mb_gid, &mb_goff, &mb_gcur, &pid, &pbox, &poff, &tune_ref, &tune_out, &tune_part};
     for (DevBuf *b : bufs) b->release();
@@ -174,6 +174,7 @@ static void do_build(Ctx &c, int64_t n, const float *x, const float *y, const fl
     }
     upload_lattice(c);
     build_tree(c, n, x, y, z, sigma);
+    if (c.n_src_part >= 0 && c.n_src_part < n) partition_sources(c, c.n_src_part);
     c.record(2 * PH_TRAVERSE);
     traverse_and_lists(c);
     c.m2lb_ok = false;
@@ -517,13 +518,16 @@ vfmm_status fmm_build_targets(vfmm_ctx *ctx, int64_t n, const float *x, const fl
             vfmm::k_fill_first<<<vfmm::cdiv(m, 256), 256, 0, c.stream>>>(m, sigma, S + n);  // any particle's core
             VFMM_LAUNCH_CHECK();
         }
+        c.n_src_part = n;  // the near field reads only the particles as sources
         vfmm::do_build(c, N, X, Y, Z, S);
+        c.n_src_part = -1;
         c.tg_n = n;
         c.tg_m = m;
         return VFMM_OK;
     } catch (const Error &e) {
         c.built = false;
         c.tg_n = -1;
+        c.n_src_part = -1;
         return vfmm::fail(&c, e);
     }
 }

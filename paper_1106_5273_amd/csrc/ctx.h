@@ -82,6 +82,9 @@ struct Ctx {
     // separate target points: combined inputs/outputs x y z sigma ax ay az + 6 outputs, float[13 (n + m)]
     DevBuf tgt;
     int64_t tg_n = -1, tg_m = 0;         // particles and targets of the last fmm_build_targets (-1: none)
+    int64_t n_src_part = -1;             // >= 0: callers' indices below it are sources, the rest targets
+    DevBuf c_nsrc;                       // per leaf: sources in front of its targets (partitioned builds)
+    DevBuf part;                         // partition scratch
     // autotuner scratch
     DevBuf tune_ref, tune_out, tune_part;
 
@@ -122,6 +125,7 @@ void compute_bounds(Ctx &c, int64_t n, const float *x, const float *y, const flo
 void build_tree(Ctx &c, int64_t n, const float *x, const float *y, const float *z, const float *sigma);
 void gather_strengths(Ctx &c, const float *ax, const float *ay, const float *az, const float *sigma);
 void gather_records64(Ctx &c, const float *ax, const float *ay, const float *az);
+void partition_sources(Ctx &c, int64_t n_src);
 void build_m2l_csr(Ctx &c);
 void p2p_prepare(Ctx &c);
 void p2p_near(Ctx &c, hipStream_t s);

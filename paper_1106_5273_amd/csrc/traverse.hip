@@ -164,6 +164,7 @@ struct P2PEntryArgs {
     float r2_small, r2_sing;  // thresholds on squared distance for the cutoff branches
     double kappa;             // length scale of the float32 near field
     double len64;             // period (0: free space)
+    const int *nsrc;          // partitioned builds: sources in front of each leaf's targets (else null)
     float4 *sh;               // out: kappa (c_t - c_s - image shift) per entry (null: not needed)
 };
 
@@ -189,7 +190,8 @@ __global__ __launch_bounds__(TPB) void k_p2p_gather(P2PEntryArgs A, const int4 *
         const float gz = fmaxf(0.f, fmaxf(sl.z + sz - th.z, tl.z - sh.z - sz));
         const float d2 = gx * gx + gy * gy + gz * gz;
         const int variant = d2 >= A.r2_sing ? 2 : (d2 >= A.r2_small ? 1 : 0);
-        out[i] = make_int4(A.start[s], A.count[s], e.z, variant);
+        const int sc = A.nsrc ? A.nsrc[s] : A.count[s];  // only sources enter the near field
+        out[i] = make_int4(A.start[s], sc, e.z, variant);
         if (A.sh) {
             const float4 ct = A.geo[t], cs = A.geo[s];
             const double L = A.len64;
@@ -198,7 +200,7 @@ __global__ __launch_bounds__(TPB) void k_p2p_gather(P2PEntryArgs A, const int4 *
             const double Dz = ((double)ct.z - (double)cs.z - (double)(e.z / (W * W) - A.B) * L) * A.kappa;
             A.sh[i] = make_float4((float)Dx, (float)Dy, (float)Dz, 0.f);
         }
-        np = (unsigned long long)A.count[t] * (unsigned long long)A.count[s];
+        np = (unsigned long long)A.count[t] * (unsigned long long)sc;
     }
     // block reduction of the pair count
     __shared__ unsigned long long sh[TPB];
@@ -356,6 +358,7 @@ void traverse_and_lists(Ctx &c) {
         E.geo = c.c_geo.as<float4>();
         E.kappa = c.var_sigma ? 1.0 : p2p_kappa(c.sigma_uniform);  // per-source cores: unscaled offsets
         E.len64 = c.prm.periodic ? c.prm.box_len : 0.0;
+        E.nsrc = c.n_src_part >= 0 && c.n_src_part < c.n ? c.c_nsrc.as<int>() : nullptr;
         E.sh = f32 ? c.p2p_sh.as<float4>() : nullptr;
         k_p2p_gather<<<cdiv(n_p2p, TPB), TPB, 0, s>>>(E, c.p2p_raw.as<int4>(), c.lval.as<uint32_t>(), n_p2p,
                                                        c.p2p_ent.as<int4>(),

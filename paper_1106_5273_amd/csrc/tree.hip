@@ -409,6 +409,64 @@ void gather_records64(Ctx &c, const float *ax, const float *ay, const float *az)
 }
 
 // ---------------------------------------------------------------------------
+// Separate target points: within every leaf the sources (caller index below
+// n_src) are moved in front of the targets (a stable partition of the leaf's
+// range, which leaves every cell's range unchanged), and each leaf records
+// its number of sources, so that the near field never reads a target as a
+// source.  One thread per leaf writes the new order of its range.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(TPB) void k_leaf_partition(int nl, const int *leaves, const int *start, const int *count,
+                                                        const int *perm, int64_t n_src, uint32_t *order,
+                                                        int *nsrc) {
+    const int l = blockIdx.x * TPB + threadIdx.x;
+    if (l >= nl) return;
+    const int cell = leaves[l];
+    const int s0 = start[cell], cnt = count[cell];
+    int w = s0;
+    for (int i = s0; i < s0 + cnt; ++i)
+        if (perm[i] < n_src) order[w++] = (uint32_t)i;
+    nsrc[cell] = w - s0;
+    for (int i = s0; i < s0 + cnt; ++i)
+        if (perm[i] >= n_src) order[w++] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(TPB) void k_apply_order(int64_t n, const uint32_t *order, const int *perm_in,
+                                                     const float4 *rec_in, const uint64_t *key_in, int *perm_out,
+                                                     float4 *pos_out, uint64_t *key_out) {
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t j = order[i];
+    perm_out[i] = perm_in[j];
+    pos_out[i] = rec_in[2 * (size_t)j];
+    key_out[i] = key_in[j];
+}
+
+void partition_sources(Ctx &c, int64_t n_src) {
+    hipStream_t s = c.stream;
+    const int64_t n = c.n;
+    c.c_nsrc.ensure(sizeof(int) * (size_t)c.ncells);
+    VFMM_HIP(hipMemsetAsync(c.c_nsrc.ptr, 0, sizeof(int) * (size_t)c.ncells, s));
+    c.valB.ensure(sizeof(uint32_t) * n);
+    c.keyB.ensure(sizeof(uint64_t) * n);
+    c.part.ensure(sizeof(int) * n + 16 + sizeof(float4) * n);
+    uint32_t *order = c.valB.as<uint32_t>();
+    k_leaf_partition<<<cdiv(c.nleaves, TPB), TPB, 0, s>>>(c.nleaves, c.leaves.as<int>(), c.c_start.as<int>(),
+                                                           c.c_count.as<int>(), c.perm.as<int>(), n_src, order,
+                                                           c.c_nsrc.as<int>());
+    VFMM_LAUNCH_CHECK();
+    // gather into scratch, then copy back (perm, position records, keys)
+    int *perm2 = c.part.as<int>();
+    float4 *rec2 = reinterpret_cast<float4 *>(c.part.as<char>() + ((sizeof(int) * n + 15) / 16) * 16);
+    k_apply_order<<<cdiv(n, TPB), TPB, 0, s>>>(n, order, c.perm.as<int>(), c.rec.as<float4>(), c.keyA.as<uint64_t>(),
+                                                perm2, rec2, c.keyB.as<uint64_t>());
+    VFMM_LAUNCH_CHECK();
+    VFMM_HIP(hipMemcpyAsync(c.perm.ptr, perm2, sizeof(int) * n, hipMemcpyDeviceToDevice, s));
+    VFMM_HIP(hipMemcpy2DAsync(c.rec.ptr, 2 * sizeof(float4), rec2, sizeof(float4), sizeof(float4), n,
+                              hipMemcpyDeviceToDevice, s));
+    VFMM_HIP(hipMemcpyAsync(c.keyA.ptr, c.keyB.ptr, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+}
+
+// ---------------------------------------------------------------------------
 // Octree, level by level.  A cell at level l holds a contiguous range of the
 // sorted keys sharing their top 3l bits; it is split while it holds more than
 // ncrit particles and l < 21.  Children of a cell are contiguous.
