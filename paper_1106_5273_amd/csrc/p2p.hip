@@ -1,9 +1,8 @@
 // Near field P2P (Sec. 3.1, Sec. 3.6) of the regularised Biot-Savart law and
-// the stretching term, Eqs. (1)-(3).  The tree path writes the near-field
-// results in sorted order and a finalize kernel adds the far field and
-// scatters to the caller's order (or, with the near field on a second
-// stream, into a buffer that the finalize kernel adds); the float64 form and
-// the direct mode finish in the P2P kernel itself.
+// the stretching term, Eqs. (1)-(3).  The P2P kernel adds the far field and
+// scatters to the caller's order itself; with the near field on a second
+// stream it writes its results in sorted order and a finalize kernel adds
+// them to the far field.
 //
 // Work item: one wave64 per block of <= 64 targets (one target per lane) of a
 // leaf; the wave walks the leaf's P2P list.  Source particles are the same
@@ -42,6 +41,10 @@
 //   full : some pair may have s < 1: Kummer series for s < 1, the erfcx form else;
 //   mid  : every pair has s >= 1: the erfcx form, no branch;
 //   sing : the float32 cutoff is 1 for every pair (s >= 5.1): G3 = G5 = 1/a.
+// Per-particle cores use unscaled offsets and evaluate the cutoff at
+// kappa_j r with each source's kappa_j (see pair()); a list entry's source
+// count covers only the sources of a leaf whose target points were moved
+// behind them.
 #include "ctx.h"
 #include "cutoff_fits.h"
 
@@ -58,7 +61,7 @@ struct P2PConst {
 };
 
 struct P2PArgs {
-    const float4 *__restrict__ rec;  // float4[3n]: (delta', alpha_x) (ah, alpha_y) (bh, alpha_z)
+    const float4 *__restrict__ rec;  // float4[3n] (uniform cores) or float4[4n] (per-particle cores) records
     const int4 *__restrict__ blocks;
     const int4 *__restrict__ ent;
     const float4 *__restrict__ sh;   // per entry: (D', 0)
