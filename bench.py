@@ -277,7 +277,7 @@ def bench_varcore(args, vf, wl):
     res, outs = {}, {}
     for name, c in (("uniform", case), ("per_particle", var)):
         t = vf.case_to_device(c)
-        ctx = vf.Context(p=args.p, theta=args.theta, ncrit=args.ncrit, periodic=0)
+        ctx = vf.Context(p=args.p, theta=args.theta, ncrit=args.ncrit, periodic=0, box_len=2 * np.pi)
         out = tuple(torch.empty(c["n"], dtype=torch.float32, device="cuda") for _ in range(6))
         for _ in range(max(args.warmup, 1)):
             ctx.build(t[0], t[1], t[2], t[6])
@@ -312,8 +312,8 @@ def bench_varcore(args, vf, wl):
     r = res["per_particle"]
     line = _line("per-particle cores at %d^3: step time" % args.n, r["p2p_pairs"] / (r["ms_per_step"] * 1e-3) / 1e9,
                  "Gpair/s", r["ms_per_step"], args,
-                 "free-space %d^3 turbulence-shaped lattice, sigma_j = 1.5 h U(0.75, 1.25) (seed 7), p=%d, "
-                 "theta=%g; the same particles with the uniform core beside it" % (args.n, args.p, args.theta),
+                 "free-space %d^3 turbulence-shaped lattice (root cube [0, 2 pi)^3), sigma_j = 1.5 h U(0.75, 1.25) "
+                 "(seed 7), p=%d, theta=%g; the same particles with the uniform core beside it" % (args.n, args.p, args.theta),
                  {"forms": res, "slowdown_vs_uniform": r["ms_per_step"] / res["uniform"]["ms_per_step"]})
     print(json.dumps(line), flush=True)
 
@@ -344,6 +344,8 @@ def bench_targets(args, vf, wl):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / args.steps
 
+    # root cube = bounding cube: a cube aligned with the particle lattice would put every probe on a
+    # cell face, where float32 rounding of the keys moves some probes into the neighbouring cell
     ctx = vf.Context(p=args.p, theta=args.theta, ncrit=args.ncrit, periodic=0)
     out = tuple(torch.empty(case["n"], dtype=torch.float32, device="cuda") for _ in range(6))
     res["particles_only_ms_per_step"] = timed(lambda: (ctx.build(t[0], t[1], t[2], t[6]), ctx.evaluate(*t, out=out)))

@@ -72,8 +72,12 @@ typedef struct vfmm_params {
     float sigma_gap;     /* M2L also requires D - R_A - R_B >= sigma_gap * sigma_max   default 5 */
     int32_t periodic;    /* 0 free space, 1 periodic cube [box_lo, box_lo + box_len)^3         */
     int32_t images;      /* periodic: K, image cells cover |n|_inf <= (3^K - 1)/2   default 3  */
-    double box_lo[3];    /* periodic cube corner                                               */
-    double box_len;      /* periodic cube side (> 0 when periodic)                             */
+    double box_lo[3];    /* periodic cube corner, or (free space, box_len > 0) root cube corner  */
+    double box_len;      /* periodic cube side (> 0 when periodic).  Free space: 0 (default) =
+                            the bounding cube of the particles; > 0 = the octree's root cube
+                            [box_lo, box_lo + box_len)^3, which must hold every position
+                            (VFMM_EDOMAIN otherwise; batched problems keep their own cubes):
+                            a cube aligned with a particle lattice gives regular cells       */
     int32_t scheme;      /* VFMM_SCHEME_TRANSPOSE (default) or VFMM_SCHEME_CLASSICAL          */
     int32_t kahan;       /* 1: compensated per-target sums in P2P (default 0: blocked sums)    */
     int32_t zero_mean;   /* periodic: subtract (1/3V) sum x_j x alpha_j (default 1)           */

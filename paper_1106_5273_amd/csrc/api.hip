@@ -53,7 +53,11 @@ static void validate(const vfmm_params &p) {
         if (!(p.box_len > 0.0) || !std::isfinite(p.box_len)) throw Error{VFMM_EINVAL, "periodic box_len must be > 0"};
         if (p.images < 1 || p.images > 12) throw Error{VFMM_EINVAL, "images must be in [1, 12]"};
         if (p.direct) throw Error{VFMM_EINVAL, "direct mode is free space only"};
+    } else if (!(p.box_len >= 0.0) || !std::isfinite(p.box_len)) {
+        throw Error{VFMM_EINVAL, "box_len must be >= 0 (free space: 0 = bounding cube of the particles)"};
     }
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(p.box_lo[d])) throw Error{VFMM_EINVAL, "box_lo must be finite"};
 }
 
 static void set_params(Ctx &c, const vfmm_params &p) {
@@ -138,6 +142,8 @@ static void do_build(Ctx &c, int64_t n, const float *x, const float *y, const fl
     VFMM_HIP(hipStreamSynchronize(s));
     if (c.hb.nonfinite) throw Error{VFMM_EDOMAIN, "non-finite position or non-positive core"};
     if (c.prm.periodic && c.hb.outside) throw Error{VFMM_EDOMAIN, "position outside the periodic cube"};
+    if (!c.prm.periodic && c.nprob == 1 && c.prm.box_len > 0.0 && c.hb.outside)
+        throw Error{VFMM_EDOMAIN, "position outside the root cube [box_lo, box_lo + box_len)"};
     if (c.nprob > 1 && (c.prm.periodic || c.prm.direct))
         throw Error{VFMM_EINVAL, "batched problems are free space and use the tree (periodic = 0, direct = 0)"};
     // per-source cores: the separation test and the cutoff-form thresholds use
@@ -156,7 +162,8 @@ static void do_build(Ctx &c, int64_t n, const float *x, const float *y, const fl
         c.built = true;
         return;
     }
-    if (c.prm.periodic) {
+    if (c.prm.periodic || (c.nprob == 1 && c.prm.box_len > 0.0)) {
+        // the periodic cell, or the root cube the caller fixed for a free-space tree
         for (int d = 0; d < 3; ++d) c.box.lo[d] = (float)c.prm.box_lo[d];
         c.box.len = (float)c.prm.box_len;
     } else if (c.nprob > 1) {

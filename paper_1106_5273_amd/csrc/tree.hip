@@ -131,7 +131,7 @@ __global__ __launch_bounds__(TPB) void k_bounds_partial(BoundsArgs A, BAcc *part
         if (!fin) { a.nf++; continue; }
         for (int d = 0; d < 3; ++d) { a.lo[d] = fmin(a.lo[d], p[d]); a.hi[d] = fmax(a.hi[d], p[d]); }
         a.smin = fmin(a.smin, sg); a.smax = fmax(a.smax, sg);
-        if (A.periodic) {
+        if (A.periodic || A.plen > 0.0) {  // the periodic cell, or a caller-given root cube
             for (int d = 0; d < 3; ++d)
                 if (!(p[d] >= A.plo[d] && p[d] < A.plo[d] + A.plen)) { a.out++; break; }
         }

@@ -717,3 +717,22 @@ def test_targets_state_and_empty_target_set():
         torch.cuda.synchronize()
         for a, b in zip(u0[:6], u1):
             assert torch.equal(a, b)  # m = 0: the same tree and sums as fmm_evaluate
+
+
+def test_free_space_root_cube_given_by_the_caller():
+    """Free space with box_len > 0: the octree's root cube is [box_lo, box_lo + box_len)^3
+    (same results as the bounding cube to the FMM error); a position outside it is refused."""
+    import torch
+    case = wl.random_cloud(5000, seed=50, L=1.0, core=0.03)
+    ref = oracle.direct(case)
+    u0, d0 = run(case, p=10)
+    u1, d1 = run(case, p=10, box_lo=(-0.5, -0.25, 0.0), box_len=2.0)
+    for u, d in ((u0, d0), (u1, d1)):
+        assert rel(u, ref["u"]) <= 1e-5 and rel(d, ref["da_t"]) <= 1e-5
+    vf = _vf()
+    t = vf.case_to_device(case)
+    with vf.Context(box_lo=(0.1, 0.0, 0.0), box_len=1.0) as ctx:
+        with pytest.raises(vf.VfmmError, match="EDOMAIN"):
+            ctx.build(t[0], t[1], t[2], t[6])
+    with pytest.raises(vf.VfmmError, match="EINVAL"):
+        vf.Context(box_len=-1.0)
