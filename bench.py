@@ -40,7 +40,7 @@ def parse():
                          "needed to fill the 64-lane P2P waves (a sweep over 128..1024 measured 384 fastest)")
     ap.add_argument("--images", type=int, default=6)
     ap.add_argument("--kahan", type=int, default=0)
-    ap.add_argument("--no-check", action="store_true", help="skip the accuracy check against the oracle")
+    ap.add_argument("--no-check", action="store_true", help="skip the accuracy check against stored FP64 oracle values")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-overlap-pass", action="store_true",
                     help="skip the extra timing of the two-stream (overlap = 1) step (profiling runs)")
@@ -64,6 +64,34 @@ def kernel_hash():
         with open(os.path.join(ROOT, "paper_1106_5273_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def golden(name, arrays):
+    """Stored FP64 oracle values at a seeded sample of targets of a workload
+    (``tests/golden/<name>``, written by ``tests/golden/make_bench_refs.py``):
+    returns (indices, values, reference).  Raises if the regenerated inputs
+    are not the ones the values were computed on."""
+    import numpy as np
+    import workloads as wl
+    path = os.path.join(ROOT, "tests", "golden", name)
+    ref, fp = "", None
+    with open(path) as f:
+        for line in f:
+            if not line.startswith("#"):
+                break
+            if line.startswith("# reference:"):
+                ref = line.split(":", 1)[1].strip()
+            elif line.startswith("# fingerprint"):
+                fp = [float(v) for v in line.split()[2:]]
+    if fp is None or not wl.checksum_matches(fp, wl.checksum(arrays)):
+        raise RuntimeError("%s was computed on other inputs than this workload's" % path)
+    tab = np.loadtxt(path, comments="#", ndmin=2)
+    return tab[:, 0].astype(np.int64), tab[:, 1:], ref
+
+
+def rel_l2(a, b):
+    import numpy as np
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def traffic_from_profile(pairs_per_launch):
@@ -245,14 +273,11 @@ def bench_precision(args, vf, wl):
     for name in ("fp32", "mixed"):
         res[name]["rel_l2_vs_fp64_form"] = {"u": rel(outs[name][0], u64), "dalpha": rel(outs[name][1], d64)}
     if not args.no_check:
-        import oracle
-        rng = np.random.default_rng(33)
-        idx = np.sort(rng.choice(case["n"], size=min(65536, case["n"]), replace=False))
-        us, Js = oracle.spectral_lattice(case)
-        das, _ = oracle.stretching(Js, np.stack([case["ax"], case["ay"], case["az"]], 1).astype(np.float64))
+        idx, ref, what = golden("bench_c3_%d.txt" % n1, wl.case_arrays(case))
         for name in ("fp64", "fp32", "mixed"):
-            res[name]["rel_l2_vs_oracle_65536"] = {"u": rel(outs[name][0][idx], us[idx]),
-                                                   "dalpha": rel(outs[name][1][idx], das[idx])}
+            res[name]["rel_l2_vs_oracle_%d" % idx.size] = {"u": rel(outs[name][0][idx], ref[:, :3]),
+                                                           "dalpha": rel(outs[name][1][idx], ref[:, 3:])}
+        res["oracle_reference"] = what
     ms = res["fp32"]["ms_per_step"]
     line = _line("precision forms at %d^3: step time and rounding error" % n1, st["p2p_pairs"] / (ms * 1e-3) / 1e9,
                  "Gpair/s", ms, args,
@@ -271,9 +296,7 @@ def bench_varcore(args, vf, wl):
     import numpy as np
     import torch
     case = wl.turbulence_case(args.n, seed=2)
-    rng = np.random.default_rng(7)
-    var = dict(case)
-    var["sigma"] = (np.asarray(case["sigma"], np.float64) * rng.uniform(0.75, 1.25, case["n"])).astype(np.float32)
+    var = wl.varcore_case(args.n)
     res, outs = {}, {}
     for name, c in (("uniform", case), ("per_particle", var)):
         t = vf.case_to_device(c)
@@ -300,15 +323,10 @@ def bench_varcore(args, vf, wl):
                      "phases_ms": {k: float(np.mean([p[k] for p in ph])) for k in ph[0]}}
         print("%s cores: %.1f ms/step" % (name, ms), file=sys.stderr, flush=True)
     if not args.no_check:
-        import oracle
-        idx = np.sort(np.random.default_rng(71).choice(var["n"], size=1024, replace=False))
-        ref = oracle.direct(var, targets=idx)
-
-        def rel(a, b):
-            return float(np.linalg.norm(a - b) / np.linalg.norm(b))
-
-        res["per_particle"]["rel_l2_vs_oracle_1024"] = {"u": rel(outs["per_particle"][0][idx], ref["u"]),
-                                                        "dalpha": rel(outs["per_particle"][1][idx], ref["da_t"])}
+        idx, ref, what = golden("bench_var_%d.txt" % args.n, wl.case_arrays(var))
+        res["per_particle"]["rel_l2_vs_oracle_%d" % idx.size] = {
+            "u": rel_l2(outs["per_particle"][0][idx], ref[:, :3]),
+            "dalpha": rel_l2(outs["per_particle"][1][idx], ref[:, 3:]), "reference": what}
     r = res["per_particle"]
     line = _line("per-particle cores at %d^3: step time" % args.n, r["p2p_pairs"] / (r["ms_per_step"] * 1e-3) / 1e9,
                  "Gpair/s", r["ms_per_step"], args,
@@ -326,10 +344,7 @@ def bench_targets(args, vf, wl):
     import numpy as np
     import torch
     case = wl.turbulence_case(args.n, seed=2)
-    h = 2 * np.pi / args.n
-    g = np.arange(args.n) * h
-    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
-    pts = [np.ascontiguousarray(a.ravel(), dtype=np.float32) for a in (X, Y, Z)]
+    pts = list(wl.corner_lattice(args.n))
     t = vf.case_to_device(case)
     T = [torch.tensor(p, device="cuda") for p in pts]
     res = {}
@@ -366,12 +381,10 @@ def bench_targets(args, vf, wl):
     res["phases_ms"] = ctx.timings()
     ctx.close()
     if not args.no_check:
-        import oracle
-        idx = np.sort(np.random.default_rng(72).choice(pts[0].size, size=1024, replace=False))
-        P = np.stack([p[idx] for p in pts], 1).astype(np.float64)
-        ref = oracle.direct_points(case, P)
+        idx, ref, what = golden("bench_targets_%d.txt" % args.n, wl.case_arrays(case) + pts)
         tu = np.stack([o.cpu().numpy() for o in outt[6:9]], 1).astype(np.float64)[idx]
-        res["rel_l2_u_targets_vs_oracle_1024"] = float(np.linalg.norm(tu - ref["u"]) / np.linalg.norm(ref["u"]))
+        res["rel_l2_u_targets_vs_oracle_%d" % idx.size] = rel_l2(tu, ref)
+        res["oracle_reference"] = what
     m = pts[0].size
     line = _line("velocity at %d^3 probe points beside %d^3 particles: step time" % (args.n, args.n),
                  m / (ms * 1e-3) / 1e6, "Mtargets/s", ms, args,
@@ -479,14 +492,11 @@ def main():
 
     acc = {}
     if not args.no_check:
-        import oracle
-        u = np.stack([o.cpu().numpy() for o in out[:3]], 1).astype(np.float64)
-        da = np.stack([o.cpu().numpy() for o in out[3:]], 1).astype(np.float64)
-        us, Js = oracle.spectral_lattice(case)
-        das, _ = oracle.stretching(Js, np.stack([case["ax"], case["ay"], case["az"]], 1).astype(np.float64))
-        acc = {"rel_l2_u": float(np.linalg.norm(u - us) / np.linalg.norm(us)),
-               "rel_l2_dalpha": float(np.linalg.norm(da - das) / np.linalg.norm(das)),
-               "reference": "exact FP64 periodic sum (Fourier series on the lattice), zero-mean convention"}
+        idx, ref, what = golden("bench_c2_%d.txt" % args.n, wl.case_arrays(case))
+        u = np.stack([o.cpu().numpy() for o in out[:3]], 1).astype(np.float64)[idx]
+        da = np.stack([o.cpu().numpy() for o in out[3:]], 1).astype(np.float64)[idx]
+        acc = {"rel_l2_u": rel_l2(u, ref[:, :3]), "rel_l2_dalpha": rel_l2(da, ref[:, 3:]),
+               "targets": int(idx.size), "reference": what}
 
     achieved = pairs * FLOPS_PER_PAIR / (p2p_ms * 1e-3) / 1e12
     traffic = traffic_from_profile(pairs)

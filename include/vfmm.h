@@ -102,8 +102,11 @@ typedef struct vfmm_params {
                             near field (P2P) runs on a second stream of the library concurrently
                             with the far field and a final kernel adds them (the small far-field
                             kernels then fill the GPU beside the P2P: about 2.5% shorter steps at
-                            128^3; the P2P and far-field phase timings overlap).  Results are
-                            bitwise the same.                                                    */
+                            128^3; the P2P and far-field phase timings overlap).  2: one
+                            stream, the near field first, then P2M ... L2P, and the final
+                            kernel (the P2P kernel then does not follow the matrix-core M2L
+                            directly; with m2l_form = 2 about 2.5% shorter steps at 128^3).
+                            Results are bitwise the same in all three.                           */
     int32_t m2l_form;    /* products of the operator-batched M2L.  0 (default) or 1: float32
                             matrix-core products.  2 (p <= 10; p = 12 uses 1): split products:
                             operator and multipole values are each split into three bfloat16

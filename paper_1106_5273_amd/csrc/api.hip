@@ -45,7 +45,7 @@ static void validate(const vfmm_params &p) {
     if (p.m2l_mode < 0 || p.m2l_mode > 2) throw Error{VFMM_EINVAL, "m2l_mode must be 0, 1 or 2"};
     if (p.use_graph != 0 && p.use_graph != 1) throw Error{VFMM_EINVAL, "use_graph must be 0 or 1"};
     if (p.use_graph && p.direct) throw Error{VFMM_EINVAL, "use_graph needs the tree path (direct = 0)"};
-    if (p.overlap != 0 && p.overlap != 1) throw Error{VFMM_EINVAL, "overlap must be 0 or 1"};
+    if (p.overlap < 0 || p.overlap > 2) throw Error{VFMM_EINVAL, "overlap must be 0, 1 or 2"};
     if (p.m2l_form < 0 || p.m2l_form > 2) throw Error{VFMM_EINVAL, "m2l_form must be 0, 1 or 2"};
     if (p.precision < VFMM_PRECISION_FP32 || p.precision > VFMM_PRECISION_FP64)
         throw Error{VFMM_EINVAL, "precision must be VFMM_PRECISION_FP32, _MIXED or _FP64"};
@@ -189,7 +189,7 @@ static void do_build(Ctx &c, int64_t n, const float *x, const float *y, const fl
     if (!c.m2lb_ok && !c.m2l_csr) build_m2l_csr(c);  // the per-pair M2L runs instead
     far_prealloc(c);
     m2lb_prealloc(c);
-    if (c.prm.precision != VFMM_PRECISION_FP64 && c.prm.overlap) ensure_side(c);
+    if (c.prm.precision != VFMM_PRECISION_FP64 && c.prm.overlap == 1) ensure_side(c);
     ++c.build_id;
     c.record(2 * PH_TRAVERSE + 1);
     c.record(2 * PH_NUM + 1);
@@ -217,6 +217,11 @@ static void do_evaluate(Ctx &c, int64_t n, const float *x, const float *y, const
             if (c.prm.precision == VFMM_PRECISION_FP64) gather_records64(c, ax, ay, az);
             far_field(c);
             p2p_and_finalize(c, ux, uy, uz, dax, day, daz);
+        } else if (c.prm.overlap == 2) {
+            // near field first, then the far field, on the library stream
+            p2p_near(c, s);
+            far_field(c);
+            finalize_near_far(c, ux, uy, uz, dax, day, daz);
         } else {
             // near field (VALU) on the side stream concurrently with the far
             // field (M2L on the matrix cores) on the library stream

@@ -1,0 +1,82 @@
+"""The stored expected values that bench.py's accuracy checks read
+(tests/golden/bench_*.txt) are the FP64 oracle's, on the inputs the bench
+regenerates: their input fingerprints match the seeded workloads and sampled
+rows agree with the oracle recomputed here."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _read(name):
+    fp, cols = None, None
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            if not line.startswith("#"):
+                break
+            if line.startswith("# fingerprint"):
+                fp = [float(v) for v in line.split()[2:]]
+            elif line.startswith("# columns:"):
+                cols = line.split()[2:]
+    tab = np.loadtxt(os.path.join(GOLDEN, name), comments="#", ndmin=2)
+    return fp, cols, tab[:, 0].astype(np.int64), tab[:, 1:]
+
+
+def _close(a, b):
+    # values are stored with 13 significant digits
+    return np.allclose(a, b, rtol=1e-11, atol=1e-11 * np.abs(b).max())
+
+
+@pytest.fixture(scope="module")
+def c2_case():
+    return wl.turbulence_case(128, seed=2)
+
+
+def test_c2_reference_is_the_spectral_oracle(c2_case):
+    fp, cols, idx, val = _read("bench_c2_128.txt")
+    assert cols == ["index", "ux", "uy", "uz", "dax", "day", "daz"]
+    assert wl.checksum_matches(fp, wl.checksum(wl.case_arrays(c2_case)))
+    assert idx.size == 2048 and np.all(np.diff(idx) > 0) and idx[-1] < c2_case["n"]
+    us, Js = oracle.spectral_lattice(c2_case)
+    alpha = np.stack([c2_case["ax"], c2_case["ay"], c2_case["az"]], 1).astype(np.float64)
+    das, _ = oracle.stretching(Js, alpha)
+    assert _close(val[:, :3], us[idx]) and _close(val[:, 3:], das[idx])
+
+
+def test_var_reference_is_the_direct_oracle():
+    var = wl.varcore_case(128)
+    fp, cols, idx, val = _read("bench_var_128.txt")
+    assert cols == ["index", "ux", "uy", "uz", "dax", "day", "daz"]
+    assert wl.checksum_matches(fp, wl.checksum(wl.case_arrays(var)))
+    s = np.arange(0, idx.size, idx.size // 8)
+    ref = oracle.direct(var, targets=idx[s])
+    assert _close(val[s, :3], ref["u"]) and _close(val[s, 3:], ref["da_t"])
+
+
+def test_targets_reference_is_the_direct_oracle(c2_case):
+    pts = wl.corner_lattice(128)
+    fp, cols, idx, val = _read("bench_targets_128.txt")
+    assert cols == ["index", "ux", "uy", "uz"]
+    assert wl.checksum_matches(fp, wl.checksum(wl.case_arrays(c2_case) + list(pts)))
+    s = np.arange(0, idx.size, idx.size // 8)
+    P = np.stack([p[idx[s]] for p in pts], 1).astype(np.float64)
+    assert _close(val[s], oracle.direct_points(c2_case, P)["u"])
+
+
+def test_fingerprint_detects_other_inputs(c2_case):
+    fp = wl.checksum(wl.case_arrays(c2_case))
+    moved = dict(c2_case)
+    moved["ax"] = np.roll(c2_case["ax"], 1)  # same values, another order
+    assert not wl.checksum_matches(fp, wl.checksum(wl.case_arrays(moved)))
+    assert wl.checksum_matches(fp, wl.checksum(wl.case_arrays(dict(c2_case))))
+
+
+def test_c3_reference_header():
+    fp, cols, idx, val = _read("bench_c3_256.txt")
+    assert cols == ["index", "ux", "uy", "uz", "dax", "day", "daz"]
+    assert len(fp) == 14 and idx.size == 2048 and idx[-1] < 256 ** 3 and np.all(np.isfinite(val))

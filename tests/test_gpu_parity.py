@@ -471,13 +471,15 @@ def test_bitwise_deterministic():
 
 
 def test_overlap_off_gives_identical_results():
-    """The near field on its own stream (overlap = 1) and the single-stream
-    evaluation (overlap = 0) produce bitwise the same outputs."""
+    """The near field on its own stream (overlap = 1), the near field first on
+    the library stream (overlap = 2) and the default order (overlap = 0)
+    produce bitwise the same outputs."""
     case = wl.turbulence_case(32, seed=6)
     kw = dict(p=8, periodic=1, box_len=2 * np.pi, images=3)
-    u1, d1 = run(case, overlap=1, **kw)
     u0, d0 = run(case, overlap=0, **kw)
-    assert np.array_equal(u1, u0) and np.array_equal(d1, d0)
+    for ov in (1, 2):
+        u1, d1 = run(case, overlap=ov, **kw)
+        assert np.array_equal(u1, u0) and np.array_equal(d1, d0), ov
 
 
 def test_outputs_follow_input_order():

@@ -12,4 +12,9 @@ from .gen import (  # noqa: F401
     ring_case,
     ring_batch,
     random_cloud,
+    varcore_case,
+    corner_lattice,
+    checksum,
+    checksum_matches,
+    case_arrays,
 )

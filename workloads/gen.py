@@ -149,3 +149,51 @@ def random_cloud(n, seed=0, L=1.0, core=0.05, lo=(0.0, 0.0, 0.0), zero_mean=Fals
     sig = np.full(n, core)
     return _pack(p[0], p[1], p[2], a[0], a[1], a[2], sig, L=L, periodic=periodic,
                  box_lo=tuple(lo), kind="random")
+
+
+def varcore_case(n=128, seed=2, core_seed=7, lo=0.75, hi=1.25):
+    """``turbulence_case`` with per-particle cores: each sigma_j is the lattice
+    core times an independent U(lo, hi) draw (seeded by ``core_seed``)."""
+    case = turbulence_case(n, seed=seed)
+    rng = np.random.default_rng(core_seed)
+    out = dict(case)
+    out["sigma"] = (np.asarray(case["sigma"], np.float64) * rng.uniform(lo, hi, case["n"])).astype(np.float32)
+    out["kind"] = "turbulence_varcore"
+    out["core_seed"] = core_seed
+    return out
+
+
+def corner_lattice(n, L=TWO_PI):
+    """Probe points at the cell corners i h, h = L/n (offset h/2 from the
+    cell-centred particle lattice), flattened [i, j, k]; float32 (x, y, z)."""
+    g = np.arange(n) * (L / n)
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    return tuple(np.ascontiguousarray(a.ravel(), dtype=np.float32) for a in (X, Y, Z))
+
+
+def checksum(arrays):
+    """Fingerprint of the given arrays, to confirm that regenerated inputs are
+    the ones stored expected values were computed on: per array, the float64
+    sum of |a_i| and the weighted sum of (1 + i mod 97) a_i (order-sensitive)."""
+    out = []
+    for a in arrays:
+        a = np.asarray(a, np.float64).ravel()
+        w = 1.0 + (np.arange(a.size) % 97)
+        out += [float(np.sum(np.abs(a))), float(np.dot(w, a))]
+    return out
+
+
+def checksum_matches(a, b):
+    """Whether two fingerprints from ``checksum`` agree to float64 summation rounding."""
+    if len(a) != len(b):
+        return False
+    for k in range(0, len(a), 2):
+        tol = 1e-11 * 98.0 * max(abs(a[k]), abs(b[k]), 1e-300)
+        if abs(a[k] - b[k]) > tol or abs(a[k + 1] - b[k + 1]) > tol:
+            return False
+    return True
+
+
+def case_arrays(case):
+    """The seven input arrays of a case in a fixed order."""
+    return [case[k] for k in ("x", "y", "z", "ax", "ay", "az", "sigma")]
