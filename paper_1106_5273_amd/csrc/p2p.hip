@@ -116,16 +116,20 @@ __device__ __forceinline__ void pair(const P2PConst &k, const Tgt &t, float4 sp,
         const float r2s = VAR ? r2 * sp.w : r2;      // (kappa_j rho)^2
         const float rinvs = VAR ? rinv * sa.w : rinv;  // 1 / (kappa_j rho)
         const float E = __builtin_amdgcn_exp2f(-r2s);
-        const float rho = r2s * rinvs;
         float pe = k.pe[VFMM_ERFCX_DEG];
 #pragma unroll
         for (int i = VFMM_ERFCX_DEG - 1; i >= 0; --i) pe = fmaf(pe, rinvs, k.pe[i]);
-        const float w3 = fmaf(rinvs, pe, rho);
-        const float g3 = fmaf(-E, w3, k.inv_a);
-        const float w5 = fmaf(r2s * rho, k.b, w3);
-        const float g5 = fmaf(-E, w5, k.inv_a);
-        F = g3 * rinv3;
-        H = (g5 * rinv3) * rinv2;
+        // G3 = 1/a - E (rho' + pe(1/rho')/rho') and G5 = G3 - b E rho'^3, so that
+        // H = (G5/G3) F / rho^2 = (F - b kappa^3 E) / rho^2 with F = G3 / rho^3
+        if (VAR) {
+            const float w3 = fmaf(rinvs, pe, r2s * rinvs);
+            F = fmaf(-E, w3, k.inv_a) * rinv3;
+            H = rinv2 * fmaf(-E * sb.w, k.b, F);  // sb.w = kappa_j^3
+        } else {
+            // scaled lengths (kappa = 1): F = (rho'^-1 / a - E (1 + rho'^-2 pe)) / rho'^2
+            F = rinv2 * fmaf(-E, fmaf(rinv2, pe, 1.f), k.inv_a * rinv);
+            H = rinv2 * fmaf(-E, k.b, F);
+        }
         if (V == 0) {
             if (__any(r2s < k.r2_small)) {
                 float q2 = k.q[VFMM_M2_DEG];

@@ -439,16 +439,23 @@ def test_periodic_turbulence_images_sweep():
     assert errs[6][0] < errs[1][0]
 
 
-def test_c2_full_size_matches_spectral_oracle():
-    """128^3 periodic turbulence-shaped lattice, p = 10, theta = 0.5: the
-    velocity and stretching of every particle against the exact FP64 periodic
-    sum, in the configuration the bench times."""
+@pytest.fixture(scope="module")
+def c2_ref():
     case = wl.turbulence_case(128, seed=2)
-    u, da = run(case, p=10, periodic=1, box_len=2 * np.pi, images=6)
     us, Js = oracle.spectral_lattice(case)
     das, _ = oracle.stretching(Js, alpha_of(case))
+    return case, us, das
+
+
+@pytest.mark.parametrize("extra", [{}, dict(sigma_gap=4.0, m2l_form=2, overlap=2)], ids=["bench", "tuned"])
+def test_c2_full_size_matches_spectral_oracle(c2_ref, extra):
+    """128^3 periodic turbulence-shaped lattice, p = 10, theta = 0.5: the
+    velocity and stretching of every particle against the exact FP64 periodic
+    sum, in the configuration the bench times and in its tuned settings."""
+    case, us, das = c2_ref
+    u, da = run(case, p=10, periodic=1, box_len=2 * np.pi, images=6, **extra)
     eu, ed = rel(u, us), rel(da, das)
-    print("C2 128^3: rel-L2 u %.3e dalpha %.3e" % (eu, ed))
+    print("C2 128^3 %s: rel-L2 u %.3e dalpha %.3e" % (extra, eu, ed))
     assert eu <= 1e-4 and ed <= 1e-4
 
 
