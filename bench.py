@@ -168,6 +168,7 @@ def bench_batched(args, vf, wl):
             ctx.evaluate(*t, out=out)
         st.synchronize()
         res["batched_evaluate_graph_ms"] = (time.perf_counter() - t0) * 1e3 / args.steps
+        batched_out = [o.cpu().numpy().astype(np.float64) for o in out]
         t0 = time.perf_counter()
         for _ in range(args.steps):
             ctx.build_batched(off, t[0], t[1], t[2], t[6])
@@ -190,6 +191,15 @@ def bench_batched(args, vf, wl):
         st.synchronize()
         res["sequential_build_evaluate_ms"] = (time.perf_counter() - t0) * 1e3
         ctx.close()
+    if not args.no_check:
+        idx, ref, what = golden("bench_c4_rings.txt", [cat[k] for k in ("x", "y", "z", "ax", "ay", "az", "sigma")])
+        seq_out = [o.cpu().numpy().astype(np.float64) for o in out]
+        for name, o in (("batched", batched_out), ("sequential", seq_out)):
+            u = np.stack(o[:3], 1)[idx]
+            da = np.stack(o[3:], 1)[idx]
+            res["rel_l2_%s_vs_oracle_%d" % (name, idx.size)] = {"u": rel_l2(u, ref[:, :3]),
+                                                               "dalpha": rel_l2(da, ref[:, 3:])}
+        res["oracle_reference"] = what
     total = res["batched_build_ms"] + res["batched_evaluate_graph_ms"]
     line = _line("512 ring problems, build+evaluate throughput", n / (total * 1e-3) / 1e6, "Mparticles/s", total, args,
                  "512 free-space Gaussian vortex rings, N log-uniform in [1024, 65536], p=8, ncrit=%d, "
@@ -214,6 +224,13 @@ def bench_rk(args, vf, wl):
     ctx.build(t[0], t[1], t[2], t[6])
     u = ctx.evaluate(*t)
     umax = float(torch.sqrt(u[0] ** 2 + u[1] ** 2 + u[2] ** 2).max())
+    acc = None
+    if not args.no_check:  # the first stage's evaluation with the tuned settings
+        idx, ref, what = golden("bench_c5_%d.txt" % n1, wl.case_arrays(case))
+        uu = np.stack([o.cpu().numpy() for o in u[:3]], 1).astype(np.float64)[idx]
+        dd = np.stack([o.cpu().numpy() for o in u[3:]], 1).astype(np.float64)[idx]
+        acc = {"rel_l2_u": rel_l2(uu, ref[:, :3]), "rel_l2_dalpha": rel_l2(dd, ref[:, 3:]), "targets": int(idx.size),
+               "reference": what}
     dt = 0.25 * h / umax
     for _ in range(args.warmup):
         ctx.rk_step(dt, 0.0, *t)
@@ -227,7 +244,7 @@ def bench_rk(args, vf, wl):
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
     line = _line("RK2 step time at 256^3 (autotuned)", ms / 1e3, "s/step", ms, args,
                  "periodic 256^3 turbulence-shaped lattice, Heun RK2 (2 x build+evaluate), autotuned",
-                 {"tune": tune, "dt": dt, "last_stage_phases_ms": {k: float(np.mean([p[k] for p in ph])) for k in ph[0]}},
+                 {"tune": tune, "dt": dt, "stage1_accuracy": acc, "last_stage_phases_ms": {k: float(np.mean([p[k] for p in ph])) for k in ph[0]}},
                  higher=False)
     print(json.dumps(line), flush=True)
 
@@ -236,7 +253,7 @@ def bench_precision(args, vf, wl):
     """256^3 periodic lattice, p = 10: the float32, mixed and float64 forms of
     the same tree.  Reports each form's step time, its difference from the
     float64 form (rounding error) and its error against the exact periodic sum
-    on 65,536 random targets."""
+    on 2,048 random targets (stored oracle values)."""
     import numpy as np
     import torch
     n1 = args.n if args.n != 128 else 256

@@ -6,7 +6,7 @@ at those targets, with a fingerprint of the inputs the values were computed on.
 Only the oracle computes them; bench.py reads the files and never runs the
 oracle itself.
 
-    python tests/golden/make_bench_refs.py [c2 c3 var targets]
+    python tests/golden/make_bench_refs.py [c2 c3 c4 c5 var targets]
 """
 import os
 import sys
@@ -76,11 +76,32 @@ def targets_refs(n=128, count=1024, sample_seed=72):
            wl.checksum(wl.case_arrays(case) + list(pts)), idx, ("ux", "uy", "uz"), ref["u"])
 
 
+def rings_refs(nprob=512, seed=4, per=4, sample_seed=74):
+    """512 free-space rings: FP64 direct sum of each problem alone at a few
+    sampled particles of that problem (indices into the concatenated arrays)."""
+    probs, off = wl.ring_batch(nprob, seed=seed)
+    rng = np.random.default_rng(sample_seed)
+    idx, vals = [], []
+    for b, pr in enumerate(probs):
+        loc = np.sort(rng.choice(pr["n"], size=per, replace=False))
+        ref = oracle.direct(pr, targets=loc)
+        idx += list(off[b] + loc)
+        vals.append(np.concatenate([ref["u"], ref["da_t"]], 1))
+    arrays = [np.concatenate([pr[k] for pr in probs]) for k in ("x", "y", "z", "ax", "ay", "az", "sigma")]
+    _write("bench_c4_rings.txt", "%d free-space Gaussian vortex rings (seed %d), %d particles of each drawn with seed %d"
+           % (nprob, seed, per, sample_seed), "FP64 direct sum over the particles of the same ring",
+           wl.checksum(arrays), np.asarray(idx), ("ux", "uy", "uz", "dax", "day", "daz"), np.concatenate(vals))
+
+
 def main(which):
     if "c2" in which:
         lattice_refs(128, 2, "bench_c2_128.txt")
     if "c3" in which:
         lattice_refs(256, 3, "bench_c3_256.txt")
+    if "c5" in which:
+        lattice_refs(256, 5, "bench_c5_256.txt")
+    if "c4" in which:
+        rings_refs()
     if "var" in which:
         varcore_refs()
     if "targets" in which:
@@ -88,4 +109,4 @@ def main(which):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["c2", "c3", "var", "targets"])
+    main(sys.argv[1:] or ["c2", "c3", "c4", "c5", "var", "targets"])

@@ -80,3 +80,23 @@ def test_c3_reference_header():
     fp, cols, idx, val = _read("bench_c3_256.txt")
     assert cols == ["index", "ux", "uy", "uz", "dax", "day", "daz"]
     assert len(fp) == 14 and idx.size == 2048 and idx[-1] < 256 ** 3 and np.all(np.isfinite(val))
+
+
+def test_c4_reference_is_the_direct_oracle():
+    probs, off = wl.ring_batch(512, seed=4)
+    arrays = [np.concatenate([pr[k] for pr in probs]) for k in ("x", "y", "z", "ax", "ay", "az", "sigma")]
+    fp, cols, idx, val = _read("bench_c4_rings.txt")
+    assert cols == ["index", "ux", "uy", "uz", "dax", "day", "daz"]
+    assert wl.checksum_matches(fp, wl.checksum(arrays))
+    assert idx.size == 4 * 512 and idx[-1] < off[-1]
+    for b in (0, 97, 300, 511):  # each stored row is the direct sum over its own ring only
+        rows = np.nonzero((idx >= off[b]) & (idx < off[b + 1]))[0]
+        assert rows.size == 4
+        ref = oracle.direct(probs[b], targets=idx[rows] - off[b])
+        assert _close(val[rows, :3], ref["u"]) and _close(val[rows, 3:], ref["da_t"])
+
+
+def test_c5_reference_header():
+    fp, cols, idx, val = _read("bench_c5_256.txt")
+    assert cols == ["index", "ux", "uy", "uz", "dax", "day", "daz"]
+    assert len(fp) == 14 and idx.size == 2048 and idx[-1] < 256 ** 3 and np.all(np.isfinite(val))

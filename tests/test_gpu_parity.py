@@ -459,6 +459,77 @@ def test_c2_full_size_matches_spectral_oracle(c2_ref, extra):
     assert eu <= 1e-4 and ed <= 1e-4
 
 
+def _stored(name, arrays):
+    """Oracle values at seeded targets of a full-size workload (tests/golden,
+    written by make_bench_refs.py from the oracle alone): (indices, values)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    fp = None
+    with open(path) as f:
+        for line in f:
+            if not line.startswith("#"):
+                break
+            if line.startswith("# fingerprint"):
+                fp = [float(v) for v in line.split()[2:]]
+    assert fp is not None and wl.checksum_matches(fp, wl.checksum(arrays)), "inputs differ from the stored ones"
+    tab = np.loadtxt(path, comments="#", ndmin=2)
+    return tab[:, 0].astype(np.int64), tab[:, 1:]
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["float32", "mixed"])
+def test_c3_full_size_forms_match_stored_oracle(precision):
+    """256^3 periodic lattice (seed 3), p = 10: the float32 and mixed forms at
+    2,048 stored targets of the exact periodic sum."""
+    case = wl.turbulence_case(256, seed=3)
+    idx, ref = _stored("bench_c3_256.txt", wl.case_arrays(case))
+    u, da = run(case, p=10, periodic=1, box_len=2 * np.pi, images=6, precision=precision)
+    eu, ed = rel(u[idx], ref[:, :3]), rel(da[idx], ref[:, 3:])
+    print("C3 256^3 precision=%d: rel-L2 u %.3e dalpha %.3e" % (precision, eu, ed))
+    assert eu <= 1e-4 and ed <= 1e-4
+
+
+def test_c5_full_size_stage1_with_tuned_settings():
+    """256^3 periodic lattice (seed 5) with the settings the autotuner picks for
+    a 1e-4 bound (p = 10, theta = 0.7, ncrit = 256, sigma-gap 4): the first RK
+    stage's evaluation at 2,048 stored targets of the exact periodic sum."""
+    case = wl.turbulence_case(256, seed=5)
+    idx, ref = _stored("bench_c5_256.txt", wl.case_arrays(case))
+    u, da = run(case, p=10, theta=0.7, ncrit=256, sigma_gap=4.0, periodic=1, box_len=2 * np.pi, images=6)
+    eu, ed = rel(u[idx], ref[:, :3]), rel(da[idx], ref[:, 3:])
+    print("C5 256^3 stage 1: rel-L2 u %.3e dalpha %.3e" % (eu, ed))
+    assert eu <= 1e-4 and ed <= 1e-4
+
+
+def test_c4_full_size_batched_graph_matches_oracle():
+    """512 free-space rings (8.8 M particles), p = 8, ncrit = 384, one batched
+    forest evaluated through its hipGraph (the launch configuration the bench
+    times): 4 stored particles per ring against the FP64 direct sum of that
+    ring alone, on the first and on a replayed evaluation."""
+    import torch
+    vf = _vf()
+    probs, off = wl.ring_batch(512, seed=4)
+    cat = {k: np.concatenate([pr[k] for pr in probs]) for k in ("x", "y", "z", "ax", "ay", "az", "sigma")}
+    idx, ref = _stored("bench_c4_rings.txt", [cat[k] for k in ("x", "y", "z", "ax", "ay", "az", "sigma")])
+    t = tuple(torch.from_numpy(cat[k]).cuda() for k in ("x", "y", "z", "ax", "ay", "az", "sigma"))
+    st = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    res = []
+    with torch.cuda.stream(st):
+        out = tuple(torch.empty(int(off[-1]), dtype=torch.float32, device="cuda") for _ in range(6))
+        with vf.Context(p=8, ncrit=384, use_graph=1, stream=st) as ctx:
+            ctx.build_batched(off, t[0], t[1], t[2], t[6])
+            for _ in range(2):
+                ctx.evaluate(*t, out=out)
+                st.synchronize()
+                res.append([o.cpu().numpy().astype(np.float64) for o in out])
+    for k, o in enumerate(res):
+        eu = rel(np.stack(o[:3], 1)[idx], ref[:, :3])
+        ed = rel(np.stack(o[3:], 1)[idx], ref[:, 3:])
+        print("C4 512 rings, evaluation %d: rel-L2 u %.3e dalpha %.3e" % (k, eu, ed))
+        assert eu <= 1e-4 and ed <= 1e-4
+    assert all(np.array_equal(a, b) for a, b in zip(res[0], res[1]))
+
+
 # ----------------------------------------------------------------------------
 # determinism, ordering, ABI errors
 # ----------------------------------------------------------------------------
