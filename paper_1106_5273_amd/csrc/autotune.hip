@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <fstream>
 #include <sstream>
 
@@ -77,6 +78,7 @@ struct Trial {
     float theta, gap;
     double eu, ed, ms;
     bool ok;
+    int64_t tree[5];  // cells, leaves, M2L entries, P2P entries, P2P pairs of the trial's build
 };
 
 }  // namespace vfmm
@@ -150,8 +152,10 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
             for (const auto &t : trials)
                 if (t.p == p && t.ncrit == ncrit && std::fabs(t.theta - theta) < 1e-6f && std::fabs(t.gap - gap) < 1e-6f)
                     return t;
-            vfmm::Trial t{p, ncrit, theta, gap, 0, 0, 0, false};
+            vfmm::Trial t{p, ncrit, theta, gap, 0, 0, 0, false, {0, 0, 0, 0, 0}};
             run(p, theta, ncrit, gap, O, t.ms);
+            const int64_t tr[5] = {c.ncells, c.nleaves, c.n_m2l, c.n_p2p, c.p2p_pairs};
+            std::copy(tr, tr + 5, t.tree);
             vfmm::rel_errors(c, n, O, R, t.eu, t.ed);
             t.ok = t.eu <= max_rel_l2 && t.ed <= max_rel_l2;
             trials.push_back(t);
@@ -165,10 +169,20 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
         for (float th : thetas)
             for (int p : ps)
                 if (trial(p, th, base.ncrit, base.sigma_gap).ok) break;
+        // fastest feasible trial; leaf sizes that build the same tree (a lattice
+        // splits into the same cells for every ncrit between two powers of 8)
+        // give the same results, and among them the largest is kept: it builds
+        // that tree again after the particles have moved a little, where a
+        // smaller one would split the first overfull leaves
         auto best_of = [&]() {
             const vfmm::Trial *b = nullptr;
             for (const auto &t : trials)
                 if (t.ok && (!b || t.ms < b->ms)) b = &t;
+            if (b)
+                for (const auto &t : trials)
+                    if (t.ok && t.p == b->p && t.theta == b->theta && t.gap == b->gap && t.ncrit > b->ncrit &&
+                        std::equal(t.tree, t.tree + 5, b->tree))
+                        b = &t;
             return b;
         };
         const vfmm::Trial *b = best_of();
