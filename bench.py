@@ -22,7 +22,7 @@ sys.path.insert(0, ROOT)
 METRIC = "FMM step time & P2P Gpair-interactions/s at 128^3 particles, p=10, ≤1e-4 err"
 PEAK_FP32_VALU_TFLOPS = 157.3        # published FP32 vector peak of MI355X (256 CU, 2.4 GHz); non-packed FMA with
                                       # vector-register operands reaches 84-94% of it, with a scalar operand half that
-FLOPS_PER_PAIR = 60                   # gfx950 ISA of the P2P pair body (s >= 1 form): 24 FMA + 7 MUL + 3 SUB + 2 TRANS, FMA = 2
+FLOPS_PER_PAIR = 59                   # gfx950 ISA of the P2P pair body (s >= 1 form): 24 FMA + 6 MUL + 3 SUB + 2 TRANS, FMA = 2
 PAPER_FLOPS_PER_PAIR = 174            # Table 1 convention (70 + 104)
 
 

@@ -19,13 +19,13 @@
 // of its own leaf, delta' = kappa (x - c_leaf), and each list entry holds the
 // offset between the two leaves, D' = kappa (c_t - c_s - image shift), so
 // that r' = (delta'_i + D') - delta'_j = y_i - delta'_j is formed from small
-// numbers.  Strengths are stored as ah = kappa^3 a alpha/(4 pi) with
-// a = (2/sqrt pi)/sqrt(lambda), together with bh = ah x delta'.
+// numbers.  Strengths are stored as ah = kappa^3 alpha/(4 pi), together with
+// bh = ah x delta'.
 //
-// Per pair, with E = 2^{-r2'} and rho' = |r'|:
-//   G3 = 1/a - E (rho' + (1/rho') pe(1/rho'))      = P(3/2, x) / a
-//   G5 = G3 - E b rho'^3,  b = 2/(3 lambda)         = P(5/2, x) / a
-//   Fh = G3 / rho'^3,  Hh = G5 / rho'^5
+// Per pair, with E = 2^{-r2'}, rho' = |r'| and a = (2/sqrt pi)/sqrt(lambda):
+//   G3 = 1 - a E (rho' + (1/rho') pe(1/rho'))      = P(3/2, x)
+//   G5 = G3 - a E b rho'^3,  b = 2/(3 lambda)       = P(5/2, x)
+//   Fh = G3 / rho'^3,  Hh = G5 / rho'^5 = (Fh - a b E) / rho'^2
 // where pe is the erfcx fit rescaled to 1/rho' and P(a, x) is the regularised
 // lower incomplete gamma function (P(3/2, x) is the cutoff g of Eq. (2)).
 // Then, in physical units, q alpha_j x r = Fh (ah_j x r') / kappa and
@@ -50,13 +50,19 @@
 
 namespace vfmm {
 
+// The uniform-core form carries the normalisation a of the cutoff in these
+// constants (its strengths are kappa^3 alpha/(4 pi)); the per-particle-core
+// form carries it in the strengths (a alpha/(4 pi)) and divides the
+// constants by a.
 struct P2PConst {
-    float inv_a;     // 1/a
-    float b;         // 2/(3 lambda)
+    float inv_a;     // per-particle cores: 1/a
+    float a;         // uniform cores: a
+    float b;         // per-particle cores: 2/(3 lambda)
+    float ab;        // uniform cores: a b
     float K3;        // series form: Fh at r = 0 is K3 (times E)
     float r2_small;  // s < 1  <=>  r2' < r2_small
     float inv_kappa; // u = U / kappa
-    float pe[VFMM_ERFCX_DEG + 1];  // erfcx fit in powers of 1/rho', divided by a
+    float pe[VFMM_ERFCX_DEG + 1];  // erfcx fit in powers of 1/rho'
     float q[VFMM_M2_DEG + 1];      // series: Hh = E sum q_k r2'^k,  Fh = E (K3 + r2' sum q_k r2'^k)
 };
 
@@ -110,7 +116,7 @@ __device__ __forceinline__ void pair(const P2PConst &k, const Tgt &t, float4 sp,
     const float rinv3 = rinv2 * rinv;
     float F, H;
     if (V == 2) {
-        F = k.inv_a * rinv3;
+        F = VAR ? k.inv_a * rinv3 : rinv3;
         H = F * rinv2;
     } else {
         const float r2s = VAR ? r2 * sp.w : r2;      // (kappa_j rho)^2
@@ -126,9 +132,9 @@ __device__ __forceinline__ void pair(const P2PConst &k, const Tgt &t, float4 sp,
             F = fmaf(-E, w3, k.inv_a) * rinv3;
             H = rinv2 * fmaf(-E * sb.w, k.b, F);  // sb.w = kappa_j^3
         } else {
-            // scaled lengths (kappa = 1): F = (rho'^-1 / a - E (1 + rho'^-2 pe)) / rho'^2
-            F = rinv2 * fmaf(-E, fmaf(rinv2, pe, 1.f), k.inv_a * rinv);
-            H = rinv2 * fmaf(-E, k.b, F);
+            // scaled lengths (kappa = 1), times a: F = (1/rho' - E (a + rho'^-2 a pe)) / rho'^2
+            F = rinv2 * fmaf(-E, fmaf(rinv2, pe, k.a), rinv);
+            H = rinv2 * fmaf(-E, k.ab, F);
         }
         if (V == 0) {
             if (__any(r2s < k.r2_small)) {
@@ -247,8 +253,13 @@ __device__ __forceinline__ void p2p_block(const P2PConst &k, const P2PArgs &A, i
     P2PConst kv = k;  // the constants of the erfcx form, in vector registers
 #pragma unroll
     for (int q = 0; q <= VFMM_ERFCX_DEG; ++q) to_vgpr(kv.pe[q]);
-    to_vgpr(kv.inv_a);
-    to_vgpr(kv.b);
+    if (VAR) {
+        to_vgpr(kv.inv_a);
+        to_vgpr(kv.b);
+    } else {
+        to_vgpr(kv.a);
+        to_vgpr(kv.ab);
+    }
     for (int e = 0; e < lc; ++e) {
         const int4 en = A.ent[l0 + e];
         const float4 D = A.sh[l0 + e];
@@ -370,7 +381,7 @@ __global__ __launch_bounds__(256) void k_p2p(P2PConst k, P2PArgs A) {
 // Records of the float32 near field (sorted order), one wave per leaf.
 // Uniform cores (kappa the scale of the shared core):
 //   rec[3i] = (kappa (x_i - c_leaf), alpha_x), rec[3i+1] = (ah_i, alpha_y),
-//   rec[3i+2] = (ah_i x delta'_i, alpha_z),   ah = kappa^3 a alpha/(4 pi).
+//   rec[3i+2] = (ah_i x delta'_i, alpha_z),   ah = kappa^3 alpha/(4 pi).
 // Per-source cores (kappa_j of each particle's own core):
 //   rec[4i] = (x_i - c_leaf, kappa_i^2), rec[4i+1] = (ah_i, 1/kappa_i),
 //   rec[4i+2] = (ah_i x delta_i, kappa_i^3), rec[4i+3] = (alpha_i, 0),  ah = a alpha/(4 pi).
@@ -576,15 +587,18 @@ static P2PConst make_const(double sigma, bool var) {
     const double lam = 1.0 / std::log(2.0);  // log2 e
     const double sqpi = std::sqrt(M_PI);
     const double a = p2p_cutoff_a();
+    const double sc = var ? 1.0 / a : 1.0;  // where the factor a sits (see P2PConst)
     k.inv_a = (float)(1.0 / a);
+    k.a = (float)a;
     k.b = (float)(2.0 / (3.0 * lam));
-    k.K3 = (float)(4.0 / (3.0 * sqpi) / (a * std::pow(lam, 1.5)));
+    k.ab = (float)(a * 2.0 / (3.0 * lam));
+    k.K3 = (float)(4.0 / (3.0 * sqpi) / std::pow(lam, 1.5) * sc);
     k.r2_small = (float)((double)VFMM_CUTOFF_XSPLIT * lam);
     k.inv_kappa = var ? 1.0f : (float)(1.0 / p2p_kappa(sigma));
     for (int i = 0; i <= VFMM_ERFCX_DEG; ++i)
-        k.pe[i] = (float)((double)VFMM_ERFCX_C[i] * std::pow(lam, 0.5 * (i + 1)) / a);
+        k.pe[i] = (float)((double)VFMM_ERFCX_C[i] * std::pow(lam, 0.5 * (i + 1)) * sc);
     for (int i = 0; i <= VFMM_M2_DEG; ++i)
-        k.q[i] = (float)(8.0 / (15.0 * sqpi) * (double)VFMM_M2_C[i] / (a * std::pow(lam, 2.5 + i)));
+        k.q[i] = (float)(8.0 / (15.0 * sqpi) * (double)VFMM_M2_C[i] / std::pow(lam, 2.5 + i) * sc);
     return k;
 }
 
@@ -593,10 +607,10 @@ static P2PConst make_const(double sigma, bool var) {
 static void p2p_records(Ctx &c, bool tree, const double *origin) {
     if (c.n == 0) return;
     const bool var = c.var_sigma;
-    // uniform: kappa of the shared core and ah = kappa^3 a alpha/(4 pi); per source: the
-    // numerator of kappa_j and ah = a alpha/(4 pi)
+    // uniform: kappa of the shared core and ah = kappa^3 alpha/(4 pi) (the factor a is in
+    // the constants); per source: the numerator of kappa_j and ah = a alpha/(4 pi)
     const double kap = var ? p2p_kappa(1.0) : p2p_kappa(c.sigma_uniform);
-    const double sa = (var ? 1.0 : kap * kap * kap) * p2p_cutoff_a();
+    const double sa = var ? p2p_cutoff_a() : kap * kap * kap;
     const int rs = var ? 4 : 3;
     c.recp.ensure(sizeof(float4) * rs * (size_t)c.n);
     const double o0 = origin ? origin[0] : 0.0, o1 = origin ? origin[1] : 0.0, o2 = origin ? origin[2] : 0.0;
