@@ -50,19 +50,15 @@
 
 namespace vfmm {
 
-// The uniform-core form carries the normalisation a of the cutoff in these
-// constants (its strengths are kappa^3 alpha/(4 pi)); the per-particle-core
-// form carries it in the strengths (a alpha/(4 pi)) and divides the
-// constants by a.
+// Constants of the scaled cutoff (the normalisation a of the cutoff is in
+// them; the strengths are kappa^3 alpha/(4 pi)).
 struct P2PConst {
-    float inv_a;     // per-particle cores: 1/a
-    float a;         // uniform cores: a
-    float b;         // per-particle cores: 2/(3 lambda)
-    float ab;        // uniform cores: a b
+    float a;         // a = (2/sqrt pi)/sqrt(lambda)
+    float ab;        // a b, b = 2/(3 lambda)
     float K3;        // series form: Fh at r = 0 is K3 (times E)
     float r2_small;  // s < 1  <=>  r2' < r2_small
     float inv_kappa; // u = U / kappa
-    float pe[VFMM_ERFCX_DEG + 1];  // erfcx fit in powers of 1/rho'
+    float pe[VFMM_ERFCX_DEG + 1];  // erfcx fit in powers of 1/rho', times a
     float q[VFMM_M2_DEG + 1];      // series: Hh = E sum q_k r2'^k,  Fh = E (K3 + r2' sum q_k r2'^k)
 };
 
@@ -102,57 +98,48 @@ struct Tgt {
 // more issue slots than it saves.
 __device__ __forceinline__ void to_vgpr(float &a) { asm("" : "+v"(a)); }
 
-// VAR (per-source cores): records hold unscaled leaf-local offsets and
-// kappa_j^2, 1/kappa_j, kappa_j^3 of the source in their fourth components;
-// the cutoff is evaluated at r' = kappa_j r and the powers of 1/rho are
-// unscaled, with ah = a alpha/(4 pi) (the same sums, kappa folded per pair).
+// VAR (per-source cores): records hold unscaled leaf-local offsets, the
+// strengths ah = kappa_j^3 alpha/(4 pi) and kappa_j^2, 1/kappa_j of the source
+// in their fourth components.  The cutoff factors are those of the scaled form
+// at r' = kappa_j r, and F ah and H (ah . (r x alpha_i)) equal the unscaled
+// sums once H carries one more kappa_j^2.
 template <int V, int SCHEME, bool MASK, bool VAR>
 __device__ __forceinline__ void pair(const P2PConst &k, const Tgt &t, float4 sp, float4 sa, float4 sb, bool ok,
                                      Acc9 &p) {
     const float dx = t.y0 - sp.x, dy = t.y1 - sp.y, dz = t.y2 - sp.z;
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float rinv0 = __builtin_amdgcn_rsqf(r2);
+    const float rinv = VAR ? rinv0 * sa.w : rinv0;  // 1 / rho' (rho' = kappa_j rho)
     const float rinv2 = rinv * rinv;
-    const float rinv3 = rinv2 * rinv;
     float F, H;
     if (V == 2) {
-        F = VAR ? k.inv_a * rinv3 : rinv3;
+        F = rinv2 * rinv;
         H = F * rinv2;
     } else {
-        const float r2s = VAR ? r2 * sp.w : r2;      // (kappa_j rho)^2
-        const float rinvs = VAR ? rinv * sa.w : rinv;  // 1 / (kappa_j rho)
+        const float r2s = VAR ? r2 * sp.w : r2;  // rho'^2
         const float E = __builtin_amdgcn_exp2f(-r2s);
         float pe = k.pe[VFMM_ERFCX_DEG];
 #pragma unroll
-        for (int i = VFMM_ERFCX_DEG - 1; i >= 0; --i) pe = fmaf(pe, rinvs, k.pe[i]);
-        // G3 = 1/a - E (rho' + pe(1/rho')/rho') and G5 = G3 - b E rho'^3, so that
-        // H = (G5/G3) F / rho^2 = (F - b kappa^3 E) / rho^2 with F = G3 / rho^3
-        if (VAR) {
-            const float w3 = fmaf(rinvs, pe, r2s * rinvs);
-            F = fmaf(-E, w3, k.inv_a) * rinv3;
-            H = rinv2 * fmaf(-E * sb.w, k.b, F);  // sb.w = kappa_j^3
-        } else {
-            // scaled lengths (kappa = 1), times a: F = (1/rho' - E (a + rho'^-2 a pe)) / rho'^2
-            F = rinv2 * fmaf(-E, fmaf(rinv2, pe, k.a), rinv);
-            H = rinv2 * fmaf(-E, k.ab, F);
-        }
+        for (int i = VFMM_ERFCX_DEG - 1; i >= 0; --i) pe = fmaf(pe, rinv, k.pe[i]);
+        // G3 = 1 - a E (rho' + pe(1/rho')/rho') and G5 = G3 - a b E rho'^3, so that
+        // F = G3 / rho'^3 = (1/rho' - E (a + rho'^-2 a pe)) / rho'^2 and
+        // H = G5 / rho'^5 = (F - a b E) / rho'^2
+        F = rinv2 * fmaf(-E, fmaf(rinv2, pe, k.a), rinv);
+        H = rinv2 * fmaf(-E, k.ab, F);
         if (V == 0) {
             if (__any(r2s < k.r2_small)) {
                 float q2 = k.q[VFMM_M2_DEG];
 #pragma unroll
                 for (int i = VFMM_M2_DEG - 1; i >= 0; --i) q2 = fmaf(q2, r2s, k.q[i]);
-                float Fs = E * fmaf(r2s, q2, k.K3);  // 2^{-r2'} K3 1F1(1; 5/2; x)
-                float Hs = E * q2;                   // 2^{-r2'} K5 1F1(1; 7/2; x)
-                if (VAR) {
-                    Fs *= sb.w;         // kappa_j^3
-                    Hs *= sb.w * sp.w;  // kappa_j^5
-                }
+                const float Fs = E * fmaf(r2s, q2, k.K3);  // 2^{-r2'} K3 1F1(1; 5/2; x)
+                const float Hs = E * q2;                   // 2^{-r2'} K5 1F1(1; 7/2; x)
                 const bool sm = r2s < k.r2_small;
                 F = sm ? Fs : F;
                 H = sm ? Hs : H;
             }
         }
     }
+    if (VAR) H *= sp.w;  // kappa_j^2
     if (MASK) {  // a padding source contributes exactly zero
         F = ok ? F : 0.f;
         H = ok ? H : 0.f;
@@ -253,13 +240,8 @@ __device__ __forceinline__ void p2p_block(const P2PConst &k, const P2PArgs &A, i
     P2PConst kv = k;  // the constants of the erfcx form, in vector registers
 #pragma unroll
     for (int q = 0; q <= VFMM_ERFCX_DEG; ++q) to_vgpr(kv.pe[q]);
-    if (VAR) {
-        to_vgpr(kv.inv_a);
-        to_vgpr(kv.b);
-    } else {
-        to_vgpr(kv.a);
-        to_vgpr(kv.ab);
-    }
+    to_vgpr(kv.a);
+    to_vgpr(kv.ab);
     for (int e = 0; e < lc; ++e) {
         const int4 en = A.ent[l0 + e];
         const float4 D = A.sh[l0 + e];
@@ -384,7 +366,7 @@ __global__ __launch_bounds__(256) void k_p2p(P2PConst k, P2PArgs A) {
 //   rec[3i+2] = (ah_i x delta'_i, alpha_z),   ah = kappa^3 alpha/(4 pi).
 // Per-source cores (kappa_j of each particle's own core):
 //   rec[4i] = (x_i - c_leaf, kappa_i^2), rec[4i+1] = (ah_i, 1/kappa_i),
-//   rec[4i+2] = (ah_i x delta_i, kappa_i^3), rec[4i+3] = (alpha_i, 0),  ah = a alpha/(4 pi).
+//   rec[4i+2] = (ah_i x delta_i, kappa_i^3), rec[4i+3] = (alpha_i, 0),  ah = kappa_i^3 alpha/(4 pi).
 // Computed in float64 and rounded once.  A null cell list means one common
 // origin for every particle (direct mode).
 template <bool VAR>
@@ -417,7 +399,8 @@ __global__ __launch_bounds__(256) void k_p2p_records(const int *__restrict__ lea
         const double kap = VAR ? kappa / (double)p.w : kappa;
         const double sc = VAR ? 1.0 : kappa;
         const double d0 = sc * ((double)p.x - cx), d1 = sc * ((double)p.y - cy), d2 = sc * ((double)p.z - cz);
-        const double h0 = sa * a.x, h1 = sa * a.y, h2 = sa * a.z;
+        const double s3 = VAR ? kap * kap * kap : sa;
+        const double h0 = s3 * a.x, h1 = s3 * a.y, h2 = s3 * a.z;
         const double b0 = h1 * d2 - h2 * d1, b1 = h2 * d0 - h0 * d2, b2 = h0 * d1 - h1 * d0;
         if (VAR) {
             out[4 * i] = make_float4((float)d0, (float)d1, (float)d2, (float)(kap * kap));
@@ -587,18 +570,15 @@ static P2PConst make_const(double sigma, bool var) {
     const double lam = 1.0 / std::log(2.0);  // log2 e
     const double sqpi = std::sqrt(M_PI);
     const double a = p2p_cutoff_a();
-    const double sc = var ? 1.0 / a : 1.0;  // where the factor a sits (see P2PConst)
-    k.inv_a = (float)(1.0 / a);
     k.a = (float)a;
-    k.b = (float)(2.0 / (3.0 * lam));
     k.ab = (float)(a * 2.0 / (3.0 * lam));
-    k.K3 = (float)(4.0 / (3.0 * sqpi) / std::pow(lam, 1.5) * sc);
+    k.K3 = (float)(4.0 / (3.0 * sqpi) / std::pow(lam, 1.5));
     k.r2_small = (float)((double)VFMM_CUTOFF_XSPLIT * lam);
     k.inv_kappa = var ? 1.0f : (float)(1.0 / p2p_kappa(sigma));
     for (int i = 0; i <= VFMM_ERFCX_DEG; ++i)
-        k.pe[i] = (float)((double)VFMM_ERFCX_C[i] * std::pow(lam, 0.5 * (i + 1)) * sc);
+        k.pe[i] = (float)((double)VFMM_ERFCX_C[i] * std::pow(lam, 0.5 * (i + 1)));
     for (int i = 0; i <= VFMM_M2_DEG; ++i)
-        k.q[i] = (float)(8.0 / (15.0 * sqpi) * (double)VFMM_M2_C[i] / std::pow(lam, 2.5 + i) * sc);
+        k.q[i] = (float)(8.0 / (15.0 * sqpi) * (double)VFMM_M2_C[i] / std::pow(lam, 2.5 + i));
     return k;
 }
 
@@ -607,10 +587,10 @@ static P2PConst make_const(double sigma, bool var) {
 static void p2p_records(Ctx &c, bool tree, const double *origin) {
     if (c.n == 0) return;
     const bool var = c.var_sigma;
-    // uniform: kappa of the shared core and ah = kappa^3 alpha/(4 pi) (the factor a is in
-    // the constants); per source: the numerator of kappa_j and ah = a alpha/(4 pi)
+    // uniform: kappa of the shared core and ah = kappa^3 alpha/(4 pi); per source: the
+    // numerator of kappa_j (the kernel scales each strength by its own kappa_j^3)
     const double kap = var ? p2p_kappa(1.0) : p2p_kappa(c.sigma_uniform);
-    const double sa = var ? p2p_cutoff_a() : kap * kap * kap;
+    const double sa = kap * kap * kap;
     const int rs = var ? 4 : 3;
     c.recp.ensure(sizeof(float4) * rs * (size_t)c.n);
     const double o0 = origin ? origin[0] : 0.0, o1 = origin ? origin[1] : 0.0, o2 = origin ? origin[2] : 0.0;
