@@ -70,28 +70,35 @@ def kernel_hash():
 def golden(name, arrays):
     """Stored FP64 oracle values at a seeded sample of targets of a workload
     (``tests/golden/<name>``, written by ``tests/golden/make_bench_refs.py``):
-    returns (indices, values, reference).  Raises if the regenerated inputs
-    are not the ones the values were computed on."""
+    returns (indices, values, reference).  A missing file, or one computed on
+    other inputs than the regenerated ones, gives no rows and says why (the
+    errors are then reported as null)."""
     import numpy as np
     import workloads as wl
     path = os.path.join(ROOT, "tests", "golden", name)
+    none = (np.zeros(0, np.int64), np.zeros((0, 6)))
     ref, fp = "", None
-    with open(path) as f:
-        for line in f:
-            if not line.startswith("#"):
-                break
-            if line.startswith("# reference:"):
-                ref = line.split(":", 1)[1].strip()
-            elif line.startswith("# fingerprint"):
-                fp = [float(v) for v in line.split()[2:]]
+    try:
+        with open(path) as f:
+            for line in f:
+                if not line.startswith("#"):
+                    break
+                if line.startswith("# reference:"):
+                    ref = line.split(":", 1)[1].strip()
+                elif line.startswith("# fingerprint"):
+                    fp = [float(v) for v in line.split()[2:]]
+        tab = np.loadtxt(path, comments="#", ndmin=2)
+    except (OSError, ValueError) as e:
+        return none + ("unavailable: %s" % e,)
     if fp is None or not wl.checksum_matches(fp, wl.checksum(arrays)):
-        raise RuntimeError("%s was computed on other inputs than this workload's" % path)
-    tab = np.loadtxt(path, comments="#", ndmin=2)
+        return none + ("unavailable: %s was computed on other inputs than this workload's" % path,)
     return tab[:, 0].astype(np.int64), tab[:, 1:], ref
 
 
 def rel_l2(a, b):
     import numpy as np
+    if b.size == 0:
+        return None
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
@@ -293,8 +300,8 @@ def bench_precision(args, vf, wl):
     if not args.no_check:
         idx, ref, what = golden("bench_c3_%d.txt" % n1, wl.case_arrays(case))
         for name in ("fp64", "fp32", "mixed"):
-            res[name]["rel_l2_vs_oracle_%d" % idx.size] = {"u": rel(outs[name][0][idx], ref[:, :3]),
-                                                           "dalpha": rel(outs[name][1][idx], ref[:, 3:])}
+            res[name]["rel_l2_vs_oracle_%d" % idx.size] = {"u": rel_l2(outs[name][0][idx], ref[:, :3]),
+                                                           "dalpha": rel_l2(outs[name][1][idx], ref[:, 3:])}
         res["oracle_reference"] = what
     ms = res["fp32"]["ms_per_step"]
     line = _line("precision forms at %d^3: step time and rounding error" % n1, st["p2p_pairs"] / (ms * 1e-3) / 1e9,
