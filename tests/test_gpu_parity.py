@@ -641,11 +641,15 @@ def test_batched_forest_matches_oracle_and_sequential():
         assert rel(u[sl], us) <= 1e-5 and rel(da[sl], ds) <= 1e-5, b
 
 
-def test_graph_replays_match_eager():
+@pytest.mark.parametrize("overlap", [0, 1, 2])
+def test_graph_replays_match_eager(overlap):
+    """Replays of the captured evaluation (single stream, near field on a
+    second stream, near field first) equal the eager result bitwise, with
+    eager work between the replays."""
     import torch
     vf = _vf()
     case = wl.turbulence_case(32, seed=9)
-    kw = dict(p=8, periodic=1, box_len=2 * np.pi, images=3)
+    kw = dict(p=8, periodic=1, box_len=2 * np.pi, images=3, overlap=overlap)
     t = vf.case_to_device(case)
     ref, _ = run(case, **kw)
     st = torch.cuda.Stream()
