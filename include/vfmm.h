@@ -177,7 +177,8 @@ vfmm_status vfmm_set_params(vfmm_ctx *ctx, const vfmm_params *params);
  * n >= 2^31, or - float32 and mixed forms, whose near field works in lengths
  * scaled by 1/sigma - cores below 1/(2e7) of the domain extent), VFMM_EDOMAIN
  * (non-finite input or non-positive core; periodic position outside the
- * cube), VFMM_ENOMEM, VFMM_EHIP. */
+ * cube), VFMM_ENOMEM (allocation failed, or the M2L or P2P list would exceed
+ * 2^31 - 1 entries: about 4e8 particles at p = 10, theta = 0.5), VFMM_EHIP. */
 vfmm_status fmm_build(vfmm_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
                       const float *sigma);
 

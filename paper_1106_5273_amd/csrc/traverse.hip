@@ -316,6 +316,11 @@ void traverse_and_lists(Ctx &c) {
         VFMM_HIP(hipMemcpyAsync(h_tot, c.pairs64.ptr, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
         VFMM_HIP(hipStreamSynchronize(s));
         const int tm = h_tot[0], tp = h_tot[1], tn = h_tot[2];
+        // list positions and frontier counts are 32-bit on the device: refuse before the
+        // write pass rather than let an offset wrap (a pair emits at most 8 of each, so
+        // a frontier below 2^28 keeps this generation's own totals exact)
+        if (tm < 0 || tp < 0 || tn < 0 || n_m2l + tm > INT32_MAX || n_p2p + tp > INT32_MAX || tn > (1 << 28))
+            throw Error{VFMM_ENOMEM, "interaction lists exceed 2^31 entries"};
         grow_keep4(c, c.m2l_raw, sizeof(int4) * (size_t)(n_m2l + tm), sizeof(int4) * (size_t)n_m2l);
         grow_keep4(c, c.p2p_raw, sizeof(int4) * (size_t)(n_p2p + tp), sizeof(int4) * (size_t)n_p2p);
         c.frB.ensure(sizeof(int4) * (size_t)std::max(tn, 1));
@@ -328,8 +333,6 @@ void traverse_and_lists(Ctx &c) {
         std::swap(c.frA, c.frB);
         nf = tn;
         split = 1;
-        if (n_m2l > (1LL << 31) - 1 || n_p2p > (1LL << 31) - 1)
-            throw Error{VFMM_ENOMEM, "interaction lists exceed 2^31 entries"};
     }
     c.n_m2l = n_m2l;
     c.n_p2p = (int)n_p2p;
