@@ -1,6 +1,8 @@
 // C ABI of the library and the host orchestration of one build / evaluate.
 #include <cmath>
 #include <cstring>
+#include <new>
+#include <stdexcept>
 
 #include "ctx.h"
 
@@ -71,6 +73,12 @@ static void set_params(Ctx &c, const vfmm_params &p) {
     }
     const int W = 2 * c.img_B + 1;
     c.img_codes = W * W * W;
+}
+
+// A host-side failure (std::bad_alloc from a host vector, a stream error)
+// becomes a status code: no exception crosses the C ABI.
+static inline Error host_error(const std::exception &x) {
+    return Error{dynamic_cast<const std::bad_alloc *>(&x) ? VFMM_ENOMEM : VFMM_EHIP, std::string("host: ") + x.what()};
 }
 
 static vfmm_status fail(Ctx *c, const Error &e) {
@@ -456,6 +464,9 @@ vfmm_status vfmm_set_params(vfmm_ctx *ctx, const vfmm_params *params) {
         return VFMM_OK;
     } catch (const Error &e) {
         return vfmm::fail(&ctx->c, e);
+    } catch (const std::exception &x) {
+        const Error e = vfmm::host_error(x);
+        return vfmm::fail(&ctx->c, e);
     }
 }
 
@@ -484,6 +495,10 @@ vfmm_status fmm_build(vfmm_ctx *ctx, int64_t n, const float *x, const float *y, 
         vfmm::do_build(c, n, x, y, z, sigma);
         return VFMM_OK;
     } catch (const Error &e) {
+        c.built = false;
+        return vfmm::fail(&c, e);
+    } catch (const std::exception &x) {
+        const Error e = vfmm::host_error(x);
         c.built = false;
         return vfmm::fail(&c, e);
     }
@@ -541,6 +556,12 @@ vfmm_status fmm_build_targets(vfmm_ctx *ctx, int64_t n, const float *x, const fl
         c.tg_n = -1;
         c.n_src_part = -1;
         return vfmm::fail(&c, e);
+    } catch (const std::exception &x) {
+        const Error e = vfmm::host_error(x);
+        c.built = false;
+        c.tg_n = -1;
+        c.n_src_part = -1;
+        return vfmm::fail(&c, e);
     }
 }
 
@@ -590,6 +611,9 @@ vfmm_status fmm_evaluate_targets(vfmm_ctx *ctx, int64_t n, const float *ax, cons
         return VFMM_OK;
     } catch (const Error &e) {
         return vfmm::fail(&c, e);
+    } catch (const std::exception &x) {
+        const Error e = vfmm::host_error(x);
+        return vfmm::fail(&c, e);
     }
 }
 
@@ -616,6 +640,11 @@ vfmm_status fmm_build_batched(vfmm_ctx *ctx, int32_t nprob, const int64_t *offse
         vfmm::do_build(c, n, x, y, z, sigma);
         return VFMM_OK;
     } catch (const Error &e) {
+        c.built = false;
+        c.nprob = 1;
+        return vfmm::fail(&c, e);
+    } catch (const std::exception &x) {
+        const Error e = vfmm::host_error(x);
         c.built = false;
         c.nprob = 1;
         return vfmm::fail(&c, e);
@@ -662,6 +691,9 @@ vfmm_status fmm_evaluate(vfmm_ctx *ctx, int64_t n, const float *x, const float *
         return VFMM_OK;
     } catch (const Error &e) {
         return vfmm::fail(&c, e);
+    } catch (const std::exception &x) {
+        const Error e = vfmm::host_error(x);
+        return vfmm::fail(&c, e);
     }
 }
 
@@ -681,6 +713,10 @@ vfmm_status rk_step(vfmm_ctx *ctx, int64_t n, float dt, float nu, float *x, floa
     } catch (const Error &e) {
         c.built = false;
         return vfmm::fail(&c, e);
+    } catch (const std::exception &x) {
+        const Error e = vfmm::host_error(x);
+        c.built = false;
+        return vfmm::fail(&c, e);
     }
 }
 
@@ -696,6 +732,9 @@ vfmm_status vfmm_get_timings(vfmm_ctx *ctx, vfmm_timings *out) {
         }
         return VFMM_OK;
     } catch (const Error &e) {
+        return vfmm::fail(&c, e);
+    } catch (const std::exception &x) {
+        const Error e = vfmm::host_error(x);
         return vfmm::fail(&c, e);
     }
 }
@@ -788,6 +827,9 @@ vfmm_status vfmm_copy_lists(vfmm_ctx *ctx, int32_t *p2p_tgt, int32_t *p2p_src, i
         }
         return VFMM_OK;
     } catch (const Error &e) {
+        return vfmm::fail(&c, e);
+    } catch (const std::exception &x) {
+        const Error e = vfmm::host_error(x);
         return vfmm::fail(&c, e);
     }
 }

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <algorithm>
 #include <fstream>
+#include <new>
 #include <sstream>
 
 #include "ctx.h"
@@ -230,5 +231,12 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
         }
         c.err = e.msg;
         return e.st;
+    } catch (const std::exception &x) {  // a host-side failure becomes a status code
+        try {
+            vfmm::set_params_public(c, base);
+        } catch (...) {
+        }
+        c.err = std::string("host: ") + x.what();
+        return dynamic_cast<const std::bad_alloc *>(&x) ? VFMM_ENOMEM : VFMM_EHIP;
     }
 }
