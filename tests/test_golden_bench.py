@@ -100,3 +100,22 @@ def test_c5_reference_header():
     fp, cols, idx, val = _read("bench_c5_256.txt")
     assert cols == ["index", "ux", "uy", "uz", "dax", "day", "daz"]
     assert len(fp) == 14 and idx.size == 2048 and idx[-1] < 256 ** 3 and np.all(np.isfinite(val))
+
+
+def test_bench_reader_refuses_other_inputs_without_aborting(c2_case):
+    """bench.py's reader gives the stored rows for the inputs they were
+    computed on, and no rows (errors reported as null) for other inputs or a
+    missing file."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "bench_for_test", os.path.join(os.path.dirname(GOLDEN), os.pardir, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    idx, val, what = bench.golden("bench_c2_128.txt", wl.case_arrays(c2_case))
+    assert idx.size == 2048 and val.shape == (2048, 6) and "Fourier" in what
+    other = dict(c2_case)
+    other["sigma"] = c2_case["sigma"] * np.float32(1.01)
+    idx, val, what = bench.golden("bench_c2_128.txt", wl.case_arrays(other))
+    assert idx.size == 0 and what.startswith("unavailable") and bench.rel_l2(val[:, :3], val[:, :3]) is None
+    idx, val, what = bench.golden("no_such_file.txt", wl.case_arrays(c2_case))
+    assert idx.size == 0 and what.startswith("unavailable")
