@@ -860,3 +860,32 @@ def test_targets_with_per_particle_cores():
     e = (rel(tu, ref["u"]), rel(u, refp["u"]), rel(da, refp["da_t"]))
     print("targets, per-particle cores: u(targets) %.2e u %.2e dalpha %.2e" % e)
     assert e[0] <= 1e-5 and e[1] <= 1e-5 and e[2] <= 1e-5
+
+
+# ----------------------------------------------------------------------------
+# the per-particle-core and probe-lattice workloads at their bench sizes
+# ----------------------------------------------------------------------------
+def test_variable_cores_full_size_match_stored_oracle():
+    """128^3 lattice in free space with sigma_j = 1.5 h U(0.75, 1.25), root
+    cube [0, 2 pi)^3, p = 10: 1,024 stored targets of the FP64 direct sum with
+    each source's own core."""
+    case = wl.varcore_case(128)
+    idx, ref = _stored("bench_var_128.txt", wl.case_arrays(case))
+    u, da = run(case, p=10, theta=0.5, box_len=2 * np.pi)
+    eu, ed = rel(u[idx], ref[:, :3]), rel(da[idx], ref[:, 3:])
+    print("per-particle cores 128^3: rel-L2 u %.3e dalpha %.3e" % (eu, ed))
+    assert eu <= 1e-4 and ed <= 1e-4
+
+
+def test_probe_lattice_full_size_matches_stored_oracle():
+    """128^3 particles in free space and the 128^3 probe lattice at the cell
+    corners in one tree (leaves of <= 128 points), p = 10: u at 1,024 stored
+    probes of the FP64 direct sum."""
+    case = wl.turbulence_case(128, seed=2)
+    pts = wl.corner_lattice(128)
+    idx, ref = _stored("bench_targets_128.txt", wl.case_arrays(case) + list(pts))
+    P = np.stack(pts, 1).astype(np.float64)
+    _, _, tu = _run_targets(case, P, p=10, theta=0.5, ncrit=128)
+    eu = rel(tu[idx], ref)
+    print("probe lattice 128^3: rel-L2 u %.3e" % eu)
+    assert eu <= 1e-4
