@@ -303,3 +303,41 @@ def test_points_match_particle_sums_and_are_divergence_free():
     off = np.random.default_rng(3).uniform(-0.2, 1.2, size=(50, 3))
     J = oracle.direct_points(case, off)["J"]
     assert np.abs(J[:, 0, 0] + J[:, 1, 1] + J[:, 2, 2]).max() <= 1e-12 * np.abs(J).max()
+
+
+# ----------------------------------------------------------------------------
+# Eq. (2) with unequal cores: each pair uses its source's core
+# ----------------------------------------------------------------------------
+def test_each_pair_uses_the_source_core():
+    """Two blobs with different cores: the velocity each induces on the other,
+    and its gradient, follow from the Gaussian vorticity of the *source* blob
+    alone (enclosed mass by quadrature, gradient by central differences of
+    that field), not from the target's core or a mix of the two."""
+    sig = np.array([0.2, 0.5])
+    x = np.array([[0.0, 0.0, 0.0], [0.3, 0.1, -0.05]])
+    a = np.array([[0.2, -0.4, 1.0], [0.7, 0.3, -0.6]])
+    case = dict(x=x[:, 0], y=x[:, 1], z=x[:, 2], ax=a[:, 0], ay=a[:, 1], az=a[:, 2], sigma=sig, n=2)
+    ref = oracle.direct(case)
+
+    def field(p, j):  # velocity at p of blob j alone: (enclosed mass / 4 pi rho^3) alpha_j x (p - x_j)
+        r = p - x[j]
+        rho = np.linalg.norm(r)
+        mass, _ = integrate.quad(lambda s: 4.0 * np.pi * s * s * gauss3(s, sig[j]), 0.0, rho,
+                                 epsabs=0.0, epsrel=1e-13, limit=200)
+        return mass / (4.0 * np.pi * rho ** 3) * np.cross(a[j], r)
+
+    h = 1e-5
+    for i, j in ((0, 1), (1, 0)):
+        u = field(x[i], j)
+        assert np.allclose(ref["u"][i], u, rtol=1e-10, atol=1e-14)
+        # the gradient also holds the particle's own blob: zero velocity at its centre but the
+        # rigid rotation omega(0)/3 there, which drops out of the stretching term
+        J = np.empty((3, 3))
+        for k in range(3):
+            e = np.zeros(3)
+            e[k] = h
+            J[k] = (field(x[i] + e, j) + field(x[i] + e, i) - field(x[i] - e, j) - field(x[i] - e, i)) / (2.0 * h)
+        assert np.allclose(ref["J"][i], J, rtol=1e-6, atol=1e-9 * np.abs(J).max())
+        # the target's own core would give a clearly different velocity here
+        other = dict(case, sigma=np.array([sig[i], sig[i]]))
+        assert not np.allclose(oracle.direct(other)["u"][i], u, rtol=1e-3)
