@@ -20,6 +20,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "FMM step time & P2P Gpair-interactions/s at 128^3 particles, p=10, ≤1e-4 err"
+PEAK_FP32_MFMA_TFLOPS = 157.3        # published dense FP32 matrix-core peak of MI355X (the M2L products)
 PEAK_FP32_VALU_TFLOPS = 157.3        # published FP32 vector peak of MI355X (256 CU, 2.4 GHz); non-packed FMA with
                                       # vector-register operands reaches 84-94% of it, with a scalar operand half that
 FLOPS_PER_PAIR = 59                   # gfx950 ISA of the P2P pair body (s >= 1 form): 24 FMA + 6 MUL + 3 SUB + 2 TRANS, FMA = 2
@@ -596,6 +597,12 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": traffic,
                      "kernel": "k_p2p", "flops_per_pair": FLOPS_PER_PAIR},
+        "m2l": {"kernel": "k_m2lb", "translations": st["m2l_entries"], "ms": mean_ph["m2l_ms"],
+                "flops_per_translation": 6 * (args.p + 1) ** 4,
+                "achieved": st["m2l_entries"] * 6 * (args.p + 1) ** 4 / (mean_ph["m2l_ms"] * 1e-3) / 1e12,
+                "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": st["m2l_entries"] * 6 * (args.p + 1) ** 4 / (mean_ph["m2l_ms"] * 1e-3) / 1e12
+                / PEAK_FP32_MFMA_TFLOPS},
         "overlap_streams": ov,
         "tuned": tuned,
     }
