@@ -23,6 +23,20 @@ Routes
 * ``surface_term``      (1/3V) sum_j x_j x alpha_j: the difference between the
                         cube-ordered image sum and the zero-mean Fourier sum.
 * ``brute_images``      cube-ordered image sum over |n|_inf <= M (tiny N).
+* ``fourier_series_points``  the series of ``fourier_points`` with each phase
+                        factored over the axes (matrix products over the
+                        particles): every particle of a 32^3 off-lattice set.
+* ``spectral_lattice(offset=delta)``  the lattice route evaluated at the
+                        lattice points shifted by delta (e.g. a probe lattice
+                        at the cell corners).
+* ``energy_spectrum``   shell-binned kinetic energy spectrum E(k) of a
+                        velocity sampled on a uniform lattice (Sec. 4.3).
+* ``heun_step``         one two-stage Runge-Kutta (Heun) step of x, alpha and
+                        sigma^2 (Sec. 2.1, Eqs. (1), (3), (4)) from any rate
+                        function (``direct`` or the Fourier series).
+* ``gaussian_sum``, ``gaussian_lattice``, ``rbf_cg``, ``rbf_lattice`` (``rbf.py``, ``gauss.c``):
+                        the Gaussian blob sum and the strengths that reproduce
+                        a vorticity field at the particles (reinitialisation).
 
 Readings of the paper taken here (its text is silent or ambiguous):
 * sign of Eq. (1): physical Biot-Savart, u = curl psi, -lap psi = omega;
@@ -50,12 +64,19 @@ def _lib():
             from . import build as _b
             _b.build()
         lib = ctypes.CDLL(path)
+        if not hasattr(lib, "oracle_gauss_sum"):  # a copy built before gauss.c existed
+            from . import build as _b
+            _b.build()
+            lib = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         lib.oracle_direct.argtypes = [ctypes.c_int64, dp, dp, dp, ctypes.c_int64, dp, dp, dp,
                                       dp, dp, dp, dp, ctypes.c_int64, dp, dp, dp]
         lib.oracle_direct.restype = None
         lib.oracle_pair_factors.argtypes = [ctypes.c_int64, dp, dp, dp, dp]
         lib.oracle_pair_factors.restype = None
+        lib.oracle_gauss_sum.argtypes = [ctypes.c_int64, dp, dp, dp, ctypes.c_int64, dp, dp, dp,
+                                         dp, dp, dp, dp, ctypes.c_int64, dp, dp]
+        lib.oracle_gauss_sum.restype = None
         _LIB = lib
     return _LIB
 
@@ -193,8 +214,9 @@ def fourier_points(case, L, kmax, targets=None, points=None):
     return u, J
 
 
-def spectral_lattice(case, aliases=None, workers=None):
-    """Exact zero-mean periodic u and J at the n^3 cell-centred lattice.
+def spectral_lattice(case, aliases=None, workers=None, offset=None):
+    """Exact zero-mean periodic u and J at the n^3 cell-centred lattice
+    (or, with ``offset`` = delta, at the lattice points shifted by delta).
 
     Sources and targets sit at x = (i+1/2) h, h = L/n, flattened [i, j, k]
     (x slowest), uniform sigma.  With A(kappa) the DFT of alpha over lattice
@@ -206,7 +228,11 @@ def spectral_lattice(case, aliases=None, workers=None):
         Q_ka(kappa) = sum_m k'_k k'_a exp(-sigma^2 |k'|^2 / 2) / |k'|^2,
     (IDFT normalised as a plain sum over kappa) with kappa centred in [-n/2, n/2) and m over {-aliases..aliases}^3 (default: enough
     folds that the first omitted Gaussian factor is below 1e-18); k'=0 is
-    dropped (zero mean).  Returns (u (N,3), J (N,3,3)) in the input order."""
+    dropped (zero mean).  Returns (u (N,3), J (N,3,3)) in the input order.
+
+    Shifted points x_t + delta: every wavevector k' picks up the phase
+    exp(i k'.delta), which differs between aliases, so P and Q are summed with
+    it (complex) before the inverse DFT; delta = 0 is the unshifted sum."""
     import scipy.fft as sfft
     n = int(case["lattice_n"])
     L = float(case["L"])
@@ -222,8 +248,10 @@ def spectral_lattice(case, aliases=None, workers=None):
     kap = np.fft.fftfreq(n, d=1.0 / n)
     kap = np.where(kap >= n // 2, kap - n, kap)  # centred: [-n/2, n/2)
     tw = 2.0 * np.pi / L
-    P = np.zeros((3, n, n, n))
-    Q = np.zeros((6, n, n, n))  # xx yy zz xy xz yz
+    shifted = offset is not None and np.any(np.asarray(offset, dtype=np.float64) != 0.0)
+    dl = np.asarray(offset if shifted else (0.0, 0.0, 0.0), dtype=np.float64)
+    P = np.zeros((3, n, n, n), dtype=np.complex128 if shifted else np.float64)
+    Q = np.zeros((6, n, n, n), dtype=P.dtype)  # xx yy zz xy xz yz
     KX, KY, KZ = np.meshgrid(kap, kap, kap, indexing="ij", sparse=True)
     rng = range(-aliases, aliases + 1)
     for mx in rng:
@@ -235,6 +263,8 @@ def spectral_lattice(case, aliases=None, workers=None):
                 k2 = kx * kx + ky * ky + kz * kz
                 with np.errstate(divide="ignore", invalid="ignore"):
                     w = np.where(k2 > 0, np.exp(-0.5 * sig * sig * k2) / k2, 0.0)
+                if shifted:
+                    w = w * np.exp(1j * (kx * dl[0] + ky * dl[1] + kz * dl[2]))
                 P[0] += kx * w
                 P[1] += ky * w
                 P[2] += kz * w
@@ -259,3 +289,101 @@ def spectral_lattice(case, aliases=None, workers=None):
         for l in range(3):
             J[:, k, l] = np.real(sfft.ifftn(-QxA[l] * (N / V), workers=workers)).reshape(N)
     return u, J
+
+
+def fourier_series_points(case, L, kmax, points=None, chunk=2048):
+    """The Fourier series of ``fourier_points`` (zero-mean periodic u and J,
+    wavevectors k = 2 pi m / L with 0 < |m|_inf <= kmax, uniform sigma), summed
+    with each phase written as a product over the axes,
+    exp(i k.x) = exp(i k_x x) exp(i k_y y) exp(i k_z z), so that
+    S(k) = sum_j alpha_j exp(-i k.x_j) and the sums at the evaluation points
+    become matrix products over the particle (or point) index: the same terms,
+    cheap enough for every particle of a 32^3 set.  ``points`` (m, 3) default
+    to the particles.  Returns (u (m,3), J (m,3,3)), J_kl = du_l/dx_k."""
+    sig = float(np.asarray(case["sigma"])[0])
+    x = np.stack([_d(case["x"]), _d(case["y"]), _d(case["z"])], axis=1)
+    a = np.stack([_d(case["ax"]), _d(case["ay"]), _d(case["az"])], axis=1)
+    xt = x if points is None else np.asarray(points, dtype=np.float64).reshape(-1, 3)
+    m = np.arange(-kmax, kmax + 1)
+    K = (2.0 * np.pi / L) * m                  # wavenumbers along one axis
+    M = K.size
+    # S[c, a, b, d] = sum_j alpha_c,j e^{-i K_a x_j} e^{-i K_b y_j} e^{-i K_d z_j}
+    S = np.zeros((3 * M, M * M), dtype=np.complex128)
+    for j0 in range(0, x.shape[0], chunk):
+        xs = x[j0:j0 + chunk]
+        ex = np.exp(-1j * np.outer(xs[:, 0], K))
+        ey = np.exp(-1j * np.outer(xs[:, 1], K))
+        ez = np.exp(-1j * np.outer(xs[:, 2], K))
+        T = (ey[:, :, None] * ez[:, None, :]).reshape(xs.shape[0], M * M)
+        Aw = (a[j0:j0 + chunk, :, None] * ex[:, None, :]).reshape(xs.shape[0], 3 * M)
+        S += Aw.T @ T
+    S = S.reshape(3, M, M, M)
+    KX, KY, KZ = np.meshgrid(K, K, K, indexing="ij")
+    k2 = KX * KX + KY * KY + KZ * KZ
+    with np.errstate(divide="ignore", invalid="ignore"):
+        w = np.where(k2 > 0, np.exp(-0.5 * sig * sig * k2) / k2, 0.0)
+    V = L ** 3
+    kxS = np.stack([KY * S[2] - KZ * S[1], KZ * S[0] - KX * S[2], KX * S[1] - KY * S[0]])
+    Cu = 1j * kxS * w / V                      # u_l(x) = Re sum_k Cu_l(k) e^{i k.x}
+    Kc = (KX, KY, KZ)
+    C = [Cu[l] for l in range(3)] + [1j * Kc[k] * Cu[l] for k in range(3) for l in range(3)]
+    C = np.stack(C).reshape(12, M, M * M)     # [q, a, (b, d)]
+    Cm = C.transpose(0, 1, 2).reshape(12 * M, M * M)
+    out = np.empty((xt.shape[0], 12))
+    for t0 in range(0, xt.shape[0], chunk):
+        pt = xt[t0:t0 + chunk]
+        ex = np.exp(1j * np.outer(pt[:, 0], K))
+        ey = np.exp(1j * np.outer(pt[:, 1], K))
+        ez = np.exp(1j * np.outer(pt[:, 2], K))
+        T = (ey[:, :, None] * ez[:, None, :]).reshape(pt.shape[0], M * M)
+        R = (T @ Cm.T).reshape(pt.shape[0], 12, M)
+        out[t0:t0 + chunk] = np.real(np.einsum("tqa,ta->tq", R, ex))
+    u = out[:, :3].copy()
+    J = out[:, 3:].reshape(-1, 3, 3).copy()
+    return u, J
+
+
+def energy_spectrum(u, n, L):
+    """Shell-binned kinetic energy spectrum of a velocity field sampled on an
+    n^3 uniform lattice (flattened [i, j, k], x index slowest; ``u`` (n^3, 3)):
+    with u_hat(kappa) = (1/n^3) sum_t u(x_t) exp(-2 pi i kappa.t / n) (the
+    Fourier coefficients of the sampled field), E(k) = 1/2 sum of |u_hat|^2
+    over the integer wavevectors kappa with round(|kappa|) = k, for
+    k = 0 .. floor(sqrt(3) n / 2).  Wavenumbers are in units of 2 pi / L (L
+    does not change the values); sum_k E(k) = 1/2 mean |u|^2 (Parseval)."""
+    u = np.asarray(u, dtype=np.float64).reshape(n, n, n, 3)
+    uh = np.fft.fftn(u, axes=(0, 1, 2)) / float(n ** 3)
+    e = 0.5 * np.sum(np.abs(uh) ** 2, axis=3)
+    kap = np.fft.fftfreq(n, d=1.0 / n)
+    KX, KY, KZ = np.meshgrid(kap, kap, kap, indexing="ij")
+    shell = np.rint(np.sqrt(KX * KX + KY * KY + KZ * KZ)).astype(np.int64)
+    return np.bincount(shell.ravel(), weights=e.ravel(), minlength=int(np.floor(np.sqrt(3.0) * n / 2)) + 1)
+
+
+def heun_step(case, dt, nu, rates, L=None, lo=(0.0, 0.0, 0.0)):
+    """One step of Heun's method (the two-stage explicit trapezoidal
+    Runge-Kutta rule) for the particle system of Sec. 2.1: dx/dt = u (Eq. 1),
+    dalpha/dt = the stretching term (Eq. 3), d sigma^2/dt = 2 nu (Eq. 4).
+
+    ``rates(x (N,3), alpha (N,3), sigma (N,))`` returns (u, dalpha), each
+    (N,3) float64.  Stage 1 at the current state; the predictor
+    x* = x + dt u, alpha* = alpha + dt dalpha, sigma*^2 = sigma^2 + 2 nu dt;
+    stage 2 at the predictor; then x += dt/2 (u + u*), alpha += dt/2
+    (dalpha + dalpha*), sigma^2 += 2 nu dt.  With a period L, positions are
+    wrapped into [lo, lo + L) after each stage.  Returns dict(x, alpha, sigma)
+    in float64."""
+    x0 = np.stack([_d(case["x"]), _d(case["y"]), _d(case["z"])], axis=1)
+    a0 = np.stack([_d(case["ax"]), _d(case["ay"]), _d(case["az"])], axis=1)
+    s0 = _d(case["sigma"])
+    lo = np.asarray(lo, dtype=np.float64)
+
+    def wrap(x):
+        return x if L is None else lo + np.mod(x - lo, L)
+
+    u1, d1 = rates(x0, a0, s0)
+    s1 = np.sqrt(s0 * s0 + 2.0 * nu * dt)
+    u2, d2 = rates(wrap(x0 + dt * u1), a0 + dt * d1, s1)
+    return dict(x=wrap(x0 + 0.5 * dt * (u1 + u2)), alpha=a0 + 0.5 * dt * (d1 + d2), sigma=s1)
+
+
+from .rbf import gaussian_sum, gaussian_lattice, rbf_cg, rbf_lattice  # noqa: E402,F401

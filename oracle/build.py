@@ -8,8 +8,8 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose=False):
-    src = os.path.join(HERE, "direct.c")
-    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", LIB, src, "-lm"]
+    srcs = [os.path.join(HERE, f) for f in ("direct.c", "gauss.c")]
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", LIB] + srcs + ["-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
