@@ -32,6 +32,14 @@
  * - The context owns the tree, expansions, interaction lists and scratch space
  *   in device memory.  These only grow; vfmm_destroy frees them.
  * - A context is not thread safe; calls on one context must not overlap.
+ * - Depth.  Morton keys hold 21 bits per axis (Sec. 3.2), so a cell is split
+ *   at most 21 times (fewer in a batch, whose keys also carry the problem id).
+ *   A cell that still holds more than ncrit particles at that depth (particles
+ *   closer than 2^-21 of the root cube, coincident ones included) stays a leaf
+ *   with all of them: its pairs go to the near field, which is exact for any
+ *   count (coincident pairs take the r -> 0 limit of the cutoff), so results
+ *   stay correct and only that leaf's work grows.  This is deliberate: no
+ *   call returns VFMM_EDEPTH; vfmm_get_stats counts such leaves.
  */
 #ifndef VFMM_H
 #define VFMM_H
@@ -48,7 +56,7 @@ typedef enum {
     VFMM_OK = 0,
     VFMM_EINVAL = -1,  /* bad argument: null pointer, n < 0, aliasing, unsupported parameter */
     VFMM_ENOMEM = -2,  /* device allocation failed                                         */
-    VFMM_EDEPTH = -3,  /* reserved: tree deeper than 21 levels (64-bit Morton keys, Sec. 3.2) */
+    VFMM_EDEPTH = -3,  /* never returned (see "Depth" below); kept so that codes stay stable        */
     VFMM_EDOMAIN = -4, /* periodic: a position outside [lo, lo+len), or a non-finite input    */
     VFMM_ESTATE = -5,  /* fmm_evaluate without a matching fmm_build                            */
     VFMM_EHIP = -6     /* a HIP runtime call failed                                            */
@@ -152,6 +160,11 @@ typedef struct vfmm_stats {
     int32_t m2l_groups;     /* batched M2L: (target block, operator) groups        */
     int32_t m2l_items;      /* batched M2L: work items (<= 24 groups of one block) */
     int32_t m2l_split;      /* batched M2L: 1 when it runs the split bf16 products */
+    int32_t stale;          /* 1 when the last fmm_evaluate found positions or cores
+                               that differ from the build's (its outputs are NaN)     */
+    int32_t overfull_leaves;/* leaves holding more than ncrit particles because the
+                               keys resolve no finer (21 levels, Sec. 3.2; fewer in a
+                               batch): coincident or nearly coincident particles      */
 } vfmm_stats;
 
 /* Fill *p with the defaults listed above (free space). */
@@ -184,11 +197,18 @@ vfmm_status fmm_build(vfmm_ctx *ctx, int64_t n, const float *x, const float *y, 
 
 /* Evaluate u (Eq. 1) and dalpha/dt (Eq. 3, reading ctx scheme) at every
  * particle, using the tree of the last fmm_build, which must have been made
- * from the same n, positions and cores (the library checks n only).  Inputs and
- * outputs are device float32[n].  Periodic with zero_mean: u is the zero-mean
- * periodic field (the cube-ordered image sum minus (1/3V) sum x_j x alpha_j).
- * Errors: VFMM_ESTATE (no build, or n differs), VFMM_EINVAL (null pointer,
- * aliasing), VFMM_EHIP. */
+ * from the same n, positions and cores.  Inputs and outputs are device
+ * float32[n].  Periodic with zero_mean: u is the zero-mean periodic field (the
+ * cube-ordered image sum minus (1/3V) sum x_j x alpha_j).
+ * The check that positions and cores are the build's: when x, y, z, sigma are
+ * other arrays than the ones given to fmm_build, the call compares a float64
+ * fingerprint of their contents with the build's before it starts
+ * (synchronising the stream once) and returns VFMM_ESTATE on a difference.
+ * When they are the same arrays, the call stays asynchronous; the device
+ * compares the fingerprints and, if the contents changed since the build,
+ * every output is NaN and vfmm_get_stats reports stale = 1.
+ * Errors: VFMM_ESTATE (no build, n differs, or other arrays whose contents
+ * differ), VFMM_EINVAL (null pointer, aliasing), VFMM_EHIP. */
 vfmm_status fmm_evaluate(vfmm_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
                          const float *ax, const float *ay, const float *az, const float *sigma,
                          float *ux, float *uy, float *uz, float *dax, float *day, float *daz);
@@ -273,11 +293,11 @@ vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, const float 
 
 /* Copy the per-phase times of the last build/evaluate to *out.  Synchronises
  * the context stream.  Errors: VFMM_EINVAL for null arguments. */
-vfmm_status vfmm_get_timings(vfmm_ctx *ctx, vfmm_timings *out);
+vfmm_status vfmm_get_timings(const vfmm_ctx *ctx, vfmm_timings *out);
 
 /* Copy the tree/list sizes of the last build to *out.  Synchronises the
  * context stream.  Errors: VFMM_EINVAL for null arguments. */
-vfmm_status vfmm_get_stats(vfmm_ctx *ctx, vfmm_stats *out);
+vfmm_status vfmm_get_stats(const vfmm_ctx *ctx, vfmm_stats *out);
 
 /* Copy the interaction lists of the last build to HOST buffers, for checking
  * that the traversal covers every (target, source, image) particle pair once.

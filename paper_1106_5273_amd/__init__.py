@@ -52,7 +52,8 @@ class Stats(ctypes.Structure):
                 ("m2l_entries", ctypes.c_int64), ("p2p_blocks", ctypes.c_int32),
                 ("images_traversed", ctypes.c_int32), ("sum_alpha", ctypes.c_double * 3),
                 ("sigma_min", ctypes.c_double), ("sigma_max", ctypes.c_double), ("m2l_keys", ctypes.c_int32),
-                ("m2l_groups", ctypes.c_int32), ("m2l_items", ctypes.c_int32), ("m2l_split", ctypes.c_int32)]
+                ("m2l_groups", ctypes.c_int32), ("m2l_items", ctypes.c_int32), ("m2l_split", ctypes.c_int32),
+                ("stale", ctypes.c_int32), ("overfull_leaves", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p

@@ -81,7 +81,7 @@ static inline Error host_error(const std::exception &x) {
     return Error{dynamic_cast<const std::bad_alloc *>(&x) ? VFMM_ENOMEM : VFMM_EHIP, std::string("host: ") + x.what()};
 }
 
-static vfmm_status fail(Ctx *c, const Error &e) {
+static vfmm_status fail(const Ctx *c, const Error &e) {
     if (c) c->err = e.msg;
     return e.st;
 }
@@ -92,7 +92,7 @@ static void ensure_events(Ctx &c) {
     c.ev_ok = true;
 }
 
-static float ev_ms(Ctx &c, int a, int b) {
+static float ev_ms(const Ctx &c, int a, int b) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, c.ev[a], c.ev[b]) != hipSuccess) {
         (void)hipGetLastError();
@@ -139,6 +139,7 @@ static void do_build(Ctx &c, int64_t n, const float *x, const float *y, const fl
     c.record(2 * PH_NUM);
     c.record(2 * PH_BOUNDS_SORT);
     c.n = n;
+    c.overfull_leaves = 0;
     if (n == 0) {
         c.ncells = c.nleaves = c.n_p2p = c.n_blocks = 0;
         c.n_m2l = c.p2p_pairs = 0;
@@ -148,6 +149,11 @@ static void do_build(Ctx &c, int64_t n, const float *x, const float *y, const fl
     compute_bounds(c, n, x, y, z, sigma, nullptr, nullptr, nullptr, false);
     VFMM_HIP(hipMemcpyAsync(&c.hb, c.bres.ptr, sizeof(Bounds), hipMemcpyDeviceToHost, s));
     VFMM_HIP(hipStreamSynchronize(s));
+    c.build_fp = c.hb.fp;
+    c.build_ptr[0] = x;
+    c.build_ptr[1] = y;
+    c.build_ptr[2] = z;
+    c.build_ptr[3] = sigma;
     if (c.hb.nonfinite) throw Error{VFMM_EDOMAIN, "non-finite position or non-positive core"};
     if (c.prm.periodic && c.hb.outside) throw Error{VFMM_EDOMAIN, "position outside the periodic cube"};
     if (!c.prm.periodic && c.nprob == 1 && c.prm.box_len > 0.0 && c.hb.outside)
@@ -283,7 +289,7 @@ static void graph_evaluate(Ctx &c, int64_t n, const float *const *in, float *con
     c.eval_timed = true;
 }
 
-static void read_timings(Ctx &c, vfmm_timings *out) {
+static void read_timings(const Ctx &c, vfmm_timings *out) {
     std::memset(out, 0, sizeof(*out));
     if (!c.ev_ok) return;
     VFMM_HIP(hipStreamSynchronize(c.stream));
@@ -314,15 +320,24 @@ struct RkArgs {
     int64_t n;
     float dt, nu;
     int periodic;
-    float lo[3], len;
+    double lo[3], len;
 };
 
-__device__ inline float wrap(float v, float lo, float len) {
-    float t = v - lo;
-    t -= floorf(t / len) * len;
+// Wraps v into the periodic cube [lo, lo + len) along one axis.  The
+// arithmetic is float64 against the float64 cube, and the float32 result is
+// then nudged by single ulps until it passes the same float64 comparison
+// lo <= v < lo + len that the bounds pass of the next build applies (a cube
+// corner such as -pi is not a float32 number, so a plain float32 wrap can
+// land a particle just outside the cube).
+__device__ inline float wrap(float v, double lo, double len) {
+    double t = (double)v - lo;
+    t -= floor(t / len) * len;
     if (t >= len) t -= len;
-    if (t < 0.f) t += len;
-    return lo + t;
+    if (t < 0.0) t += len;
+    float r = (float)(lo + t);
+    for (int k = 0; k < 4 && (double)r < lo; ++k) r = nextafterf(r, INFINITY);
+    for (int k = 0; k < 4 && (double)r >= lo + len; ++k) r = nextafterf(r, -INFINITY);
+    return r;
 }
 
 // stage 1 predictor: xs = x + dt u1, as = a + dt da1, ss = sqrt(s^2 + 2 nu dt)
@@ -375,8 +390,8 @@ static void do_rk(Ctx &c, int64_t n, float dt, float nu, float *x, float *y, flo
     A.dt = dt;
     A.nu = nu;
     A.periodic = c.prm.periodic;
-    for (int d = 0; d < 3; ++d) A.lo[d] = (float)c.prm.box_lo[d];
-    A.len = (float)c.prm.box_len;
+    for (int d = 0; d < 3; ++d) A.lo[d] = c.prm.box_lo[d];
+    A.len = c.prm.box_len;
     do_build(c, n, x, y, z, sigma);
     do_evaluate(c, n, x, y, z, ax, ay, az, sigma, U1, U1 + n, U1 + 2 * n, U1 + 3 * n, U1 + 4 * n, U1 + 5 * n);
     read_timings(c, &c.t_stage1);
@@ -680,6 +695,14 @@ vfmm_status fmm_evaluate(vfmm_ctx *ctx, int64_t n, const float *x, const float *
                     if (overlaps(outp[a], p, n)) throw Error{VFMM_EINVAL, "an output aliases an input"};
             }
         }
+        if (n > 0 && (x != c.build_ptr[0] || y != c.build_ptr[1] || z != c.build_ptr[2] || sigma != c.build_ptr[3])) {
+            // other arrays than the build's: their contents must be the build's positions and cores
+            vfmm::compute_bounds(c, n, x, y, z, sigma, ax, ay, az, true);
+            vfmm::Bounds b;
+            VFMM_HIP(hipMemcpyAsync(&b, c.bres.ptr, sizeof(b), hipMemcpyDeviceToHost, c.stream));
+            VFMM_HIP(hipStreamSynchronize(c.stream));
+            if (b.stale) throw Error{VFMM_ESTATE, "fmm_evaluate: positions or cores differ from those of the last build"};
+        }
         c.err.clear();
         if (c.prm.use_graph && n > 0) {
             const float *in[7] = {x, y, z, ax, ay, az, sigma};
@@ -720,9 +743,9 @@ vfmm_status rk_step(vfmm_ctx *ctx, int64_t n, float dt, float nu, float *x, floa
     }
 }
 
-vfmm_status vfmm_get_timings(vfmm_ctx *ctx, vfmm_timings *out) {
+vfmm_status vfmm_get_timings(const vfmm_ctx *ctx, vfmm_timings *out) {
     if (!ctx || !out) return VFMM_EINVAL;
-    Ctx &c = ctx->c;
+    const Ctx &c = ctx->c;
     try {
         vfmm::read_timings(c, out);
         if (c.last_was_rk) {
@@ -739,9 +762,9 @@ vfmm_status vfmm_get_timings(vfmm_ctx *ctx, vfmm_timings *out) {
     }
 }
 
-vfmm_status vfmm_get_stats(vfmm_ctx *ctx, vfmm_stats *out) {
+vfmm_status vfmm_get_stats(const vfmm_ctx *ctx, vfmm_stats *out) {
     if (!ctx || !out) return VFMM_EINVAL;
-    Ctx &c = ctx->c;
+    const Ctx &c = ctx->c;
     std::memset(out, 0, sizeof(*out));
     if (hipStreamSynchronize(c.stream) != hipSuccess) {
         c.err = "stream synchronisation failed";
@@ -764,10 +787,13 @@ vfmm_status vfmm_get_stats(vfmm_ctx *ctx, vfmm_stats *out) {
         out->m2l_items = c.mb_nitems;
         out->m2l_split = c.mb_x6 ? 1 : 0;
     }
+    out->overfull_leaves = c.overfull_leaves;
     if (c.bres.ptr && c.n > 0) {
         vfmm::Bounds b;
-        if (hipMemcpy(&b, c.bres.ptr, sizeof(b), hipMemcpyDeviceToHost) == hipSuccess)
+        if (hipMemcpy(&b, c.bres.ptr, sizeof(b), hipMemcpyDeviceToHost) == hipSuccess) {
             for (int d = 0; d < 3; ++d) out->sum_alpha[d] = b.sum_a[d];
+            out->stale = b.stale;
+        }
     }
     return VFMM_OK;
 }

@@ -83,9 +83,11 @@ struct Bounds {
     double sig_min, sig_max;
     double sum_a[3];
     double sum_xa[3];  // sum (x_j - ref) x alpha_j, ref = periodic cube centre (or 0)
+    double fp;         // fingerprint of positions and cores: sum_i (1 + i mod 61)(x + 3y + 5z + 7 sigma)_i
     int nonfinite;
     int outside;       // periodic: positions outside the cube
-    int pad[2];
+    int stale;         // evaluation: the fingerprint differs from the build's (outputs are NaN)
+    int overfull;      // build: leaves above ncrit at the key-resolution depth limit
 };
 
 // Geometry of the root cube used for Morton keys and cell centres.

@@ -11,7 +11,7 @@ enum Phase { PH_BOUNDS_SORT = 0, PH_TREE, PH_TRAVERSE, PH_P2M_M2M, PH_LATTICE, P
 struct Ctx {
     vfmm_params prm{};
     hipStream_t stream = nullptr;
-    std::string err;
+    mutable std::string err;
     int device = 0;
 
     // ---- state of the last build ----
@@ -31,6 +31,9 @@ struct Ctx {
     int key_levels = 21;                 // Morton levels per axis below the problem id
     std::vector<int64_t> h_poff;         // problem offsets (host)
     int images_traversed = 0;
+    double build_fp = 0.0;               // fingerprint of the build's positions and cores (Bounds::fp)
+    const void *build_ptr[4] = {nullptr, nullptr, nullptr, nullptr};  // x, y, z, sigma of the build
+    int overfull_leaves = 0;             // leaves above ncrit at the key-resolution depth limit
 
     // ---- device buffers (grow-only) ----
     DevBuf bpart, bres;                  // bounds partials / result

@@ -334,6 +334,7 @@ __device__ __forceinline__ void p2p_block(const P2PConst &k, const P2PArgs &A, i
         u1 -= (float)(A.bounds->sum_xa[1]) * A.inv3V;
         u2 -= (float)(A.bounds->sum_xa[2]) * A.inv3V;
     }
+    if (A.bounds->stale) u0 = u1 = u2 = d0 = d1 = d2 = __builtin_nanf("");  // positions differ from the build's
     const int o = A.perm[i];
     A.ux[o] = u0;
     A.uy[o] = u1;
@@ -546,6 +547,7 @@ __global__ __launch_bounds__(64) void k_p2p64(P2P64Args A) {
         u1 -= A.bounds->sum_xa[1] * A.inv3V;
         u2 -= A.bounds->sum_xa[2] * A.inv3V;
     }
+    if (A.bounds->stale) u0 = u1 = u2 = d0 = d1 = d2 = __builtin_nan("");  // positions differ from the build's
     const int o = A.perm[i];
     A.ux[o] = (float)u0;
     A.uy[o] = (float)u1;
@@ -664,13 +666,14 @@ __global__ __launch_bounds__(256) void k_finalize(P2PArgs A, const float *__rest
     if (i >= A.n) return;
     const int64_t n = A.n;
     float u0 = near[i] + A.far_u[i], u1 = near[n + i] + A.far_u[n + i], u2 = near[2 * n + i] + A.far_u[2 * n + i];
-    const float d0 = near[3 * n + i] + A.far_da[i], d1 = near[4 * n + i] + A.far_da[n + i],
-                d2 = near[5 * n + i] + A.far_da[2 * n + i];
+    float d0 = near[3 * n + i] + A.far_da[i], d1 = near[4 * n + i] + A.far_da[n + i],
+          d2 = near[5 * n + i] + A.far_da[2 * n + i];
     if (A.surface) {
         u0 -= (float)(A.bounds->sum_xa[0]) * A.inv3V;
         u1 -= (float)(A.bounds->sum_xa[1]) * A.inv3V;
         u2 -= (float)(A.bounds->sum_xa[2]) * A.inv3V;
     }
+    if (A.bounds->stale) u0 = u1 = u2 = d0 = d1 = d2 = __builtin_nanf("");  // positions differ from the build's
     const int o = A.perm[i];
     A.ux[o] = u0;
     A.uy[o] = u1;

@@ -87,7 +87,7 @@ void scan_excl_i32(Ctx &c, const int *in, int *out, int64_t n) {
 // stage reduction.
 // ---------------------------------------------------------------------------
 struct BAcc {
-    double lo[3], hi[3], smin, smax, sa[3], sxa[3];
+    double lo[3], hi[3], smin, smax, sa[3], sxa[3], fp;
     int nf, out;
 };
 
@@ -95,7 +95,7 @@ __device__ inline void bacc_init(BAcc &a) {
     for (int d = 0; d < 3; ++d) {
         a.lo[d] = 1e300; a.hi[d] = -1e300; a.sa[d] = 0; a.sxa[d] = 0;
     }
-    a.smin = 1e300; a.smax = -1e300; a.nf = 0; a.out = 0;
+    a.smin = 1e300; a.smax = -1e300; a.fp = 0; a.nf = 0; a.out = 0;
 }
 
 __device__ inline void bacc_merge(BAcc &a, const BAcc &b) {
@@ -104,6 +104,7 @@ __device__ inline void bacc_merge(BAcc &a, const BAcc &b) {
         a.sa[d] += b.sa[d]; a.sxa[d] += b.sxa[d];
     }
     a.smin = fmin(a.smin, b.smin); a.smax = fmax(a.smax, b.smax);
+    a.fp += b.fp;
     a.nf += b.nf; a.out += b.out;
 }
 
@@ -113,6 +114,8 @@ struct BoundsArgs {
     int with_alpha, periodic;
     double ref[3];
     double plo[3], plen;
+    int check_fp;  // evaluation: compare the fingerprint with fp_ref (the build's)
+    double fp_ref;
 };
 
 __global__ __launch_bounds__(TPB) void k_bounds_partial(BoundsArgs A, BAcc *part) {
@@ -128,6 +131,7 @@ __global__ __launch_bounds__(TPB) void k_bounds_partial(BoundsArgs A, BAcc *part
             al[0] = A.ax[i]; al[1] = A.ay[i]; al[2] = A.az[i];
             fin = fin && isfinite(al[0]) && isfinite(al[1]) && isfinite(al[2]);
         }
+        a.fp += (double)(1 + i % 61) * (p[0] + 3.0 * p[1] + 5.0 * p[2] + 7.0 * sg);
         if (!fin) { a.nf++; continue; }
         for (int d = 0; d < 3; ++d) { a.lo[d] = fmin(a.lo[d], p[d]); a.hi[d] = fmax(a.hi[d], p[d]); }
         a.smin = fmin(a.smin, sg); a.smax = fmax(a.smax, sg);
@@ -152,7 +156,8 @@ __global__ __launch_bounds__(TPB) void k_bounds_partial(BoundsArgs A, BAcc *part
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-__global__ __launch_bounds__(TPB) void k_bounds_final(const BAcc *part, int np, Bounds *res) {
+__global__ __launch_bounds__(TPB) void k_bounds_final(const BAcc *part, int np, int check_fp, double fp_ref,
+                                                      Bounds *res) {
     __shared__ BAcc sh[TPB];
     BAcc a;
     bacc_init(a);
@@ -170,8 +175,11 @@ __global__ __launch_bounds__(TPB) void k_bounds_final(const BAcc *part, int np, 
             b.sum_a[d] = sh[0].sa[d]; b.sum_xa[d] = sh[0].sxa[d];
         }
         b.sig_min = sh[0].smin; b.sig_max = sh[0].smax;
+        b.fp = sh[0].fp;
         b.nonfinite = sh[0].nf; b.outside = sh[0].out;
-        b.pad[0] = b.pad[1] = 0;
+        // the two-stage sum is deterministic: equal inputs give a bitwise equal fingerprint
+        b.stale = (check_fp && !(sh[0].fp == fp_ref)) ? 1 : 0;
+        b.overfull = 0;
         *res = b;
     }
 }
@@ -193,7 +201,9 @@ void compute_bounds(Ctx &c, int64_t n, const float *x, const float *y, const flo
     c.bres.ensure(sizeof(Bounds));
     k_bounds_partial<<<nb, TPB, 0, c.stream>>>(A, c.bpart.as<BAcc>());
     VFMM_LAUNCH_CHECK();
-    k_bounds_final<<<1, TPB, 0, c.stream>>>(c.bpart.as<BAcc>(), nb, c.bres.as<Bounds>());
+    // an evaluation checks its positions and cores against those of the build
+    k_bounds_final<<<1, TPB, 0, c.stream>>>(c.bpart.as<BAcc>(), nb, with_alpha ? 1 : 0, c.build_fp,
+                                            c.bres.as<Bounds>());
     VFMM_LAUNCH_CHECK();
 }
 
@@ -474,11 +484,15 @@ void partition_sources(Ctx &c, int64_t n_src) {
 __device__ inline int octant_at(uint64_t key, int lchild, int KL) { return (int)((key >> (3 * (KL - lchild))) & 7); }
 
 __global__ __launch_bounds__(TPB) void k_count_children(int c0, int c1, int lvl, int ncrit, int KL, const int *start,
-                                                        const int *count, const uint64_t *keys, int *nchild) {
+                                                        const int *count, const uint64_t *keys, int *nchild,
+                                                        Bounds *res) {
     const int cell = c0 + blockIdx.x * TPB + threadIdx.x;
     if (cell >= c1) return;
     const int s = start[cell], cnt = count[cell];
     int nc = 0;
+    // keys resolve no finer than level KL: such a leaf keeps all its particles
+    // (coincident or nearly coincident ones), which the near field handles
+    if (cnt > ncrit && lvl >= KL) atomicAdd(&res->overfull, 1);
     if (cnt > ncrit && lvl < KL) {
         // octants are non-decreasing along the range: count distinct values
         int lo = s;
@@ -686,7 +700,7 @@ void build_tree(Ctx &c, int64_t n, const float *x, const float *y, const float *
         int *nch = c.c_tmp.as<int>();
         int *off = nch + nl + 1;
         k_count_children<<<cdiv(nl, TPB), TPB, 0, s>>>(c0, c1, lvl, c.prm.ncrit, KL, c.c_start.as<int>(),
-                                                        c.c_count.as<int>(), keys, nch);
+                                                        c.c_count.as<int>(), keys, nch, c.bres.as<Bounds>());
         VFMM_LAUNCH_CHECK();
         scan_excl_i32(c, nch, off, nl);
         VFMM_HIP(hipMemcpyAsync(&h_tot[0], off + nl - 1, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -737,8 +751,11 @@ void build_tree(Ctx &c, int64_t n, const float *x, const float *y, const float *
     scan_excl_i32(c, flag, pos, nc);
     VFMM_HIP(hipMemcpyAsync(&h_tot[0], pos + nc - 1, sizeof(int), hipMemcpyDeviceToHost, s));
     VFMM_HIP(hipMemcpyAsync(&h_tot[1], flag + nc - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    int h_ovf = 0;
+    VFMM_HIP(hipMemcpyAsync(&h_ovf, &c.bres.as<Bounds>()->overfull, sizeof(int), hipMemcpyDeviceToHost, s));
     VFMM_HIP(hipStreamSynchronize(s));
     c.nleaves = h_tot[0] + h_tot[1];
+    c.overfull_leaves = h_ovf;
     c.leaves.ensure(sizeof(int) * (size_t)c.nleaves);
     k_leaf_compact<<<cdiv(nc, TPB), TPB, 0, s>>>(nc, c.c_nchild.as<int>(), pos, c.leaves.as<int>());
     VFMM_LAUNCH_CHECK();
