@@ -85,3 +85,17 @@ def test_unknown_parameter_is_rejected():
     import paper_1106_5273_amd as vf
     with pytest.raises(TypeError):
         vf.default_params(thetta=0.4)
+
+
+def test_header_documents_readers_as_const_and_depth_policy():
+    """Timings and statistics take a const context; VFMM_EDEPTH is documented
+    as never returned (an overfull leaf at the key depth limit stays a leaf
+    and is counted in the statistics)."""
+    txt = open(HEADER).read()
+    assert re.search(r"vfmm_get_timings\(const vfmm_ctx \*ctx", txt)
+    assert re.search(r"vfmm_get_stats\(const vfmm_ctx \*ctx", txt)
+    assert re.search(r"VFMM_EDEPTH = -3,\s*/\* never returned", txt)
+    assert "overfull_leaves" in txt and "stale" in txt
+    import paper_1106_5273_amd as vf
+    names = [f for f, _ in vf.Stats._fields_]
+    assert names[-2:] == ["stale", "overfull_leaves"]

@@ -76,10 +76,22 @@ def test_fingerprint_detects_other_inputs(c2_case):
     assert wl.checksum_matches(fp, wl.checksum(wl.case_arrays(dict(c2_case))))
 
 
-def test_c3_reference_header():
-    fp, cols, idx, val = _read("bench_c3_256.txt")
+@pytest.mark.slow
+@pytest.mark.parametrize("name,seed", [("bench_c3_256.txt", 3), ("bench_c5_256.txt", 5)])
+def test_256_reference_is_the_spectral_oracle(name, seed):
+    """Every stored row of the 256^3 workloads recomputed with the exact
+    periodic sum (about a minute and 5 GB per workload)."""
+    case = wl.turbulence_case(256, seed=seed)
+    fp, cols, idx, val = _read(name)
     assert cols == ["index", "ux", "uy", "uz", "dax", "day", "daz"]
-    assert len(fp) == 14 and idx.size == 2048 and idx[-1] < 256 ** 3 and np.all(np.isfinite(val))
+    assert wl.checksum_matches(fp, wl.checksum(wl.case_arrays(case)))
+    assert idx.size == 2048 and np.all(np.diff(idx) > 0) and idx[-1] < case["n"]
+    us, Js = oracle.spectral_lattice(case)
+    us = us[idx]
+    alpha = np.stack([case["ax"], case["ay"], case["az"]], 1).astype(np.float64)[idx]
+    das, _ = oracle.stretching(Js[idx], alpha)
+    del Js
+    assert _close(val[:, :3], us) and _close(val[:, 3:], das)
 
 
 def test_c4_reference_is_the_direct_oracle():
@@ -94,12 +106,6 @@ def test_c4_reference_is_the_direct_oracle():
         assert rows.size == 4
         ref = oracle.direct(probs[b], targets=idx[rows] - off[b])
         assert _close(val[rows, :3], ref["u"]) and _close(val[rows, 3:], ref["da_t"])
-
-
-def test_c5_reference_header():
-    fp, cols, idx, val = _read("bench_c5_256.txt")
-    assert cols == ["index", "ux", "uy", "uz", "dax", "day", "daz"]
-    assert len(fp) == 14 and idx.size == 2048 and idx[-1] < 256 ** 3 and np.all(np.isfinite(val))
 
 
 def test_bench_reader_refuses_other_inputs_without_aborting(c2_case):

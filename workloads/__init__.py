@@ -14,6 +14,7 @@ from .gen import (  # noqa: F401
     random_cloud,
     varcore_case,
     corner_lattice,
+    jittered,
     checksum,
     checksum_matches,
     case_arrays,

@@ -171,6 +171,27 @@ def corner_lattice(n, L=TWO_PI):
     return tuple(np.ascontiguousarray(a.ravel(), dtype=np.float32) for a in (X, Y, Z))
 
 
+def jittered(case, frac=0.4, seed=0):
+    """The particles of a lattice case moved off the lattice: each coordinate
+    gets an independent U(-frac h, frac h) displacement (seeded), wrapped into
+    the periodic cube [0, L).  Strengths and cores are unchanged.  A value that
+    rounds up to L in float32 is moved down by one float32 ulp, so every
+    coordinate stays inside the cube."""
+    L = float(case["L"])
+    h = float(case["h"])
+    rng = np.random.default_rng(seed)
+    out = dict(case)
+    for k in ("x", "y", "z"):
+        v = np.mod(np.asarray(case[k], np.float64) + rng.uniform(-frac * h, frac * h, case["n"]), L)
+        f = v.astype(np.float32)
+        f = np.where(f.astype(np.float64) >= L, np.nextafter(f, np.float32(0)), f)
+        out[k] = np.ascontiguousarray(f, dtype=np.float32)
+    out["kind"] = str(case.get("kind", "")) + "_jittered"
+    out.pop("lattice_n", None)
+    out["jitter"] = (frac, seed)
+    return out
+
+
 def checksum(arrays):
     """Fingerprint of the given arrays, to confirm that regenerated inputs are
     the ones stored expected values were computed on: per array, the float64
