@@ -213,6 +213,29 @@ vfmm_status fmm_evaluate(vfmm_ctx *ctx, int64_t n, const float *x, const float *
                          const float *ax, const float *ay, const float *az, const float *sigma,
                          float *ux, float *uy, float *uz, float *dax, float *day, float *daz);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Computes what
+ * fmm_build followed by fmm_evaluate compute on a context with direct = 1 (the
+ * all-pairs near-field sum of Eqs. 1-3, free space, no tree), with the
+ * context's scheme, kahan and precision (float32 or mixed), and the same
+ * results bit for bit; the context's tree and lists are left as they were.
+ * Inputs and outputs as in fmm_evaluate (device float32[n], caller order).
+ * It allocates nothing: its scratch space is one device array of about
+ * 6.7 MB compiled into the library, which every GPU that the library runs on
+ * holds until the process ends, and it is limited to n <= VFMM_STATIC_MAX_N.
+ * Every call on one GPU uses that GPU's one array: calls that overlap on one
+ * GPU (from several contexts, streams or threads) race and give wrong
+ * results; calls in sequence on one stream are safe.  It synchronises the
+ * context stream once (the particles' bounds and cores decide the kernels'
+ * constants).  Errors: VFMM_EINVAL (null pointer, aliasing, n < 0 or
+ * n > VFMM_STATIC_MAX_N, a periodic context, the float64 form, cores below
+ * 1/(2e7) of the extent), VFMM_EDOMAIN (non-finite input, non-positive core,
+ * a position outside a root cube fixed by box_len), VFMM_EHIP. */
+#define VFMM_STATIC_MAX_N 65536
+vfmm_status fmm_direct_static(vfmm_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
+                              const float *ax, const float *ay, const float *az, const float *sigma,
+                              float *ux, float *uy, float *uz, float *dax, float *day, float *daz);
+
 /* Velocity at target points that are not particles (Eq. 1 holds at any point
  * x; e.g. a probe lattice for spectra).  fmm_build_targets builds one tree
  * over the n particles and the m target points (targets carry no strength

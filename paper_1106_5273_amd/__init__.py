@@ -71,6 +71,7 @@ _lib.fmm_build_batched.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_
 _lib.fmm_evaluate_batched.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)] + [_vp] * 13
 _lib.fmm_build_targets.argtypes = [_vp, _i64] + [_vp] * 4 + [_i64] + [_vp] * 3
 _lib.fmm_evaluate_targets.argtypes = [_vp, _i64] + [_vp] * 3 + [_i64] + [_vp] * 9
+_lib.fmm_direct_static.argtypes = [_vp, _i64] + [_vp] * 13
 _lib.vfmm_get_timings.argtypes = [_vp, ctypes.POINTER(Timings)]
 _lib.vfmm_get_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
 _lib.vfmm_copy_lists.argtypes = [_vp] + [_i32p] * 9
@@ -80,13 +81,14 @@ _lib.vfmm_destroy.argtypes = [_vp]
 _lib.vfmm_destroy.restype = None
 for _f in ("vfmm_create", "vfmm_set_params", "fmm_build", "fmm_evaluate", "rk_step", "vfmm_get_timings",
            "vfmm_get_stats", "vfmm_copy_lists", "fmm_build_batched", "fmm_evaluate_batched", "vfmm_autotune",
-           "fmm_build_targets", "fmm_evaluate_targets"):
+           "fmm_build_targets", "fmm_evaluate_targets", "fmm_direct_static"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("vfmm_default_params", "vfmm_create", "vfmm_set_params", "fmm_build", "fmm_evaluate", "rk_step",
             "vfmm_get_timings", "vfmm_get_stats", "vfmm_copy_lists", "vfmm_last_error", "vfmm_destroy",
             "fmm_build_batched", "fmm_evaluate_batched", "vfmm_autotune", "fmm_build_targets",
-            "fmm_evaluate_targets")
+            "fmm_evaluate_targets", "fmm_direct_static")
+STATIC_MAX_N = 65536  # VFMM_STATIC_MAX_N
 
 
 class VfmmError(RuntimeError):
@@ -172,6 +174,19 @@ class Context:
             out = tuple(torch.empty(n, dtype=torch.float32, device=x.device) for _ in range(6))
         args = [_ptr(t) for t in (x, y, z, ax, ay, az, sigma)] + [_ptr(t) for t in out]
         self._raise(_lib.fmm_evaluate(self._h, n, *args))
+        return out
+
+    def direct_static(self, x, y, z, ax, ay, az, sigma, out=None):
+        """fmm_direct_static: the all-pairs evaluation without device allocation
+        in the library (n <= STATIC_MAX_N).  Returns the six outputs."""
+        import torch
+        n = x.numel()
+        for t, nm in ((x, "x"), (y, "y"), (z, "z"), (ax, "ax"), (ay, "ay"), (az, "az"), (sigma, "sigma")):
+            _check_tensor(t, n, nm)
+        if out is None:
+            out = tuple(torch.empty(n, dtype=torch.float32, device=x.device) for _ in range(6))
+        args = [_ptr(t) for t in (x, y, z, ax, ay, az, sigma)] + [_ptr(t) for t in out]
+        self._raise(_lib.fmm_direct_static(self._h, n, *args))
         return out
 
     def build_targets(self, x, y, z, sigma, tx, ty, tz):

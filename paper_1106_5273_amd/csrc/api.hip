@@ -459,6 +459,8 @@ vfmm_status vfmm_create(const vfmm_params *params, void *hip_stream, vfmm_ctx **
         vfmm::set_params(h->c, *params);
         h->c.stream = (hipStream_t)hip_stream;
         VFMM_HIP(hipGetDevice(&h->c.device));
+        // the device address of fmm_direct_static's scratch array on this device
+        vfmm::resolve_static_scratch(h->c.device);
         *out = h;
         return VFMM_OK;
     } catch (const Error &e) {

@@ -123,6 +123,13 @@ struct Ctx {
 };
 
 // tree.hip
+// bytes of the partial-sum buffer of the bounds pass (any n)
+size_t bounds_scratch_bytes();
+// the bounds pass into caller-given buffers: part (bounds_scratch_bytes()) and res;
+// check_fp compares the positions' fingerprint with fp_ref (Bounds::stale)
+void launch_bounds(const Ctx &c, hipStream_t s, int64_t n, const float *x, const float *y, const float *z,
+                   const float *sigma, const float *ax, const float *ay, const float *az, bool with_alpha,
+                   bool check_fp, double fp_ref, void *part, Bounds *res);
 void compute_bounds(Ctx &c, int64_t n, const float *x, const float *y, const float *z, const float *sigma,
                     const float *ax, const float *ay, const float *az, bool with_alpha);
 void build_tree(Ctx &c, int64_t n, const float *x, const float *y, const float *z, const float *sigma);
@@ -148,10 +155,27 @@ void p2p_and_finalize(Ctx &c, float *ux, float *uy, float *uz, float *dax, float
 void direct_all_pairs(Ctx &c, const float *x, const float *y, const float *z, const float *ax,
                       const float *ay, const float *az, const float *sigma, float *ux, float *uy,
                       float *uz, float *dax, float *day, float *daz);
+// Device buffers of the float32 all-pairs evaluation of n particles.
+struct DirectBufs {
+    float4 *rec;     // float4[2n]  (x, y, z, sigma), alpha/(4 pi)
+    int *perm;       // int[n]
+    int4 *blocks;    // int4[ceil(n/64)]
+    int4 *ent;       // int4[ceil(n/64)]
+    float4 *sh;      // float4[ceil(n/64)]
+    float4 *recp;    // float4[3n] (uniform cores) or float4[4n] (per-particle cores)
+    Bounds *bounds;  // bounds of the n particles (already computed)
+};
+// float32 (and mixed) all-pairs near field of n free-space particles into the
+// outputs (caller order); hb: the bounds' host copy (cores, extent).
+void direct_f32(const Ctx &c, hipStream_t s, int64_t n, const Bounds &hb, const DirectBufs &b, const float *x,
+                const float *y, const float *z, const float *ax, const float *ay, const float *az,
+                const float *sigma, float *ux, float *uy, float *uz, float *dax, float *day, float *daz);
 // Scale of the float32 near field: lengths times kappa = log2(e)^(1/2) / (sqrt 2 sigma)
 // turn the Gaussian e^{-rho^2/(2 sigma^2)} into 2^{-rho'^2}; a = (2/sqrt pi) ln(2)^(1/2).
 inline double p2p_kappa(double sigma) { return std::sqrt(1.0 / std::log(2.0)) / (std::sqrt(2.0) * sigma); }
 inline double p2p_cutoff_a() { return 2.0 / std::sqrt(M_PI) * std::sqrt(std::log(2.0)); }
+// direct_static.hip: looks up the scratch array's address on a device (once per device)
+void resolve_static_scratch(int device);
 // lattice_host.cpp
 void lattice_operator_host(int p, int K, std::vector<double> &op);
 

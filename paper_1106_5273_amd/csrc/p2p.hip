@@ -584,33 +584,34 @@ static P2PConst make_const(double sigma, bool var) {
     return k;
 }
 
-// Builds the float32 near-field records from the sorted records (tree: per
-// leaf, offsets from the leaf centre; direct: from one common origin).
-static void p2p_records(Ctx &c, bool tree, const double *origin) {
-    if (c.n == 0) return;
-    const bool var = c.var_sigma;
+// Launches the float32 near-field records from the sorted records rec into
+// recp (tree: one wave per leaf, offsets from the leaf centre; direct: waves of
+// 64 particles, offsets from one common origin).
+static void launch_records(hipStream_t s, bool var, float sigma_uniform, const int *lv, int nl, const int *start,
+                           const int *count, const float4 *geo, int64_t n, const double *origin,
+                           const float4 *rec, float4 *recp) {
     // uniform: kappa of the shared core and ah = kappa^3 alpha/(4 pi); per source: the
     // numerator of kappa_j (the kernel scales each strength by its own kappa_j^3)
-    const double kap = var ? p2p_kappa(1.0) : p2p_kappa(c.sigma_uniform);
+    const double kap = var ? p2p_kappa(1.0) : p2p_kappa(sigma_uniform);
     const double sa = kap * kap * kap;
-    const int rs = var ? 4 : 3;
-    c.recp.ensure(sizeof(float4) * rs * (size_t)c.n);
     const double o0 = origin ? origin[0] : 0.0, o1 = origin ? origin[1] : 0.0, o2 = origin ? origin[2] : 0.0;
-    const int *lv = tree ? c.leaves.as<int>() : nullptr;
-    const int nl = tree ? c.nleaves : 0;
-    const unsigned grid = tree ? cdiv(c.nleaves, 4) : cdiv(cdiv(c.n, 64), 4);
+    const unsigned grid = lv ? cdiv(nl, 4) : cdiv(cdiv(n, 64), 4);
     if (var)
-        k_p2p_records<true><<<grid, 256, 0, c.stream>>>(lv, nl, c.c_start.as<int>(), c.c_count.as<int>(),
-                                                        c.c_geo.as<float4>(), c.n, o0, o1, o2, kap, sa,
-                                                        c.rec.as<float4>(), c.recp.as<float4>());
+        k_p2p_records<true><<<grid, 256, 0, s>>>(lv, nl, start, count, geo, n, o0, o1, o2, kap, sa, rec, recp);
     else
-        k_p2p_records<false><<<grid, 256, 0, c.stream>>>(lv, nl, c.c_start.as<int>(), c.c_count.as<int>(),
-                                                         c.c_geo.as<float4>(), c.n, o0, o1, o2, kap, sa,
-                                                         c.rec.as<float4>(), c.recp.as<float4>());
+        k_p2p_records<false><<<grid, 256, 0, s>>>(lv, nl, start, count, geo, n, o0, o1, o2, kap, sa, rec, recp);
     VFMM_LAUNCH_CHECK();
 }
 
-void p2p_prepare(Ctx &c) { p2p_records(c, true, nullptr); }
+// The float32 near-field records of the tree's leaves.
+static void p2p_records(Ctx &c) {
+    if (c.n == 0) return;
+    c.recp.ensure(sizeof(float4) * (c.var_sigma ? 4 : 3) * (size_t)c.n);
+    launch_records(c.stream, c.var_sigma, c.sigma_uniform, c.leaves.as<int>(), c.nleaves, c.c_start.as<int>(),
+                   c.c_count.as<int>(), c.c_geo.as<float4>(), c.n, nullptr, c.rec.as<float4>(), c.recp.as<float4>());
+}
+
+void p2p_prepare(Ctx &c) { p2p_records(c); }
 
 template <int SCHEME, bool KAHAN>
 static void launch_p2p(const P2PConst &k, const P2PArgs &A, bool var, hipStream_t s) {
@@ -622,14 +623,14 @@ static void launch_p2p(const P2PConst &k, const P2PArgs &A, bool var, hipStream_
     VFMM_LAUNCH_CHECK();
 }
 
-static void dispatch_p2p(Ctx &c, const P2PConst &k, const P2PArgs &A, hipStream_t s) {
-    const bool kah = c.prm.kahan != 0 || c.prm.precision == VFMM_PRECISION_MIXED;
-    if (c.prm.scheme == VFMM_SCHEME_TRANSPOSE) {
-        if (kah) launch_p2p<VFMM_SCHEME_TRANSPOSE, true>(k, A, c.var_sigma, s);
-        else launch_p2p<VFMM_SCHEME_TRANSPOSE, false>(k, A, c.var_sigma, s);
+static void dispatch_p2p(const vfmm_params &prm, bool var, const P2PConst &k, const P2PArgs &A, hipStream_t s) {
+    const bool kah = prm.kahan != 0 || prm.precision == VFMM_PRECISION_MIXED;
+    if (prm.scheme == VFMM_SCHEME_TRANSPOSE) {
+        if (kah) launch_p2p<VFMM_SCHEME_TRANSPOSE, true>(k, A, var, s);
+        else launch_p2p<VFMM_SCHEME_TRANSPOSE, false>(k, A, var, s);
     } else {
-        if (kah) launch_p2p<VFMM_SCHEME_CLASSICAL, true>(k, A, c.var_sigma, s);
-        else launch_p2p<VFMM_SCHEME_CLASSICAL, false>(k, A, c.var_sigma, s);
+        if (kah) launch_p2p<VFMM_SCHEME_CLASSICAL, true>(k, A, var, s);
+        else launch_p2p<VFMM_SCHEME_CLASSICAL, false>(k, A, var, s);
     }
 }
 
@@ -656,7 +657,7 @@ void p2p_near(Ctx &c, hipStream_t s) {
     P2PArgs A = tree_args(c);
     A.near = c.near.as<float>();
     c.record(2 * PH_P2P, s);
-    dispatch_p2p(c, k, A, s);
+    dispatch_p2p(c.prm, c.var_sigma, k, A, s);
     c.record(2 * PH_P2P + 1, s);
 }
 
@@ -721,7 +722,7 @@ void p2p_and_finalize(Ctx &c, float *ux, float *uy, float *uz, float *dax, float
     A.far_da = c.far_da.as<float>();
     A.ux = ux; A.uy = uy; A.uz = uz; A.dax = dax; A.day = day; A.daz = daz;
     c.record(2 * PH_P2P);
-    dispatch_p2p(c, k, A, c.stream);
+    dispatch_p2p(c.prm, c.var_sigma, k, A, c.stream);
     c.record(2 * PH_P2P + 1);
 }
 
@@ -763,6 +764,49 @@ __global__ __launch_bounds__(256) void k_direct_blocks(int64_t n, int nb, int4 *
     }
 }
 
+// The float32 (and mixed) all-pairs evaluation into caller-given buffers; the
+// near-field kernel's interval is timed on ctx's events when tc is given.
+static void direct_f32_impl(const Ctx &c, Ctx *tc, hipStream_t s, int64_t n, const Bounds &hb, const DirectBufs &b,
+                            const float *x, const float *y, const float *z, const float *ax, const float *ay,
+                            const float *az, const float *sigma, float *ux, float *uy, float *uz, float *dax,
+                            float *day, float *daz) {
+    if (n == 0) return;
+    const int nb = (int)cdiv(n, 64);
+    k_direct_setup<<<cdiv(n, 256), 256, 0, s>>>(n, x, y, z, ax, ay, az, sigma, b.rec, b.perm);
+    VFMM_LAUNCH_CHECK();
+    k_direct_blocks<<<cdiv(nb, 256), 256, 0, s>>>(n, nb, b.blocks, b.ent, b.sh);
+    VFMM_LAUNCH_CHECK();
+    // per-source cores when they differ by more than 1e-6 relative (as a build decides)
+    const bool var = hb.sig_max > hb.sig_min * (1.0 + 1e-6);
+    const float sig = (float)hb.sig_max;
+    // one origin for every record: the centre of the bounding box
+    const double org[3] = {0.5 * (hb.lo[0] + hb.hi[0]), 0.5 * (hb.lo[1] + hb.hi[1]), 0.5 * (hb.lo[2] + hb.hi[2])};
+    launch_records(s, var, sig, nullptr, 0, nullptr, nullptr, nullptr, n, org, b.rec, b.recp);
+    const P2PConst k = make_const(sig, var);
+    P2PArgs A{};
+    A.rec = b.recp;
+    A.blocks = b.blocks;
+    A.ent = b.ent;
+    A.sh = b.sh;
+    A.nblocks = nb;
+    A.far_u = nullptr;
+    A.far_da = nullptr;
+    A.n = n;
+    A.perm = b.perm;
+    A.bounds = b.bounds;
+    A.surface = 0;
+    A.ux = ux; A.uy = uy; A.uz = uz; A.dax = dax; A.day = day; A.daz = daz;
+    if (tc) tc->record(2 * PH_P2P, s);
+    dispatch_p2p(c.prm, var, k, A, s);
+    if (tc) tc->record(2 * PH_P2P + 1, s);
+}
+
+void direct_f32(const Ctx &c, hipStream_t s, int64_t n, const Bounds &hb, const DirectBufs &b, const float *x,
+                const float *y, const float *z, const float *ax, const float *ay, const float *az,
+                const float *sigma, float *ux, float *uy, float *uz, float *dax, float *day, float *daz) {
+    direct_f32_impl(c, nullptr, s, n, hb, b, x, y, z, ax, ay, az, sigma, ux, uy, uz, dax, day, daz);
+}
+
 void direct_all_pairs(Ctx &c, const float *x, const float *y, const float *z, const float *ax, const float *ay,
                       const float *az, const float *sigma, float *ux, float *uy, float *uz, float *dax, float *day,
                       float *daz) {
@@ -772,17 +816,15 @@ void direct_all_pairs(Ctx &c, const float *x, const float *y, const float *z, co
     const int nb = (int)cdiv(n, 64);
     c.blocks.ensure(sizeof(int4) * nb);
     c.p2p_ent.ensure(sizeof(int4) * nb);
-    const bool f32 = c.prm.precision != VFMM_PRECISION_FP64;
-    if (f32) c.p2p_sh.ensure(sizeof(float4) * nb);
-    k_direct_setup<<<cdiv(n, 256), 256, 0, c.stream>>>(n, x, y, z, ax, ay, az, sigma, c.rec.as<float4>(),
-                                                        c.perm.as<int>());
-    VFMM_LAUNCH_CHECK();
-    k_direct_blocks<<<cdiv(nb, 256), 256, 0, c.stream>>>(n, nb, c.blocks.as<int4>(), c.p2p_ent.as<int4>(),
-                                                          f32 ? c.p2p_sh.as<float4>() : nullptr);
-    VFMM_LAUNCH_CHECK();
     c.n_blocks = nb;
     c.p2p_pairs = n * n;
     if (c.prm.precision == VFMM_PRECISION_FP64) {
+        k_direct_setup<<<cdiv(n, 256), 256, 0, c.stream>>>(n, x, y, z, ax, ay, az, sigma, c.rec.as<float4>(),
+                                                            c.perm.as<int>());
+        VFMM_LAUNCH_CHECK();
+        k_direct_blocks<<<cdiv(nb, 256), 256, 0, c.stream>>>(n, nb, c.blocks.as<int4>(), c.p2p_ent.as<int4>(),
+                                                              nullptr);
+        VFMM_LAUNCH_CHECK();
         c.rec64.ensure(sizeof(double4) * 2 * n);
         k_direct_setup64<<<cdiv(n, 256), 256, 0, c.stream>>>(n, x, y, z, ax, ay, az, sigma, c.rec64.as<double4>(),
                                                               c.perm.as<int>());
@@ -801,29 +843,11 @@ void direct_all_pairs(Ctx &c, const float *x, const float *y, const float *z, co
         c.record(2 * PH_P2P + 1);
         return;
     }
-    // one origin for every record: the centre of the bounding box
-    const double org[3] = {0.5 * (c.hb.lo[0] + c.hb.hi[0]), 0.5 * (c.hb.lo[1] + c.hb.hi[1]),
-                           0.5 * (c.hb.lo[2] + c.hb.hi[2])};
-    p2p_records(c, false, org);
-    const P2PConst k = make_const(c.sigma_uniform, c.var_sigma);
-    P2PArgs A{};
-    A.rec = c.recp.as<float4>();
-    A.blocks = c.blocks.as<int4>();
-    A.ent = c.p2p_ent.as<int4>();
-    A.sh = c.p2p_sh.as<float4>();
-    A.nblocks = nb;
-    A.far_u = nullptr;
-    A.far_da = nullptr;
-    A.n = n;
-    A.perm = c.perm.as<int>();
-    A.bounds = c.bres.as<Bounds>();
-    A.surface = 0;
-    A.ux = ux; A.uy = uy; A.uz = uz; A.dax = dax; A.day = day; A.daz = daz;
-    c.n_blocks = nb;
-    c.p2p_pairs = n * n;
-    c.record(2 * PH_P2P);
-    dispatch_p2p(c, k, A, c.stream);
-    c.record(2 * PH_P2P + 1);
+    c.p2p_sh.ensure(sizeof(float4) * nb);
+    c.recp.ensure(sizeof(float4) * (c.var_sigma ? 4 : 3) * (size_t)n);
+    DirectBufs b{c.rec.as<float4>(), c.perm.as<int>(), c.blocks.as<int4>(), c.p2p_ent.as<int4>(),
+                 c.p2p_sh.as<float4>(), c.recp.as<float4>(), c.bres.as<Bounds>()};
+    direct_f32_impl(c, &c, c.stream, n, c.hb, b, x, y, z, ax, ay, az, sigma, ux, uy, uz, dax, day, daz);
 }
 
 }  // namespace vfmm

@@ -7,6 +7,8 @@
 namespace vfmm {
 
 static constexpr int TPB = 256;
+// work-groups of the first bounds pass (each reduces a strided share of the particles)
+static constexpr int BOUNDS_MAX_PARTS = 1024;
 
 // ---------------------------------------------------------------------------
 // Exclusive scan of int32 (in-place allowed).  2048 items per block, block
@@ -184,8 +186,11 @@ __global__ __launch_bounds__(TPB) void k_bounds_final(const BAcc *part, int np, 
     }
 }
 
-void compute_bounds(Ctx &c, int64_t n, const float *x, const float *y, const float *z, const float *sigma,
-                    const float *ax, const float *ay, const float *az, bool with_alpha) {
+size_t bounds_scratch_bytes() { return sizeof(BAcc) * BOUNDS_MAX_PARTS; }
+
+void launch_bounds(const Ctx &c, hipStream_t s, int64_t n, const float *x, const float *y, const float *z,
+                   const float *sigma, const float *ax, const float *ay, const float *az, bool with_alpha,
+                   bool check_fp, double fp_ref, void *part, Bounds *res) {
     BoundsArgs A{};
     A.x = x; A.y = y; A.z = z; A.s = sigma; A.ax = ax; A.ay = ay; A.az = az;
     A.n = n;
@@ -196,15 +201,20 @@ void compute_bounds(Ctx &c, int64_t n, const float *x, const float *y, const flo
         A.ref[d] = c.prm.periodic ? c.prm.box_lo[d] + 0.5 * c.prm.box_len : 0.0;
     }
     A.plen = c.prm.box_len;
-    const int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(n, TPB)));
-    c.bpart.ensure(sizeof(BAcc) * nb);
+    const int nb = (int)std::min<int64_t>(BOUNDS_MAX_PARTS, std::max<int64_t>(1, cdiv(n, TPB)));
+    k_bounds_partial<<<nb, TPB, 0, s>>>(A, (BAcc *)part);
+    VFMM_LAUNCH_CHECK();
+    k_bounds_final<<<1, TPB, 0, s>>>((const BAcc *)part, nb, check_fp ? 1 : 0, fp_ref, res);
+    VFMM_LAUNCH_CHECK();
+}
+
+void compute_bounds(Ctx &c, int64_t n, const float *x, const float *y, const float *z, const float *sigma,
+                    const float *ax, const float *ay, const float *az, bool with_alpha) {
+    c.bpart.ensure(bounds_scratch_bytes());
     c.bres.ensure(sizeof(Bounds));
-    k_bounds_partial<<<nb, TPB, 0, c.stream>>>(A, c.bpart.as<BAcc>());
-    VFMM_LAUNCH_CHECK();
     // an evaluation checks its positions and cores against those of the build
-    k_bounds_final<<<1, TPB, 0, c.stream>>>(c.bpart.as<BAcc>(), nb, with_alpha ? 1 : 0, c.build_fp,
-                                            c.bres.as<Bounds>());
-    VFMM_LAUNCH_CHECK();
+    launch_bounds(c, c.stream, n, x, y, z, sigma, ax, ay, az, with_alpha, with_alpha, c.build_fp, c.bpart.ptr,
+                  c.bres.as<Bounds>());
 }
 
 // ---------------------------------------------------------------------------
