@@ -47,11 +47,11 @@ def parse():
                     help="skip the extra timings of the two-stream (overlap = 1) step and of the tuned settings "
                          "(profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "var", "targets"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "var", "targets", "rbf"],
                     help="c2: 128^3 periodic step (default, the headline line); c3: 256^3 float32 vs "
                          "mixed vs float64 forms; c4: 512 batched ring problems vs sequential; c5: 256^3 "
                          "autotuned RK2 step; var: 128^3 free space with per-particle cores vs uniform; targets: "
-                         "128^3 particles and a 128^3 probe lattice")
+                         "128^3 particles and a 128^3 probe lattice; rbf: 128^3 reinitialisation of the strengths")
     ap.add_argument("--microbench", action="store_true",
                     help="only measure VALU FP32 FMA / exp2 / rsq issue rates and exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -420,6 +420,55 @@ def bench_targets(args, vf, wl):
     print(json.dumps(line), flush=True)
 
 
+GAUSS_FLOPS_PER_PAIR = 15  # gfx950 ISA of the Gaussian-sum pair body: 3 SUB + 1 MUL + 5 FMA (x2) + 1 EXP2
+
+
+def bench_rbf(args, vf, wl):
+    """Radial-basis-function reinitialisation of the strengths on the 128^3
+    periodic turbulence-shaped lattice (sigma = 1.5h): the tree built once with
+    core-overlap gap 6, then conjugate gradients to a relative residual of
+    1e-4 from omega = alpha / h^3, each product a Gaussian-sum pass over the
+    near-field lists.  The residual is the solver's own (the parity tests check
+    the true residual with the FP64 periodic operator)."""
+    import numpy as np
+    import torch
+    L = 2 * np.pi
+    case = wl.turbulence_case(args.n, seed=2)
+    t = vf.case_to_device(case)
+    h = case["h"]
+    om = [torch.from_numpy((np.asarray(case[k], np.float64) / h ** 3).astype(np.float32)).cuda()
+          for k in ("ax", "ay", "az")]
+    ctx = vf.Context(p=args.p, theta=args.theta, ncrit=args.ncrit, sigma_gap=6.0, periodic=1, box_len=L,
+                     images=args.images)
+    ctx.build(t[0], t[1], t[2], t[6])
+    g = tuple(torch.empty(case["n"], dtype=torch.float32, device="cuda") for _ in range(3))
+    for _ in range(max(1, args.warmup)):
+        ctx.rbf_reinit(*om, tol=1e-4, maxiter=200, out=g)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos.append(ctx.rbf_reinit(*om, tol=1e-4, maxiter=200, out=g)[1])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    info = infos[-1]
+    mv = float(np.mean([i["matvec_ms"] / max(1, i["matvecs"]) for i in infos]))
+    pairs = info["pairs"]
+    ach = pairs * GAUSS_FLOPS_PER_PAIR / (mv * 1e-3) / 1e12
+    ctx.close()
+    res = {"iterations": list(info["iterations"]), "residual": list(info["residual"]), "gaussian_sums": info["matvecs"],
+           "pairs_per_sum": pairs, "gaussian_sum_kernel_ms": mv, "gaussian_sum_gpair_s": pairs / (mv * 1e-3) / 1e9,
+           "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                        "frac": ach / PEAK_FP32_VALU_TFLOPS, "traffic": None, "kernel": "k_gauss",
+                        "flops_per_pair": GAUSS_FLOPS_PER_PAIR}}
+    line = _line("RBF reinitialisation of %d^3 strengths to 1e-4 residual: time per solve" % args.n,
+                 case["n"] / (ms * 1e-3) / 1e6, "Mparticles/s", ms, args,
+                 "periodic %d^3 turbulence-shaped lattice, sigma=1.5h, Gaussian sums over the near-field lists "
+                 "(p=%d, theta=%g, ncrit=%d, sigma_gap=6), conjugate gradients from zero to 1e-4"
+                 % (args.n, args.p, args.theta, args.ncrit), res)
+    print(json.dumps(line), flush=True)
+
+
 def _time_overlap(ctx1, t, case, args, pairs):
     """Time the same steps with the near field on its own stream beside the far field."""
     import torch
@@ -523,6 +572,8 @@ def main():
         return bench_varcore(args, vf, wl)
     if args.workload == "c3":
         return bench_precision(args, vf, wl)
+    if args.workload == "rbf":
+        return bench_rbf(args, vf, wl)
     L = 2 * np.pi
     case = wl.turbulence_case(args.n, seed=2)
     t = vf.case_to_device(case)

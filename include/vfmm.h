@@ -213,6 +213,59 @@ vfmm_status fmm_evaluate(vfmm_ctx *ctx, int64_t n, const float *x, const float *
                          const float *ax, const float *ay, const float *az, const float *sigma,
                          float *ux, float *uy, float *uz, float *dax, float *day, float *daz);
 
+/* Radial-basis-function reinitialisation of the strengths (Sec. 2.1, last
+ * paragraph; Sec. 2.2; Sec. 3.4).  The vorticity of particles with strengths
+ * gamma_j and cores sigma_j is omega(x) = sum_j gamma_j zeta_j(x - x_j), with
+ * zeta_j(r) = (2 pi sigma_j^2)^{-3/2} exp(-|r|^2 / (2 sigma_j^2)) the Gaussian
+ * whose enclosed mass is the cutoff of Eq. (2).
+ *
+ * Both calls work on the particles (positions and cores) of the last
+ * fmm_build, reusing its tree and near-field lists, as the paper reuses its
+ * tree for particles reinitialised at the same positions; they need a plain
+ * fmm_build (not batched, not with separate targets), the tree path
+ * (direct = 0) and the float32 or mixed form.  The sum runs over the build's
+ * near-field (P2P) lists only: pairs farther apart than sigma_gap * sigma_max
+ * (those the traversal sends to M2L) are dropped, which leaves out the
+ * Gaussian mass beyond that radius, 1 - g(c sigma) = 1.5e-5 at c = 5 and
+ * 7.5e-8 at c = 6 (build with sigma_gap >= 6 for float32-level sums), and
+ * leaf pairs at least 7.2 sigma_max apart are skipped (below e^-26 of the
+ * peak).  Periodic builds sum over the image cells of their lists.  Arrays
+ * are device float32[n] in the caller's order; n must equal the build's. */
+
+/* w_i = sum_j zeta_j(x_i - x_j) gamma_j (each component), the matrix-vector
+ * product of the reinitialisation.  Asynchronous.  Errors: VFMM_ESTATE (no
+ * build, or n differs), VFMM_EINVAL (null pointer, aliasing, a build of the
+ * wrong kind), VFMM_ENOMEM, VFMM_EHIP. */
+vfmm_status fmm_gaussian_sum(vfmm_ctx *ctx, int64_t n, const float *gx, const float *gy, const float *gz,
+                             float *wx, float *wy, float *wz);
+
+typedef struct vfmm_rbf_info {
+    int32_t iterations[3];  /* conjugate-gradient iterations of each component        */
+    int32_t matvecs;        /* Gaussian sums evaluated (the largest of the three)       */
+    double  residual[3];    /* final ||omega - A gamma|| / ||omega|| per component
+                               (the iteration's recursive residual)                   */
+    int64_t pairs;          /* particle pairs one Gaussian sum evaluates               */
+    float   solve_ms;       /* the whole call, HIP events on the context stream        */
+    float   matvec_ms;      /* the Gaussian-sum kernels alone, summed over iterations  */
+} vfmm_rbf_info;
+
+/* Strengths gamma that reproduce the vorticity omega = (wx, wy, wz) at the
+ * particles: sum_j zeta_j(x_i - x_j) gamma_j = omega_i for every i, each
+ * component solved by plain conjugate gradients from gamma = 0 (the matrix is
+ * symmetric positive definite for one shared core), iterating until
+ * ||omega - A gamma|| <= tol ||omega|| (recursive residual) or maxiter
+ * iterations.  The iteration's vectors are float64, the Gaussian sums
+ * float32; the float32 sums limit the reachable residual to about 1e-5
+ * relative.  Synchronises the stream once per iteration.  info (host, may be
+ * null) receives iteration counts, residuals and times.  Errors: as
+ * fmm_gaussian_sum, and VFMM_EINVAL for tol < 0 or maxiter < 0. */
+vfmm_status rbf_reinit(vfmm_ctx *ctx, int64_t n, const float *wx, const float *wy, const float *wz, float *gx,
+                       float *gy, float *gz, double tol, int32_t maxiter, vfmm_rbf_info *info);
+
+/* Duration of the last fmm_gaussian_sum's kernel (ms, HIP events on the
+ * context stream); synchronises the stream.  Errors: VFMM_EINVAL. */
+vfmm_status vfmm_get_gaussian_ms(const vfmm_ctx *ctx, float *ms);
+
 /* For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.  Computes what
  * fmm_build followed by fmm_evaluate compute on a context with direct = 1 (the

@@ -62,16 +62,21 @@ def gaussian_sum(case, gamma, points=None, shifts=None):
     return out
 
 
-def rbf_cg(case, omega, tol=1e-10, maxiter=1000, shifts=None):
+def rbf_cg(case, omega, tol=1e-10, maxiter=1000, shifts=None, matvec=None):
     """Strengths gamma with sum_j zeta(x_i - x_j) gamma_j = omega_i by plain
     conjugate gradients from gamma = 0, for each of the three components on
-    its own, until ||r|| <= tol ||omega|| (r = omega - A gamma) or maxiter
-    iterations.  Returns (gamma (N,3), iterations (3,), relative residual (3,))."""
+    its own, until ||r|| <= tol ||omega|| (r = omega - A gamma, updated
+    recursively) or maxiter iterations.  The product A v is the direct sum
+    (``gaussian_sum``, free space or over ``shifts``) unless ``matvec`` (a
+    function of an (N, 3) array) is given, e.g. ``gaussian_lattice`` for every
+    periodic image of a lattice.  Returns (gamma (N,3), iterations (3,),
+    relative residual (3,))."""
     om = np.asarray(omega, dtype=np.float64).reshape(-1, 3)
     zero = np.zeros_like(om)
 
-    def matvec(v):
-        return gaussian_sum(case, v, shifts=shifts)
+    if matvec is None:
+        def matvec(v):
+            return gaussian_sum(case, v, shifts=shifts)
 
     gamma = zero.copy()
     iters = np.zeros(3, dtype=np.int64)

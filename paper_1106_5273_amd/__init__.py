@@ -46,6 +46,11 @@ class TuneResult(ctypes.Structure):
                 ("tried", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
 
 
+class RbfInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32 * 3), ("matvecs", ctypes.c_int32), ("residual", ctypes.c_double * 3),
+                ("pairs", ctypes.c_int64), ("solve_ms", ctypes.c_float), ("matvec_ms", ctypes.c_float)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("ncells", ctypes.c_int32), ("nleaves", ctypes.c_int32),
                 ("depth", ctypes.c_int32), ("p2p_entries", ctypes.c_int32), ("p2p_pairs", ctypes.c_int64),
@@ -72,6 +77,9 @@ _lib.fmm_evaluate_batched.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes
 _lib.fmm_build_targets.argtypes = [_vp, _i64] + [_vp] * 4 + [_i64] + [_vp] * 3
 _lib.fmm_evaluate_targets.argtypes = [_vp, _i64] + [_vp] * 3 + [_i64] + [_vp] * 9
 _lib.fmm_direct_static.argtypes = [_vp, _i64] + [_vp] * 13
+_lib.fmm_gaussian_sum.argtypes = [_vp, _i64] + [_vp] * 6
+_lib.rbf_reinit.argtypes = [_vp, _i64] + [_vp] * 6 + [ctypes.c_double, ctypes.c_int32, ctypes.POINTER(RbfInfo)]
+_lib.vfmm_get_gaussian_ms.argtypes = [_vp, ctypes.POINTER(ctypes.c_float)]
 _lib.vfmm_get_timings.argtypes = [_vp, ctypes.POINTER(Timings)]
 _lib.vfmm_get_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
 _lib.vfmm_copy_lists.argtypes = [_vp] + [_i32p] * 9
@@ -81,13 +89,14 @@ _lib.vfmm_destroy.argtypes = [_vp]
 _lib.vfmm_destroy.restype = None
 for _f in ("vfmm_create", "vfmm_set_params", "fmm_build", "fmm_evaluate", "rk_step", "vfmm_get_timings",
            "vfmm_get_stats", "vfmm_copy_lists", "fmm_build_batched", "fmm_evaluate_batched", "vfmm_autotune",
-           "fmm_build_targets", "fmm_evaluate_targets", "fmm_direct_static"):
+           "fmm_build_targets", "fmm_evaluate_targets", "fmm_direct_static", "fmm_gaussian_sum", "rbf_reinit",
+           "vfmm_get_gaussian_ms"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("vfmm_default_params", "vfmm_create", "vfmm_set_params", "fmm_build", "fmm_evaluate", "rk_step",
             "vfmm_get_timings", "vfmm_get_stats", "vfmm_copy_lists", "vfmm_last_error", "vfmm_destroy",
             "fmm_build_batched", "fmm_evaluate_batched", "vfmm_autotune", "fmm_build_targets",
-            "fmm_evaluate_targets", "fmm_direct_static")
+            "fmm_evaluate_targets", "fmm_direct_static", "fmm_gaussian_sum", "rbf_reinit", "vfmm_get_gaussian_ms")
 STATIC_MAX_N = 65536  # VFMM_STATIC_MAX_N
 
 
@@ -188,6 +197,38 @@ class Context:
         args = [_ptr(t) for t in (x, y, z, ax, ay, az, sigma)] + [_ptr(t) for t in out]
         self._raise(_lib.fmm_direct_static(self._h, n, *args))
         return out
+
+    def gaussian_sum(self, gx, gy, gz, out=None):
+        """fmm_gaussian_sum on the particles of the last build: returns (wx, wy, wz)."""
+        import torch
+        n = gx.numel()
+        for t, nm in ((gx, "gx"), (gy, "gy"), (gz, "gz")):
+            _check_tensor(t, n, nm)
+        if out is None:
+            out = tuple(torch.empty(n, dtype=torch.float32, device=gx.device) for _ in range(3))
+        self._raise(_lib.fmm_gaussian_sum(self._h, n, _ptr(gx), _ptr(gy), _ptr(gz), *[_ptr(t) for t in out]))
+        return out
+
+    def gaussian_ms(self):
+        ms = ctypes.c_float()
+        self._raise(_lib.vfmm_get_gaussian_ms(self._h, ctypes.byref(ms)))
+        return ms.value
+
+    def rbf_reinit(self, wx, wy, wz, tol=1e-4, maxiter=200, out=None):
+        """rbf_reinit on the particles of the last build: returns ((gx, gy, gz), info dict)."""
+        import torch
+        n = wx.numel()
+        for t, nm in ((wx, "wx"), (wy, "wy"), (wz, "wz")):
+            _check_tensor(t, n, nm)
+        if out is None:
+            out = tuple(torch.empty(n, dtype=torch.float32, device=wx.device) for _ in range(3))
+        info = RbfInfo()
+        self._raise(_lib.rbf_reinit(self._h, n, _ptr(wx), _ptr(wy), _ptr(wz), *[_ptr(t) for t in out],
+                                    float(tol), int(maxiter), ctypes.byref(info)))
+        d = {f: getattr(info, f) for f, _ in RbfInfo._fields_}
+        d["iterations"] = tuple(info.iterations)
+        d["residual"] = tuple(info.residual)
+        return out, d
 
     def build_targets(self, x, y, z, sigma, tx, ty, tz):
         """One tree over the particles and the target points (which carry no strength)."""

@@ -16,7 +16,7 @@ void Ctx::release_all() {
                       &c_tmp, &leaves, &frA, &frB, &tcnt, &m2l_raw, &p2p_raw, &lkey, &lkey2, &lval, &lval2,
                       &m2l_off, &m2l_src, &p2p_off, &p2p_ent, &p2p_sh, &recp, &tgt, &c_nsrc, &part, &blocks, &pairs64, &Mexp, &Lexp, &lat_op, &far_u,
                       &far_da, &near, &dsurf, &rk, &m2l_tgt, &mb_eq, &mb_flag, &mb_pos, &mb_kid, &mb_ukey,
-                      &mb_tab, &mb_bcells, &mb_ent, &mb_groups, &mb_blk, &mb_items, &mb_mr, &mb_partial, &mb_cls, &mb_cellbs, &mb_gcnt, &mb_gid, &mb_goff, &mb_gcur, &pid, &pbox, &poff, &tune_ref, &tune_out, &tune_part};
+                      &mb_tab, &mb_bcells, &mb_ent, &mb_groups, &mb_blk, &mb_items, &mb_mr, &mb_partial, &mb_cls, &mb_cellbs, &mb_gcnt, &mb_gid, &mb_goff, &mb_gcur, &pid, &pbox, &poff, &tune_ref, &tune_out, &tune_part, &rbf};
     for (DevBuf *b : bufs) b->release();
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -30,6 +30,9 @@ void Ctx::release_all() {
         (void)hipStreamDestroy(side);
         side = nullptr;
     }
+    if (rbf_ev_ok)
+        for (auto &e : rbf_ev) (void)hipEventDestroy(e);
+    rbf_ev_ok = false;
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     ev_fork = ev_join = nullptr;
@@ -741,6 +744,67 @@ vfmm_status rk_step(vfmm_ctx *ctx, int64_t n, float dt, float nu, float *x, floa
     } catch (const std::exception &x) {
         const Error e = vfmm::host_error(x);
         c.built = false;
+        return vfmm::fail(&c, e);
+    }
+}
+
+vfmm_status fmm_gaussian_sum(vfmm_ctx *ctx, int64_t n, const float *gx, const float *gy, const float *gz,
+                             float *wx, float *wy, float *wz) {
+    if (!ctx) return VFMM_EINVAL;
+    Ctx &c = ctx->c;
+    try {
+        if (n < 0 || n >= (1LL << 31)) throw Error{VFMM_EINVAL, "n must be in [0, 2^31)"};
+        if (n > 0 && (!gx || !gy || !gz || !wx || !wy || !wz)) throw Error{VFMM_EINVAL, "null pointer"};
+        const float *in[3] = {gx, gy, gz};
+        float *out[3] = {wx, wy, wz};
+        for (int a = 0; a < 3; ++a) {
+            for (const float *p : in)
+                if (overlaps_ab(out[a], n, p, n)) throw Error{VFMM_EINVAL, "an output aliases an input"};
+            for (int b = 0; b < a; ++b)
+                if (overlaps_ab(out[a], n, out[b], n)) throw Error{VFMM_EINVAL, "two outputs alias"};
+        }
+        c.err.clear();
+        vfmm::gaussian_sum_run(c, n, gx, gy, gz, wx, wy, wz);
+        return VFMM_OK;
+    } catch (const Error &e) {
+        return vfmm::fail(&c, e);
+    } catch (const std::exception &x) {
+        return vfmm::fail(&c, vfmm::host_error(x));
+    }
+}
+
+vfmm_status rbf_reinit(vfmm_ctx *ctx, int64_t n, const float *wx, const float *wy, const float *wz, float *gx,
+                       float *gy, float *gz, double tol, int32_t maxiter, vfmm_rbf_info *info) {
+    if (!ctx) return VFMM_EINVAL;
+    Ctx &c = ctx->c;
+    try {
+        if (n < 0 || n >= (1LL << 31)) throw Error{VFMM_EINVAL, "n must be in [0, 2^31)"};
+        if (n > 0 && (!gx || !gy || !gz || !wx || !wy || !wz)) throw Error{VFMM_EINVAL, "null pointer"};
+        const float *in[3] = {wx, wy, wz};
+        float *out[3] = {gx, gy, gz};
+        for (int a = 0; a < 3; ++a) {
+            for (const float *p : in)
+                if (overlaps_ab(out[a], n, p, n)) throw Error{VFMM_EINVAL, "an output aliases an input"};
+            for (int b = 0; b < a; ++b)
+                if (overlaps_ab(out[a], n, out[b], n)) throw Error{VFMM_EINVAL, "two outputs alias"};
+        }
+        c.err.clear();
+        vfmm::rbf_reinit_run(c, n, wx, wy, wz, gx, gy, gz, tol, maxiter, info);
+        return VFMM_OK;
+    } catch (const Error &e) {
+        return vfmm::fail(&c, e);
+    } catch (const std::exception &x) {
+        return vfmm::fail(&c, vfmm::host_error(x));
+    }
+}
+
+vfmm_status vfmm_get_gaussian_ms(const vfmm_ctx *ctx, float *ms) {
+    if (!ctx || !ms) return VFMM_EINVAL;
+    const Ctx &c = ctx->c;
+    try {
+        *ms = vfmm::gaussian_sum_ms(c);
+        return VFMM_OK;
+    } catch (const Error &e) {
         return vfmm::fail(&c, e);
     }
 }

@@ -88,6 +88,12 @@ struct Ctx {
     int64_t n_src_part = -1;             // >= 0: callers' indices below it are sources, the rest targets
     DevBuf c_nsrc;                       // per leaf: sources in front of its targets (partitioned builds)
     DevBuf part;                         // partition scratch
+    // radial-basis-function reinitialisation: Gaussian-sum and conjugate-gradient buffers
+    DevBuf rbf;
+    hipEvent_t rbf_ev[4] = {};           // solve start/end, Gaussian-sum kernel start/end
+    bool rbf_ev_ok = false, gauss_timed = false;
+    int64_t gauss_pairs = 0;             // particle pairs of one Gaussian sum on this tree
+    uint64_t gauss_build_id = ~0ull;     // build the pair count belongs to
     // autotuner scratch
     DevBuf tune_ref, tune_out, tune_part;
 
@@ -176,6 +182,12 @@ inline double p2p_kappa(double sigma) { return std::sqrt(1.0 / std::log(2.0)) / 
 inline double p2p_cutoff_a() { return 2.0 / std::sqrt(M_PI) * std::sqrt(std::log(2.0)); }
 // direct_static.hip: looks up the scratch array's address on a device (once per device)
 void resolve_static_scratch(int device);
+// rbf.hip
+void gaussian_sum_run(Ctx &c, int64_t n, const float *gx, const float *gy, const float *gz, float *wx, float *wy,
+                      float *wz);
+float gaussian_sum_ms(const Ctx &c);
+void rbf_reinit_run(Ctx &c, int64_t n, const float *wx, const float *wy, const float *wz, float *gx, float *gy,
+                    float *gz, double tol, int maxiter, vfmm_rbf_info *info);
 // lattice_host.cpp
 void lattice_operator_host(int p, int K, std::vector<double> &op);
 

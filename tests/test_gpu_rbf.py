@@ -1,0 +1,170 @@
+"""Radial-basis-function reinitialisation (Sec. 2.1, last paragraph; Sec. 2.2;
+Sec. 3.4) through the C ABI against the FP64 oracle.
+
+The Gaussian blob sum (the system's matrix-vector product) is compared
+element by element with the oracle's direct sum (free space) and its DFT route
+over every periodic image (lattice): rel-L2 <= 1e-5, from float32 arithmetic
+(the exp2 argument |r'|^2 <= 37 carries a relative rounding of about 2e-6 into
+the farthest Gaussians) and a truncation below 1e-7 (builds with sigma_gap 6).
+
+The solve is checked by what is unique about it: the vorticity its strengths
+reproduce.  Conjugate gradients stopped at a residual tolerance do not fix
+the strengths in the directions the badly conditioned matrix hardly sees
+(cores of 1.5 lattice spacings), so the strengths themselves are compared
+only where the exact solution is reached (a Taylor-Green field, a single
+eigenvector: gamma = omega / lambda); elsewhere the true residual
+||omega - A gamma|| / ||omega||, computed by the FP64 oracle with the exact
+periodic operator, must meet the tolerance (plus the float32 floor), and the
+iteration counts must be those of the oracle's FP64 conjugate gradients within
+two."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from parity_util import check
+
+pytestmark = pytest.mark.gpu
+
+L2PI = 2.0 * np.pi
+
+
+def _vf():
+    import paper_1106_5273_amd as vf
+    return vf
+
+
+def _alpha(case):
+    return np.stack([case["ax"], case["ay"], case["az"]], 1).astype(np.float64)
+
+
+def _dev(a):
+    import torch
+    return tuple(torch.from_numpy(np.ascontiguousarray(a[:, k], dtype=np.float32)).cuda() for k in range(3))
+
+
+def _host3(t):
+    return np.stack([x.cpu().numpy() for x in t], 1).astype(np.float64)
+
+
+def _ctx(case, **kw):
+    vf = _vf()
+    t = vf.case_to_device(case)
+    ctx = vf.Context(**kw)
+    ctx.build(t[0], t[1], t[2], t[6])
+    return ctx
+
+
+def _varcores(case, seed):
+    c = dict(case)
+    c["sigma"] = (case["sigma"].astype(np.float64) * np.random.default_rng(seed).uniform(0.6, 1.6, case["n"])
+                  ).astype(np.float32)
+    return c
+
+
+@pytest.mark.parametrize("cores", ["uniform", "per_particle"])
+def test_gaussian_sum_free_space_matches_fp64(cores):
+    case = wl.random_cloud(6000, seed=61, L=1.0, core=0.03)
+    if cores == "per_particle":
+        case = _varcores(case, 62)
+    g = np.random.default_rng(63).standard_normal((case["n"], 3))
+    ref = oracle.gaussian_sum(case, g.astype(np.float32).astype(np.float64))
+    with _ctx(case, p=8, sigma_gap=6.0) as ctx:
+        w = _host3(ctx.gaussian_sum(*_dev(g)))
+    check("gaussian sum, cloud 6000, %s cores" % cores, w, ref, 1e-5, 1e-4)
+
+
+@pytest.mark.parametrize("n", [32, 128])
+def test_gaussian_sum_periodic_lattice_matches_dft(n):
+    """The periodic blob sum of the turbulence-shaped strengths (sigma = 1.5h)
+    against the oracle's sum over every image; 128^3 is the bench size."""
+    case = wl.turbulence_case(n, seed=2 if n == 128 else 64)
+    ref = oracle.gaussian_lattice(case, _alpha(case))
+    with _ctx(case, p=10, periodic=1, box_len=L2PI, images=6, sigma_gap=6.0) as ctx:
+        w = _host3(ctx.gaussian_sum(*_dev(_alpha(case))))
+        st = ctx.stats()
+    print("periodic %d^3: %d P2P pairs" % (n, st["p2p_pairs"]))
+    check("gaussian sum, periodic lattice %d^3" % n, w, ref, 1e-5, 1e-4)
+
+
+def test_rbf_reinit_taylor_green_closed_form():
+    """omega = omega_TG on a periodic 32^3 lattice is one eigenvector of the
+    lattice system (three equal-|k| modes), so the exact strengths are
+    omega / lambda; conjugate gradients reach them in one iteration."""
+    n = 32
+    case = wl.taylor_green_case(n, periodic=True)
+    x, y, z, h = wl.lattice_positions(n)
+    om = np.stack([-np.cos(x) * np.sin(y) * np.sin(z), -np.sin(x) * np.cos(y) * np.sin(z),
+                   2.0 * np.sin(x) * np.sin(y) * np.cos(z)], 1)
+    # the oracle's periodic operator maps omega_TG to lambda omega_TG; the exact
+    # strengths are omega_TG / lambda (a division of the DFT by the symbol at
+    # every mode would amplify float64 rounding by the condition number, ~1e14)
+    Aom = oracle.gaussian_lattice(case, om)
+    lam = float(np.sum(om * Aom) / np.sum(om * om))
+    assert np.abs(Aom - lam * om).max() <= 1e-12 * lam
+    exact = om / lam
+    with _ctx(case, p=10, periodic=1, box_len=L2PI, images=6, sigma_gap=6.0) as ctx:
+        g, info = ctx.rbf_reinit(*_dev(om), tol=1e-6, maxiter=50)
+    g = _host3(g)
+    print("Taylor-Green reinit:", info)
+    assert max(info["iterations"]) <= 2
+    check("reinit Taylor-Green 32^3 gamma", g, exact, 1e-5, 1e-4)
+    back = oracle.gaussian_lattice(case, g)
+    check("reinit Taylor-Green 32^3 omega", back, om, 1e-5, 1e-4)
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_rbf_reinit_turbulence_lattice(n):
+    """The turbulence-shaped vorticity omega = alpha / h^3 on the periodic n^3
+    lattice, sigma = 1.5h (128^3: the bench field): the strengths the library
+    finds reproduce omega to the tolerance under the exact periodic operator,
+    in as many iterations as the oracle's float64 conjugate gradients."""
+    case = wl.turbulence_case(n, seed=2)
+    h = case["h"]
+    om32 = (_alpha(case) / h ** 3).astype(np.float32)
+    om = om32.astype(np.float64)
+    tol = 1e-4
+    with _ctx(case, p=10, periodic=1, box_len=L2PI, images=6, sigma_gap=6.0) as ctx:
+        g, info = ctx.rbf_reinit(*_dev(om32), tol=tol, maxiter=200)
+    g = _host3(g)
+    print("turbulence %d^3 reinit:" % n, info)
+    res = np.linalg.norm(oracle.gaussian_lattice(case, g) - om, axis=0) / np.linalg.norm(om, axis=0)
+    print("true residual per component:", res)
+    assert np.all(res <= 1.2 * tol), res
+    assert np.all(np.asarray(info["residual"]) <= tol)
+    _, it, _ = oracle.rbf_cg(case, om, tol=tol, maxiter=200, matvec=lambda v: oracle.gaussian_lattice(case, v))
+    print("oracle iterations", it)
+    assert np.all(np.abs(np.asarray(info["iterations"]) - it) <= 2), (info["iterations"], it)
+
+
+def test_rbf_state_and_errors():
+    import torch
+    vf = _vf()
+    case = wl.random_cloud(500, seed=64, L=1.0, core=0.05)
+    t = vf.case_to_device(case)
+    w = _dev(np.ones((case["n"], 3)))
+    with vf.Context(p=6) as ctx:
+        with pytest.raises(vf.VfmmError, match="ESTATE"):
+            ctx.rbf_reinit(*w)
+        ctx.build(t[0], t[1], t[2], t[6])
+        with pytest.raises(vf.VfmmError, match="ESTATE"):
+            ctx.gaussian_sum(*(x[:100].contiguous() for x in w))
+        with pytest.raises(vf.VfmmError, match="EINVAL"):
+            ctx.rbf_reinit(*w, out=(w[0], t[0], t[1]))
+        with pytest.raises(vf.VfmmError, match="EINVAL"):
+            ctx.rbf_reinit(*w, tol=-1.0)
+        g, info = ctx.rbf_reinit(*w, maxiter=0)
+        assert info["matvecs"] == 0 and bool((g[0] == 0).all())
+        pts = tuple(x[:50].contiguous() for x in t[:3])
+        ctx.build_targets(t[0], t[1], t[2], t[6], *pts)
+        with pytest.raises(vf.VfmmError, match="EINVAL"):
+            ctx.gaussian_sum(*w)
+    with vf.Context(p=6, precision=2) as ctx:
+        ctx.build(t[0], t[1], t[2], t[6])
+        with pytest.raises(vf.VfmmError, match="float32 and mixed"):
+            ctx.gaussian_sum(*w)
+    with vf.Context(direct=1) as ctx:
+        ctx.build(t[0], t[1], t[2], t[6])
+        with pytest.raises(vf.VfmmError, match="direct"):
+            ctx.gaussian_sum(*w)
+    torch.cuda.synchronize()

@@ -111,3 +111,15 @@ def test_lattice_solution_reproduces_the_vorticity_in_real_space(n, seed):
     g = oracle.rbf_lattice(case, om)
     back = oracle.gaussian_sum(case, g, shifts=oracle.image_shifts(2, L))
     assert np.abs(back - om).max() <= 1e-10 * np.abs(om).max()
+
+
+def test_conjugate_gradients_with_the_lattice_product_match_the_lattice_solution():
+    """CG with the DFT product over every periodic image (the route the GPU
+    reinitialisation is checked with at lattice sizes the real-space sum cannot
+    reach) converges to the Fourier-diagonal solution."""
+    n = 10
+    case, om = _smooth_lattice(n, seed=9, kmax=2, sigma_h=1.0)
+    gl = oracle.rbf_lattice(case, om)
+    gc, it, res = oracle.rbf_cg(case, om, tol=1e-13, maxiter=2000, matvec=lambda v: oracle.gaussian_lattice(case, v))
+    assert np.all(res <= 1e-13) and np.all(it >= 2)
+    assert np.linalg.norm(gl - gc) <= 1e-10 * np.linalg.norm(gl)
