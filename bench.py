@@ -316,15 +316,18 @@ def bench_precision(args, vf, wl):
 def bench_varcore(args, vf, wl):
     """Per-particle cores (Eq. 2 with each source's own sigma_j): the 128^3
     turbulence-shaped lattice in free space with sigma_j = 1.5 h U(0.75, 1.25),
-    against the same particles with the uniform core.  Reports both step
-    times and the error of the per-particle run on 1,024 random targets
-    against the float64 direct sum."""
+    against the same particles with the uniform core, and with cores graded
+    across the box (1.5 h (1 + 0.5 sin x)), where each source cell's own
+    largest core sets its core gap.  Reports the step times and the error of
+    the per-particle run on 1,024 random targets against the float64 direct
+    sum."""
     import numpy as np
     import torch
     case = wl.turbulence_case(args.n, seed=2)
     var = wl.varcore_case(args.n)
+    graded = wl.graded_cores(case, 0.5)
     res, outs = {}, {}
-    for name, c in (("uniform", case), ("per_particle", var)):
+    for name, c in (("uniform", case), ("per_particle", var), ("graded", graded)):
         t = vf.case_to_device(c)
         ctx = vf.Context(p=args.p, theta=args.theta, ncrit=args.ncrit, periodic=0, box_len=2 * np.pi)
         out = tuple(torch.empty(c["n"], dtype=torch.float32, device="cuda") for _ in range(6))

@@ -25,6 +25,8 @@ struct TravArgs {
     const float4 *geo;
     const float *rad;
     float theta, gap;  // gap = sigma_gap * sigma_max
+    const float4 *hi;  // per-source cores: cell boxes whose .w is the cell's largest core (else null)
+    float sgap;        // sigma_gap (with hi)
     float len;         // periodic cube side (0 in free space)
     int B;             // image range |n|_inf <= B
 };
@@ -53,8 +55,10 @@ __device__ inline int interact(const TravArgs &A, int a, int b, int img) {
     const float dx = ga.x - gb.x - sx, dy = ga.y - gb.y - sy, dz = ga.z - gb.z - sz;
     const float D = sqrtf(dx * dx + dy * dy + dz * dz);
     const float ra = A.rad[a], rb = A.rad[b];
-    // the MAC and the core gap, both failing on (near-)ties
-    if (ra + rb < A.theta * D * (1.0f - TIE_TOL) && D - ra - rb >= A.gap + TIE_TOL * D) return 0;
+    // the MAC and the core gap, both failing on (near-)ties; with per-source
+    // cores the gap is measured in the largest core of the source cell b
+    const float gap = A.hi ? A.sgap * A.hi[b].w : A.gap;
+    if (ra + rb < A.theta * D * (1.0f - TIE_TOL) && D - ra - rb >= gap + TIE_TOL * D) return 0;
     if (A.nchild[a] == 0 && A.nchild[b] == 0) return 1;
     return 2;
 }
@@ -162,6 +166,7 @@ struct P2PEntryArgs {
     float len;
     int B;
     float r2_small, r2_sing;  // thresholds on squared distance for the cutoff branches
+    int per_cell;             // per-source cores: thresholds from the source leaf's largest core (hi.w)
     double kappa;             // length scale of the float32 near field
     double len64;             // period (0: free space)
     const int *nsrc;          // partitioned builds: sources in front of each leaf's targets (else null)
@@ -189,7 +194,13 @@ __global__ __launch_bounds__(TPB) void k_p2p_gather(P2PEntryArgs A, const int4 *
         const float gy = fmaxf(0.f, fmaxf(sl.y + sy - th.y, tl.y - sh.y - sy));
         const float gz = fmaxf(0.f, fmaxf(sl.z + sz - th.z, tl.z - sh.z - sz));
         const float d2 = gx * gx + gy * gy + gz * gz;
-        const int variant = d2 >= A.r2_sing ? 2 : (d2 >= A.r2_small ? 1 : 0);
+        float r2s = A.r2_small, r2g = A.r2_sing;
+        if (A.per_cell) {  // every pair's source core is at most the source leaf's largest
+            const float s2 = 2.0f * sh.w * sh.w;
+            r2s = s2 * VFMM_CUTOFF_XSPLIT * 1.0001f;
+            r2g = s2 * 26.0f;
+        }
+        const int variant = d2 >= r2g ? 2 : (d2 >= r2s ? 1 : 0);
         const int sc = A.nsrc ? A.nsrc[s] : A.count[s];  // only sources enter the near field
         out[i] = make_int4(A.start[s], sc, e.z, variant);
         if (A.sh) {
@@ -289,6 +300,10 @@ void traverse_and_lists(Ctx &c) {
     A.rad = c.c_rad.as<float>();
     A.theta = c.prm.theta;
     A.gap = (float)(c.prm.sigma_gap * c.hb.sig_max);
+    if (c.var_sigma) {  // the core gap of each source cell's own largest core
+        A.hi = c.c_hi.as<float4>();
+        A.sgap = c.prm.sigma_gap;
+    }
     A.len = c.prm.periodic ? (float)c.prm.box_len : 0.f;
     A.B = c.img_B;
     const int ncode = c.img_codes;
@@ -358,6 +373,7 @@ void traverse_and_lists(Ctx &c) {
         const float s2 = 2.0f * (float)(c.hb.sig_max * c.hb.sig_max);
         E.r2_small = s2 * VFMM_CUTOFF_XSPLIT * 1.0001f;
         E.r2_sing = s2 * 26.0f;
+        E.per_cell = c.var_sigma ? 1 : 0;
         E.geo = c.c_geo.as<float4>();
         E.kappa = c.var_sigma ? 1.0 : p2p_kappa(c.sigma_uniform);  // per-source cores: unscaled offsets
         E.len64 = c.prm.periodic ? c.prm.box_len : 0.0;

@@ -590,6 +590,7 @@ __global__ __launch_bounds__(TPB) void k_leaf_geometry(int ncell, const RootBox 
             r2 = fmaxf(r2, dx * dx + dy * dy + dz * dz);
             lo.x = fminf(lo.x, p.x); lo.y = fminf(lo.y, p.y); lo.z = fminf(lo.z, p.z);
             hi.x = fmaxf(hi.x, p.x); hi.y = fmaxf(hi.y, p.y); hi.z = fmaxf(hi.z, p.z);
+            hi.w = fmaxf(hi.w, p.w);  // the cell's largest core
         }
         // round the radius up by a few ulps so float rounding never makes it short
         rad[cell] = sqrtf(r2) * (1.0f + 4.0e-7f);
@@ -599,7 +600,8 @@ __global__ __launch_bounds__(TPB) void k_leaf_geometry(int ncell, const RootBox 
 }
 
 // Internal cells, one level at a time bottom-up: radius bounded by the
-// children's spheres, bounding box the union of the children's boxes.
+// children's spheres, bounding box the union of the children's boxes, largest
+// core (the box's fourth component) the largest of the children's.
 __global__ __launch_bounds__(TPB) void k_internal_geometry(int c0, int c1, const int *child, const int *nchild,
                                                            const float4 *geo, float *rad, float4 *blo, float4 *bhi) {
     const int cell = c0 + blockIdx.x * TPB + threadIdx.x;
@@ -617,6 +619,7 @@ __global__ __launch_bounds__(TPB) void k_internal_geometry(int c0, int c1, const
         const float4 cl = blo[f + k], chh = bhi[f + k];
         lo.x = fminf(lo.x, cl.x); lo.y = fminf(lo.y, cl.y); lo.z = fminf(lo.z, cl.z);
         hi.x = fmaxf(hi.x, chh.x); hi.y = fmaxf(hi.y, chh.y); hi.z = fmaxf(hi.z, chh.z);
+        hi.w = fmaxf(hi.w, chh.w);
     }
     rad[cell] = r * (1.0f + 4.0e-7f);
     blo[cell] = lo;

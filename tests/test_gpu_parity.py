@@ -138,6 +138,27 @@ def test_variable_cores_fmm_matches_fp64():
         assert e[0] <= 1e-4 and e[1] <= 1e-4
 
 
+def test_variable_cores_per_cell_gap_graded_cores():
+    """Cores graded across the box (a factor 3 from one side to the other):
+    the core gap and the cutoff forms take each source cell's own largest core,
+    so the near field shrinks where the cores are small, against the float64
+    direct sum with each source's core, p = 10."""
+    case = wl.graded_cores(wl.turbulence_case(32, seed=14), 0.5)
+    ref = oracle.direct(case)
+    u, da, ctx = run(case, ret_ctx=True, p=10, box_len=2 * np.pi)
+    st = ctx.stats()
+    ctx.close()
+    big = dict(case)
+    big["sigma"] = np.full(case["n"], case["sigma"].max(), np.float32)
+    _, _, ctx = run(big, ret_ctx=True, p=10, box_len=2 * np.pi)
+    st_big = ctx.stats()
+    ctx.close()
+    print("graded cores 32^3: P2P pairs %d (all cores at the largest: %d)" % (st["p2p_pairs"], st_big["p2p_pairs"]))
+    assert st["p2p_pairs"] < 0.8 * st_big["p2p_pairs"]
+    check("graded cores 32^3 u", u, ref["u"], 1e-4, WORST)
+    check("graded cores 32^3 dalpha", da, ref["da_t"], 1e-4, WORST)
+
+
 def test_variable_cores_path_agrees_with_uniform_path():
     """Cores that differ by 1e-5 take the per-source path; its result equals
     the uniform-core path's up to that perturbation (periodic 32^3 lattice)."""

@@ -15,6 +15,7 @@ from .gen import (  # noqa: F401
     varcore_case,
     corner_lattice,
     jittered,
+    graded_cores,
     checksum,
     checksum_matches,
     case_arrays,

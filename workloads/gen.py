@@ -163,6 +163,20 @@ def varcore_case(n=128, seed=2, core_seed=7, lo=0.75, hi=1.25):
     return out
 
 
+def graded_cores(case, amp=0.5):
+    """``case`` with cores that vary smoothly across the domain, as after core
+    spreading in a region of strong diffusion: sigma_j = sigma_j (1 + amp
+    sin(2 pi x_j / L)), so the cores in one part of the box are up to (1+amp)
+    /(1-amp) times those in another while neighbouring particles have nearly
+    equal cores."""
+    L = float(case["L"])
+    out = dict(case)
+    f = 1.0 + amp * np.sin(TWO_PI * np.asarray(case["x"], np.float64) / L)
+    out["sigma"] = (np.asarray(case["sigma"], np.float64) * f).astype(np.float32)
+    out["kind"] = str(case.get("kind", "")) + "_graded_cores"
+    return out
+
+
 def corner_lattice(n, L=TWO_PI):
     """Probe points at the cell corners i h, h = L/n (offset h/2 from the
     cell-centred particle lattice), flattened [i, j, k]; float32 (x, y, z)."""
