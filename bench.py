@@ -493,13 +493,15 @@ def _time_overlap(ctx1, t, case, args, pairs):
 
 
 def _time_tuned(vf, wl, t, case, args, params):
-    """The same workload and accuracy check with the fastest measured settings:
-    core-overlap gap 4 (at theta = 0.5 the MAC alone already keeps leaf pairs
-    about 4.6 sigma apart), split-product M2L, near field first."""
+    """The same workload and accuracy check with the settings vfmm_autotune
+    chooses for a 1e-4 bound (p, theta, ncrit, core-overlap gap, precision
+    form, M2L product form, evaluation order), timed like the main line."""
     import numpy as np
     import torch
-    kw = dict(params, sigma_gap=4.0, m2l_form=2, overlap=2)
-    ctx = vf.Context(**kw)
+    ctx = vf.Context(**params)
+    t0 = time.perf_counter()
+    r = ctx.autotune(*t, max_rel_l2=1e-4)
+    tune_s = time.perf_counter() - t0
     out = tuple(torch.empty(case["n"], dtype=torch.float32, device="cuda") for _ in range(6))
     for _ in range(max(1, args.warmup)):
         ctx.build(t[0], t[1], t[2], t[6])
@@ -515,7 +517,11 @@ def _time_tuned(vf, wl, t, case, args, params):
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
     st = ctx.stats()
     ctx.close()
-    res = {"sigma_gap": 4.0, "m2l_form": 2, "overlap": 2, "ms_per_step": ms, "p2p_pairs_per_step": st["p2p_pairs"],
+    res = {"chosen_by": "vfmm_autotune, max_rel_l2 = 1e-4 against its p = 12, theta = 0.35 reference",
+           "p": r["p"], "theta": r["theta"], "ncrit": r["ncrit"], "sigma_gap": r["sigma_gap"],
+           "precision": r["precision"], "m2l_form": r["m2l_form"], "overlap": r["overlap"],
+           "tuner_err_u": r["err_u"], "tuner_err_dalpha": r["err_dalpha"], "configurations_tried": r["tried"],
+           "tuner_seconds": tune_s, "ms_per_step": ms, "p2p_pairs_per_step": st["p2p_pairs"],
            "m2l_translations": st["m2l_entries"],
            "phases_ms": {k: float(np.mean([p[k] for p in ph])) for k in ph[0]}}
     if not args.no_check:

@@ -341,27 +341,36 @@ typedef struct vfmm_tune_result {
     float theta;           /* chosen acceptance parameter                              */
     int32_t ncrit;         /* chosen leaf size                                         */
     float sigma_gap;       /* chosen core-overlap gap of the M2L test                  */
+    int32_t precision;     /* chosen precision form (VFMM_PRECISION_FP32 or _MIXED)     */
+    int32_t m2l_form;      /* chosen batched-M2L products (0 float32, 2 split bf16)     */
+    int32_t overlap;       /* chosen evaluation order (0, 1, 2 as in vfmm_params)       */
     float err_u, err_dalpha; /* rel-L2 of u and dalpha vs the high-accuracy reference  */
     float ms;              /* build + evaluate time of the chosen configuration        */
     int32_t tried;         /* configurations timed                                     */
     int32_t from_cache;    /* 1 when read from cache_path                              */
 } vfmm_tune_result;
 
-/* Choose p in {6,8,10,12}, theta in {0.3,...,0.7}, ncrit in {32,...,512} and
- * sigma_gap in {4,5,6} minimising the time of fmm_build + fmm_evaluate on
- * these particles subject to rel-L2(u) <= max_rel_l2 and rel-L2(dalpha) <=
- * max_rel_l2, where the error is measured against the library's own
- * p = 12, theta = 0.35, sigma_gap = max(sigma_gap, 6) evaluation of the same
- * input.  Search: smallest feasible p for each theta at the context's ncrit
- * and sigma_gap, then ncrit at the best (theta, p) (p + 2 if accuracy drops),
- * then sigma_gap at the best (theta, p, ncrit).  Every candidate is built and
- * evaluated twice on the GPU (the second is timed).  The chosen values are
- * written into the context's parameters (the caller builds again).
- * cache_path (may be NULL) is a text file of previous results keyed by the
- * device architecture, n, periodicity, images, scheme, precision and
- * max_rel_l2; a hit skips the search.  Synchronises.  Inputs are device
- * float32[n] as for fmm_evaluate.  Errors: VFMM_EINVAL (null pointer, n <= 0,
- * max_rel_l2 <= 0, direct context, no feasible configuration) and those of
+/* Choose p in {6,8,10,12}, theta in {0.3,...,0.7}, ncrit in {32,...,512},
+ * sigma_gap in {4,5,6}, the precision form (float32 or mixed), the batched
+ * M2L products (m2l_form 0 or 2) and the evaluation order (overlap 0, 1, 2)
+ * minimising the time of fmm_build + fmm_evaluate on these particles subject
+ * to rel-L2(u) <= max_rel_l2 and rel-L2(dalpha) <= max_rel_l2, where the error
+ * is measured against the library's own p = 12, theta = 0.35,
+ * sigma_gap = max(sigma_gap, 6), mixed-form evaluation of the same input.
+ * Search: smallest feasible p for each theta at the context's ncrit,
+ * sigma_gap and forms, then ncrit at the best (theta, p) (p + 2 if accuracy
+ * drops), then sigma_gap at the best (theta, p, ncrit), then the 12
+ * combinations of the three forms at the best (theta, p, ncrit, gap).  Every
+ * candidate is built and evaluated twice on the GPU (the second is timed).
+ * The chosen values are written into the context's parameters (the caller
+ * builds again).  cache_path (may be NULL) is a text file of previous results
+ * keyed by the device architecture, n, periodicity, images, box, scheme,
+ * kahan, max_rel_l2 and a fingerprint of the inputs (float64 sums of
+ * positions, cores, strengths and x_j x alpha_j, the core range); a hit skips
+ * the search.
+ * Synchronises.  Inputs are device float32[n] as for fmm_evaluate.  Errors:
+ * VFMM_EINVAL (null pointer, n <= 0, max_rel_l2 <= 0, direct context, a
+ * float64-form context, no feasible configuration) and those of
  * build/evaluate; on error the context's parameters are restored. */
 vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, const float *y, const float *z,
                           const float *ax, const float *ay, const float *az, const float *sigma,

@@ -42,7 +42,8 @@ class Timings(ctypes.Structure):
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("theta", ctypes.c_float), ("ncrit", ctypes.c_int32),
-                ("sigma_gap", ctypes.c_float), ("err_u", ctypes.c_float), ("err_dalpha", ctypes.c_float), ("ms", ctypes.c_float),
+                ("sigma_gap", ctypes.c_float), ("precision", ctypes.c_int32), ("m2l_form", ctypes.c_int32),
+                ("overlap", ctypes.c_int32), ("err_u", ctypes.c_float), ("err_dalpha", ctypes.c_float), ("ms", ctypes.c_float),
                 ("tried", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
 
 
@@ -270,6 +271,7 @@ class Context:
                                        float(max_rel_l2), cp, ctypes.byref(r)))
         self.params.p, self.params.theta, self.params.ncrit = r.p, r.theta, r.ncrit
         self.params.sigma_gap = r.sigma_gap
+        self.params.precision, self.params.m2l_form, self.params.overlap = r.precision, r.m2l_form, r.overlap
         return {f: getattr(r, f) for f, _ in TuneResult._fields_}
 
     def timings(self):

@@ -1,11 +1,14 @@
 // Autotuner: chooses the expansion degree p, the acceptance parameter theta,
-// the leaf size ncrit and the core-overlap gap of the M2L test (sigma_gap)
-// that minimise the time of one build + evaluate on the caller's particles
-// while keeping the relative L2 error of u and of dalpha/dt below a bound.
-// The error of each candidate is measured against the library's own
-// high-accuracy configuration (p = 12, theta = 0.35, sigma_gap >= 6) on the
-// same input.  The paper fixes p and does not tune (Sec. 4.2); this is a
-// library feature for choosing the accuracy/time operating point.
+// the leaf size ncrit, the core-overlap gap of the M2L test (sigma_gap), the
+// precision form (float32 or mixed), the product form of the batched M2L
+// (float32 or split bfloat16 products) and the evaluation order (one stream,
+// near field on a second stream, near field first) that minimise the time of
+// one build + evaluate on the caller's particles while keeping the relative
+// L2 error of u and of dalpha/dt below a bound.  The error of each candidate
+// is measured against the library's own high-accuracy configuration (p = 12,
+// theta = 0.35, sigma_gap >= 6, mixed form) on the same input.  The paper
+// fixes p and does not tune (Sec. 4.2); this is a library feature for
+// choosing the accuracy/time operating point.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -61,7 +64,11 @@ static void rel_errors(Ctx &c, int64_t n, const float *a, const float *b, double
     ed = s[3] > 0 ? std::sqrt(s[2] / s[3]) : 0.0;
 }
 
-static std::string cache_key(const Ctx &c, int64_t n, float tol) {
+// Key of a cached result: the device, the fixed parameters, the bound and a
+// fingerprint of the inputs (the bounds pass's float64 sums: positions and
+// cores weighted by index, strengths, x_j x alpha_j, the core range), so that
+// a hit on other particles of the same count is not taken for this input.
+static std::string cache_key(const Ctx &c, int64_t n, float tol, const Bounds &b) {
     std::string arch = "unknown";
     int dev = 0;
     hipDeviceProp_t prop;
@@ -69,14 +76,20 @@ static std::string cache_key(const Ctx &c, int64_t n, float tol) {
     for (char &ch : arch)
         if (ch == ' ' || ch == '|') ch = '_';
     std::ostringstream k;
+    k.precision(17);
     k << "arch=" << arch << " n=" << n << " periodic=" << c.prm.periodic << " images=" << c.prm.images
-      << " scheme=" << c.prm.scheme << " precision=" << c.prm.precision << " tol=" << tol;
+      << " box_len=" << c.prm.box_len << " box_lo=" << c.prm.box_lo[0] << "," << c.prm.box_lo[1] << ","
+      << c.prm.box_lo[2] << " scheme=" << c.prm.scheme << " kahan=" << c.prm.kahan << " tol=" << tol
+      << " fp=" << b.fp << " sum_a=" << b.sum_a[0] << "," << b.sum_a[1] << "," << b.sum_a[2]
+      << " sum_xa=" << b.sum_xa[0] << "," << b.sum_xa[1] << "," << b.sum_xa[2]
+      << " sigma=" << b.sig_min << "," << b.sig_max;
     return k.str();
 }
 
 struct Trial {
     int p, ncrit;
     float theta, gap;
+    int prec, form, overlap;  // precision form, M2L product form, evaluation order
     double eu, ed, ms;
     bool ok;
     int64_t tree[5];  // cells, leaves, M2L entries, P2P entries, P2P pairs of the trial's build
@@ -98,8 +111,15 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
             throw Error{VFMM_EINVAL, "autotune needs n > 0 and every input"};
         if (!(max_rel_l2 > 0.f)) throw Error{VFMM_EINVAL, "max_rel_l2 must be > 0"};
         if (c.prm.direct) throw Error{VFMM_EINVAL, "autotune applies to the tree path (direct = 0)"};
+        if (c.prm.precision == VFMM_PRECISION_FP64)
+            throw Error{VFMM_EINVAL, "autotune chooses between the float32 and mixed forms (precision 0 or 1)"};
         std::memset(out, 0, sizeof(*out));
-        const std::string key = vfmm::cache_key(c, n, max_rel_l2);
+        // fingerprint of the inputs for the cache key
+        vfmm::compute_bounds(c, n, x, y, z, sigma, ax, ay, az, true);
+        vfmm::Bounds fb;
+        VFMM_HIP(hipMemcpyAsync(&fb, c.bres.ptr, sizeof(fb), hipMemcpyDeviceToHost, c.stream));
+        VFMM_HIP(hipStreamSynchronize(c.stream));
+        const std::string key = vfmm::cache_key(c, n, max_rel_l2, fb);
         if (cache_path) {
             std::ifstream in(cache_path);
             std::string line;
@@ -108,7 +128,8 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
                 if (bar == std::string::npos || line.substr(0, bar) != key) continue;
                 std::istringstream v(line.substr(bar + 3));
                 vfmm_tune_result r{};
-                if (v >> r.p >> r.theta >> r.ncrit >> r.sigma_gap >> r.err_u >> r.err_dalpha >> r.ms) {
+                if (v >> r.p >> r.theta >> r.ncrit >> r.sigma_gap >> r.precision >> r.m2l_form >> r.overlap >>
+                    r.err_u >> r.err_dalpha >> r.ms) {
                     r.from_cache = 1;
                     *out = r;
                 }
@@ -119,6 +140,9 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
                 p.theta = out->theta;
                 p.ncrit = out->ncrit;
                 p.sigma_gap = out->sigma_gap;
+                p.precision = out->precision;
+                p.m2l_form = out->m2l_form;
+                p.overlap = out->overlap;
                 vfmm::set_params_public(c, p);
                 return VFMM_OK;
             }
@@ -126,12 +150,15 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
         c.tune_ref.ensure(sizeof(float) * 6 * (size_t)n);
         c.tune_out.ensure(sizeof(float) * 6 * (size_t)n);
         float *R = c.tune_ref.as<float>(), *O = c.tune_out.as<float>();
-        auto run = [&](int p, float theta, int ncrit, float gap, float *dst, double &ms) {
+        auto run = [&](int p, float theta, int ncrit, float gap, int prec, int form, int ov, float *dst, double &ms) {
             vfmm_params q = base;
             q.p = p;
             q.theta = theta;
             q.ncrit = ncrit;
             q.sigma_gap = gap;
+            q.precision = prec;
+            q.m2l_form = form;
+            q.overlap = ov;
             q.use_graph = 0;
             vfmm::set_params_public(c, q);
             // first pass warms the buffers; the second is timed
@@ -147,14 +174,15 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
             ms = (double)b + (double)e;
         };
         double ref_ms = 0;
-        run(12, 0.35f, base.ncrit, std::max(base.sigma_gap, 6.0f), R, ref_ms);
+        run(12, 0.35f, base.ncrit, std::max(base.sigma_gap, 6.0f), VFMM_PRECISION_MIXED, 0, 0, R, ref_ms);
         std::vector<vfmm::Trial> trials;
-        auto trial = [&](int p, float theta, int ncrit, float gap) {
+        auto trial = [&](int p, float theta, int ncrit, float gap, int prec, int form, int ov) {
             for (const auto &t : trials)
-                if (t.p == p && t.ncrit == ncrit && std::fabs(t.theta - theta) < 1e-6f && std::fabs(t.gap - gap) < 1e-6f)
+                if (t.p == p && t.ncrit == ncrit && std::fabs(t.theta - theta) < 1e-6f &&
+                    std::fabs(t.gap - gap) < 1e-6f && t.prec == prec && t.form == form && t.overlap == ov)
                     return t;
-            vfmm::Trial t{p, ncrit, theta, gap, 0, 0, 0, false, {0, 0, 0, 0, 0}};
-            run(p, theta, ncrit, gap, O, t.ms);
+            vfmm::Trial t{p, ncrit, theta, gap, prec, form, ov, 0, 0, 0, false, {0, 0, 0, 0, 0}};
+            run(p, theta, ncrit, gap, prec, form, ov, O, t.ms);
             const int64_t tr[5] = {c.ncells, c.nleaves, c.n_m2l, c.n_p2p, c.p2p_pairs};
             std::copy(tr, tr + 5, t.tree);
             vfmm::rel_errors(c, n, O, R, t.eu, t.ed);
@@ -166,10 +194,11 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
         const float thetas[] = {0.3f, 0.4f, 0.5f, 0.6f, 0.7f};
         const int ncrits[] = {32, 64, 128, 256, 512};
         const float gaps[] = {4.0f, 5.0f, 6.0f};
-        // (theta, p) at the caller's ncrit and sigma_gap: smallest feasible p per theta
+        const int bprec = base.precision, bform = base.m2l_form, bov = base.overlap;
+        // (theta, p) at the caller's ncrit, sigma_gap and forms: smallest feasible p per theta
         for (float th : thetas)
             for (int p : ps)
-                if (trial(p, th, base.ncrit, base.sigma_gap).ok) break;
+                if (trial(p, th, base.ncrit, base.sigma_gap, bprec, bform, bov).ok) break;
         // fastest feasible trial; leaf sizes that build the same tree (a lattice
         // splits into the same cells for every ncrit between two powers of 8)
         // give the same results, and among them the largest is kept: it builds
@@ -182,6 +211,7 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
             if (b)
                 for (const auto &t : trials)
                     if (t.ok && t.p == b->p && t.theta == b->theta && t.gap == b->gap && t.ncrit > b->ncrit &&
+                        t.prec == b->prec && t.form == b->form && t.overlap == b->overlap &&
                         std::equal(t.tree, t.tree + 5, b->tree))
                         b = &t;
             return b;
@@ -193,20 +223,33 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
         // leaf size at the best (theta, p), raising p once if accuracy drops
         for (int nc : ncrits) {
             if (nc == base.ncrit) continue;
-            if (!trial(bp, bth, nc, base.sigma_gap).ok && bp + 2 <= 12) trial(bp + 2, bth, nc, base.sigma_gap);
+            if (!trial(bp, bth, nc, base.sigma_gap, bprec, bform, bov).ok && bp + 2 <= 12)
+                trial(bp + 2, bth, nc, base.sigma_gap, bprec, bform, bov);
         }
         // gap of the M2L core-overlap test at the best (theta, p, ncrit)
         b = best_of();
         {
             const vfmm::Trial bb = *b;
             for (float gp : gaps)
-                if (std::fabs(gp - bb.gap) > 1e-6f) trial(bb.p, bb.theta, bb.ncrit, gp);
+                if (std::fabs(gp - bb.gap) > 1e-6f) trial(bb.p, bb.theta, bb.ncrit, gp, bprec, bform, bov);
+        }
+        // forms at the best (theta, p, ncrit, gap): precision (float32, mixed),
+        // M2L products (float32, split bfloat16), evaluation order (0, 1, 2)
+        b = best_of();
+        {
+            const vfmm::Trial bb = *b;
+            for (int prec : {VFMM_PRECISION_FP32, VFMM_PRECISION_MIXED})
+                for (int form : {0, 2})
+                    for (int ov : {0, 1, 2}) trial(bb.p, bb.theta, bb.ncrit, bb.gap, prec, form, ov);
         }
         b = best_of();
         out->p = b->p;
         out->theta = b->theta;
         out->ncrit = b->ncrit;
         out->sigma_gap = b->gap;
+        out->precision = b->prec;
+        out->m2l_form = b->form;
+        out->overlap = b->overlap;
         out->err_u = (float)b->eu;
         out->err_dalpha = (float)b->ed;
         out->ms = (float)b->ms;
@@ -217,11 +260,15 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
         p.theta = b->theta;
         p.ncrit = b->ncrit;
         p.sigma_gap = b->gap;
+        p.precision = b->prec;
+        p.m2l_form = b->form;
+        p.overlap = b->overlap;
         vfmm::set_params_public(c, p);
         if (cache_path) {
             std::ofstream o(cache_path, std::ios::app);
             o << key << " | " << out->p << " " << out->theta << " " << out->ncrit << " " << out->sigma_gap << " "
-              << out->err_u << " " << out->err_dalpha << " " << out->ms << "\n";
+              << out->precision << " " << out->m2l_form << " " << out->overlap << " " << out->err_u << " "
+              << out->err_dalpha << " " << out->ms << "\n";
         }
         return VFMM_OK;
     } catch (const Error &e) {

@@ -479,7 +479,7 @@ def c2_ref():
     return case, us, das
 
 
-@pytest.mark.parametrize("extra", [{}, dict(sigma_gap=4.0, m2l_form=2, overlap=2)], ids=["bench", "tuned"])
+@pytest.mark.parametrize("extra", [{}, dict(sigma_gap=4.0, m2l_form=2, overlap=2)], ids=["bench", "gap4_split_nearfirst"])
 def test_c2_full_size_matches_spectral_oracle(c2_ref, extra):
     """128^3 periodic turbulence-shaped lattice, p = 10, theta = 0.5: the
     velocity and stretching of every particle against the exact FP64 periodic
@@ -488,6 +488,26 @@ def test_c2_full_size_matches_spectral_oracle(c2_ref, extra):
     u, da = run(case, p=10, periodic=1, box_len=2 * np.pi, images=6, **extra)
     check("C2 128^3 %s u" % extra, u, us, 1e-4, WORST)
     check("C2 128^3 %s dalpha" % extra, da, das, 1e-4, WORST)
+
+
+def test_c2_full_size_autotuned_matches_spectral_oracle(c2_ref):
+    """The settings vfmm_autotune picks at 128^3 for a 1e-4 bound (against its
+    own p = 12 reference) meet the bound against the exact periodic sum at
+    every particle."""
+    import torch
+    vf = _vf()
+    case, us, das = c2_ref
+    t = vf.case_to_device(case)
+    with vf.Context(p=10, periodic=1, box_len=2 * np.pi, images=6) as ctx:
+        r = ctx.autotune(*t, max_rel_l2=1e-4)
+        print("autotune 128^3:", r)
+        ctx.build(t[0], t[1], t[2], t[6])
+        out = ctx.evaluate(*t)
+        torch.cuda.synchronize()
+    u = np.stack([o.cpu().numpy() for o in out[:3]], 1).astype(np.float64)
+    da = np.stack([o.cpu().numpy() for o in out[3:]], 1).astype(np.float64)
+    check("C2 128^3 autotuned u", u, us, 1e-4, WORST)
+    check("C2 128^3 autotuned dalpha", da, das, 1e-4, WORST)
 
 
 def _stored(name, arrays):
@@ -769,9 +789,12 @@ def test_autotune_meets_bound_and_reuses_cache(tmp_path):
     with vf.Context(**kw) as ctx:
         r = ctx.autotune(*t, max_rel_l2=1e-4, cache_path=cache)
         print("autotune 32^3 periodic:", r)
-        assert r["from_cache"] == 0 and r["tried"] >= 5
+        assert r["from_cache"] == 0 and r["tried"] >= 5 + 11
         assert r["err_u"] <= 1e-4 and r["err_dalpha"] <= 1e-4
         assert r["p"] in (4, 6, 8, 10, 12) and r["ncrit"] in (32, 64, 128, 256, 512)
+        assert r["precision"] in (0, 1) and r["m2l_form"] in (0, 2) and r["overlap"] in (0, 1, 2)
+        assert (ctx.params.precision, ctx.params.m2l_form, ctx.params.overlap) == (
+            r["precision"], r["m2l_form"], r["overlap"])
         # on the 32^3 lattice ncrit = 64, 128 and 256 build the same tree (leaves of 64);
         # of such equal trees the tuner keeps the largest leaf size
         assert r["ncrit"] not in (64, 128)
@@ -789,7 +812,15 @@ def test_autotune_meets_bound_and_reuses_cache(tmp_path):
         assert r2["from_cache"] == 1
         assert (r2["p"], r2["ncrit"]) == (r["p"], r["ncrit"]) and abs(r2["theta"] - r["theta"]) < 1e-6
         assert abs(r2["sigma_gap"] - r["sigma_gap"]) < 1e-6 and r["sigma_gap"] in (4.0, 5.0, 6.0)
+        assert (r2["precision"], r2["m2l_form"], r2["overlap"]) == (r["precision"], r["m2l_form"], r["overlap"])
         assert (ctx.params.p, ctx.params.ncrit) == (r["p"], r["ncrit"])
+    # other particles of the same count are not a cache hit
+    moved = dict(case)
+    moved["ax"] = np.roll(case["ax"], 5)
+    tm = vf.case_to_device(moved)
+    with vf.Context(**kw) as ctx:
+        r3 = ctx.autotune(*tm, max_rel_l2=1e-4, cache_path=cache)
+        assert r3["from_cache"] == 0
 
 
 # ----------------------------------------------------------------------------
