@@ -414,11 +414,43 @@ def bench_targets(args, vf, wl):
         tu = np.stack([o.cpu().numpy() for o in outt[6:9]], 1).astype(np.float64)[idx]
         res["rel_l2_u_targets_vs_oracle_%d" % idx.size] = rel_l2(tu, ref)
         res["oracle_reference"] = what
+    # periodic: the same particles and probes in the periodic cube, and the
+    # energy spectrum of the probe velocities
+    # the periodic cube starts a quarter spacing below 0, so that neither the particles ((i + 1/2) h) nor the
+    # probes (i h) sit on an octree face: every leaf then holds both points of each of its lattice cells
+    q = -0.25 * case["h"]
+    ctx = vf.Context(p=args.p, theta=args.theta, ncrit=2 * args.ncrit, periodic=1, box_len=2 * np.pi,
+                     box_lo=(q, q, q), images=args.images)
+    ms_p = timed(step)
+    st = ctx.stats()
+    E = None
+
+    def spectrum():
+        nonlocal E
+        E = ctx.energy_spectrum(args.n, *outt[6:9])
+
+    ms_e = timed(spectrum)
+    per = {"ms_per_step": ms_p, "p2p_pairs": st["p2p_pairs"], "phases_ms": ctx.timings(),
+           "energy_spectrum_ms": ms_e, "energy_spectrum_shells_1_to_12": [float(v) for v in E[1:13]]}
+    ctx.close()
+    if not args.no_check:
+        idx, ref, what = golden("bench_targets_periodic_%d.txt" % args.n, wl.case_arrays(case) + pts)
+        tu = np.stack([o.cpu().numpy() for o in outt[6:9]], 1).astype(np.float64)[idx]
+        per["rel_l2_u_targets_vs_oracle_%d" % idx.size] = rel_l2(tu, ref)
+        per["oracle_reference"] = what
+        ks, Eref, what = golden("bench_spectrum_periodic_%d.txt" % args.n, wl.case_arrays(case) + pts)
+        if Eref.size:
+            Eref = Eref[:, 0]
+            per["energy_spectrum_max_shell_error_vs_oracle"] = float(np.max(np.abs(E - Eref) / (Eref + 1e-30 * Eref.sum())
+                                                                     * (Eref > 1e-8 * Eref.sum())))
+            per["energy_spectrum_total_vs_oracle"] = float(E.sum() / Eref.sum() - 1.0)
+    res["periodic"] = per
     m = pts[0].size
     line = _line("velocity at %d^3 probe points beside %d^3 particles: step time" % (args.n, args.n),
                  m / (ms * 1e-3) / 1e6, "Mtargets/s", ms, args,
                  "free-space %d^3 turbulence-shaped lattice with a %d^3 probe lattice at the cell corners, p=%d, "
-                 "theta=%g, ncrit=%d (particles and probes); one tree over both, against the particles alone"
+                 "theta=%g, ncrit=%d (particles and probes); one tree over both, against the particles alone; "
+                 "the periodic cube with the energy spectrum of the probe velocities beside it"
                  % (args.n, args.n, args.p, args.theta, 2 * args.ncrit), res)
     print(json.dumps(line), flush=True)
 

@@ -266,6 +266,20 @@ vfmm_status rbf_reinit(vfmm_ctx *ctx, int64_t n, const float *wx, const float *w
  * context stream); synchronises the stream.  Errors: VFMM_EINVAL. */
 vfmm_status vfmm_get_gaussian_ms(const vfmm_ctx *ctx, float *ms);
 
+/* Kinetic-energy spectrum of a velocity field sampled on a uniform n^3
+ * lattice (Sec. 4.3, the spectrum of the velocity at a lattice of probe
+ * points, e.g. from fmm_evaluate_targets): with
+ * u_hat(kappa) = n^-3 sum_t u(x_t) exp(-2 pi i kappa.t / n) over the lattice
+ * indices t = (i, j, k) (input index i n^2 + j n + k), E[k] = 1/2 sum of
+ * |u_hat(kappa)|^2 over the integer wavevectors with round(|kappa|) = k, for
+ * k = 0 .. round(sqrt(3) n / 2) (wavenumbers in units of 2 pi / L; the sum
+ * of E is half the mean of |u|^2).  ux, uy, uz: device float32[n^3]; E: HOST
+ * float64[round(sqrt(3) n / 2) + 1].  Float64 FFTs on the GPU; synchronises.
+ * Errors: VFMM_EINVAL (null pointer, n not a power of two in [2, 1024]),
+ * VFMM_ENOMEM, VFMM_EHIP. */
+vfmm_status vfmm_energy_spectrum(vfmm_ctx *ctx, int32_t n, const float *ux, const float *uy, const float *uz,
+                                 double *E);
+
 /* For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.  Computes what
  * fmm_build followed by fmm_evaluate compute on a context with direct = 1 (the

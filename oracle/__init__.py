@@ -349,7 +349,8 @@ def energy_spectrum(u, n, L):
     with u_hat(kappa) = (1/n^3) sum_t u(x_t) exp(-2 pi i kappa.t / n) (the
     Fourier coefficients of the sampled field), E(k) = 1/2 sum of |u_hat|^2
     over the integer wavevectors kappa with round(|kappa|) = k, for
-    k = 0 .. floor(sqrt(3) n / 2).  Wavenumbers are in units of 2 pi / L (L
+    k = 0 .. round(sqrt(3) n / 2) (the lattice corner |kappa| = sqrt(3) n / 2
+    rounds up).  Wavenumbers are in units of 2 pi / L (L
     does not change the values); sum_k E(k) = 1/2 mean |u|^2 (Parseval)."""
     u = np.asarray(u, dtype=np.float64).reshape(n, n, n, 3)
     uh = np.fft.fftn(u, axes=(0, 1, 2)) / float(n ** 3)

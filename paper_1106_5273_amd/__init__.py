@@ -81,6 +81,7 @@ _lib.fmm_direct_static.argtypes = [_vp, _i64] + [_vp] * 13
 _lib.fmm_gaussian_sum.argtypes = [_vp, _i64] + [_vp] * 6
 _lib.rbf_reinit.argtypes = [_vp, _i64] + [_vp] * 6 + [ctypes.c_double, ctypes.c_int32, ctypes.POINTER(RbfInfo)]
 _lib.vfmm_get_gaussian_ms.argtypes = [_vp, ctypes.POINTER(ctypes.c_float)]
+_lib.vfmm_energy_spectrum.argtypes = [_vp, ctypes.c_int32] + [_vp] * 3 + [ctypes.POINTER(ctypes.c_double)]
 _lib.vfmm_get_timings.argtypes = [_vp, ctypes.POINTER(Timings)]
 _lib.vfmm_get_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
 _lib.vfmm_copy_lists.argtypes = [_vp] + [_i32p] * 9
@@ -91,13 +92,14 @@ _lib.vfmm_destroy.restype = None
 for _f in ("vfmm_create", "vfmm_set_params", "fmm_build", "fmm_evaluate", "rk_step", "vfmm_get_timings",
            "vfmm_get_stats", "vfmm_copy_lists", "fmm_build_batched", "fmm_evaluate_batched", "vfmm_autotune",
            "fmm_build_targets", "fmm_evaluate_targets", "fmm_direct_static", "fmm_gaussian_sum", "rbf_reinit",
-           "vfmm_get_gaussian_ms"):
+           "vfmm_get_gaussian_ms", "vfmm_energy_spectrum"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("vfmm_default_params", "vfmm_create", "vfmm_set_params", "fmm_build", "fmm_evaluate", "rk_step",
             "vfmm_get_timings", "vfmm_get_stats", "vfmm_copy_lists", "vfmm_last_error", "vfmm_destroy",
             "fmm_build_batched", "fmm_evaluate_batched", "vfmm_autotune", "fmm_build_targets",
-            "fmm_evaluate_targets", "fmm_direct_static", "fmm_gaussian_sum", "rbf_reinit", "vfmm_get_gaussian_ms")
+            "fmm_evaluate_targets", "fmm_direct_static", "fmm_gaussian_sum", "rbf_reinit", "vfmm_get_gaussian_ms",
+            "vfmm_energy_spectrum")
 STATIC_MAX_N = 65536  # VFMM_STATIC_MAX_N
 
 
@@ -230,6 +232,16 @@ class Context:
         d["iterations"] = tuple(info.iterations)
         d["residual"] = tuple(info.residual)
         return out, d
+
+    def energy_spectrum(self, n, ux, uy, uz):
+        """vfmm_energy_spectrum of a velocity on an n^3 lattice: numpy float64 E[k]."""
+        import numpy as np
+        for t, nm in ((ux, "ux"), (uy, "uy"), (uz, "uz")):
+            _check_tensor(t, n ** 3, nm)
+        E = np.zeros(int(np.rint(np.sqrt(3.0) * n / 2)) + 1, dtype=np.float64)
+        self._raise(_lib.vfmm_energy_spectrum(self._h, int(n), _ptr(ux), _ptr(uy), _ptr(uz),
+                                              E.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return E
 
     def build_targets(self, x, y, z, sigma, tx, ty, tz):
         """One tree over the particles and the target points (which carry no strength)."""

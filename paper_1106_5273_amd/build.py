@@ -15,7 +15,7 @@ OUT = os.path.join(HERE, "libvfmm.so")
 MB_OUT = os.path.join(HERE, "libvfmm_mb.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["api.hip", "tree.hip", "traverse.hip", "far.hip", "m2lb.hip", "p2p.hip", "autotune.hip",
-           "direct_static.hip", "rbf.hip", "lattice_host.cpp"]
+           "direct_static.hip", "rbf.hip", "spectrum.hip", "lattice_host.cpp"]
 ARCH = os.environ.get("VFMM_ARCH", "gfx950")
 
 

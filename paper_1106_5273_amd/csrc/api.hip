@@ -16,7 +16,7 @@ void Ctx::release_all() {
                       &c_tmp, &leaves, &frA, &frB, &tcnt, &m2l_raw, &p2p_raw, &lkey, &lkey2, &lval, &lval2,
                       &m2l_off, &m2l_src, &p2p_off, &p2p_ent, &p2p_sh, &recp, &tgt, &c_nsrc, &part, &blocks, &pairs64, &Mexp, &Lexp, &lat_op, &far_u,
                       &far_da, &near, &dsurf, &rk, &m2l_tgt, &mb_eq, &mb_flag, &mb_pos, &mb_kid, &mb_ukey,
-                      &mb_tab, &mb_bcells, &mb_ent, &mb_groups, &mb_blk, &mb_items, &mb_mr, &mb_partial, &mb_cls, &mb_cellbs, &mb_gcnt, &mb_gid, &mb_goff, &mb_gcur, &pid, &pbox, &poff, &tune_ref, &tune_out, &tune_part, &rbf};
+                      &mb_tab, &mb_bcells, &mb_ent, &mb_groups, &mb_blk, &mb_items, &mb_mr, &mb_partial, &mb_cls, &mb_cellbs, &mb_gcnt, &mb_gid, &mb_goff, &mb_gcur, &pid, &pbox, &poff, &tune_ref, &tune_out, &tune_part, &rbf, &spec};
     for (DevBuf *b : bufs) b->release();
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -790,6 +790,22 @@ vfmm_status rbf_reinit(vfmm_ctx *ctx, int64_t n, const float *wx, const float *w
         }
         c.err.clear();
         vfmm::rbf_reinit_run(c, n, wx, wy, wz, gx, gy, gz, tol, maxiter, info);
+        return VFMM_OK;
+    } catch (const Error &e) {
+        return vfmm::fail(&c, e);
+    } catch (const std::exception &x) {
+        return vfmm::fail(&c, vfmm::host_error(x));
+    }
+}
+
+vfmm_status vfmm_energy_spectrum(vfmm_ctx *ctx, int32_t n, const float *ux, const float *uy, const float *uz,
+                                 double *E) {
+    if (!ctx) return VFMM_EINVAL;
+    Ctx &c = ctx->c;
+    try {
+        if (!ux || !uy || !uz || !E) throw Error{VFMM_EINVAL, "null pointer"};
+        c.err.clear();
+        vfmm::energy_spectrum_run(c, n, ux, uy, uz, E);
         return VFMM_OK;
     } catch (const Error &e) {
         return vfmm::fail(&c, e);

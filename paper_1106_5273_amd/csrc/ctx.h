@@ -94,6 +94,8 @@ struct Ctx {
     bool rbf_ev_ok = false, gauss_timed = false;
     int64_t gauss_pairs = 0;             // particle pairs of one Gaussian sum on this tree
     uint64_t gauss_build_id = ~0ull;     // build the pair count belongs to
+    // energy spectrum: complex float64 [3][n^3] field, partial and final shell sums
+    DevBuf spec;
     // autotuner scratch
     DevBuf tune_ref, tune_out, tune_part;
 
@@ -188,6 +190,9 @@ void gaussian_sum_run(Ctx &c, int64_t n, const float *gx, const float *gy, const
 float gaussian_sum_ms(const Ctx &c);
 void rbf_reinit_run(Ctx &c, int64_t n, const float *wx, const float *wy, const float *wz, float *gx, float *gy,
                     float *gz, double tol, int maxiter, vfmm_rbf_info *info);
+// spectrum.hip
+int spectrum_bins(int n);
+void energy_spectrum_run(Ctx &c, int n, const float *ux, const float *uy, const float *uz, double *E_host);
 // lattice_host.cpp
 void lattice_operator_host(int p, int K, std::vector<double> &op);
 

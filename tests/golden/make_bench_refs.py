@@ -6,7 +6,7 @@ at those targets, with a fingerprint of the inputs the values were computed on.
 Only the oracle computes them; bench.py reads the files and never runs the
 oracle itself.
 
-    python tests/golden/make_bench_refs.py [c2 c3 c4 c5 var targets]
+    python tests/golden/make_bench_refs.py [c2 c3 c4 c5 var targets ptargets]
 """
 import os
 import sys
@@ -76,6 +76,27 @@ def targets_refs(n=128, count=1024, sample_seed=72):
            wl.checksum(wl.case_arrays(case) + list(pts)), idx, ("ux", "uy", "uz"), ref["u"])
 
 
+def periodic_targets_refs(n=128, count=1024, sample_seed=73):
+    """Periodic, probe lattice at the cell corners: the exact zero-mean
+    periodic sum at the lattice shifted by -h/2 (Fourier series) at sampled
+    probes, and the energy spectrum E(k) of that exact field at every probe."""
+    case = wl.turbulence_case(n, seed=2)
+    pts = wl.corner_lattice(n)
+    h = case["h"]
+    us, _ = oracle.spectral_lattice(case, offset=(-0.5 * h, -0.5 * h, -0.5 * h))
+    idx = np.sort(np.random.default_rng(sample_seed).choice(pts[0].size, size=count, replace=False))
+    fp = wl.checksum(wl.case_arrays(case) + list(pts))
+    _write("bench_targets_periodic_%d.txt" % n, "periodic %d^3 turbulence-shaped lattice (seed 2) and the %d^3 probe "
+           "lattice at the cell corners, %d probes drawn with seed %d" % (n, n, count, sample_seed),
+           "exact FP64 zero-mean periodic sum (Fourier series at the lattice shifted by -h/2)",
+           fp, idx, ("ux", "uy", "uz"), us[idx])
+    E = oracle.energy_spectrum(us, n, case["L"])
+    _write("bench_spectrum_periodic_%d.txt" % n, "energy spectrum of the exact velocity at every probe of the "
+           "periodic %d^3 probe lattice (same inputs)" % n,
+           "oracle.energy_spectrum of the exact FP64 zero-mean periodic velocity at the %d^3 probes" % n,
+           fp, np.arange(E.size), ("E",), E[:, None])
+
+
 def rings_refs(nprob=512, seed=4, per=4, sample_seed=74):
     """512 free-space rings: FP64 direct sum of each problem alone at a few
     sampled particles of that problem (indices into the concatenated arrays)."""
@@ -106,7 +127,9 @@ def main(which):
         varcore_refs()
     if "targets" in which:
         targets_refs()
+    if "ptargets" in which:
+        periodic_targets_refs()
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["c2", "c3", "c4", "c5", "var", "targets"])
+    main(sys.argv[1:] or ["c2", "c3", "c4", "c5", "var", "targets", "ptargets"])

@@ -68,6 +68,20 @@ def test_targets_reference_is_the_direct_oracle(c2_case):
     assert _close(val[s], oracle.direct_points(c2_case, P)["u"])
 
 
+def test_periodic_targets_and_spectrum_references_are_the_spectral_oracle(c2_case):
+    pts = wl.corner_lattice(128)
+    fp, cols, idx, val = _read("bench_targets_periodic_128.txt")
+    fp2, cols2, ks, E = _read("bench_spectrum_periodic_128.txt")
+    assert cols == ["index", "ux", "uy", "uz"] and cols2 == ["index", "E"]
+    arrays = wl.case_arrays(c2_case) + list(pts)
+    assert wl.checksum_matches(fp, wl.checksum(arrays)) and wl.checksum_matches(fp2, wl.checksum(arrays))
+    h = c2_case["h"]
+    us, _ = oracle.spectral_lattice(c2_case, offset=(-0.5 * h, -0.5 * h, -0.5 * h))
+    assert _close(val, us[idx])
+    Eref = oracle.energy_spectrum(us, 128, c2_case["L"])
+    assert np.array_equal(ks, np.arange(Eref.size)) and _close(E[:, 0], Eref)
+
+
 def test_fingerprint_detects_other_inputs(c2_case):
     fp = wl.checksum(wl.case_arrays(c2_case))
     moved = dict(c2_case)
