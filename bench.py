@@ -116,10 +116,23 @@ def traffic_from_profile(pairs_per_launch):
     return d.get("hbm_bytes_per_launch")
 
 
+def _omp_threads(k):
+    """Sets the OpenMP thread count of the host process (the oracle's C code is
+    OpenMP) through libgomp; returns False where libgomp cannot be loaded."""
+    import ctypes
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        return False
+    gomp.omp_set_num_threads(int(k))
+    return True
+
+
 def cpu_baseline(case, seconds):
     """FP64 direct oracle on a bounded sample: random targets against all
     sources of the central box, on every host core, in growing chunks until
-    about `seconds` of CPU work have been timed."""
+    about `seconds` of CPU work have been timed; then a smaller sample on one
+    core.  Also the full N^2 time these rates imply at 128^3 and 256^3."""
     import numpy as np
 
     import oracle
@@ -127,20 +140,36 @@ def cpu_baseline(case, seconds):
     n = case["n"]
     order = np.random.default_rng(123).permutation(n)
     oracle.direct(case, targets=order[:4])  # load the library, fault in the inputs
-    done, chunk, dt = 0, 16, 0.0
-    while dt < seconds and done < n:
-        idx = order[done:done + chunk]
-        t0 = time.perf_counter()
-        oracle.direct(case, targets=idx)
-        el = time.perf_counter() - t0
-        dt += el
-        done += len(idx)
-        if el < 0.25 * seconds:
-            chunk *= 2
-    pairs = done * n
-    return {"value": pairs / dt / 1e9, "unit": "Gpair/s", "cores": cores, "kind": "oracle",
-            "sample": "%d random targets x %d sources of the central box (free-space FP64 direct sum), %.1f s"
-                      % (done, n, dt)}
+
+    def timed_sample(start, budget):
+        done, chunk, dt = 0, 16, 0.0
+        while dt < budget and start + done < n:
+            idx = order[start + done:start + done + chunk]
+            t0 = time.perf_counter()
+            oracle.direct(case, targets=idx)
+            el = time.perf_counter() - t0
+            dt += el
+            done += len(idx)
+            if el < 0.25 * budget:
+                chunk *= 2
+        return done, dt
+
+    done, dt = timed_sample(0, seconds)
+    rate = done * n / dt
+    res = {"value": rate / 1e9, "unit": "Gpair/s", "cores": cores, "kind": "oracle",
+           "sample": "%d random targets x %d sources of the central box (free-space FP64 direct sum), %.1f s"
+                     % (done, n, dt),
+           "full_n2_seconds_128cubed": float(128 ** 3) ** 2 / rate,
+           "full_n2_seconds_256cubed": float(256 ** 3) ** 2 / rate}
+    if _omp_threads(1):
+        d1, t1 = timed_sample(done, max(2.0, seconds / 4))
+        _omp_threads(cores)
+        r1 = d1 * n / t1
+        res["single_core"] = {"value": r1 / 1e9, "unit": "Gpair/s", "cores": 1,
+                              "sample": "%d further targets x %d sources, %.1f s" % (d1, n, t1),
+                              "full_n2_seconds_128cubed": float(128 ** 3) ** 2 / r1,
+                              "full_n2_seconds_256cubed": float(256 ** 3) ** 2 / r1}
+    return res
 
 
 def _line(metric, value, unit, ms, args, workload, extra, higher=True):
