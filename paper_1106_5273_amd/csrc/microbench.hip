@@ -2,7 +2,8 @@
 // independent chains of float32 FMA (v_fmac_f32 with vector-register
 // operands only, or with one scalar-register operand; the instruction is
 // written out so that the compiler cannot pick another form), v_exp_f32 and
-// v_rsq_f32, timed with HIP events.  Built into its own small library
+// v_rsq_f32, FMA with a DPP row-broadcast operand and the VOP3 FMA, timed
+// with HIP events.  Built into its own small library
 // (libvfmm_mb.so); not part of the vfmm C ABI.
 #include <hip/hip_runtime.h>
 
@@ -28,6 +29,10 @@ __global__ __launch_bounds__(256) void k_rate(float *out, int iters, float a, fl
                 if (KIND == 1) asm volatile("v_fmac_f32_e32 %0, %1, %2" : "+v"(v[i]) : "s"(sa), "v"(vb));
                 if (KIND == 2) v[i] = __builtin_amdgcn_exp2f(v[i]);
                 if (KIND == 3) v[i] = __builtin_amdgcn_rsqf(v[i]);
+                if (KIND == 4)
+                    asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:5 row_mask:0xf bank_mask:0xf"
+                                 : "+v"(v[i]) : "v"(va), "v"(vb));
+                if (KIND == 5) asm volatile("v_fma_f32 %0, %1, %2, %0" : "+v"(v[i]) : "v"(va), "v"(vb));
             }
         }
     }
@@ -40,7 +45,8 @@ __global__ __launch_bounds__(256) void k_rate(float *out, int iters, float a, fl
 
 extern "C" {
 
-// Runs kind (0: FMA vector operands, 1: FMA scalar operand, 2: exp2, 3: rsq)
+// Runs kind (0: FMA vector operands, 1: FMA scalar operand, 2: exp2, 3: rsq,
+// 4: FMA with a DPP row-broadcast operand, 5: FMA in its three-operand VOP3 form)
 // on `blocks` work-groups of 256 threads for `iters` x 16 x 8 operations per
 // lane.  Returns the device time in milliseconds (< 0 on error).
 float vfmm_mb_rate(int kind, int blocks, int iters) {
@@ -54,6 +60,8 @@ float vfmm_mb_rate(int kind, int blocks, int iters) {
             case 0: k_rate<0><<<blocks, 256>>>(out, iters, 0.999f, 0.9999f); break;
             case 1: k_rate<1><<<blocks, 256>>>(out, iters, 0.999f, 0.9999f); break;
             case 2: k_rate<2><<<blocks, 256>>>(out, iters, 0.999f, 0.9999f); break;
+            case 4: k_rate<4><<<blocks, 256>>>(out, iters, 0.999f, 0.9999f); break;
+            case 5: k_rate<5><<<blocks, 256>>>(out, iters, 0.999f, 0.9999f); break;
             default: k_rate<3><<<blocks, 256>>>(out, iters, 0.999f, 0.9999f); break;
         }
     };
