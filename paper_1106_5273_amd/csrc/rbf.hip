@@ -74,24 +74,37 @@ __device__ __forceinline__ void gauss_block(const GaussArgs &A, int t0, int tc, 
     const int i = t0 + (valid ? tl : 0);
     const float4 pi = A.pos[i];
     float S0 = 0.f, S1 = 0.f, S2 = 0.f;
+    // the next entry's list record and shift are loaded while this one runs
+    int4 en_n = lc > 0 ? A.ent[l0] : make_int4(0, 0, 0, 2);
+    float4 D_n = lc > 0 ? A.sh[l0] : make_float4(0.f, 0.f, 0.f, 0.f);
     for (int e = 0; e < lc; ++e) {
-        const int4 en = A.ent[l0 + e];
+        const int4 en = en_n;
+        const float4 D = D_n;
+        if (e + 1 < lc) {
+            en_n = A.ent[l0 + e + 1];
+            D_n = A.sh[l0 + e + 1];
+        }
         if (__builtin_amdgcn_readfirstlane(en.w) == 2) continue;  // every pair beyond 7.2 sigma_max
         const int s0 = __builtin_amdgcn_readfirstlane(en.x);
         const int sc = __builtin_amdgcn_readfirstlane(en.y);
-        const float4 D = A.sh[l0 + e];
         const float y0 = pi.x + D.x, y1 = pi.y + D.y, y2 = pi.z + D.z;
         const float4 *sp = A.pos + s0;
         const float4 *sg = A.str + s0;
         float w0 = 0.f, w1 = 0.f, w2 = 0.f;
         if (SPLIT == 1) {
+            // eight sources per batch of scalar loads: one load latency per 80 instructions
             int j = 0;
-            for (; j + 2 <= sc; j += 2) {
-                const float4 p0 = sp[j], g0 = sg[j], p1 = sp[j + 1], g1 = sg[j + 1];
-                gpair<VAR, false>(y0, y1, y2, p0, g0, true, w0, w1, w2);
-                gpair<VAR, false>(y0, y1, y2, p1, g1, true, w0, w1, w2);
+            for (; j + 8 <= sc; j += 8) {
+                float4 P[8], G[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    P[q] = sp[j + q];
+                    G[q] = sg[j + q];
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) gpair<VAR, false>(y0, y1, y2, P[q], G[q], true, w0, w1, w2);
             }
-            if (j < sc) gpair<VAR, false>(y0, y1, y2, sp[j], sg[j], true, w0, w1, w2);
+            for (; j < sc; ++j) gpair<VAR, false>(y0, y1, y2, sp[j], sg[j], true, w0, w1, w2);
         } else {
             // lane groups take every SPLIT-th source; a group past the end
             // re-reads the last source with its Gaussian forced to zero
