@@ -41,6 +41,8 @@ def parse():
                          "needed to fill the 64-lane P2P waves (a sweep over 128..1024 measured 384 fastest)")
     ap.add_argument("--images", type=int, default=6)
     ap.add_argument("--kahan", type=int, default=0)
+    ap.add_argument("--m2l-form", type=int, default=None, help="batched-M2L products (library default if not given)")
+    ap.add_argument("--overlap", type=int, default=None, help="evaluation order (library default if not given)")
     ap.add_argument("--no-check", action="store_true", help="skip the accuracy check against stored FP64 oracle values")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-overlap-pass", action="store_true",
@@ -581,7 +583,8 @@ def _time_tuned(vf, wl, t, case, args, params):
     res = {"chosen_by": "vfmm_autotune, max_rel_l2 = 1e-4 against its p = 12, theta = 0.35 reference",
            "p": r["p"], "theta": r["theta"], "ncrit": r["ncrit"], "sigma_gap": r["sigma_gap"],
            "precision": r["precision"], "m2l_form": r["m2l_form"], "overlap": r["overlap"],
-           "tuner_err_u": r["err_u"], "tuner_err_dalpha": r["err_dalpha"], "configurations_tried": r["tried"],
+           "tuner_err_u": r["err_u"], "tuner_err_dalpha": r["err_dalpha"], "tuner_worst_u": r["worst_u"],
+           "tuner_worst_dalpha": r["worst_dalpha"], "configurations_tried": r["tried"],
            "tuner_seconds": tune_s, "ms_per_step": ms, "p2p_pairs_per_step": st["p2p_pairs"],
            "m2l_translations": st["m2l_entries"],
            "phases_ms": {k: float(np.mean([p[k] for p in ph])) for k in ph[0]}}
@@ -650,6 +653,10 @@ def main():
     t = vf.case_to_device(case)
     params = dict(p=args.p, theta=args.theta, ncrit=args.ncrit, sigma_gap=5.0, periodic=1, box_len=L,
                   images=args.images, kahan=args.kahan)
+    if args.m2l_form is not None:
+        params["m2l_form"] = args.m2l_form
+    if args.overlap is not None:
+        params["overlap"] = args.overlap
     ctx = vf.Context(**params)
     out = tuple(torch.empty(case["n"], dtype=torch.float32, device="cuda") for _ in range(6))
 
@@ -686,7 +693,7 @@ def main():
     # the same steps with the near field on a second stream beside the far field
     # (overlap = 1, informational: the P2P kernel then shares the GPU)
     ov = None
-    ctx1 = None if args.no_overlap_pass else vf.Context(overlap=1, **params)
+    ctx1 = None if args.no_overlap_pass else vf.Context(**dict(params, overlap=1))
     if ctx1 is not None:
         ov = _time_overlap(ctx1, t, case, args, pairs)
     tuned = None if args.no_overlap_pass else _time_tuned(vf, wl, t, case, args, params)
@@ -706,7 +713,8 @@ def main():
         "config": {"workload": "periodic 128^3 turbulence-shaped lattice, one velocity+stretching FMM step "
                                "(build+evaluate)" if args.n == 128 else "periodic %d^3 lattice" % args.n,
                    "n": case["n"], "p": args.p, "theta": args.theta, "ncrit": args.ncrit, "sigma_gap": 5.0,
-                   "images": args.images, "kahan": args.kahan, "seed": 2},
+                   "images": args.images, "kahan": args.kahan, "seed": 2,
+                   "m2l_form": ctx.params.m2l_form, "overlap": ctx.params.overlap},
         "p2p_pairs_per_step": pairs,
         "p2p_kernel_ms": p2p_ms,
         "p2p_kernel_gpair_s": pairs / (p2p_ms * 1e-3) / 1e9,
@@ -720,6 +728,11 @@ def main():
                      "frac": achieved / PEAK_FP32_VALU_TFLOPS, "traffic": traffic,
                      "kernel": "k_p2p", "flops_per_pair": FLOPS_PER_PAIR},
         "m2l": {"kernel": "k_m2lb", "translations": st["m2l_entries"], "ms": mean_ph["m2l_ms"],
+                "products": "split bfloat16 (six bf16 products per float32 product)" if st["m2l_split"]
+                else "float32",
+                "issued_bf16_tflops": (6 * st["m2l_entries"] * 6 * (args.p + 1) ** 4 / (mean_ph["m2l_ms"] * 1e-3)
+                                       / 1e12) if st["m2l_split"] else None,
+                "bf16_peak": 2500.0,
                 "flops_per_translation": 6 * (args.p + 1) ** 4,
                 "achieved": st["m2l_entries"] * 6 * (args.p + 1) ** 4 / (mean_ph["m2l_ms"] * 1e-3) / 1e12,
                 "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",

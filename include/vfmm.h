@@ -106,24 +106,21 @@ typedef struct vfmm_params {
                             form), outputs rounded to float32 once; with the same tree and lists
                             as the other forms, its difference from them is their rounding error
                             (Sec. 4.2 normalises the expansions so that float32 stays in range). */
-    int32_t overlap;     /* 0 (default): one stream, the phases run one after the other.  1: the
-                            near field (P2P) runs on a second stream of the library concurrently
-                            with the far field and a final kernel adds them (the small far-field
-                            kernels then fill the GPU beside the P2P: about 2.5% shorter steps at
-                            128^3; the P2P and far-field phase timings overlap).  2: one
-                            stream, the near field first, then P2M ... L2P, and the final
-                            kernel (the P2P kernel then does not follow the matrix-core M2L
-                            directly; with m2l_form = 2 about 2.5% shorter steps at 128^3).
-                            Results are bitwise the same in all three.                           */
-    int32_t m2l_form;    /* products of the operator-batched M2L.  0 (default) or 1: float32
-                            matrix-core products.  2 (p <= 10; p = 12 uses 1): split products:
+    int32_t overlap;     /* 0: one stream, the phases run one after the other (P2P last).  1:
+                            the near field (P2P) runs on a second stream of the library
+                            concurrently with the far field and a final kernel adds them (the
+                            small far-field kernels then fill the GPU beside the P2P; the P2P
+                            and far-field phase timings overlap).  2 (default): one stream, the
+                            near field first, then P2M ... L2P, and the final kernel.  At 128^3,
+                            p = 10 with m2l_form = 2: 27.5 ms (2), 26.8 ms (1) and 28.5 ms (0)
+                            per build + evaluate.  Results are bitwise the same in all three. */
+    int32_t m2l_form;    /* products of the operator-batched M2L.  0 or 1: float32 matrix-core
+                            products.  2 (default; p <= 10, p = 12 uses 1): split products:
                             operator and multipole values are each split into three bfloat16
                             parts (24 significant bits) and the six leading partial products
                             run on the bfloat16 matrix cores with float32 accumulation; the
                             translations agree with form 1 to float32 rounding and the M2L
-                            kernel is about 1.2x faster at 128^3, p = 10 (but the P2P kernel
-                            that follows it then measured slower, leaving the step nearly
-                            unchanged).                                                          */
+                            kernel takes 7.1-7.5 ms instead of 9.0 ms at 128^3, p = 10.        */
 } vfmm_params;
 
 /* Per-phase device times of the last fmm_build / fmm_evaluate, in milliseconds,
@@ -359,6 +356,8 @@ typedef struct vfmm_tune_result {
     int32_t m2l_form;      /* chosen batched-M2L products (0 float32, 2 split bf16)     */
     int32_t overlap;       /* chosen evaluation order (0, 1, 2 as in vfmm_params)       */
     float err_u, err_dalpha; /* rel-L2 of u and dalpha vs the high-accuracy reference  */
+    float worst_u, worst_dalpha; /* largest single-target error over the RMS target
+                                    magnitude, vs the same reference                  */
     float ms;              /* build + evaluate time of the chosen configuration        */
     int32_t tried;         /* configurations timed                                     */
     int32_t from_cache;    /* 1 when read from cache_path                              */
@@ -368,8 +367,9 @@ typedef struct vfmm_tune_result {
  * sigma_gap in {4,5,6}, the precision form (float32 or mixed), the batched
  * M2L products (m2l_form 0 or 2) and the evaluation order (overlap 0, 1, 2)
  * minimising the time of fmm_build + fmm_evaluate on these particles subject
- * to rel-L2(u) <= max_rel_l2 and rel-L2(dalpha) <= max_rel_l2, where the error
- * is measured against the library's own p = 12, theta = 0.35,
+ * to rel-L2(u) <= max_rel_l2 and rel-L2(dalpha) <= max_rel_l2, and no single
+ * target's error above 10 max_rel_l2 of the RMS target magnitude (u and
+ * dalpha), where the errors are measured against the library's own p = 12, theta = 0.35,
  * sigma_gap = max(sigma_gap, 6), mixed-form evaluation of the same input.
  * Search: smallest feasible p for each theta at the context's ncrit,
  * sigma_gap and forms, then ncrit at the best (theta, p) (p + 2 if accuracy

@@ -43,7 +43,8 @@ class Timings(ctypes.Structure):
 class TuneResult(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("theta", ctypes.c_float), ("ncrit", ctypes.c_int32),
                 ("sigma_gap", ctypes.c_float), ("precision", ctypes.c_int32), ("m2l_form", ctypes.c_int32),
-                ("overlap", ctypes.c_int32), ("err_u", ctypes.c_float), ("err_dalpha", ctypes.c_float), ("ms", ctypes.c_float),
+                ("overlap", ctypes.c_int32), ("err_u", ctypes.c_float), ("err_dalpha", ctypes.c_float),
+                ("worst_u", ctypes.c_float), ("worst_dalpha", ctypes.c_float), ("ms", ctypes.c_float),
                 ("tried", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
 
 

@@ -446,8 +446,8 @@ void vfmm_default_params(vfmm_params *p) {
     p->direct = 0;
     p->m2l_mode = 0;
     p->use_graph = 0;
-    p->overlap = 0;
-    p->m2l_form = 0;
+    p->overlap = 2;
+    p->m2l_form = 2;
 }
 
 vfmm_status vfmm_create(const vfmm_params *params, void *hip_stream, vfmm_ctx **out) {

@@ -27,47 +27,61 @@ void do_evaluate_public(Ctx &c, int64_t n, const float *x, const float *y, const
                         float *dax, float *day, float *daz);
 void set_params_public(Ctx &c, const vfmm_params &p);
 
-// sums of (a - b)^2 and b^2 over the u block (3n) and the dalpha block (3n)
-__global__ __launch_bounds__(256) void k_err_partial(int64_t n3, const float *a, const float *b, double *part) {
-    __shared__ double s[4][256];
-    double du = 0, ru = 0, dd = 0, rd = 0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (int64_t)gridDim.x * 256) {
-        const double x = a[i], y = b[i], x2 = a[n3 + i], y2 = b[n3 + i];
-        du += (x - y) * (x - y);
-        ru += y * y;
-        dd += (x2 - y2) * (x2 - y2);
-        rd += y2 * y2;
+// per block: sums of |a_i - b_i|^2 and |b_i|^2 over the targets i, and the
+// largest |a_i - b_i|^2, for the u block and the dalpha block ([3][n] each)
+__global__ __launch_bounds__(256) void k_err_partial(int64_t n, const float *a, const float *b, double *part) {
+    __shared__ double s[6][256];
+    double du = 0, ru = 0, dd = 0, rd = 0, mu = 0, md = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        double eu = 0, qu = 0, ed = 0, qd = 0;
+        for (int c = 0; c < 3; ++c) {
+            const double x = a[c * n + i], y = b[c * n + i];
+            const double x2 = a[(3 + c) * n + i], y2 = b[(3 + c) * n + i];
+            eu += (x - y) * (x - y);
+            qu += y * y;
+            ed += (x2 - y2) * (x2 - y2);
+            qd += y2 * y2;
+        }
+        du += eu; ru += qu; dd += ed; rd += qd;
+        mu = fmax(mu, eu);
+        md = fmax(md, ed);
     }
     s[0][threadIdx.x] = du; s[1][threadIdx.x] = ru; s[2][threadIdx.x] = dd; s[3][threadIdx.x] = rd;
+    s[4][threadIdx.x] = mu; s[5][threadIdx.x] = md;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o)
+        if (threadIdx.x < o) {
             for (int q = 0; q < 4; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + o];
+            for (int q = 4; q < 6; ++q) s[q][threadIdx.x] = fmax(s[q][threadIdx.x], s[q][threadIdx.x + o]);
+        }
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        for (int q = 0; q < 4; ++q) part[4 * blockIdx.x + q] = s[q][0];
+        for (int q = 0; q < 6; ++q) part[6 * blockIdx.x + q] = s[q][0];
 }
 
-static void rel_errors(Ctx &c, int64_t n, const float *a, const float *b, double &eu, double &ed) {
+// relative L2 errors of u and dalpha, and the largest per-target error over the
+// RMS per-target magnitude (wu, wd)
+static void rel_errors(Ctx &c, int64_t n, const float *a, const float *b, double &eu, double &ed, double &wu,
+                       double &wd) {
     const int nb = 512;
-    c.tune_part.ensure(sizeof(double) * 4 * nb);
-    k_err_partial<<<nb, 256, 0, c.stream>>>(3 * n, a, b, c.tune_part.as<double>());
+    c.tune_part.ensure(sizeof(double) * 6 * nb);
+    k_err_partial<<<nb, 256, 0, c.stream>>>(n, a, b, c.tune_part.as<double>());
     VFMM_LAUNCH_CHECK();
-    std::vector<double> h(4 * nb);
-    VFMM_HIP(hipMemcpyAsync(h.data(), c.tune_part.ptr, sizeof(double) * 4 * nb, hipMemcpyDeviceToHost, c.stream));
+    std::vector<double> h(6 * nb);
+    VFMM_HIP(hipMemcpyAsync(h.data(), c.tune_part.ptr, sizeof(double) * 6 * nb, hipMemcpyDeviceToHost, c.stream));
     VFMM_HIP(hipStreamSynchronize(c.stream));
-    double s[4] = {0, 0, 0, 0};
-    for (int i = 0; i < nb; ++i)
-        for (int q = 0; q < 4; ++q) s[q] += h[4 * i + q];
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = 0; i < nb; ++i) {
+        for (int q = 0; q < 4; ++q) s[q] += h[6 * i + q];
+        for (int q = 4; q < 6; ++q) s[q] = std::max(s[q], h[6 * i + q]);
+    }
     eu = s[1] > 0 ? std::sqrt(s[0] / s[1]) : 0.0;
     ed = s[3] > 0 ? std::sqrt(s[2] / s[3]) : 0.0;
+    wu = s[1] > 0 ? std::sqrt(s[4] / (s[1] / (double)n)) : 0.0;
+    wd = s[3] > 0 ? std::sqrt(s[5] / (s[3] / (double)n)) : 0.0;
 }
 
-// Key of a cached result: the device, the fixed parameters, the bound and a
-// fingerprint of the inputs (the bounds pass's float64 sums: positions and
-// cores weighted by index, strengths, x_j x alpha_j, the core range), so that
-// a hit on other particles of the same count is not taken for this input.
 static std::string cache_key(const Ctx &c, int64_t n, float tol, const Bounds &b) {
     std::string arch = "unknown";
     int dev = 0;
@@ -91,6 +105,7 @@ struct Trial {
     float theta, gap;
     int prec, form, overlap;  // precision form, M2L product form, evaluation order
     double eu, ed, ms;
+    double wu, wd;  // worst target over the RMS target magnitude
     bool ok;
     int64_t tree[5];  // cells, leaves, M2L entries, P2P entries, P2P pairs of the trial's build
 };
@@ -129,7 +144,7 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
                 std::istringstream v(line.substr(bar + 3));
                 vfmm_tune_result r{};
                 if (v >> r.p >> r.theta >> r.ncrit >> r.sigma_gap >> r.precision >> r.m2l_form >> r.overlap >>
-                    r.err_u >> r.err_dalpha >> r.ms) {
+                    r.err_u >> r.err_dalpha >> r.worst_u >> r.worst_dalpha >> r.ms) {
                     r.from_cache = 1;
                     *out = r;
                 }
@@ -181,12 +196,13 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
                 if (t.p == p && t.ncrit == ncrit && std::fabs(t.theta - theta) < 1e-6f &&
                     std::fabs(t.gap - gap) < 1e-6f && t.prec == prec && t.form == form && t.overlap == ov)
                     return t;
-            vfmm::Trial t{p, ncrit, theta, gap, prec, form, ov, 0, 0, 0, false, {0, 0, 0, 0, 0}};
+            vfmm::Trial t{p, ncrit, theta, gap, prec, form, ov, 0, 0, 0, 0, 0, false, {0, 0, 0, 0, 0}};
             run(p, theta, ncrit, gap, prec, form, ov, O, t.ms);
             const int64_t tr[5] = {c.ncells, c.nleaves, c.n_m2l, c.n_p2p, c.p2p_pairs};
             std::copy(tr, tr + 5, t.tree);
-            vfmm::rel_errors(c, n, O, R, t.eu, t.ed);
-            t.ok = t.eu <= max_rel_l2 && t.ed <= max_rel_l2;
+            vfmm::rel_errors(c, n, O, R, t.eu, t.ed, t.wu, t.wd);
+            // the L2 bound, and no single target off by more than ten times it
+            t.ok = t.eu <= max_rel_l2 && t.ed <= max_rel_l2 && t.wu <= 10.0 * max_rel_l2 && t.wd <= 10.0 * max_rel_l2;
             trials.push_back(t);
             return t;
         };
@@ -250,6 +266,8 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
         out->precision = b->prec;
         out->m2l_form = b->form;
         out->overlap = b->overlap;
+        out->worst_u = (float)b->wu;
+        out->worst_dalpha = (float)b->wd;
         out->err_u = (float)b->eu;
         out->err_dalpha = (float)b->ed;
         out->ms = (float)b->ms;
@@ -268,7 +286,7 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
             std::ofstream o(cache_path, std::ios::app);
             o << key << " | " << out->p << " " << out->theta << " " << out->ncrit << " " << out->sigma_gap << " "
               << out->precision << " " << out->m2l_form << " " << out->overlap << " " << out->err_u << " "
-              << out->err_dalpha << " " << out->ms << "\n";
+              << out->err_dalpha << " " << out->worst_u << " " << out->worst_dalpha << " " << out->ms << "\n";
         }
         return VFMM_OK;
     } catch (const Error &e) {

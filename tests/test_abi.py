@@ -78,7 +78,7 @@ def test_default_parameters():
     p = vf.default_params()
     assert (p.p, p.ncrit, p.periodic, p.images, p.scheme, p.zero_mean, p.direct) == (10, 64, 0, 3, 0, 1, 0)
     assert abs(p.theta - 0.5) < 1e-7 and abs(p.sigma_gap - 5.0) < 1e-7
-    assert (p.kahan, p.m2l_mode, p.use_graph, p.precision, p.overlap, p.m2l_form) == (0, 0, 0, 0, 0, 0)
+    assert (p.kahan, p.m2l_mode, p.use_graph, p.precision, p.overlap, p.m2l_form) == (0, 0, 0, 0, 2, 2)
 
 
 def test_unknown_parameter_is_rejected():

@@ -791,6 +791,7 @@ def test_autotune_meets_bound_and_reuses_cache(tmp_path):
         print("autotune 32^3 periodic:", r)
         assert r["from_cache"] == 0 and r["tried"] >= 5 + 11
         assert r["err_u"] <= 1e-4 and r["err_dalpha"] <= 1e-4
+        assert r["worst_u"] <= 1e-3 and r["worst_dalpha"] <= 1e-3
         assert r["p"] in (4, 6, 8, 10, 12) and r["ncrit"] in (32, 64, 128, 256, 512)
         assert r["precision"] in (0, 1) and r["m2l_form"] in (0, 2) and r["overlap"] in (0, 1, 2)
         assert (ctx.params.precision, ctx.params.m2l_form, ctx.params.overlap) == (
