@@ -61,10 +61,10 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_hash():
-    """Hash of the sources the P2P kernel is compiled from."""
+def kernel_hash(names=("p2p.hip", "cutoff_fits.h", "common.h")):
+    """Hash of the sources a kernel is compiled from (default: the P2P kernel's)."""
     h = hashlib.sha256()
-    for name in ("p2p.hip", "cutoff_fits.h", "common.h"):
+    for name in names:
         with open(os.path.join(ROOT, "paper_1106_5273_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -522,10 +522,17 @@ def bench_rbf(args, vf, wl):
     pairs = info["pairs"]
     ach = pairs * GAUSS_FLOPS_PER_PAIR / (mv * 1e-3) / 1e12
     ctx.close()
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "gaussian_sum_traffic.json")
+    if os.path.exists(tpath):
+        with open(tpath) as f:
+            tj = json.load(f)
+        if tj.get("source_sha256_16") == kernel_hash(("rbf.hip", "common.h")):
+            traffic = tj.get("hbm_bytes_per_launch")
     res = {"iterations": list(info["iterations"]), "residual": list(info["residual"]), "gaussian_sums": info["matvecs"],
            "pairs_per_sum": pairs, "gaussian_sum_kernel_ms": mv, "gaussian_sum_gpair_s": pairs / (mv * 1e-3) / 1e9,
            "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
-                        "frac": ach / PEAK_FP32_VALU_TFLOPS, "traffic": None, "kernel": "k_gauss",
+                        "frac": ach / PEAK_FP32_VALU_TFLOPS, "traffic": traffic, "kernel": "k_gauss",
                         "flops_per_pair": GAUSS_FLOPS_PER_PAIR}}
     line = _line("RBF reinitialisation of %d^3 strengths to 1e-4 residual: time per solve" % args.n,
                  case["n"] / (ms * 1e-3) / 1e6, "Mparticles/s", ms, args,
