@@ -33,6 +33,9 @@ __global__ __launch_bounds__(256) void k_rate(float *out, int iters, float a, fl
                     asm volatile("v_fmac_f32_dpp %0, %1, %2 row_newbcast:5 row_mask:0xf bank_mask:0xf"
                                  : "+v"(v[i]) : "v"(va), "v"(vb));
                 if (KIND == 5) asm volatile("v_fma_f32 %0, %1, %2, %0" : "+v"(v[i]) : "v"(va), "v"(vb));
+                if (KIND == 6) asm volatile("v_fma_f32 %0, %1, %2, %0" : "+v"(v[i]) : "v"(va), "s"(sa));
+                if (KIND == 7) asm volatile("v_fma_f32 %0, %1, %2, %3" : "=v"(v[i]) : "v"(va), "v"(v[i]), "s"(sa));
+                if (KIND == 8) asm volatile("v_mov_b32 %0, %1" : "=v"(v[i]) : "s"(sa));
             }
         }
     }
@@ -46,7 +49,9 @@ __global__ __launch_bounds__(256) void k_rate(float *out, int iters, float a, fl
 extern "C" {
 
 // Runs kind (0: FMA vector operands, 1: FMA scalar operand, 2: exp2, 3: rsq,
-// 4: FMA with a DPP row-broadcast operand, 5: FMA in its three-operand VOP3 form)
+// 4: FMA with a DPP row-broadcast operand, 5: FMA in its three-operand VOP3 form,
+// 6: VOP3 FMA with a scalar register as its second operand, 7: as its addend,
+// 8: v_mov_b32 from a scalar register)
 // on `blocks` work-groups of 256 threads for `iters` x 16 x 8 operations per
 // lane.  Returns the device time in milliseconds (< 0 on error).
 float vfmm_mb_rate(int kind, int blocks, int iters) {
@@ -62,6 +67,9 @@ float vfmm_mb_rate(int kind, int blocks, int iters) {
             case 2: k_rate<2><<<blocks, 256>>>(out, iters, 0.999f, 0.9999f); break;
             case 4: k_rate<4><<<blocks, 256>>>(out, iters, 0.999f, 0.9999f); break;
             case 5: k_rate<5><<<blocks, 256>>>(out, iters, 0.999f, 0.9999f); break;
+            case 6: k_rate<6><<<blocks, 256>>>(out, iters, 0.999f, 0.9999f); break;
+            case 7: k_rate<7><<<blocks, 256>>>(out, iters, 0.999f, 0.9999f); break;
+            case 8: k_rate<8><<<blocks, 256>>>(out, iters, 0.999f, 0.9999f); break;
             default: k_rate<3><<<blocks, 256>>>(out, iters, 0.999f, 0.9999f); break;
         }
     };
