@@ -255,7 +255,9 @@ typedef struct vfmm_rbf_info {
  * float32; the float32 sums limit the reachable residual to about 1e-5
  * relative.  Synchronises the stream once per iteration.  info (host, may be
  * null) receives iteration counts, residuals and times.  Errors: as
- * fmm_gaussian_sum, and VFMM_EINVAL for tol < 0 or maxiter < 0. */
+ * fmm_gaussian_sum, and VFMM_EINVAL for tol < 0, maxiter < 0 or per-particle
+ * cores (the system is then not symmetric; core spreading by Eq. 4 keeps one
+ * shared core). */
 vfmm_status rbf_reinit(vfmm_ctx *ctx, int64_t n, const float *wx, const float *wy, const float *wz, float *gx,
                        float *gy, float *gz, double tol, int32_t maxiter, vfmm_rbf_info *info);
 

@@ -479,6 +479,9 @@ void rbf_reinit_run(Ctx &c, int64_t n, const float *wx, const float *wy, const f
                     float *gz, double tol, int maxiter, vfmm_rbf_info *info) {
     rbf_check(c, n, "rbf_reinit");
     if (!(tol >= 0.0) || maxiter < 0) throw Error{VFMM_EINVAL, "rbf_reinit: tol must be >= 0 and maxiter >= 0"};
+    // with cores that differ per particle the matrix zeta_j(x_i - x_j) is not symmetric,
+    // and conjugate gradients do not apply
+    if (c.var_sigma) throw Error{VFMM_EINVAL, "rbf_reinit: needs one shared core (per-particle cores give a nonsymmetric system)"};
     ensure_rbf_events(c);
     vfmm_rbf_info I;
     std::memset(&I, 0, sizeof(I));

@@ -159,6 +159,13 @@ def test_rbf_state_and_errors():
         ctx.build_targets(t[0], t[1], t[2], t[6], *pts)
         with pytest.raises(vf.VfmmError, match="EINVAL"):
             ctx.gaussian_sum(*w)
+    with vf.Context(p=6) as ctx:
+        sig = t[6].clone()
+        sig[7] *= 1.5
+        ctx.build(t[0], t[1], t[2], sig)
+        ctx.gaussian_sum(*w)  # the blob sum takes per-particle cores
+        with pytest.raises(vf.VfmmError, match="shared core"):
+            ctx.rbf_reinit(*w)
     with vf.Context(p=6, precision=2) as ctx:
         ctx.build(t[0], t[1], t[2], t[6])
         with pytest.raises(vf.VfmmError, match="float32 and mixed"):
