@@ -623,9 +623,11 @@ def main():
         res = {}
         for kind, name in ((0, "fma_vector_operand"), (1, "fma_scalar_operand"), (2, "exp2"), (3, "rsq"),
                            (4, "fma_dpp_row_broadcast_operand"), (5, "fma_vop3"), (6, "fma_vop3_scalar_src1"),
-                           (7, "fma_vop3_scalar_addend"), (8, "mov_from_scalar")):
-            ms = mb.vfmm_mb_rate(kind, blocks, iters if kind in (0, 1, 4, 5, 6, 7, 8) else iters // 4)
-            n_ops = ops if kind in (0, 1, 4, 5, 6, 7, 8) else ops / 4
+                           (7, "fma_vop3_scalar_addend"), (8, "mov_from_scalar"),
+                           (9, "fma_accumulator_bank_shared_with_source"), (10, "fma_fixed_registers_no_shared_bank"),
+                           (11, "fma7_exp1_mix")):
+            ms = mb.vfmm_mb_rate(kind, blocks, iters if kind not in (2, 3) else iters // 4)
+            n_ops = ops if kind not in (2, 3) else ops / 4
             res[name + "_lane_ops_per_s"] = n_ops / (ms * 1e-3)
         res["fma_tflops"] = 2 * res["fma_vector_operand_lane_ops_per_s"] / 1e12
         print(json.dumps(res), flush=True)

@@ -44,6 +44,38 @@ __global__ __launch_bounds__(256) void k_rate(float *out, int iters, float a, fl
     if (s == 12345.678f) out[threadIdx.x] = s;  // keep the chains live
 }
 
+// Loops written out in one asm statement with fixed registers, so that the
+// register banks (register number mod 4) and the instruction order are known:
+// 9: v_fmac_f32 whose accumulators share a bank with one source (v32, v36, ..
+// against v20), 10: the same with the accumulators in another bank (v33, v37,
+// ..), 11: seven of kind 10's FMAs and one independent v_exp_f32 in every
+// eight instructions.  16 x 8 instructions per trip, as in k_rate.
+#define MB_INIT                                                                                             \
+    "v_mov_b32 v20, 0.5\nv_mov_b32 v22, 0.5\nv_mov_b32 v32, 0.5\nv_mov_b32 v33, 0.5\nv_mov_b32 v36, 0.5\n" \
+    "v_mov_b32 v37, 0.5\nv_mov_b32 v40, 0.5\nv_mov_b32 v41, 0.5\nv_mov_b32 v44, 0.5\nv_mov_b32 v45, 0.5\n" \
+    "v_mov_b32 v48, 0.5\nv_mov_b32 v49, 0.5\nv_mov_b32 v52, 0.5\nv_mov_b32 v53, 0.5\nv_mov_b32 v56, 0.5\n" \
+    "v_mov_b32 v57, 0.5\nv_mov_b32 v60, 0.5\nv_mov_b32 v61, 0.5\n"
+#define MB_F(r) "v_fmac_f32_e32 v" #r ", v20, v22\n"
+#define MB_SAME MB_F(32) MB_F(36) MB_F(40) MB_F(44) MB_F(48) MB_F(52) MB_F(56) MB_F(60)
+#define MB_OTHER MB_F(33) MB_F(37) MB_F(41) MB_F(45) MB_F(49) MB_F(53) MB_F(57) MB_F(61)
+#define MB_EXP MB_F(33) MB_F(37) MB_F(41) MB_F(45) MB_F(49) MB_F(53) MB_F(57) "v_exp_f32_e32 v60, v20\n"
+#define MB_X16(g) g g g g g g g g g g g g g g g g
+#define MB_LOOP(g)                                                                                      \
+    asm volatile(MB_INIT "s_mov_b32 s40, %0\n1:\n" MB_X16(g) "s_sub_u32 s40, s40, 1\ns_cmp_lg_u32 s40, 0\n" \
+                 "s_cbranch_scc1 1b\n"                                                                  \
+                 :                                                                                      \
+                 : "s"(iters)                                                                           \
+                 : "v20", "v22", "v32", "v33", "v36", "v37", "v40", "v41", "v44", "v45", "v48", "v49", "v52", \
+                   "v53", "v56", "v57", "v60", "v61", "s40", "scc")
+
+template <int KIND>
+__global__ __launch_bounds__(256) void k_fixed(int iters) {
+    if (iters < 1) return;
+    if (KIND == 9) MB_LOOP(MB_SAME);
+    if (KIND == 10) MB_LOOP(MB_OTHER);
+    if (KIND == 11) MB_LOOP(MB_EXP);
+}
+
 }  // namespace
 
 extern "C" {
@@ -51,9 +83,11 @@ extern "C" {
 // Runs kind (0: FMA vector operands, 1: FMA scalar operand, 2: exp2, 3: rsq,
 // 4: FMA with a DPP row-broadcast operand, 5: FMA in its three-operand VOP3 form,
 // 6: VOP3 FMA with a scalar register as its second operand, 7: as its addend,
-// 8: v_mov_b32 from a scalar register)
+// 8: v_mov_b32 from a scalar register, 9: FMA whose accumulator shares a
+// register bank with a source, 10: the same FMAs without the shared bank,
+// 11: seven FMAs of kind 10 and one v_exp_f32 in every eight instructions)
 // on `blocks` work-groups of 256 threads for `iters` x 16 x 8 operations per
-// lane.  Returns the device time in milliseconds (< 0 on error).
+// lane (kinds 2 and 3: one per operation; kind 11 counts the exp as one).  Returns the device time in milliseconds (< 0 on error).
 float vfmm_mb_rate(int kind, int blocks, int iters) {
     float *out = nullptr;
     if (hipMalloc(&out, 256 * sizeof(float)) != hipSuccess) return -1.f;
@@ -70,6 +104,9 @@ float vfmm_mb_rate(int kind, int blocks, int iters) {
             case 6: k_rate<6><<<blocks, 256>>>(out, iters, 0.999f, 0.9999f); break;
             case 7: k_rate<7><<<blocks, 256>>>(out, iters, 0.999f, 0.9999f); break;
             case 8: k_rate<8><<<blocks, 256>>>(out, iters, 0.999f, 0.9999f); break;
+            case 9: k_fixed<9><<<blocks, 256>>>(iters); break;
+            case 10: k_fixed<10><<<blocks, 256>>>(iters); break;
+            case 11: k_fixed<11><<<blocks, 256>>>(iters); break;
             default: k_rate<3><<<blocks, 256>>>(out, iters, 0.999f, 0.9999f); break;
         }
     };
