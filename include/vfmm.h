@@ -414,6 +414,38 @@ vfmm_status vfmm_copy_lists(vfmm_ctx *ctx, int32_t *p2p_tgt, int32_t *p2p_src, i
                             int32_t *m2l_tgt, int32_t *m2l_src, int32_t *m2l_img,
                             int32_t *cell_start, int32_t *cell_count, int32_t *perm);
 
+/* Copy the tree and the expansions of the last build and evaluation to HOST
+ * buffers, for checking each far-field operator (Sec. 3.1: P2M, M2M, L2L,
+ * L2P) against its definition.  Pass NULL for any array not wanted; ncells,
+ * n and p as in vfmm_get_stats and the parameters.  Per cell i:
+ *   level[i], parent[i] (-1 at a root), first_child[i], nchild[i] (its
+ *   children are first_child .. first_child + nchild - 1; 0 for a leaf);
+ *   geo[5i .. 5i+4] = centre x, y, z, cube side s and the radius used by the
+ *   acceptance test (float32 values widened to double).
+ * mult and loc: double[ncells][3][NC][2], NC = (p+1)(p+2)/2, the coefficients
+ * c_n^m (0 <= m <= n <= p at index n(n+1)/2 + m; real, imaginary part; the
+ * other orders are c_n^{-m} = (-1)^m conj(c_n^m)) of the Laplace potentials
+ * psi_k(x) = sum_j q_jk / |x - x_j|, q_j = alpha_j / (4 pi), k = x, y, z, with
+ *   R_n^m(r) = r^n P_n^m(cos t) e^{i m phi} / (n+m)!,
+ *   I_n^m(r) = (n-m)! P_n^m(cos t) e^{i m phi} / r^{n+1}
+ * (associated Legendre functions with the Condon-Shortley phase):
+ *   mult: Mt_n^m = sum_j q_j conj(R_n^m((x_j - c)/s)) over the cell's
+ *         particles, psi = (1/s) sum_{n <= p, |m| <= n} Mt_n^m I_n^m((x - c)/s)
+ *         away from the cell;
+ *   loc:  psi(x) = (1/s) sum Lt_n^m R_n^m((x - c)/s) is the part of the field
+ *         the far field delivers to the cell (its own translations and its
+ *         ancestors', and the periodic lattice term).
+ * far_u, far_da: double[3][n] in the library's sorted order (perm of
+ * vfmm_copy_lists): the far-field part of u and dalpha at each particle (L2P
+ * of its leaf's local expansion).  The values are the library's float32
+ * numbers (float64 in the float64 form).  Synchronises.  Errors: VFMM_EINVAL
+ * (null ctx), VFMM_ESTATE (no tree: no build, direct mode, n = 0, or after
+ * rk_step; and for mult, loc, far_u, far_da when no evaluation has run since
+ * the build). */
+vfmm_status vfmm_copy_expansions(vfmm_ctx *ctx, int32_t *level, int32_t *parent, int32_t *first_child,
+                                 int32_t *nchild, double *geo, double *mult, double *loc, double *far_u,
+                                 double *far_da);
+
 /* Text of the last error on ctx (never NULL; "" when none).  Valid until the
  * next call on ctx.  A NULL ctx returns the last vfmm_create failure. */
 const char *vfmm_last_error(const vfmm_ctx *ctx);

@@ -86,6 +86,8 @@ _lib.vfmm_energy_spectrum.argtypes = [_vp, ctypes.c_int32] + [_vp] * 3 + [ctypes
 _lib.vfmm_get_timings.argtypes = [_vp, ctypes.POINTER(Timings)]
 _lib.vfmm_get_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
 _lib.vfmm_copy_lists.argtypes = [_vp] + [_i32p] * 9
+_f64p = ctypes.POINTER(ctypes.c_double)
+_lib.vfmm_copy_expansions.argtypes = [_vp] + [_i32p] * 4 + [_f64p] * 5
 _lib.vfmm_last_error.argtypes = [_vp]
 _lib.vfmm_last_error.restype = ctypes.c_char_p
 _lib.vfmm_destroy.argtypes = [_vp]
@@ -93,14 +95,14 @@ _lib.vfmm_destroy.restype = None
 for _f in ("vfmm_create", "vfmm_set_params", "fmm_build", "fmm_evaluate", "rk_step", "vfmm_get_timings",
            "vfmm_get_stats", "vfmm_copy_lists", "fmm_build_batched", "fmm_evaluate_batched", "vfmm_autotune",
            "fmm_build_targets", "fmm_evaluate_targets", "fmm_direct_static", "fmm_gaussian_sum", "rbf_reinit",
-           "vfmm_get_gaussian_ms", "vfmm_energy_spectrum"):
+           "vfmm_get_gaussian_ms", "vfmm_energy_spectrum", "vfmm_copy_expansions"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("vfmm_default_params", "vfmm_create", "vfmm_set_params", "fmm_build", "fmm_evaluate", "rk_step",
             "vfmm_get_timings", "vfmm_get_stats", "vfmm_copy_lists", "vfmm_last_error", "vfmm_destroy",
             "fmm_build_batched", "fmm_evaluate_batched", "vfmm_autotune", "fmm_build_targets",
             "fmm_evaluate_targets", "fmm_direct_static", "fmm_gaussian_sum", "rbf_reinit", "vfmm_get_gaussian_ms",
-            "vfmm_energy_spectrum")
+            "vfmm_energy_spectrum", "vfmm_copy_expansions")
 STATIC_MAX_N = 65536  # VFMM_STATIC_MAX_N
 
 
@@ -310,6 +312,28 @@ class Context:
         ptrs = [a[k].ctypes.data_as(_i32p) for k in ("p2p_tgt", "p2p_src", "p2p_img", "m2l_tgt", "m2l_src",
                                                      "m2l_img", "cell_start", "cell_count", "perm")]
         self._raise(_lib.vfmm_copy_lists(self._h, *ptrs))
+        return a
+
+    def expansions(self):
+        """Host copies of the tree and its expansions after an evaluation (numpy):
+        level, parent, first_child, nchild (int32[ncells]); geo (ncells, 5):
+        centre, side, radius; mult, loc complex (ncells, 3, (p+1)(p+2)/2);
+        far_u, far_da (3, n) in sorted order."""
+        import numpy as np
+        st = self.stats()
+        nc, n, p = st["ncells"], st["n"], self.params.p
+        ncp = (p + 1) * (p + 2) // 2
+        a = {k: np.zeros(nc, dtype=np.int32) for k in ("level", "parent", "first_child", "nchild")}
+        geo = np.zeros((nc, 5))
+        mult = np.zeros((nc, 3, ncp, 2))
+        loc = np.zeros((nc, 3, ncp, 2))
+        fu = np.zeros((3, n))
+        fd = np.zeros((3, n))
+        ptrs = [a[k].ctypes.data_as(_i32p) for k in ("level", "parent", "first_child", "nchild")]
+        ptrs += [x.ctypes.data_as(_f64p) for x in (geo, mult, loc, fu, fd)]
+        self._raise(_lib.vfmm_copy_expansions(self._h, *ptrs))
+        a.update(geo=geo, mult=mult[..., 0] + 1j * mult[..., 1], loc=loc[..., 0] + 1j * loc[..., 1], far_u=fu,
+                 far_da=fd)
         return a
 
     def close(self):

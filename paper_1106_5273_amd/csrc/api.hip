@@ -252,6 +252,7 @@ static void do_evaluate(Ctx &c, int64_t n, const float *x, const float *y, const
             finalize_near_far(c, ux, uy, uz, dax, day, daz);
         }
     }
+    if (!c.prm.direct) c.far_build_id = c.build_id;
     c.record(2 * PH_NUM + 3);
     c.eval_timed = true;
 }
@@ -288,6 +289,7 @@ static void graph_evaluate(Ctx &c, int64_t n, const float *const *in, float *con
     }
     c.record(2 * PH_NUM + 2);
     VFMM_HIP(hipGraphLaunch(c.graph_exec, c.stream));
+    if (!c.prm.direct && n > 0) c.far_build_id = c.build_id;
     c.record(2 * PH_NUM + 3);
     c.eval_timed = true;
 }
@@ -933,6 +935,64 @@ vfmm_status vfmm_copy_lists(vfmm_ctx *ctx, int32_t *p2p_tgt, int32_t *p2p_src, i
                     if (m2l_img) m2l_img[e] = src[e].y;
                 }
         }
+        return VFMM_OK;
+    } catch (const Error &e) {
+        return vfmm::fail(&c, e);
+    } catch (const std::exception &x) {
+        const Error e = vfmm::host_error(x);
+        return vfmm::fail(&c, e);
+    }
+}
+
+vfmm_status vfmm_copy_expansions(vfmm_ctx *ctx, int32_t *level, int32_t *parent, int32_t *first_child,
+                                 int32_t *nchild, double *geo, double *mult, double *loc, double *far_u,
+                                 double *far_da) {
+    if (!ctx) return VFMM_EINVAL;
+    Ctx &c = ctx->c;
+    if (!c.built || c.prm.direct || c.n == 0 || c.ncells == 0) {
+        c.err = "no tree built";
+        return VFMM_ESTATE;
+    }
+    if ((mult || loc || far_u || far_da) && c.far_build_id != c.build_id) {
+        c.err = "no evaluation on this tree";
+        return VFMM_ESTATE;
+    }
+    try {
+        VFMM_HIP(hipStreamSynchronize(c.stream));
+        const int nc = c.ncells;
+        if (level) VFMM_HIP(hipMemcpy(level, c.c_level.ptr, sizeof(int) * nc, hipMemcpyDeviceToHost));
+        if (parent) VFMM_HIP(hipMemcpy(parent, c.c_parent.ptr, sizeof(int) * nc, hipMemcpyDeviceToHost));
+        if (first_child) VFMM_HIP(hipMemcpy(first_child, c.c_child.ptr, sizeof(int) * nc, hipMemcpyDeviceToHost));
+        if (nchild) VFMM_HIP(hipMemcpy(nchild, c.c_nchild.ptr, sizeof(int) * nc, hipMemcpyDeviceToHost));
+        if (geo) {
+            std::vector<float4> g(nc);
+            std::vector<float> r(nc);
+            VFMM_HIP(hipMemcpy(g.data(), c.c_geo.ptr, sizeof(float4) * nc, hipMemcpyDeviceToHost));
+            VFMM_HIP(hipMemcpy(r.data(), c.c_rad.ptr, sizeof(float) * nc, hipMemcpyDeviceToHost));
+            for (int i = 0; i < nc; ++i) {
+                geo[5 * i] = g[i].x;
+                geo[5 * i + 1] = g[i].y;
+                geo[5 * i + 2] = g[i].z;
+                geo[5 * i + 3] = g[i].w;
+                geo[5 * i + 4] = r[i];
+            }
+        }
+        // expansions and far-field outputs are float64 in the float64 form, float32 otherwise
+        const bool dbl = c.prm.precision == VFMM_PRECISION_FP64;
+        auto copy_real = [&](const void *src, double *dst, size_t cnt) {
+            if (dbl) {
+                VFMM_HIP(hipMemcpy(dst, src, sizeof(double) * cnt, hipMemcpyDeviceToHost));
+            } else {
+                std::vector<float> t(cnt);
+                VFMM_HIP(hipMemcpy(t.data(), src, sizeof(float) * cnt, hipMemcpyDeviceToHost));
+                for (size_t i = 0; i < cnt; ++i) dst[i] = t[i];
+            }
+        };
+        const size_t ncoef = (size_t)nc * 3 * vfmm::NC(c.prm.p) * 2;
+        if (mult) copy_real(c.Mexp.ptr, mult, ncoef);
+        if (loc) copy_real(c.Lexp.ptr, loc, ncoef);
+        if (far_u) copy_real(c.far_u.ptr, far_u, 3 * (size_t)c.n);
+        if (far_da) copy_real(c.far_da.ptr, far_da, 3 * (size_t)c.n);
         return VFMM_OK;
     } catch (const Error &e) {
         return vfmm::fail(&c, e);

@@ -105,6 +105,7 @@ struct Ctx {
     std::vector<const void *> graph_args;
     bool capturing = false;
     uint64_t build_id = 0, graph_build_id = 0;
+    uint64_t far_build_id = ~0ull;       // build whose expansions the last evaluation computed
 
     // near field on a second stream, concurrent with the far field
     hipStream_t side = nullptr;          // non-blocking, default priority; created on first use

@@ -12,6 +12,7 @@ from .gen import (  # noqa: F401
     ring_case,
     ring_batch,
     random_cloud,
+    clustered_cloud,
     varcore_case,
     corner_lattice,
     jittered,

@@ -151,6 +151,20 @@ def random_cloud(n, seed=0, L=1.0, core=0.05, lo=(0.0, 0.0, 0.0), zero_mean=Fals
                  box_lo=tuple(lo), kind="random")
 
 
+def clustered_cloud(n, seed=0, centres=((0.3, 0.3, 0.3), (0.7, 0.65, 0.7)), width=0.06, core=0.004):
+    """Gaussian clusters of equal size (a deep, adaptive octree with sparse
+    outskirts) inside the unit cube, Gaussian-random strengths."""
+    rng = np.random.default_rng(seed)
+    c = np.asarray(centres, dtype=np.float64)
+    k = rng.integers(0, len(c), size=n)
+    p = c[k] + width * rng.standard_normal((n, 3))
+    p = np.clip(p, 0.02, 0.98).T
+    a = rng.standard_normal((3, n)) / max(n, 1)
+    sig = np.full(n, core)
+    return _pack(p[0], p[1], p[2], a[0], a[1], a[2], sig, L=1.0, periodic=False, box_lo=(0.0, 0.0, 0.0),
+                 kind="clusters")
+
+
 def varcore_case(n=128, seed=2, core_seed=7, lo=0.75, hi=1.25):
     """``turbulence_case`` with per-particle cores: each sigma_j is the lattice
     core times an independent U(lo, hi) draw (seeded by ``core_seed``)."""
