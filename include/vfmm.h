@@ -120,7 +120,13 @@ typedef struct vfmm_params {
                             parts (24 significant bits) and the six leading partial products
                             run on the bfloat16 matrix cores with float32 accumulation; the
                             translations agree with form 1 to float32 rounding and the M2L
-                            kernel takes 7.1-7.5 ms instead of 9.0 ms at 128^3, p = 10.        */
+                            kernel takes 7.1-7.5 ms instead of 9.0 ms at 128^3, p = 10.
+                            3: reduced-precision split products: two bfloat16 parts per
+                            operand (16 significant bits) and only the three leading partial
+                            products, half the matrix-core work of form 2; each translation
+                            carries relative errors of order 1e-5, meant for error bounds near
+                            1e-4 (the autotuner chooses it only where the bound holds).  p = 12
+                            uses form 1 for 2 and 3.                                           */
 } vfmm_params;
 
 /* Per-phase device times of the last fmm_build / fmm_evaluate, in milliseconds,
@@ -156,7 +162,8 @@ typedef struct vfmm_stats {
     int32_t m2l_keys;       /* batched M2L: distinct translation operators (0 if per pair) */
     int32_t m2l_groups;     /* batched M2L: (target block, operator) groups        */
     int32_t m2l_items;      /* batched M2L: work items (<= 24 groups of one block) */
-    int32_t m2l_split;      /* batched M2L: 1 when it runs the split bf16 products */
+    int32_t m2l_split;      /* batched M2L: 1 when it runs the split bf16 products
+                               (six per product), 2 for the three-product form      */
     int32_t stale;          /* 1 when the last fmm_evaluate found positions or cores
                                that differ from the build's (its outputs are NaN)     */
     int32_t overfull_leaves;/* leaves holding more than ncrit particles because the
@@ -355,7 +362,8 @@ typedef struct vfmm_tune_result {
     int32_t ncrit;         /* chosen leaf size                                         */
     float sigma_gap;       /* chosen core-overlap gap of the M2L test                  */
     int32_t precision;     /* chosen precision form (VFMM_PRECISION_FP32 or _MIXED)     */
-    int32_t m2l_form;      /* chosen batched-M2L products (0 float32, 2 split bf16)     */
+    int32_t m2l_form;      /* chosen batched-M2L products (0 float32, 2 split bf16, 3
+                              reduced-precision split bf16)                            */
     int32_t overlap;       /* chosen evaluation order (0, 1, 2 as in vfmm_params)       */
     float err_u, err_dalpha; /* rel-L2 of u and dalpha vs the high-accuracy reference  */
     float worst_u, worst_dalpha; /* largest single-target error over the RMS target
@@ -367,7 +375,7 @@ typedef struct vfmm_tune_result {
 
 /* Choose p in {6,8,10,12}, theta in {0.3,...,0.7}, ncrit in {32,...,512},
  * sigma_gap in {4,5,6}, the precision form (float32 or mixed), the batched
- * M2L products (m2l_form 0 or 2) and the evaluation order (overlap 0, 1, 2)
+ * M2L products (m2l_form 0, 2 or 3) and the evaluation order (overlap 0, 1, 2)
  * minimising the time of fmm_build + fmm_evaluate on these particles subject
  * to rel-L2(u) <= max_rel_l2 and rel-L2(dalpha) <= max_rel_l2, and no single
  * target's error above 50 max_rel_l2 of the RMS target magnitude (u and

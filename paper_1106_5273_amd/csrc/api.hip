@@ -51,7 +51,7 @@ static void validate(const vfmm_params &p) {
     if (p.use_graph != 0 && p.use_graph != 1) throw Error{VFMM_EINVAL, "use_graph must be 0 or 1"};
     if (p.use_graph && p.direct) throw Error{VFMM_EINVAL, "use_graph needs the tree path (direct = 0)"};
     if (p.overlap < 0 || p.overlap > 2) throw Error{VFMM_EINVAL, "overlap must be 0, 1 or 2"};
-    if (p.m2l_form < 0 || p.m2l_form > 2) throw Error{VFMM_EINVAL, "m2l_form must be 0, 1 or 2"};
+    if (p.m2l_form < 0 || p.m2l_form > 3) throw Error{VFMM_EINVAL, "m2l_form must be 0, 1, 2 or 3"};
     if (p.precision < VFMM_PRECISION_FP32 || p.precision > VFMM_PRECISION_FP64)
         throw Error{VFMM_EINVAL, "precision must be VFMM_PRECISION_FP32, _MIXED or _FP64"};
     if (p.periodic) {
@@ -869,7 +869,7 @@ vfmm_status vfmm_get_stats(const vfmm_ctx *ctx, vfmm_stats *out) {
         out->m2l_keys = c.mb_nkeys;
         out->m2l_groups = c.mb_ngroups;
         out->m2l_items = c.mb_nitems;
-        out->m2l_split = c.mb_x6 ? 1 : 0;
+        out->m2l_split = c.mb_x6 ? (c.mb_nsplit == 2 ? 2 : 1) : 0;
     }
     out->overfull_leaves = c.overfull_leaves;
     if (c.bres.ptr && c.n > 0) {

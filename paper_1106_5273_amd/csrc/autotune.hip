@@ -1,7 +1,8 @@
 // Autotuner: chooses the expansion degree p, the acceptance parameter theta,
 // the leaf size ncrit, the core-overlap gap of the M2L test (sigma_gap), the
 // precision form (float32 or mixed), the product form of the batched M2L
-// (float32 or split bfloat16 products) and the evaluation order (one stream,
+// (float32 products, or split bfloat16 products: six, float32-accurate, or
+// three, reduced precision) and the evaluation order (one stream,
 // near field on a second stream, near field first) that minimise the time of
 // one build + evaluate on the caller's particles while keeping the relative
 // L2 error of u and of dalpha/dt below a bound.  The error of each candidate
@@ -252,12 +253,13 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
                 if (std::fabs(gp - bb.gap) > 1e-6f) trial(bb.p, bb.theta, bb.ncrit, gp, bprec, bform, bov);
         }
         // forms at the best (theta, p, ncrit, gap): precision (float32, mixed),
-        // M2L products (float32, split bfloat16), evaluation order (0, 1, 2)
+        // M2L products (float32, split bfloat16 with six or three products),
+        // evaluation order (0, 1, 2)
         b = best_of();
         {
             const vfmm::Trial bb = *b;
             for (int prec : {VFMM_PRECISION_FP32, VFMM_PRECISION_MIXED})
-                for (int form : {0, 2})
+                for (int form : {0, 2, 3})
                     for (int ov : {0, 1, 2}) trial(bb.p, bb.theta, bb.ncrit, bb.gap, prec, form, ov);
         }
         b = best_of();

@@ -73,6 +73,8 @@ struct Ctx {
     int m2lb_lds_set = 0;                // dynamic LDS size the batched M2L kernel has been allowed
     int m2lbx_lds_set = 0;               // the same for its split-product form
     bool mb_x6 = false;                  // the plan's operator table is in the split bf16 form
+    int mb_nsplit = 3;                   // bf16 parts per operand the split form multiplies (3 or 2)
+    int m2lbx3_lds_set = 0;              // dynamic LDS allowed for the two-part split kernel
     int mb_nblk = 0, mb_nkeys = 0, mb_ngroups = 0, mb_nitems = 0;
     int mb_fmt[4] = {0, 0, 0, 0};
     DevBuf mb_eq, mb_flag, mb_pos, mb_kid, mb_ukey, mb_tab, mb_bcells, mb_ent, mb_groups, mb_blk, mb_items,

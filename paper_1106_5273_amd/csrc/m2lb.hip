@@ -22,6 +22,7 @@
 // added per block in item order, so results are bit-reproducible.  Trees
 // whose groups stay sparse (irregular particle sets) use the per-pair M2L.
 #include <algorithm>
+#include <type_traits>
 #include <utility>
 
 #include "ctx.h"
@@ -537,9 +538,13 @@ __global__ __launch_bounds__(256) void k_m2lb(const int4 *__restrict__ items, co
 // T M is then the sum of the six products Ti Mj with i + j <= 2, each on
 // v_mfma_f32_16x16x32_bf16 (exact bf16 products, float32 accumulation); the
 // three dropped products and the splitting residuals are each of order
-// 2^-26 |T| |M|.  A work-group of RTI waves (eight at p = 10) takes one work
-// item; a wave owns two row tiles (32 output rows) of 32 of the 64 targets,
-// for the three potentials.
+// 2^-26 |T| |M|.  With NS = 2 parts per operand (T0 + T1, M0 + M1: 16
+// significant bits) only the three products T1 M0, T0 M1, T0 M0 are taken, at
+// half the matrix-core work; each dropped term is then of order 2^-16 |T| |M|
+// (m2l_form 3, a reduced-precision form for error bounds near 1e-4).  A
+// work-group of RTI waves (eight at p = 10) takes one work item; a wave owns
+// two row tiles (32 output rows) of 32 of the 64 targets, for the three
+// potentials.
 template <int P>
 struct MbxCfg {
     using C = MbCfg<P>;
@@ -583,7 +588,7 @@ __device__ __forceinline__ vf4 mfma_bf16(u32x4 a, u32x4 b, vf4 c) {
                                                   0, 0, 0);
 }
 
-template <int P>
+template <int P, int NS>
 __global__ __launch_bounds__(MbxCfg<P>::WAVES * 64) void k_m2lb_x6(const int4 *__restrict__ items,
                                                                   const int4 *__restrict__ groups,
                                                                   const int2 *__restrict__ ent,
@@ -596,8 +601,8 @@ __global__ __launch_bounds__(MbxCfg<P>::WAVES * 64) void k_m2lb_x6(const int4 *_
     const int item = xcd_logical(blockIdx.x, gridDim.x);
     if (item >= nitems) return;
     extern __shared__ float smem[];
-    uint16_t *Bs = reinterpret_cast<uint16_t *>(smem);                     // [2][3][64][BSX]
-    int *src_of = reinterpret_cast<int *>(smem) + 2 * 3 * X::PLANE / 2;      // [64]
+    uint16_t *Bs = reinterpret_cast<uint16_t *>(smem);                     // [2][NS][64][BSX]
+    int *src_of = reinterpret_cast<int *>(smem) + 2 * NS * X::PLANE / 2;     // [64]
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
@@ -627,14 +632,14 @@ __global__ __launch_bounds__(MbxCfg<P>::WAVES * 64) void k_m2lb_x6(const int4 *_
             src_of[en.y] = en.x;
         }
         // this wave's two row tiles of the operator: A[j][kb][split]
-        u32x4 A[2][X::KB][3];
+        u32x4 A[2][X::KB][NS];
         const u32x4 *T4 = reinterpret_cast<const u32x4 *>(tab + (size_t)key * C::OPX);
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int kb = 0; kb < X::KB; ++kb)
 #pragma unroll
-                for (int sp = 0; sp < 3; ++sp)
+                for (int sp = 0; sp < NS; ++sp)
                     A[j][kb][sp] = T4[(((size_t)(ra0 + j) * X::KB + kb) * 3 + sp) * 64 + lane];
         __syncthreads();
         // float4 number q = tid + NT i of a staged tile: column q / (RP/4), inputs 4 (q % (RP/4)) ..
@@ -650,10 +655,10 @@ __global__ __launch_bounds__(MbxCfg<P>::WAVES * 64) void k_m2lb_x6(const int4 *_
             const int off = (q / (C::RP / 4)) * X::BSX + 4 * (q % (C::RP / 4));
             u32x2 h, m, l;
             split4(x, h, m, l);
-            uint16_t *base = Bs + (size_t)buf * 3 * X::PLANE + off;
+            uint16_t *base = Bs + (size_t)buf * NS * X::PLANE + off;
             *reinterpret_cast<u32x2 *>(base) = h;
             *reinterpret_cast<u32x2 *>(base + X::PLANE) = m;
-            *reinterpret_cast<u32x2 *>(base + 2 * X::PLANE) = l;
+            if (NS == 3) *reinterpret_cast<u32x2 *>(base + 2 * X::PLANE) = l;
         };
         {
             vf4 pre[X::F4];
@@ -665,7 +670,7 @@ __global__ __launch_bounds__(MbxCfg<P>::WAVES * 64) void k_m2lb_x6(const int4 *_
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const uint16_t *Bc = Bs + (size_t)(c & 1) * 3 * X::PLANE;
+            const uint16_t *Bc = Bs + (size_t)(c & 1) * NS * X::PLANE;
             vf4 nxt[X::F4];
             if (c < 2) {
 #pragma unroll
@@ -673,17 +678,19 @@ __global__ __launch_bounds__(MbxCfg<P>::WAVES * 64) void k_m2lb_x6(const int4 *_
             }
 #pragma unroll
             for (int kb = 0; kb < X::KB; ++kb) {
-                u32x4 Bv[2][3];
+                u32x4 Bv[2][NS];
 #pragma unroll
                 for (int b = 0; b < 2; ++b)
 #pragma unroll
-                    for (int sp = 0; sp < 3; ++sp)
+                    for (int sp = 0; sp < NS; ++sp)
                         Bv[b][sp] = *reinterpret_cast<const u32x4 *>(
                             Bc + sp * X::PLANE + (16 * (cb0 + b) + i16) * X::BSX + 32 * kb + 8 * kq);
-                // smallest products first: (2,0) (1,1) (0,2) (1,0) (0,1) (0,0)
+                // smallest products first: (2,0) (1,1) (0,2) (1,0) (0,1) (0,0); with two
+                // parts per operand only the last three
                 constexpr int TA[6] = {2, 1, 0, 1, 0, 0}, TB[6] = {0, 1, 2, 0, 1, 0};
+                constexpr int T0 = NS == 3 ? 0 : 3;
 #pragma unroll
-                for (int t = 0; t < 6; ++t)
+                for (int t = T0; t < 6; ++t)
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -713,10 +720,10 @@ __global__ __launch_bounds__(MbxCfg<P>::WAVES * 64) void k_m2lb_x6(const int4 *_
     }
 }
 
-template <int P>
+template <int P, int NS>
 static size_t m2lb_x6_lds_bytes() {
     using X = MbxCfg<P>;
-    return sizeof(uint16_t) * 2 * 3 * X::PLANE + sizeof(int) * 64;
+    return sizeof(uint16_t) * 2 * NS * X::PLANE + sizeof(int) * 64;
 }
 
 template <int P>
@@ -765,8 +772,9 @@ __global__ __launch_bounds__(TPB) void k_m2lb_reduce(int nblk, const int *blk_it
 // host side
 // ---------------------------------------------------------------------------
 // Product form of the batched M2L: split bf16 products when asked for
-// (m2l_form 2) and the padded inputs make whole k blocks of 32.
-static bool m2lb_split_form(const Ctx &c, bool fits) { return fits && c.prm.m2l_form == 2; }
+// (m2l_form 2: six products, 3: three) and the padded inputs make whole k
+// blocks of 32.
+static bool m2lb_split_form(const Ctx &c, bool fits) { return fits && (c.prm.m2l_form == 2 || c.prm.m2l_form == 3); }
 
 static int bits_for_range(int64_t maxabs) {
     int b = 1;
@@ -947,6 +955,7 @@ static void m2lb_plan_p(Ctx &c) {
         k_m2lb_optab<P, 0><<<nkeys, 256, 0, s>>>(nkeys, c.mb_ukey.as<uint64_t>(), f, c.mb_tab.as<float>());
     VFMM_LAUNCH_CHECK();
     c.mb_x6 = x6;
+    c.mb_nsplit = x6 && c.prm.m2l_form == 3 ? 2 : 3;
     c.mb_nkeys = nkeys;
     c.mb_fmt[0] = f.bq;
     c.mb_fmt[1] = f.bdl;
@@ -998,15 +1007,23 @@ static void m2lb_run_p(Ctx &c) {
     c.mb_partial.ensure(sizeof(float) * (size_t)c.mb_nitems * 3 * R * 64);
     if (c.mb_x6) {
         using X = MbxCfg<P>;
-        const size_t lds = m2lb_x6_lds_bytes<P>();
-        if (c.m2lbx_lds_set < (int)lds) {  // once per context (a context lives on one device)
-            VFMM_HIP(hipFuncSetAttribute((const void *)k_m2lb_x6<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)lds));
-            c.m2lbx_lds_set = (int)lds;
-        }
-        k_m2lb_x6<P><<<xcd_grid(c.mb_nitems), X::WAVES * 64, lds, s>>>(
-            c.mb_items.as<int4>(), c.mb_groups.as<int4>(), c.mb_ent.as<int2>(), c.mb_mr.as<float>(),
-            c.mb_tab.as<uint32_t>(), c.ncells, c.mb_nitems, c.mb_partial.as<float>());
+        auto launch = [&](auto ns) {
+            constexpr int NS = decltype(ns)::value;
+            const size_t lds = m2lb_x6_lds_bytes<P, NS>();
+            int &set = NS == 3 ? c.m2lbx_lds_set : c.m2lbx3_lds_set;
+            if (set < (int)lds) {  // once per context (a context lives on one device)
+                VFMM_HIP(hipFuncSetAttribute((const void *)k_m2lb_x6<P, NS>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+                set = (int)lds;
+            }
+            k_m2lb_x6<P, NS><<<xcd_grid(c.mb_nitems), X::WAVES * 64, lds, s>>>(
+                c.mb_items.as<int4>(), c.mb_groups.as<int4>(), c.mb_ent.as<int2>(), c.mb_mr.as<float>(),
+                c.mb_tab.as<uint32_t>(), c.ncells, c.mb_nitems, c.mb_partial.as<float>());
+        };
+        if (c.mb_nsplit == 2)
+            launch(std::integral_constant<int, 2>{});
+        else
+            launch(std::integral_constant<int, 3>{});
     } else {
         const size_t lds = m2lb_lds_bytes<P>();
         if (c.m2lb_lds_set < (int)lds) {  // once per context (a context lives on one device)

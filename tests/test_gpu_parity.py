@@ -370,6 +370,16 @@ def test_m2l_split_products_match_float32_products(p):
     assert st1["m2l_split"] == 0
     print("p=%d split vs float32 products: u %.2e dalpha %.2e" % (p, rel(u2, u1), rel(d2, d1)))
     assert rel(u2, u1) <= 1e-6 and rel(d2, d1) <= 1e-6
+    # three products of two-part operands: each dropped term of order 2^-16
+    # of the product, so the translations differ from float32 at about 1e-5
+    # relative (and the velocities by that times the far field's share)
+    u3, d3, ctx = run(case, ret_ctx=True, m2l_form=3, **kw)
+    st3 = ctx.stats()
+    ctx.close()
+    assert st3["m2l_split"] == 2
+    print("p=%d three-product split vs float32 products: u %.2e dalpha %.2e" % (p, rel(u3, u1), rel(d3, d1)))
+    assert rel(u3, u1) <= 1e-4 and rel(d3, d1) <= 1e-4
+    assert rel(u3, u1) > rel(u2, u1)
 
 
 # ----------------------------------------------------------------------------
@@ -479,11 +489,13 @@ def c2_ref():
     return case, us, das
 
 
-@pytest.mark.parametrize("extra", [{}, dict(sigma_gap=4.0, m2l_form=2, overlap=2)], ids=["bench", "gap4_split_nearfirst"])
+@pytest.mark.parametrize("extra", [{}, dict(sigma_gap=4.0, m2l_form=2, overlap=2), dict(m2l_form=3)],
+                         ids=["bench", "gap4_split_nearfirst", "split3"])
 def test_c2_full_size_matches_spectral_oracle(c2_ref, extra):
     """128^3 periodic turbulence-shaped lattice, p = 10, theta = 0.5: the
     velocity and stretching of every particle against the exact FP64 periodic
-    sum, in the configuration the bench times and in its tuned settings."""
+    sum, in the configuration the bench times, in its tuned settings and with
+    the reduced-precision (three-product) M2L."""
     case, us, das = c2_ref
     u, da = run(case, p=10, periodic=1, box_len=2 * np.pi, images=6, **extra)
     check("C2 128^3 %s u" % extra, u, us, 1e-4, WORST)
@@ -540,15 +552,18 @@ def test_c3_full_size_forms_match_stored_oracle(precision):
     check("C3 256^3 precision=%d dalpha" % precision, da[idx], ref[:, 3:], 1e-4, WORST)
 
 
-def test_c5_full_size_stage1_with_tuned_settings():
+@pytest.mark.parametrize("form", [2, 3])
+def test_c5_full_size_stage1_with_tuned_settings(form):
     """256^3 periodic lattice (seed 5) with the settings the autotuner picks for
-    a 1e-4 bound (p = 10, theta = 0.7, ncrit = 256, sigma-gap 4): the first RK
-    stage's evaluation at 2,048 stored targets of the exact periodic sum."""
+    a 1e-4 bound (p = 10, theta = 0.7, ncrit = 256, sigma-gap 4; six- or
+    three-product M2L): the first RK stage's evaluation at 2,048 stored targets
+    of the exact periodic sum."""
     case = wl.turbulence_case(256, seed=5)
     idx, ref = _stored("bench_c5_256.txt", wl.case_arrays(case))
-    u, da = run(case, p=10, theta=0.7, ncrit=256, sigma_gap=4.0, periodic=1, box_len=2 * np.pi, images=6)
-    check("C5 256^3 stage 1 u", u[idx], ref[:, :3], 1e-4, WORST)
-    check("C5 256^3 stage 1 dalpha", da[idx], ref[:, 3:], 1e-4, WORST)
+    u, da = run(case, p=10, theta=0.7, ncrit=256, sigma_gap=4.0, periodic=1, box_len=2 * np.pi, images=6,
+                m2l_form=form)
+    check("C5 256^3 stage 1 form %d u" % form, u[idx], ref[:, :3], 1e-4, WORST)
+    check("C5 256^3 stage 1 form %d dalpha" % form, da[idx], ref[:, 3:], 1e-4, WORST)
 
 
 def test_c4_full_size_batched_graph_matches_oracle():
@@ -795,7 +810,7 @@ def test_autotune_meets_bound_and_reuses_cache(tmp_path):
         assert r["err_u"] <= 1e-4 and r["err_dalpha"] <= 1e-4
         assert r["worst_u"] <= 5e-3 and r["worst_dalpha"] <= 5e-3
         assert r["p"] in (4, 6, 8, 10, 12) and r["ncrit"] in (32, 64, 128, 256, 512)
-        assert r["precision"] in (0, 1) and r["m2l_form"] in (0, 2) and r["overlap"] in (0, 1, 2)
+        assert r["precision"] in (0, 1) and r["m2l_form"] in (0, 2, 3) and r["overlap"] in (0, 1, 2)
         assert (ctx.params.precision, ctx.params.m2l_form, ctx.params.overlap) == (
             r["precision"], r["m2l_form"], r["overlap"])
         # on the 32^3 lattice ncrit = 64, 128 and 256 build the same tree (leaves of 64);
