@@ -262,6 +262,22 @@ extern "C" vfmm_status vfmm_autotune(vfmm_ctx *ctx, int64_t n, const float *x, c
                 for (int form : {0, 2, 3})
                     for (int ov : {0, 1, 2}) trial(bb.p, bb.theta, bb.ncrit, bb.gap, prec, form, ov);
         }
+        // the neighbouring leaf sizes and acceptance parameters again with the
+        // chosen forms (a cheaper M2L form moves the balance toward more
+        // translations and fewer near-field pairs)
+        b = best_of();
+        {
+            const vfmm::Trial bb = *b;
+            for (int nc : {bb.ncrit / 2, bb.ncrit * 2})
+                if (nc >= ncrits[0] && nc <= ncrits[4] &&
+                    !trial(bb.p, bb.theta, nc, bb.gap, bb.prec, bb.form, bb.overlap).ok && bb.p + 2 <= 12)
+                    trial(bb.p + 2, bb.theta, nc, bb.gap, bb.prec, bb.form, bb.overlap);
+            for (float th : {bb.theta - 0.1f, bb.theta + 0.1f}) {
+                if (th < thetas[0] - 1e-4f || th > thetas[4] + 1e-4f) continue;
+                for (int p : ps)
+                    if (p >= bb.p - 2 && trial(p, th, bb.ncrit, bb.gap, bb.prec, bb.form, bb.overlap).ok) break;
+            }
+        }
         b = best_of();
         out->p = b->p;
         out->theta = b->theta;
