@@ -84,6 +84,80 @@ __global__ __launch_bounds__(TPB) void k_cell_class(int ncells, const int *level
     cls[c] = v;
 }
 
+// Blocks from the classes on the device: a cell's bucket is 64 level + class;
+// a stable sort by bucket keeps the cells of a bucket in cell (Morton) order,
+// and the blocks of 64 are numbered bucket by bucket.
+constexpr int NBUCKET = 64 * 23;
+
+__global__ __launch_bounds__(TPB) void k_cell_bucket(int nc, const int *level, const int *cls, uint64_t *key,
+                                                     uint32_t *val) {
+    const int c = blockIdx.x * TPB + threadIdx.x;
+    if (c >= nc) return;
+    key[c] = (uint64_t)(64 * level[c] + cls[c]);
+    val[c] = (uint32_t)c;
+}
+
+// first and one-past-last sorted position of every bucket that holds cells
+__global__ __launch_bounds__(TPB) void k_bucket_ranges(int nc, const uint64_t *key, int *bstart, int *bend) {
+    const int j = blockIdx.x * TPB + threadIdx.x;
+    if (j >= nc) return;
+    const int k = (int)key[j];
+    if (j == 0 || (int)key[j - 1] != k) bstart[k] = j;
+    if (j == nc - 1 || (int)key[j + 1] != k) bend[k] = j + 1;
+}
+
+// block offset of every bucket (exclusive scan of its block count) and the
+// total, in one work-group of 1024 threads, two buckets per thread
+__global__ __launch_bounds__(1024) void k_bucket_blocks(const int *bstart, const int *bend, int *boff, int *nblk) {
+    static_assert(2 * 1024 >= NBUCKET, "two buckets per thread");
+    __shared__ int wsum[16];
+    const int t = threadIdx.x;
+    int v[2], tot = 0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int k = 2 * t + q;
+        v[q] = k < NBUCKET ? (bend[k] - bstart[k] + 63) / 64 : 0;
+        tot += v[q];
+    }
+    int x = tot;  // inclusive scan within the wave
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if ((t & 63) >= o) x += y;
+    }
+    if ((t & 63) == 63) wsum[t >> 6] = x;
+    __syncthreads();
+    if (t < 64) {
+        int w = t < 16 ? wsum[t] : 0;
+        for (int o = 1; o < 16; o <<= 1) {
+            const int y = __shfl_up(w, o, 64);
+            if (t >= o) w += y;
+        }
+        if (t < 16) wsum[t] = w;
+    }
+    __syncthreads();
+    int e = x - tot + ((t >> 6) ? wsum[(t >> 6) - 1] : 0);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int k = 2 * t + q;
+        if (k < NBUCKET) boff[k] = e;
+        e += v[q];
+    }
+    if (t == 1023) *nblk = e;
+}
+
+__global__ __launch_bounds__(TPB) void k_bucket_assign(int nc, const uint64_t *key, const uint32_t *val,
+                                                       const int *bstart, const int *boff, int2 *cell_bs,
+                                                       int *bcells) {
+    const int j = blockIdx.x * TPB + threadIdx.x;
+    if (j >= nc) return;
+    const int k = (int)key[j];
+    const int i = j - bstart[k];
+    const int blk = boff[k] + i / 64, slot = i % 64;
+    const int cell = (int)val[j];
+    cell_bs[cell] = make_int2(blk, slot);
+    bcells[(size_t)blk * 64 + slot] = cell;
+}
+
 // ---------------------------------------------------------------------------
 // per entry: level difference and quantised offset; track the ranges
 // ---------------------------------------------------------------------------
@@ -861,39 +935,34 @@ static void m2lb_plan_p(Ctx &c) {
         cm.m[l] = (l >= 2 && cnt >= 64 * 64) ? 2 : (l >= 1 && cnt >= 64 * 8) ? 1 : 0;
     }
     const int nc = c.ncells;
+    if (c.depth >= 23) return;  // buckets hold levels 0..22: per-pair M2L
     c.mb_cls.ensure(sizeof(int) * (size_t)nc);
     k_cell_class<<<cdiv(nc, TPB), TPB, 0, s>>>(nc, c.c_level.as<int>(), c.c_start.as<int>(), c.keyA.as<uint64_t>(),
                                                c.key_levels, cm, c.mb_cls.as<int>());
     VFMM_LAUNCH_CHECK();
-    std::vector<int> cls(nc);
-    VFMM_HIP(hipMemcpyAsync(cls.data(), c.mb_cls.ptr, sizeof(int) * nc, hipMemcpyDeviceToHost, s));
-    VFMM_HIP(hipStreamSynchronize(s));
-    std::vector<int2> cell_bs(nc);
-    std::vector<int> bcells;
+    c.lkey.ensure(sizeof(uint64_t) * (size_t)nc);
+    c.lval.ensure(sizeof(uint32_t) * (size_t)nc);
+    k_cell_bucket<<<cdiv(nc, TPB), TPB, 0, s>>>(nc, c.c_level.as<int>(), c.mb_cls.as<int>(), c.lkey.as<uint64_t>(),
+                                                c.lval.as<uint32_t>());
+    VFMM_LAUNCH_CHECK();
+    sort_pairs_u64(c, c.lkey, c.lval, c.lkey2, c.lval2, nc, 11);  // buckets < 2^11
+    c.mb_bkt.ensure(sizeof(int) * (3 * NBUCKET + 1));
+    int *bstart = c.mb_bkt.as<int>(), *bend = bstart + NBUCKET, *boff = bend + NBUCKET, *dnblk = boff + NBUCKET;
+    VFMM_HIP(hipMemsetAsync(bstart, 0, sizeof(int) * 2 * NBUCKET, s));
+    k_bucket_ranges<<<cdiv(nc, TPB), TPB, 0, s>>>(nc, c.lkey.as<uint64_t>(), bstart, bend);
+    VFMM_LAUNCH_CHECK();
+    k_bucket_blocks<<<1, 1024, 0, s>>>(bstart, bend, boff, dnblk);
+    VFMM_LAUNCH_CHECK();
     int nblk = 0;
-    {
-        std::vector<std::vector<int>> bucket(64);
-        for (int l = 0; l <= c.depth; ++l) {
-            const int ncl = cm.m[l] == 2 ? 64 : cm.m[l] == 1 ? 8 : 1;
-            for (int q = 0; q < ncl; ++q) bucket[q].clear();
-            for (int cell = c.lvl_off[l]; cell < c.lvl_off[l + 1]; ++cell) bucket[cls[cell]].push_back(cell);
-            for (int q = 0; q < ncl; ++q)
-                for (size_t i = 0; i < bucket[q].size(); ++i) {
-                    if (i % 64 == 0) {
-                        bcells.resize(bcells.size() + 64, -1);
-                        ++nblk;
-                    }
-                    const int cell = bucket[q][i];
-                    bcells[(size_t)(nblk - 1) * 64 + i % 64] = cell;
-                    cell_bs[cell] = make_int2(nblk - 1, (int)(i % 64));
-                }
-        }
-    }
+    VFMM_HIP(hipMemcpyAsync(&nblk, dnblk, sizeof(int), hipMemcpyDeviceToHost, s));
+    VFMM_HIP(hipStreamSynchronize(s));
     c.mb_nblk = nblk;
-    c.mb_bcells.ensure(sizeof(int) * bcells.size());
+    c.mb_bcells.ensure(sizeof(int) * 64 * (size_t)nblk);
     c.mb_cellbs.ensure(sizeof(int2) * (size_t)nc);
-    VFMM_HIP(hipMemcpyAsync(c.mb_bcells.ptr, bcells.data(), sizeof(int) * bcells.size(), hipMemcpyHostToDevice, s));
-    VFMM_HIP(hipMemcpyAsync(c.mb_cellbs.ptr, cell_bs.data(), sizeof(int2) * nc, hipMemcpyHostToDevice, s));
+    VFMM_HIP(hipMemsetAsync(c.mb_bcells.ptr, 0xff, sizeof(int) * 64 * (size_t)nblk, s));  // -1: empty slot
+    k_bucket_assign<<<cdiv(nc, TPB), TPB, 0, s>>>(nc, c.lkey.as<uint64_t>(), c.lval.as<uint32_t>(), bstart, boff,
+                                                  c.mb_cellbs.as<int2>(), c.mb_bcells.as<int>());
+    VFMM_LAUNCH_CHECK();
     // ---- groups (block, key) in (block, key) order ----
     const int64_t T = (int64_t)nblk * nkeys;
     if (T > ((int64_t)1 << 28)) return;  // table too large: per-pair M2L
