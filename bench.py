@@ -305,9 +305,18 @@ def bench_rk(args, vf, wl):
         ph.append(ctx.timings())
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    phases = {k: float(np.mean([p[k] for p in ph])) for k in ph[0]}
+    # the tree statistics describe the last build (the step's second stage);
+    # both stages are off the lattice after the warm-up steps, so twice its
+    # pair count estimates the pairs of one step
+    pairs2 = ctx.stats()["p2p_pairs"]
+    gps = 2 * pairs2 / (phases["p2p_ms"] * 1e-3)
     line = _line("RK2 step time at 256^3 (autotuned)", ms / 1e3, "s/step", ms, args,
                  "periodic 256^3 turbulence-shaped lattice, Heun RK2 (2 x build+evaluate), autotuned",
-                 {"tune": tune, "dt": dt, "stage1_accuracy": acc, "last_stage_phases_ms": {k: float(np.mean([p[k] for p in ph])) for k in ph[0]}},
+                 {"tune": tune, "dt": dt, "stage1_accuracy": acc,
+                  "step_phases_ms": phases, "phases_note": "summed over the two stages of a step",
+                  "p2p_pairs_last_stage": pairs2, "p2p_gpair_s_estimate": gps / 1e9,
+                  "p2p_frac_estimate": gps * FLOPS_PER_PAIR / 1e12 / PEAK_FP32_VALU_TFLOPS},
                  higher=False)
     print(json.dumps(line), flush=True)
 
