@@ -77,6 +77,8 @@ struct P2PArgs {
     int surface;
     float *ux, *uy, *uz, *dax, *day, *daz;
     float *near;  // non-null: write u and dalpha in sorted order to near[6][n] instead of finishing
+    int halves;   // 2: each block's list is taken in two halves by two waves, the second half
+                  // writing to near + 6n (the finalize kernel adds the halves); else 1
 };
 
 struct Acc9 {
@@ -296,7 +298,8 @@ __device__ __forceinline__ void leaf_loop_split(const P2PConst &k, const float4 
 }
 
 template <int SCHEME, bool KAHAN, int SPLIT, bool VAR>
-__device__ __forceinline__ void p2p_block(const P2PConst &k, const P2PArgs &A, int t0, int tc, int l0, int lc) {
+__device__ __forceinline__ void p2p_block(const P2PConst &k, const P2PArgs &A, int t0, int tc, int l0, int lc,
+                                          float *near) {
     const int lane = threadIdx.x & 63;
     constexpr int GL = 64 / SPLIT;  // lanes per group
     const int tl = lane % GL, grp = lane / GL;
@@ -393,13 +396,13 @@ __device__ __forceinline__ void p2p_block(const P2PConst &k, const P2PArgs &A, i
     d1 = fmaf(-3.0f, S[7], d1);
     d2 = fmaf(-3.0f, S[8], d2);
     float u0 = S[0] * k.inv_kappa, u1 = S[1] * k.inv_kappa, u2 = S[2] * k.inv_kappa;
-    if (A.near) {
-        A.near[i] = u0;
-        A.near[A.n + i] = u1;
-        A.near[2 * A.n + i] = u2;
-        A.near[3 * A.n + i] = d0;
-        A.near[4 * A.n + i] = d1;
-        A.near[5 * A.n + i] = d2;
+    if (near) {
+        near[i] = u0;
+        near[A.n + i] = u1;
+        near[2 * A.n + i] = u2;
+        near[3 * A.n + i] = d0;
+        near[4 * A.n + i] = d1;
+        near[5 * A.n + i] = d2;
         return;
     }
     if (A.far_u) {
@@ -427,19 +430,33 @@ __device__ __forceinline__ void p2p_block(const P2PConst &k, const P2PArgs &A, i
 
 template <int SCHEME, bool KAHAN, bool VAR>
 __global__ __launch_bounds__(256) void k_p2p(P2PConst k, P2PArgs A) {
-    const int b = xcd_logical(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    const int item = xcd_logical(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    // with halves, the two waves of a block are neighbours (they share its
+    // target records and much of its source data in the caches)
+    const int b = A.halves == 2 ? item >> 1 : item;
     if (b >= A.nblocks) return;
     const int4 blk = A.blocks[b];
     const int t0 = __builtin_amdgcn_readfirstlane(blk.x);
     const int tc = __builtin_amdgcn_readfirstlane(blk.y);
-    const int l0 = __builtin_amdgcn_readfirstlane(blk.z);
-    const int lc = __builtin_amdgcn_readfirstlane(blk.w);
+    int l0 = __builtin_amdgcn_readfirstlane(blk.z);
+    int lc = __builtin_amdgcn_readfirstlane(blk.w);
+    float *near = A.near;
+    if (A.halves == 2) {
+        const int first = (lc + 1) / 2;
+        if (item & 1) {
+            l0 += first;
+            lc -= first;
+            near += 6 * A.n;
+        } else {
+            lc = first;
+        }
+    }
     if (tc <= 16)
-        p2p_block<SCHEME, KAHAN, 4, VAR>(k, A, t0, tc, l0, lc);
+        p2p_block<SCHEME, KAHAN, 4, VAR>(k, A, t0, tc, l0, lc, near);
     else if (tc <= 32)
-        p2p_block<SCHEME, KAHAN, 2, VAR>(k, A, t0, tc, l0, lc);
+        p2p_block<SCHEME, KAHAN, 2, VAR>(k, A, t0, tc, l0, lc, near);
     else
-        p2p_block<SCHEME, KAHAN, 1, VAR>(k, A, t0, tc, l0, lc);
+        p2p_block<SCHEME, KAHAN, 1, VAR>(k, A, t0, tc, l0, lc, near);
 }
 
 // Records of the float32 near field (sorted order), one wave per leaf.
@@ -697,10 +714,11 @@ void p2p_prepare(Ctx &c) { p2p_records(c); }
 template <int SCHEME, bool KAHAN>
 static void launch_p2p(const P2PConst &k, const P2PArgs &A, bool var, hipStream_t s) {
     if (A.nblocks == 0) return;
+    const int64_t items = (int64_t)A.nblocks * (A.halves == 2 ? 2 : 1);
     if (var)
-        k_p2p<SCHEME, KAHAN, true><<<xcd_grid(cdiv(A.nblocks, 4)), 256, 0, s>>>(k, A);
+        k_p2p<SCHEME, KAHAN, true><<<xcd_grid(cdiv(items, 4)), 256, 0, s>>>(k, A);
     else
-        k_p2p<SCHEME, KAHAN, false><<<xcd_grid(cdiv(A.nblocks, 4)), 256, 0, s>>>(k, A);
+        k_p2p<SCHEME, KAHAN, false><<<xcd_grid(cdiv(items, 4)), 256, 0, s>>>(k, A);
     VFMM_LAUNCH_CHECK();
 }
 
@@ -730,26 +748,36 @@ static P2PArgs tree_args(Ctx &c) {
     return A;
 }
 
-// Near field alone, on stream s, into c.near (sorted order); the far field
-// runs meanwhile on the library stream and finalize_near_far adds the two.
+// Near field alone, on stream s, into c.near (sorted order, two halves of
+// every block's list in near[0 .. 6n) and near[6n .. 12n)); the far field
+// runs before, after or beside it on the library stream and
+// finalize_near_far adds the three.  Halving the lists doubles the waves: at
+// 128^3 the 32,768 one-block waves fill every SIMD exactly four times over,
+// and the uneven end of the last round costs a few percent.
 void p2p_near(Ctx &c, hipStream_t s) {
     const P2PConst k = make_const(c.sigma_uniform, c.var_sigma);
-    c.near.ensure(sizeof(float) * 6 * (size_t)c.n);
+    c.near.ensure(sizeof(float) * 12 * (size_t)c.n);
     P2PArgs A = tree_args(c);
     A.near = c.near.as<float>();
+    A.halves = 2;
     c.record(2 * PH_P2P, s);
     dispatch_p2p(c.prm, c.var_sigma, k, A, s);
     c.record(2 * PH_P2P + 1, s);
 }
 
-// out[perm[i]] = near[i] + far[i] (- the zero-mean surface term for u)
+// out[perm[i]] = (near half 1 + near half 2)[i] + far[i] (- the zero-mean
+// surface term for u)
 __global__ __launch_bounds__(256) void k_finalize(P2PArgs A, const float *__restrict__ near) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= A.n) return;
     const int64_t n = A.n;
-    float u0 = near[i] + A.far_u[i], u1 = near[n + i] + A.far_u[n + i], u2 = near[2 * n + i] + A.far_u[2 * n + i];
-    float d0 = near[3 * n + i] + A.far_da[i], d1 = near[4 * n + i] + A.far_da[n + i],
-          d2 = near[5 * n + i] + A.far_da[2 * n + i];
+    const float *h2 = near + 6 * n;
+    float u0 = (near[i] + h2[i]) + A.far_u[i];
+    float u1 = (near[n + i] + h2[n + i]) + A.far_u[n + i];
+    float u2 = (near[2 * n + i] + h2[2 * n + i]) + A.far_u[2 * n + i];
+    float d0 = (near[3 * n + i] + h2[3 * n + i]) + A.far_da[i];
+    float d1 = (near[4 * n + i] + h2[4 * n + i]) + A.far_da[n + i];
+    float d2 = (near[5 * n + i] + h2[5 * n + i]) + A.far_da[2 * n + i];
     if (A.surface) {
         u0 -= (float)(A.bounds->sum_xa[0]) * A.inv3V;
         u1 -= (float)(A.bounds->sum_xa[1]) * A.inv3V;
@@ -797,14 +825,10 @@ void p2p_and_finalize(Ctx &c, float *ux, float *uy, float *uz, float *dax, float
         c.record(2 * PH_P2P + 1);
         return;
     }
-    const P2PConst k = make_const(c.sigma_uniform, c.var_sigma);
-    P2PArgs A = tree_args(c);
-    A.far_u = c.far_u.as<float>();
-    A.far_da = c.far_da.as<float>();
-    A.ux = ux; A.uy = uy; A.uz = uz; A.dax = dax; A.day = day; A.daz = daz;
-    c.record(2 * PH_P2P);
-    dispatch_p2p(c.prm, c.var_sigma, k, A, c.stream);
-    c.record(2 * PH_P2P + 1);
+    // the same near-field halves and finalize as the other evaluation orders,
+    // so that every order gives bitwise the same results
+    p2p_near(c, c.stream);
+    finalize_near_far(c, ux, uy, uz, dax, day, daz);
 }
 
 // ---------------------------------------------------------------------------
