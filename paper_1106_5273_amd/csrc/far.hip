@@ -570,7 +570,7 @@ static void far_prealloc_p(Ctx &c) {
     c.far_da.ensure(rs * 3 * (size_t)c.n);
     if (c.prm.precision == VFMM_PRECISION_FP64) c.rec64.ensure(sizeof(double4) * 2 * (size_t)c.n);
     else {
-        c.near.ensure(sizeof(float) * 12 * (size_t)c.n);  // two near-field halves
+        c.near.ensure(sizeof(float) * 24 * (size_t)c.n);  // up to four near-field parts
         c.recp.ensure(sizeof(float4) * (c.var_sigma ? 4 : 3) * (size_t)c.n);
     }
 }

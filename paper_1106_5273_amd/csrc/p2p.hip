@@ -1,12 +1,11 @@
 // Near field P2P (Sec. 3.1, Sec. 3.6) of the regularised Biot-Savart law and
-// the stretching term, Eqs. (1)-(3).  The P2P kernel adds the far field and
-// scatters to the caller's order itself; with the near field on a second
-// stream it writes its results in sorted order and a finalize kernel adds
-// them to the far field.
+// the stretching term, Eqs. (1)-(3).  The P2P kernel writes its results in
+// sorted order, one buffer per part of the lists (below), and a finalize
+// kernel adds the parts and the far field and scatters to the caller's order.
 //
-// Work item: one wave64 per block of <= 64 targets (one target per lane) of a
-// leaf; the wave walks the leaf's P2P list.  Source particles are the same
-// for every lane at a given step, so their records are read with scalar
+// Work item: one wave64 per part (a quarter) of the P2P list of a block of
+// <= 64 targets of a leaf (one target per lane).  Source particles are the
+// same for every lane at a given step, so their records are read with scalar
 // loads and enter the vector ALU as scalar operands: no LDS staging and no
 // cross-lane traffic in the pair loop.  Per-target sums are accumulated per
 // source leaf and then added to the running total (blocked summation, with an
@@ -77,8 +76,9 @@ struct P2PArgs {
     int surface;
     float *ux, *uy, *uz, *dax, *day, *daz;
     float *near;  // non-null: write u and dalpha in sorted order to near[6][n] instead of finishing
-    int halves;   // 2: each block's list is taken in two halves by two waves, the second half
-                  // writing to near + 6n (the finalize kernel adds the halves); else 1
+    int parts;    // 2 or 4: each block's list is taken in that many parts by neighbouring
+                  // waves, part q writing to near + 6 n q (the finalize kernel adds the
+                  // parts); else 1
 };
 
 struct Acc9 {
@@ -431,9 +431,10 @@ __device__ __forceinline__ void p2p_block(const P2PConst &k, const P2PArgs &A, i
 template <int SCHEME, bool KAHAN, bool VAR>
 __global__ __launch_bounds__(256) void k_p2p(P2PConst k, P2PArgs A) {
     const int item = xcd_logical(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
-    // with halves, the two waves of a block are neighbours (they share its
-    // target records and much of its source data in the caches)
-    const int b = A.halves == 2 ? item >> 1 : item;
+    // the waves of a block's parts are neighbours (they share its target
+    // records and much of its source data in the caches)
+    const int np = A.parts == 4 ? 4 : (A.parts == 2 ? 2 : 1);
+    const int b = item / np;
     if (b >= A.nblocks) return;
     const int4 blk = A.blocks[b];
     const int t0 = __builtin_amdgcn_readfirstlane(blk.x);
@@ -441,15 +442,12 @@ __global__ __launch_bounds__(256) void k_p2p(P2PConst k, P2PArgs A) {
     int l0 = __builtin_amdgcn_readfirstlane(blk.z);
     int lc = __builtin_amdgcn_readfirstlane(blk.w);
     float *near = A.near;
-    if (A.halves == 2) {
-        const int first = (lc + 1) / 2;
-        if (item & 1) {
-            l0 += first;
-            lc -= first;
-            near += 6 * A.n;
-        } else {
-            lc = first;
-        }
+    if (np > 1) {  // part q: entries [q lc / np, (q + 1) lc / np)
+        const int q = item % np;
+        const int e0 = (q * lc) / np, e1 = ((q + 1) * lc) / np;
+        l0 += e0;
+        lc = e1 - e0;
+        near += 6 * A.n * q;
     }
     if (tc <= 16)
         p2p_block<SCHEME, KAHAN, 4, VAR>(k, A, t0, tc, l0, lc, near);
@@ -714,7 +712,7 @@ void p2p_prepare(Ctx &c) { p2p_records(c); }
 template <int SCHEME, bool KAHAN>
 static void launch_p2p(const P2PConst &k, const P2PArgs &A, bool var, hipStream_t s) {
     if (A.nblocks == 0) return;
-    const int64_t items = (int64_t)A.nblocks * (A.halves == 2 ? 2 : 1);
+    const int64_t items = (int64_t)A.nblocks * (A.parts == 4 ? 4 : (A.parts == 2 ? 2 : 1));
     if (var)
         k_p2p<SCHEME, KAHAN, true><<<xcd_grid(cdiv(items, 4)), 256, 0, s>>>(k, A);
     else
@@ -748,36 +746,44 @@ static P2PArgs tree_args(Ctx &c) {
     return A;
 }
 
-// Near field alone, on stream s, into c.near (sorted order, two halves of
-// every block's list in near[0 .. 6n) and near[6n .. 12n)); the far field
-// runs before, after or beside it on the library stream and
-// finalize_near_far adds the three.  Halving the lists doubles the waves: at
-// 128^3 the 32,768 one-block waves fill every SIMD exactly four times over,
-// and the uneven end of the last round costs a few percent.
+// Parts of every block's list (see p2p_near).
+constexpr int P2P_PARTS = 4;
+// Near field alone, on stream s, into c.near (sorted order; part q of every
+// block's list in near[6 n q .. 6 n (q + 1))); the far field runs before,
+// after or beside it on the library stream and finalize_near_far adds the
+// parts and the far field.  Four parts per block quadruple the waves: at
+// 128^3 the 32,768 one-block waves would fill every SIMD exactly four times
+// over, and the uneven end of the last round costs a few percent; a
+// work-group then also covers one block instead of four, so fewer target
+// neighbourhoods are in flight on each XCD and more source records hit in L2.
 void p2p_near(Ctx &c, hipStream_t s) {
     const P2PConst k = make_const(c.sigma_uniform, c.var_sigma);
-    c.near.ensure(sizeof(float) * 12 * (size_t)c.n);
+    c.near.ensure(sizeof(float) * 6 * P2P_PARTS * (size_t)c.n);
     P2PArgs A = tree_args(c);
     A.near = c.near.as<float>();
-    A.halves = 2;
+    A.parts = P2P_PARTS;
     c.record(2 * PH_P2P, s);
     dispatch_p2p(c.prm, c.var_sigma, k, A, s);
     c.record(2 * PH_P2P + 1, s);
 }
 
-// out[perm[i]] = (near half 1 + near half 2)[i] + far[i] (- the zero-mean
+// out[perm[i]] = (sum of the near-field parts)[i] + far[i] (- the zero-mean
 // surface term for u)
 __global__ __launch_bounds__(256) void k_finalize(P2PArgs A, const float *__restrict__ near) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= A.n) return;
     const int64_t n = A.n;
-    const float *h2 = near + 6 * n;
-    float u0 = (near[i] + h2[i]) + A.far_u[i];
-    float u1 = (near[n + i] + h2[n + i]) + A.far_u[n + i];
-    float u2 = (near[2 * n + i] + h2[2 * n + i]) + A.far_u[2 * n + i];
-    float d0 = (near[3 * n + i] + h2[3 * n + i]) + A.far_da[i];
-    float d1 = (near[4 * n + i] + h2[4 * n + i]) + A.far_da[n + i];
-    float d2 = (near[5 * n + i] + h2[5 * n + i]) + A.far_da[2 * n + i];
+    // the four parts in a fixed pairwise order: (p0 + p1) + (p2 + p3), then the far field
+    float v[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const float *q = near + (int64_t)c * n + i;
+        float a = q[0] + q[6 * n];
+        a += q[12 * n] + q[18 * n];
+        v[c] = a;
+    }
+    float u0 = v[0] + A.far_u[i], u1 = v[1] + A.far_u[n + i], u2 = v[2] + A.far_u[2 * n + i];
+    float d0 = v[3] + A.far_da[i], d1 = v[4] + A.far_da[n + i], d2 = v[5] + A.far_da[2 * n + i];
     if (A.surface) {
         u0 -= (float)(A.bounds->sum_xa[0]) * A.inv3V;
         u1 -= (float)(A.bounds->sum_xa[1]) * A.inv3V;
@@ -825,7 +831,7 @@ void p2p_and_finalize(Ctx &c, float *ux, float *uy, float *uz, float *dax, float
         c.record(2 * PH_P2P + 1);
         return;
     }
-    // the same near-field halves and finalize as the other evaluation orders,
+    // the same near-field parts and finalize as the other evaluation orders,
     // so that every order gives bitwise the same results
     p2p_near(c, c.stream);
     finalize_near_far(c, ux, uy, uz, dax, day, daz);
