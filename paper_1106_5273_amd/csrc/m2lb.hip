@@ -282,6 +282,20 @@ __global__ __launch_bounds__(TPB) void k_gk_scatter(int64_t n, const int4 *raw, 
     ent[pos] = make_int2(r.y, bs.y);
 }
 
+// Launch order of the work items: by their position in their block's item
+// list, then by block.  Blocks of one octant class hold nearly the same
+// translation keys in the same order, so the work-groups that run together on
+// one XCD (consecutive in this order) load the same operators, which their L2
+// then serves once; the partial sums stay indexed by item.
+__global__ __launch_bounds__(TPB) void k_item_order_keys(int nitems, const int4 *items, const int *blk_item0, int bshift,
+                                                         uint64_t *key, uint32_t *val) {
+    const int it = blockIdx.x * TPB + threadIdx.x;
+    if (it >= nitems) return;
+    const int b = items[it].x;
+    key[it] = ((uint64_t)(it - blk_item0[b]) << bshift) | (uint64_t)b;
+    val[it] = (uint32_t)it;
+}
+
 // group counts (from the next group's start) and the per-block first group
 __global__ __launch_bounds__(TPB) void k_group_counts(int ng, int64_t n, int4 *groups, int *blk_first) {
     const int g = blockIdx.x * TPB + threadIdx.x;
@@ -485,13 +499,15 @@ __global__ __launch_bounds__(256) void k_m2lb_optab(int nkeys, const uint64_t *_
 // buffered, while the previous potential's products
 // [16 rows x 4 inputs] x [4 inputs x 16 targets] run on v_mfma_f32_16x16x4f32.
 template <int P>
-__global__ __launch_bounds__(256) void k_m2lb(const int4 *__restrict__ items, const int4 *__restrict__ groups,
+__global__ __launch_bounds__(256) void k_m2lb(const int4 *__restrict__ items, const int *__restrict__ order,
+                                              const int4 *__restrict__ groups,
                                               const int2 *__restrict__ ent, const float *__restrict__ Mr,
                                               const float *__restrict__ tab, int zero_cell, int nitems,
                                               float *__restrict__ partial) {
     using C = MbCfg<P>;
-    const int item = xcd_logical(blockIdx.x, gridDim.x);
-    if (item >= nitems) return;
+    const int li = xcd_logical(blockIdx.x, gridDim.x);
+    if (li >= nitems) return;
+    const int item = order[li];
     static_assert(64 * C::RP / 4 == 256 * C::KC, "one float4 per thread and chunk");
     extern __shared__ float smem[];
     float *Bs = smem;                                                // [2][64][BS]
@@ -664,6 +680,7 @@ __device__ __forceinline__ vf4 mfma_bf16(u32x4 a, u32x4 b, vf4 c) {
 
 template <int P, int NS>
 __global__ __launch_bounds__(MbxCfg<P>::WAVES * 64) void k_m2lb_x6(const int4 *__restrict__ items,
+                                                                  const int *__restrict__ order,
                                                                   const int4 *__restrict__ groups,
                                                                   const int2 *__restrict__ ent,
                                                                   const float *__restrict__ Mr,
@@ -672,8 +689,9 @@ __global__ __launch_bounds__(MbxCfg<P>::WAVES * 64) void k_m2lb_x6(const int4 *_
     using C = MbCfg<P>;
     using X = MbxCfg<P>;
     constexpr int NT = X::WAVES * 64;
-    const int item = xcd_logical(blockIdx.x, gridDim.x);
-    if (item >= nitems) return;
+    const int li = xcd_logical(blockIdx.x, gridDim.x);
+    if (li >= nitems) return;
+    const int item = order[li];
     extern __shared__ float smem[];
     uint16_t *Bs = reinterpret_cast<uint16_t *>(smem);                     // [2][NS][64][BSX]
     int *src_of = reinterpret_cast<int *>(smem) + 2 * NS * X::PLANE / 2;     // [64]
@@ -1012,6 +1030,18 @@ static void m2lb_plan_p(Ctx &c) {
     k_items<<<cdiv(ng, TPB), TPB, 0, s>>>(ng, c.mb_groups.as<int4>(), flag, pos, c.mb_items.as<int4>(), blk_item0,
                                            blk_nitem);
     VFMM_LAUNCH_CHECK();
+    {
+        const int bshift = bits_for_range(nblk);  // block ids below 2^bshift
+        const int kbits = bits_for_range(nitems);  // an item's position in its block < nitems
+        c.lkey.ensure(sizeof(uint64_t) * (size_t)nitems);
+        c.lval.ensure(sizeof(uint32_t) * (size_t)nitems);
+        k_item_order_keys<<<cdiv(nitems, TPB), TPB, 0, s>>>(nitems, c.mb_items.as<int4>(), blk_item0, bshift,
+                                                            c.lkey.as<uint64_t>(), c.lval.as<uint32_t>());
+        VFMM_LAUNCH_CHECK();
+        sort_pairs_u64(c, c.lkey, c.lval, c.lkey2, c.lval2, nitems, bshift + kbits);
+        c.mb_order.ensure(sizeof(int) * (size_t)nitems);
+        VFMM_HIP(hipMemcpyAsync(c.mb_order.ptr, c.lval.ptr, sizeof(int) * (size_t)nitems, hipMemcpyDeviceToDevice, s));
+    }
     // ---- one operator per key ----
     using C = MbCfg<P>;
     const bool x6 = m2lb_split_form(c, C::X6);
@@ -1086,7 +1116,7 @@ static void m2lb_run_p(Ctx &c) {
                 set = (int)lds;
             }
             k_m2lb_x6<P, NS><<<xcd_grid(c.mb_nitems), X::WAVES * 64, lds, s>>>(
-                c.mb_items.as<int4>(), c.mb_groups.as<int4>(), c.mb_ent.as<int2>(), c.mb_mr.as<float>(),
+                c.mb_items.as<int4>(), c.mb_order.as<int>(), c.mb_groups.as<int4>(), c.mb_ent.as<int2>(), c.mb_mr.as<float>(),
                 c.mb_tab.as<uint32_t>(), c.ncells, c.mb_nitems, c.mb_partial.as<float>());
         };
         if (c.mb_nsplit == 2)
@@ -1100,7 +1130,8 @@ static void m2lb_run_p(Ctx &c) {
                                          (int)lds));
             c.m2lb_lds_set = (int)lds;
         }
-        k_m2lb<P><<<xcd_grid(c.mb_nitems), 256, lds, s>>>(c.mb_items.as<int4>(), c.mb_groups.as<int4>(),
+        k_m2lb<P><<<xcd_grid(c.mb_nitems), 256, lds, s>>>(c.mb_items.as<int4>(), c.mb_order.as<int>(),
+                                                           c.mb_groups.as<int4>(),
                                                            c.mb_ent.as<int2>(), c.mb_mr.as<float>(),
                                                            c.mb_tab.as<float>(), c.ncells, c.mb_nitems,
                                                            c.mb_partial.as<float>());
