@@ -711,11 +711,30 @@ __global__ __launch_bounds__(MbxCfg<P>::WAVES * 64) void k_m2lb_x6(const int4 *_
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int b = 0; b < 2; ++b) acc[c][j][b] = vf4{0.f, 0.f, 0.f, 0.f};
+    // this wave's two row tiles of the operator: A[j][kb][split].  The first
+    // group's operator is loaded here; each later group's is loaded k block
+    // by k block while the group before it does its last potential, as soon as
+    // that k block's products have been issued.
+    u32x4 A[2][X::KB][NS];
+    auto load_a = [&](int key, int kb) {
+        const u32x4 *T4 = reinterpret_cast<const u32x4 *>(tab + (size_t)key * C::OPX);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int sp = 0; sp < NS; ++sp)
+                A[j][kb][sp] = T4[(((size_t)(ra0 + j) * X::KB + kb) * 3 + sp) * 64 + lane];
+    };
+    if (g0 < g1) {
+        const int key0 = __builtin_amdgcn_readfirstlane(groups[g0].x);
+#pragma unroll
+        for (int kb = 0; kb < X::KB; ++kb) load_a(key0, kb);
+    }
     for (int g = g0; g < g1; ++g) {
         const int4 gr = groups[g];
-        const int key = __builtin_amdgcn_readfirstlane(gr.x);
         const int e0 = __builtin_amdgcn_readfirstlane(gr.y);
         const int ne = __builtin_amdgcn_readfirstlane(gr.z);
+        const bool more = g + 1 < g1;
+        const int nkey = more ? __builtin_amdgcn_readfirstlane(groups[g + 1].x) : 0;
         __syncthreads();  // the previous key's tiles and slots are no longer read
         if (tid < 64) src_of[tid] = zero_cell;
         __syncthreads();
@@ -723,16 +742,6 @@ __global__ __launch_bounds__(MbxCfg<P>::WAVES * 64) void k_m2lb_x6(const int4 *_
             const int2 en = ent[e0 + tid];
             src_of[en.y] = en.x;
         }
-        // this wave's two row tiles of the operator: A[j][kb][split]
-        u32x4 A[2][X::KB][NS];
-        const u32x4 *T4 = reinterpret_cast<const u32x4 *>(tab + (size_t)key * C::OPX);
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int kb = 0; kb < X::KB; ++kb)
-#pragma unroll
-                for (int sp = 0; sp < NS; ++sp)
-                    A[j][kb][sp] = T4[(((size_t)(ra0 + j) * X::KB + kb) * 3 + sp) * 64 + lane];
         __syncthreads();
         // float4 number q = tid + NT i of a staged tile: column q / (RP/4), inputs 4 (q % (RP/4)) ..
         int scol[X::F4];
@@ -788,6 +797,7 @@ __global__ __launch_bounds__(MbxCfg<P>::WAVES * 64) void k_m2lb_x6(const int4 *_
 #pragma unroll
                         for (int b = 0; b < 2; ++b)
                             acc[c][j][b] = mfma_bf16(A[j][kb][TA[t]], Bv[b][TB[t]], acc[c][j][b]);
+                if (c == 2 && more) load_a(nkey, kb);  // this k block's last use in this group
             }
             if (c < 2) {
 #pragma unroll
