@@ -78,7 +78,7 @@ struct Ctx {
     int mb_nblk = 0, mb_nkeys = 0, mb_ngroups = 0, mb_nitems = 0;
     int mb_fmt[4] = {0, 0, 0, 0};
     DevBuf mb_eq, mb_flag, mb_pos, mb_kid, mb_ukey, mb_tab, mb_bcells, mb_ent, mb_groups, mb_blk, mb_items,
-        mb_mr, mb_partial, mb_cls, mb_cellbs, mb_gcnt, mb_gid, mb_goff, mb_gcur, mb_bkt, mb_order;
+        mb_mr, mb_partial, mb_cls, mb_cellbs, mb_gcnt, mb_gid, mb_goff, mb_gcur, mb_bkt, mb_order, mb_slots;
     // outputs of the far field, sorted order: float [3n] each
     DevBuf far_u, far_da;
     DevBuf dsurf;                        // float[4] surface velocity term

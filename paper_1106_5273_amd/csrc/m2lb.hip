@@ -272,7 +272,8 @@ __global__ __launch_bounds__(TPB) void k_gk_groups(int64_t T, const int *cnt, co
 }
 
 __global__ __launch_bounds__(TPB) void k_gk_scatter(int64_t n, const int4 *raw, const int2 *cell_bs, const int *kid,
-                                                    int nkeys, const int *eoff, int *cursor, int2 *ent) {
+                                                    int nkeys, const int *eoff, int *cursor, int2 *ent,
+                                                    const int *gid, int *slots) {
     const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (e >= n) return;
     const int4 r = raw[e];
@@ -280,6 +281,12 @@ __global__ __launch_bounds__(TPB) void k_gk_scatter(int64_t n, const int4 *raw, 
     const int64_t gk = (int64_t)bs.x * nkeys + kid[e];
     const int pos = eoff[gk] + atomicAdd(&cursor[gk], 1);
     ent[pos] = make_int2(r.y, bs.y);
+    slots[(int64_t)gid[gk] * 64 + bs.y] = r.y;  // the group's source of target slot bs.y
+}
+
+__global__ __launch_bounds__(TPB) void k_fill_i32(int64_t n, int v, int *p) {
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 // Launch order of the work items: by their position in their block's item
@@ -682,10 +689,10 @@ template <int P, int NS>
 __global__ __launch_bounds__(MbxCfg<P>::WAVES * 64) void k_m2lb_x6(const int4 *__restrict__ items,
                                                                   const int *__restrict__ order,
                                                                   const int4 *__restrict__ groups,
-                                                                  const int2 *__restrict__ ent,
+                                                                  const int *__restrict__ slots,
                                                                   const float *__restrict__ Mr,
-                                                                  const uint32_t *__restrict__ tab, int zero_cell,
-                                                                  int nitems, float *__restrict__ partial) {
+                                                                  const uint32_t *__restrict__ tab, int nitems,
+                                                                  float *__restrict__ partial) {
     using C = MbCfg<P>;
     using X = MbxCfg<P>;
     constexpr int NT = X::WAVES * 64;
@@ -694,7 +701,6 @@ __global__ __launch_bounds__(MbxCfg<P>::WAVES * 64) void k_m2lb_x6(const int4 *_
     const int item = order[li];
     extern __shared__ float smem[];
     uint16_t *Bs = reinterpret_cast<uint16_t *>(smem);                     // [2][NS][64][BSX]
-    int *src_of = reinterpret_cast<int *>(smem) + 2 * NS * X::PLANE / 2;     // [64]
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
@@ -729,45 +735,42 @@ __global__ __launch_bounds__(MbxCfg<P>::WAVES * 64) void k_m2lb_x6(const int4 *_
 #pragma unroll
         for (int kb = 0; kb < X::KB; ++kb) load_a(key0, kb);
     }
+    // float4 number q = tid + NT i of a staged tile: column q / (RP/4), inputs 4 (q % (RP/4)) ..;
+    // the source cell of every column of a group comes from its dense slot table (the
+    // current group's until its last potential, then the next group's)
+    int scol[X::F4];
+    auto load_cols = [&](int g) {
+#pragma unroll
+        for (int i = 0; i < X::F4; ++i) scol[i] = slots[(size_t)g * 64 + (tid + NT * i) / (C::RP / 4)];
+    };
+    auto src4 = [&](int i, int c) {
+        return reinterpret_cast<const vf4 *>(Mr + ((size_t)scol[i] * 3 + c) * C::RP +
+                                             4 * ((tid + NT * i) % (C::RP / 4)));
+    };
+    auto put = [&](int buf, int i, vf4 x) {
+        const int q = tid + NT * i;
+        const int off = (q / (C::RP / 4)) * X::BSX + 4 * (q % (C::RP / 4));
+        u32x2 h, m, l;
+        split4(x, h, m, l);
+        uint16_t *base = Bs + (size_t)buf * NS * X::PLANE + off;
+        *reinterpret_cast<u32x2 *>(base) = h;
+        *reinterpret_cast<u32x2 *>(base + X::PLANE) = m;
+        if (NS == 3) *reinterpret_cast<u32x2 *>(base + 2 * X::PLANE) = l;
+    };
+    // the first potential's multipoles of a group: loaded for the first group
+    // here, for each later one while the group before it does its last potential
+    vf4 pre[X::F4];
+    if (g0 < g1) {
+        load_cols(g0);
+#pragma unroll
+        for (int i = 0; i < X::F4; ++i) pre[i] = *src4(i, 0);
+    }
     for (int g = g0; g < g1; ++g) {
-        const int4 gr = groups[g];
-        const int e0 = __builtin_amdgcn_readfirstlane(gr.y);
-        const int ne = __builtin_amdgcn_readfirstlane(gr.z);
         const bool more = g + 1 < g1;
         const int nkey = more ? __builtin_amdgcn_readfirstlane(groups[g + 1].x) : 0;
-        __syncthreads();  // the previous key's tiles and slots are no longer read
-        if (tid < 64) src_of[tid] = zero_cell;
-        __syncthreads();
-        if (tid < ne) {
-            const int2 en = ent[e0 + tid];
-            src_of[en.y] = en.x;
-        }
-        __syncthreads();
-        // float4 number q = tid + NT i of a staged tile: column q / (RP/4), inputs 4 (q % (RP/4)) ..
-        int scol[X::F4];
+        __syncthreads();  // the previous group's tiles are no longer read
 #pragma unroll
-        for (int i = 0; i < X::F4; ++i) scol[i] = src_of[(tid + NT * i) / (C::RP / 4)];
-        auto src4 = [&](int i, int c) {
-            return reinterpret_cast<const vf4 *>(Mr + ((size_t)scol[i] * 3 + c) * C::RP +
-                                                 4 * ((tid + NT * i) % (C::RP / 4)));
-        };
-        auto put = [&](int buf, int i, vf4 x) {
-            const int q = tid + NT * i;
-            const int off = (q / (C::RP / 4)) * X::BSX + 4 * (q % (C::RP / 4));
-            u32x2 h, m, l;
-            split4(x, h, m, l);
-            uint16_t *base = Bs + (size_t)buf * NS * X::PLANE + off;
-            *reinterpret_cast<u32x2 *>(base) = h;
-            *reinterpret_cast<u32x2 *>(base + X::PLANE) = m;
-            if (NS == 3) *reinterpret_cast<u32x2 *>(base + 2 * X::PLANE) = l;
-        };
-        {
-            vf4 pre[X::F4];
-#pragma unroll
-            for (int i = 0; i < X::F4; ++i) pre[i] = *src4(i, 0);
-#pragma unroll
-            for (int i = 0; i < X::F4; ++i) put(0, i, pre[i]);
-        }
+        for (int i = 0; i < X::F4; ++i) put(0, i, pre[i]);
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -776,6 +779,10 @@ __global__ __launch_bounds__(MbxCfg<P>::WAVES * 64) void k_m2lb_x6(const int4 *_
             if (c < 2) {
 #pragma unroll
                 for (int i = 0; i < X::F4; ++i) nxt[i] = *src4(i, c + 1);
+            } else if (more) {
+                load_cols(g + 1);
+#pragma unroll
+                for (int i = 0; i < X::F4; ++i) pre[i] = *src4(i, 0);
             }
 #pragma unroll
             for (int kb = 0; kb < X::KB; ++kb) {
@@ -825,7 +832,7 @@ __global__ __launch_bounds__(MbxCfg<P>::WAVES * 64) void k_m2lb_x6(const int4 *_
 template <int P, int NS>
 static size_t m2lb_x6_lds_bytes() {
     using X = MbxCfg<P>;
-    return sizeof(uint16_t) * 2 * NS * X::PLANE + sizeof(int) * 64;
+    return sizeof(uint16_t) * 2 * NS * X::PLANE;
 }
 
 template <int P>
@@ -1021,8 +1028,13 @@ static void m2lb_plan_p(Ctx &c) {
     c.mb_groups.ensure(sizeof(int4) * ng);
     k_gk_groups<<<cdiv(T, TPB), TPB, 0, s>>>(T, gcnt, gid, goff, nkeys, c.mb_groups.as<int4>(), gcur);
     VFMM_LAUNCH_CHECK();
+    // dense slot tables: the source cell of each of a group's 64 target slots
+    // (the zero row for an empty slot)
+    c.mb_slots.ensure(sizeof(int) * 64 * (size_t)ng);
+    k_fill_i32<<<cdiv(64 * (int64_t)ng, TPB), TPB, 0, s>>>(64 * (int64_t)ng, nc, c.mb_slots.as<int>());
+    VFMM_LAUNCH_CHECK();
     k_gk_scatter<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.m2l_raw.as<int4>(), c.mb_cellbs.as<int2>(), c.mb_kid.as<int>(),
-                                               nkeys, goff, gcur, c.mb_ent.as<int2>());
+                                               nkeys, goff, gcur, c.mb_ent.as<int2>(), gid, c.mb_slots.as<int>());
     VFMM_LAUNCH_CHECK();
     c.mb_blk.ensure(sizeof(int) * 3 * (size_t)nblk);
     int *blk_first = c.mb_blk.as<int>(), *blk_item0 = blk_first + nblk, *blk_nitem = blk_item0 + nblk;
@@ -1126,8 +1138,9 @@ static void m2lb_run_p(Ctx &c) {
                 set = (int)lds;
             }
             k_m2lb_x6<P, NS><<<xcd_grid(c.mb_nitems), X::WAVES * 64, lds, s>>>(
-                c.mb_items.as<int4>(), c.mb_order.as<int>(), c.mb_groups.as<int4>(), c.mb_ent.as<int2>(), c.mb_mr.as<float>(),
-                c.mb_tab.as<uint32_t>(), c.ncells, c.mb_nitems, c.mb_partial.as<float>());
+                c.mb_items.as<int4>(), c.mb_order.as<int>(), c.mb_groups.as<int4>(), c.mb_slots.as<int>(),
+                c.mb_mr.as<float>(),
+                c.mb_tab.as<uint32_t>(), c.mb_nitems, c.mb_partial.as<float>());
         };
         if (c.mb_nsplit == 2)
             launch(std::integral_constant<int, 2>{});
