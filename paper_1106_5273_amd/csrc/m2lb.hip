@@ -272,8 +272,7 @@ __global__ __launch_bounds__(TPB) void k_gk_groups(int64_t T, const int *cnt, co
 }
 
 __global__ __launch_bounds__(TPB) void k_gk_scatter(int64_t n, const int4 *raw, const int2 *cell_bs, const int *kid,
-                                                    int nkeys, const int *eoff, int *cursor, int2 *ent,
-                                                    const int *gid, int *slots) {
+                                                    int nkeys, const int *eoff, int *cursor, int2 *ent) {
     const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (e >= n) return;
     const int4 r = raw[e];
@@ -281,12 +280,23 @@ __global__ __launch_bounds__(TPB) void k_gk_scatter(int64_t n, const int4 *raw, 
     const int64_t gk = (int64_t)bs.x * nkeys + kid[e];
     const int pos = eoff[gk] + atomicAdd(&cursor[gk], 1);
     ent[pos] = make_int2(r.y, bs.y);
-    slots[(int64_t)gid[gk] * 64 + bs.y] = r.y;  // the group's source of target slot bs.y
 }
 
-__global__ __launch_bounds__(TPB) void k_fill_i32(int64_t n, int v, int *p) {
-    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
-    if (i < n) p[i] = v;
+// Dense slot table of every group: the source cell of each of its 64 target
+// slots, the zero row (zero_cell) where the group has no entry.  One wave per
+// group; a group holds at most one entry per slot.
+__global__ __launch_bounds__(64) void k_group_slots(int zero_cell, const int4 *groups, const int2 *ent, int *slots) {
+    __shared__ int src[64];
+    const int g = blockIdx.x, t = threadIdx.x;
+    src[t] = zero_cell;
+    __syncthreads();
+    const int4 gr = groups[g];  // (key, first entry, count, block)
+    if (t < gr.z) {
+        const int2 e = ent[gr.y + t];
+        src[e.y] = e.x;
+    }
+    __syncthreads();
+    slots[(size_t)g * 64 + t] = src[t];
 }
 
 // Launch order of the work items: by their position in their block's item
@@ -1028,13 +1038,8 @@ static void m2lb_plan_p(Ctx &c) {
     c.mb_groups.ensure(sizeof(int4) * ng);
     k_gk_groups<<<cdiv(T, TPB), TPB, 0, s>>>(T, gcnt, gid, goff, nkeys, c.mb_groups.as<int4>(), gcur);
     VFMM_LAUNCH_CHECK();
-    // dense slot tables: the source cell of each of a group's 64 target slots
-    // (the zero row for an empty slot)
-    c.mb_slots.ensure(sizeof(int) * 64 * (size_t)ng);
-    k_fill_i32<<<cdiv(64 * (int64_t)ng, TPB), TPB, 0, s>>>(64 * (int64_t)ng, nc, c.mb_slots.as<int>());
-    VFMM_LAUNCH_CHECK();
     k_gk_scatter<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.m2l_raw.as<int4>(), c.mb_cellbs.as<int2>(), c.mb_kid.as<int>(),
-                                               nkeys, goff, gcur, c.mb_ent.as<int2>(), gid, c.mb_slots.as<int>());
+                                               nkeys, goff, gcur, c.mb_ent.as<int2>());
     VFMM_LAUNCH_CHECK();
     c.mb_blk.ensure(sizeof(int) * 3 * (size_t)nblk);
     int *blk_first = c.mb_blk.as<int>(), *blk_item0 = blk_first + nblk, *blk_nitem = blk_item0 + nblk;
@@ -1070,6 +1075,11 @@ static void m2lb_plan_p(Ctx &c) {
     const size_t tab_bytes = (x6 ? sizeof(uint32_t) * C::OPX : sizeof(float) * C::OP) * (size_t)nkeys;
     if (tab_bytes > MAX_TABLE_BYTES) return;  // too many distinct offsets: generic kernel
     c.mb_tab.ensure(tab_bytes);
+    if (x6) {  // the split-product kernel reads each group's sources from its slot table
+        c.mb_slots.ensure(sizeof(int) * 64 * (size_t)ng);
+        k_group_slots<<<ng, 64, 0, s>>>(nc, c.mb_groups.as<int4>(), c.mb_ent.as<int2>(), c.mb_slots.as<int>());
+        VFMM_LAUNCH_CHECK();
+    }
     if (x6)
         k_m2lb_optab<P, 1><<<nkeys, 256, 0, s>>>(nkeys, c.mb_ukey.as<uint64_t>(), f, c.mb_tab.as<float>());
     else
