@@ -258,6 +258,15 @@ __global__ __launch_bounds__(TPB) void k_gk_count(int64_t n, const int4 *raw, co
     atomicAdd(&cnt[(int64_t)cell_bs[raw[e].x].x * nkeys + kid[e]], 1);
 }
 
+// occupancy only (every writer stores the same value): the split-product
+// kernel needs which groups exist and their slot tables, not their entry lists
+__global__ __launch_bounds__(TPB) void k_gk_mark(int64_t n, const int4 *raw, const int2 *cell_bs, const int *kid,
+                                                 int nkeys, int *cnt) {
+    const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (e >= n) return;
+    cnt[(int64_t)cell_bs[raw[e].x].x * nkeys + kid[e]] = 1;
+}
+
 __global__ __launch_bounds__(TPB) void k_gk_flags(int64_t T, const int *cnt, int *flag) {
     const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (i < T) flag[i] = cnt[i] > 0 ? 1 : 0;
@@ -268,7 +277,7 @@ __global__ __launch_bounds__(TPB) void k_gk_groups(int64_t T, const int *cnt, co
     const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (i >= T) return;
     cursor[i] = 0;
-    if (cnt[i] > 0) groups[gid[i]] = make_int4((int)(i % nkeys), eoff[i], cnt[i], (int)(i / nkeys));
+    if (cnt[i] > 0) groups[gid[i]] = make_int4((int)(i % nkeys), eoff ? eoff[i] : 0, cnt[i], (int)(i / nkeys));
 }
 
 __global__ __launch_bounds__(TPB) void k_gk_scatter(int64_t n, const int4 *raw, const int2 *cell_bs, const int *kid,
@@ -283,20 +292,20 @@ __global__ __launch_bounds__(TPB) void k_gk_scatter(int64_t n, const int4 *raw, 
 }
 
 // Dense slot table of every group: the source cell of each of its 64 target
-// slots, the zero row (zero_cell) where the group has no entry.  One wave per
-// group; a group holds at most one entry per slot.
-__global__ __launch_bounds__(64) void k_group_slots(int zero_cell, const int4 *groups, const int2 *ent, int *slots) {
-    __shared__ int src[64];
-    const int g = blockIdx.x, t = threadIdx.x;
-    src[t] = zero_cell;
-    __syncthreads();
-    const int4 gr = groups[g];  // (key, first entry, count, block)
-    if (t < gr.z) {
-        const int2 e = ent[gr.y + t];
-        src[e.y] = e.x;
-    }
-    __syncthreads();
-    slots[(size_t)g * 64 + t] = src[t];
+// slots (filled beforehand with the zero row).  A group holds at most one
+// entry per slot, so every slot is written at most once.
+__global__ __launch_bounds__(TPB) void k_gk_slots(int64_t n, const int4 *raw, const int2 *cell_bs, const int *kid,
+                                                  int nkeys, const int *gid, int *slots) {
+    const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (e >= n) return;
+    const int4 r = raw[e];
+    const int2 bs = cell_bs[r.x];
+    slots[(int64_t)gid[(int64_t)bs.x * nkeys + kid[e]] * 64 + bs.y] = r.y;
+}
+
+__global__ __launch_bounds__(TPB) void k_fill_i32(int64_t n, int v, int *p) {
+    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 // Launch order of the work items: by their position in their block's item
@@ -313,13 +322,14 @@ __global__ __launch_bounds__(TPB) void k_item_order_keys(int nitems, const int4 
     val[it] = (uint32_t)it;
 }
 
-// group counts (from the next group's start) and the per-block first group
-__global__ __launch_bounds__(TPB) void k_group_counts(int ng, int64_t n, int4 *groups, int *blk_first) {
+// group counts (from the next group's start; groups without entry lists keep
+// first entry and count 0) and the per-block first group
+__global__ __launch_bounds__(TPB) void k_group_counts(int ng, int64_t n, bool lists, int4 *groups, int *blk_first) {
     const int g = blockIdx.x * TPB + threadIdx.x;
     if (g >= ng) return;
     int4 gr = groups[g];
     const int next = (g + 1 < ng) ? groups[g + 1].y : (int)n;
-    gr.z = next - gr.y;
+    gr.z = lists ? next - gr.y : 0;
     groups[g] = gr;
     if (g == 0 || groups[g - 1].w != gr.w) blk_first[gr.w] = g;
 }
@@ -1017,11 +1027,19 @@ static void m2lb_plan_p(Ctx &c) {
     c.mb_gcur.ensure(sizeof(int) * (size_t)(T + 1));
     int *gcnt = c.mb_gcnt.as<int>(), *gid = c.mb_gid.as<int>(), *goff = c.mb_goff.as<int>(),
         *gcur = c.mb_gcur.as<int>();
+    using C = MbCfg<P>;
+    const bool x6 = m2lb_split_form(c, C::X6);
     VFMM_HIP(hipMemsetAsync(gcnt, 0, sizeof(int) * (size_t)T, s));
-    k_gk_count<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.m2l_raw.as<int4>(), c.mb_cellbs.as<int2>(), c.mb_kid.as<int>(), nkeys,
-                                             gcnt);
-    VFMM_LAUNCH_CHECK();
-    scan_excl_i32(c, gcnt, goff, T);
+    if (x6) {
+        k_gk_mark<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.m2l_raw.as<int4>(), c.mb_cellbs.as<int2>(), c.mb_kid.as<int>(),
+                                                nkeys, gcnt);
+        VFMM_LAUNCH_CHECK();
+    } else {
+        k_gk_count<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.m2l_raw.as<int4>(), c.mb_cellbs.as<int2>(), c.mb_kid.as<int>(),
+                                                 nkeys, gcnt);
+        VFMM_LAUNCH_CHECK();
+        scan_excl_i32(c, gcnt, goff, T);
+    }
     k_gk_flags<<<cdiv(T, TPB), TPB, 0, s>>>(T, gcnt, gcur);  // flags, then reused as cursors
     VFMM_LAUNCH_CHECK();
     scan_excl_i32(c, gcur, gid, T);
@@ -1034,17 +1052,26 @@ static void m2lb_plan_p(Ctx &c) {
     // 6-7 translations of the per-pair kernel, so sparse groups (irregular
     // trees: many offsets, few targets sharing each) go to the per-pair M2L.
     if (c.prm.m2l_mode == 0 && n < (int64_t)MIN_GROUP_FILL * ng) return;
-    c.mb_ent.ensure(sizeof(int2) * n);
     c.mb_groups.ensure(sizeof(int4) * ng);
-    k_gk_groups<<<cdiv(T, TPB), TPB, 0, s>>>(T, gcnt, gid, goff, nkeys, c.mb_groups.as<int4>(), gcur);
+    k_gk_groups<<<cdiv(T, TPB), TPB, 0, s>>>(T, gcnt, gid, x6 ? nullptr : goff, nkeys, c.mb_groups.as<int4>(), gcur);
     VFMM_LAUNCH_CHECK();
-    k_gk_scatter<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.m2l_raw.as<int4>(), c.mb_cellbs.as<int2>(), c.mb_kid.as<int>(),
-                                               nkeys, goff, gcur, c.mb_ent.as<int2>());
-    VFMM_LAUNCH_CHECK();
+    if (x6) {  // the split-product kernel reads each group's sources from its slot table
+        c.mb_slots.ensure(sizeof(int) * 64 * (size_t)ng);
+        k_fill_i32<<<cdiv(64 * (int64_t)ng, TPB), TPB, 0, s>>>(64 * (int64_t)ng, nc, c.mb_slots.as<int>());
+        VFMM_LAUNCH_CHECK();
+        k_gk_slots<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.m2l_raw.as<int4>(), c.mb_cellbs.as<int2>(), c.mb_kid.as<int>(),
+                                                 nkeys, gid, c.mb_slots.as<int>());
+        VFMM_LAUNCH_CHECK();
+    } else {  // the float32-product kernel reads each group's entry list
+        c.mb_ent.ensure(sizeof(int2) * n);
+        k_gk_scatter<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.m2l_raw.as<int4>(), c.mb_cellbs.as<int2>(),
+                                                   c.mb_kid.as<int>(), nkeys, goff, gcur, c.mb_ent.as<int2>());
+        VFMM_LAUNCH_CHECK();
+    }
     c.mb_blk.ensure(sizeof(int) * 3 * (size_t)nblk);
     int *blk_first = c.mb_blk.as<int>(), *blk_item0 = blk_first + nblk, *blk_nitem = blk_item0 + nblk;
     VFMM_HIP(hipMemsetAsync(c.mb_blk.ptr, 0, sizeof(int) * 3 * (size_t)nblk, s));
-    k_group_counts<<<cdiv(ng, TPB), TPB, 0, s>>>(ng, n, c.mb_groups.as<int4>(), blk_first);
+    k_group_counts<<<cdiv(ng, TPB), TPB, 0, s>>>(ng, n, !x6, c.mb_groups.as<int4>(), blk_first);
     VFMM_LAUNCH_CHECK();
     k_item_flags<<<cdiv(ng, TPB), TPB, 0, s>>>(ng, c.mb_groups.as<int4>(), blk_first, flag);
     VFMM_LAUNCH_CHECK();
@@ -1070,16 +1097,9 @@ static void m2lb_plan_p(Ctx &c) {
         VFMM_HIP(hipMemcpyAsync(c.mb_order.ptr, c.lval.ptr, sizeof(int) * (size_t)nitems, hipMemcpyDeviceToDevice, s));
     }
     // ---- one operator per key ----
-    using C = MbCfg<P>;
-    const bool x6 = m2lb_split_form(c, C::X6);
     const size_t tab_bytes = (x6 ? sizeof(uint32_t) * C::OPX : sizeof(float) * C::OP) * (size_t)nkeys;
     if (tab_bytes > MAX_TABLE_BYTES) return;  // too many distinct offsets: generic kernel
     c.mb_tab.ensure(tab_bytes);
-    if (x6) {  // the split-product kernel reads each group's sources from its slot table
-        c.mb_slots.ensure(sizeof(int) * 64 * (size_t)ng);
-        k_group_slots<<<ng, 64, 0, s>>>(nc, c.mb_groups.as<int4>(), c.mb_ent.as<int2>(), c.mb_slots.as<int>());
-        VFMM_LAUNCH_CHECK();
-    }
     if (x6)
         k_m2lb_optab<P, 1><<<nkeys, 256, 0, s>>>(nkeys, c.mb_ukey.as<uint64_t>(), f, c.mb_tab.as<float>());
     else
