@@ -61,6 +61,37 @@ struct P2PConst {
     float q[VFMM_M2_DEG + 1];      // series: Hh = E sum q_k r2'^k,  Fh = E (K3 + r2' sum q_k r2'^k)
 };
 
+// The same constants evaluated at compile time (lam = log2 e, a = (2/sqrt pi)
+// sqrt(ln 2)), so that the pair loop takes them as instruction literals
+// (v_fmaak_f32 and the like) instead of reading them from registers: a
+// constant in a vector register can share a register bank with another
+// operand of the same instruction, which halves that instruction's issue rate.
+// The host's constants are these values (make_const).
+namespace cutoff_ce {
+constexpr double sqrt_newton(double x) {
+    double r = x > 1.0 ? x : 1.0;
+    for (int i = 0; i < 200; ++i) r = 0.5 * (r + x / r);
+    return r;
+}
+constexpr double LN2 = 0.693147180559945309417232121458;
+constexpr double PI = 3.14159265358979323846264338328;
+constexpr double LAM = 1.0 / LN2;
+constexpr double SQRT_LAM = sqrt_newton(LAM);
+constexpr double SQRT_PI = sqrt_newton(PI);
+constexpr double lam_pow_half(int k) {  // lam^(k/2)
+    double r = 1.0;
+    for (int i = 0; i < k / 2; ++i) r *= LAM;
+    return (k & 1) ? r * SQRT_LAM : r;
+}
+constexpr double A = 2.0 / SQRT_PI * sqrt_newton(LN2);
+constexpr float a = (float)A;
+constexpr float ab = (float)(A * 2.0 / (3.0 * LAM));
+constexpr float K3 = (float)(4.0 / (3.0 * SQRT_PI) / lam_pow_half(3));
+constexpr float r2_small = (float)((double)VFMM_CUTOFF_XSPLIT * LAM);
+constexpr float pe(int i) { return (float)((double)VFMM_ERFCX_C[i] * lam_pow_half(i + 1)); }
+constexpr float q(int i) { return (float)(8.0 / (15.0 * SQRT_PI) * (double)VFMM_M2_C[i] / lam_pow_half(5 + 2 * i)); }
+}  // namespace cutoff_ce
+
 struct P2PArgs {
     const float4 *__restrict__ rec;  // float4[3n] (uniform cores) or float4[4n] (per-particle cores) records
     const int4 *__restrict__ blocks;
@@ -92,13 +123,13 @@ struct Tgt {
     float ai0, ai1, ai2;  // alpha_i
 };
 
-// On gfx950 an FP32 VALU operation that reads a scalar register issues at
-// half the rate of one whose operands are all vector registers (measured:
-// 38.7e12 against 66-74e12 lane operations/s).  The loop-invariant constants
-// of the cutoff are therefore held in vector registers.  The source records
-// stay scalar operands: copying them into vector registers every step costs
-// more issue slots than it saves.
-__device__ __forceinline__ void to_vgpr(float &a) { asm("" : "+v"(a)); }
+// On gfx950 a run of FP32 VALU operations that read a scalar register issues
+// at half the rate of ones whose operands are all vector registers (measured:
+// 38.7e12 against 66-74e12 lane operations/s), and so does one whose vector
+// operands share a register bank.  The loop-invariant constants of the cutoff
+// are instruction literals (cutoff_ce).  The source records stay scalar
+// operands: copying them into vector registers every step costs more issue
+// slots than it saves.
 
 // VAR (per-source cores): records hold unscaled leaf-local offsets, the
 // strengths ah = kappa_j^3 alpha/(4 pi) and kappa_j^2, 1/kappa_j of the source
@@ -144,22 +175,23 @@ __device__ __forceinline__ void pair_rest(const P2PConst &k, const Tgt &t, const
     } else {
         const float r2s = g.r2s;
         const float E = g.E;
-        float pe = k.pe[VFMM_ERFCX_DEG];
+        namespace ce = cutoff_ce;
+        float pe = ce::pe(VFMM_ERFCX_DEG);
 #pragma unroll
-        for (int i = VFMM_ERFCX_DEG - 1; i >= 0; --i) pe = fmaf(pe, rinv, k.pe[i]);
+        for (int i = VFMM_ERFCX_DEG - 1; i >= 0; --i) pe = fmaf(pe, rinv, ce::pe(i));
         // G3 = 1 - a E (rho' + pe(1/rho')/rho') and G5 = G3 - a b E rho'^3, so that
         // F = G3 / rho'^3 = (1/rho' - E (a + rho'^-2 a pe)) / rho'^2 and
         // H = G5 / rho'^5 = (F - a b E) / rho'^2
-        F = rinv2 * fmaf(-E, fmaf(rinv2, pe, k.a), rinv);
-        H = rinv2 * fmaf(-E, k.ab, F);
+        F = rinv2 * fmaf(-E, fmaf(rinv2, pe, ce::a), rinv);
+        H = rinv2 * fmaf(-E, ce::ab, F);
         if (V == 0) {
-            if (__any(r2s < k.r2_small)) {
-                float q2 = k.q[VFMM_M2_DEG];
+            if (__any(r2s < ce::r2_small)) {
+                float q2 = ce::q(VFMM_M2_DEG);
 #pragma unroll
-                for (int i = VFMM_M2_DEG - 1; i >= 0; --i) q2 = fmaf(q2, r2s, k.q[i]);
-                const float Fs = E * fmaf(r2s, q2, k.K3);  // 2^{-r2'} K3 1F1(1; 5/2; x)
+                for (int i = VFMM_M2_DEG - 1; i >= 0; --i) q2 = fmaf(q2, r2s, ce::q(i));
+                const float Fs = E * fmaf(r2s, q2, ce::K3);  // 2^{-r2'} K3 1F1(1; 5/2; x)
                 const float Hs = E * q2;                   // 2^{-r2'} K5 1F1(1; 7/2; x)
-                const bool sm = r2s < k.r2_small;
+                const bool sm = r2s < ce::r2_small;
                 F = sm ? Fs : F;
                 H = sm ? Hs : H;
             }
@@ -321,11 +353,6 @@ __device__ __forceinline__ void p2p_block(const P2PConst &k, const P2PArgs &A, i
     }
     float S[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     float Cc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    P2PConst kv = k;  // the constants of the erfcx form, in vector registers
-#pragma unroll
-    for (int q = 0; q <= VFMM_ERFCX_DEG; ++q) to_vgpr(kv.pe[q]);
-    to_vgpr(kv.a);
-    to_vgpr(kv.ab);
     for (int e = 0; e < lc; ++e) {
         const int4 en = A.ent[l0 + e];
         const float4 D = A.sh[l0 + e];
@@ -343,18 +370,18 @@ __device__ __forceinline__ void p2p_block(const P2PConst &k, const P2PArgs &A, i
         Acc9 p = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         if (SPLIT == 1) {
             if (var == 1)
-                leaf_loop<1, SCHEME, VAR>(kv, A.rec, s0, sc, t, p);
+                leaf_loop<1, SCHEME, VAR>(k, A.rec, s0, sc, t, p);
             else if (var == 0)
-                leaf_loop<0, SCHEME, VAR>(kv, A.rec, s0, sc, t, p);
+                leaf_loop<0, SCHEME, VAR>(k, A.rec, s0, sc, t, p);
             else
-                leaf_loop<2, SCHEME, VAR>(kv, A.rec, s0, sc, t, p);
+                leaf_loop<2, SCHEME, VAR>(k, A.rec, s0, sc, t, p);
         } else {
             if (var == 1)
-                leaf_loop_split<1, SCHEME, SPLIT, VAR>(kv, A.rec, s0, sc, grp, t, p);
+                leaf_loop_split<1, SCHEME, SPLIT, VAR>(k, A.rec, s0, sc, grp, t, p);
             else if (var == 0)
-                leaf_loop_split<0, SCHEME, SPLIT, VAR>(kv, A.rec, s0, sc, grp, t, p);
+                leaf_loop_split<0, SCHEME, SPLIT, VAR>(k, A.rec, s0, sc, grp, t, p);
             else
-                leaf_loop_split<2, SCHEME, SPLIT, VAR>(kv, A.rec, s0, sc, grp, t, p);
+                leaf_loop_split<2, SCHEME, SPLIT, VAR>(k, A.rec, s0, sc, grp, t, p);
         }
         float u0 = p.u0, u1 = p.u1, u2 = p.u2;
         if (SCHEME == VFMM_SCHEME_TRANSPOSE) {  // Ah x y_i - Bh
@@ -665,18 +692,14 @@ static void launch_p2p64(Ctx &c, P2P64Args A) {
 // Constants of the scaled form; every one but kappa is independent of sigma.
 static P2PConst make_const(double sigma, bool var) {
     P2PConst k{};
-    const double lam = 1.0 / std::log(2.0);  // log2 e
-    const double sqpi = std::sqrt(M_PI);
-    const double a = p2p_cutoff_a();
-    k.a = (float)a;
-    k.ab = (float)(a * 2.0 / (3.0 * lam));
-    k.K3 = (float)(4.0 / (3.0 * sqpi) / std::pow(lam, 1.5));
-    k.r2_small = (float)((double)VFMM_CUTOFF_XSPLIT * lam);
+    namespace ce = cutoff_ce;
+    k.a = ce::a;
+    k.ab = ce::ab;
+    k.K3 = ce::K3;
+    k.r2_small = ce::r2_small;
     k.inv_kappa = var ? 1.0f : (float)(1.0 / p2p_kappa(sigma));
-    for (int i = 0; i <= VFMM_ERFCX_DEG; ++i)
-        k.pe[i] = (float)((double)VFMM_ERFCX_C[i] * std::pow(lam, 0.5 * (i + 1)));
-    for (int i = 0; i <= VFMM_M2_DEG; ++i)
-        k.q[i] = (float)(8.0 / (15.0 * sqpi) * (double)VFMM_M2_C[i] / std::pow(lam, 2.5 + i));
+    for (int i = 0; i <= VFMM_ERFCX_DEG; ++i) k.pe[i] = ce::pe(i);
+    for (int i = 0; i <= VFMM_M2_DEG; ++i) k.q[i] = ce::q(i);
     return k;
 }
 
