@@ -60,11 +60,82 @@ __global__ __launch_bounds__(TPB) void k_scan_add(int *out, int64_t n, const int
     }
 }
 
+// Up to SCAN_FEW_TILES tiles: reduce-then-scan in two launches, each tile's
+// offset summed by its own work-group from the totals of the tiles before it.
+static constexpr int SCAN_FEW_TILES = 1024;
+
+__global__ __launch_bounds__(TPB) void k_scan_tile_sums(const int *in, int64_t n, int *block_sums) {
+    __shared__ int wsum[TPB / 64];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+    int run = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) run += base + i < n ? in[base + i] : 0;
+    for (int o = 32; o > 0; o >>= 1) run += __shfl_xor(run, o, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = run;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < TPB / 64; ++w) t += wsum[w];
+        block_sums[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_scan_tile_offset(const int *in, int *out, int64_t n, const int *block_sums) {
+    __shared__ int wsum[TPB / 64];
+    __shared__ int boff;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // offset of this tile: the totals of the tiles before it (at most SCAN_FEW_TILES - 1)
+    int o = 0;
+    for (int i = tid; i < (int)blockIdx.x; i += TPB) o += block_sums[i];
+    for (int d = 32; d > 0; d >>= 1) o += __shfl_xor(o, d, 64);
+    if (lane == 0) wsum[w] = o;
+    __syncthreads();
+    if (tid == 0) {
+        int t = 0;
+        for (int i = 0; i < TPB / 64; ++i) t += wsum[i];
+        boff = t;
+    }
+    __syncthreads();  // wsum is reused below
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)tid * SCAN_ITEMS;
+    int v[SCAN_ITEMS];
+    int run = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        const int64_t k = base + i;
+        v[i] = k < n ? in[k] : 0;
+        run += v[i];
+    }
+    int incl = run;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += t;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int woff = boff;
+    for (int i = 0; i < w; ++i) woff += wsum[i];
+    int ex = woff + incl - run;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        const int64_t k = base + i;
+        if (k < n) out[k] = ex;
+        ex += v[i];
+    }
+}
+
 static void scan_rec(hipStream_t s, const int *in, int *out, int64_t n, int *scratch) {
     if (n <= 0) return;
     const unsigned nb = cdiv(n, SCAN_TILE);
     if (nb == 1) {
         k_scan_tile<<<1, TPB, 0, s>>>(in, out, n, nullptr);
+        VFMM_LAUNCH_CHECK();
+        return;
+    }
+    if (nb <= (unsigned)SCAN_FEW_TILES) {  // in may alias out: the totals are taken before any write
+        k_scan_tile_sums<<<nb, TPB, 0, s>>>(in, n, scratch);
+        VFMM_LAUNCH_CHECK();
+        k_scan_tile_offset<<<nb, TPB, 0, s>>>(in, out, n, scratch);
         VFMM_LAUNCH_CHECK();
         return;
     }
