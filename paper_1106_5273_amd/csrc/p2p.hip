@@ -49,24 +49,24 @@
 
 namespace vfmm {
 
-// Constants of the scaled cutoff (the normalisation a of the cutoff is in
-// them; the strengths are kappa^3 alpha/(4 pi)).
+// The launch constant that depends on the core: the strengths are
+// kappa^3 alpha/(4 pi) and the velocity sum is scaled back by 1/kappa.
 struct P2PConst {
-    float a;         // a = (2/sqrt pi)/sqrt(lambda)
-    float ab;        // a b, b = 2/(3 lambda)
-    float K3;        // series form: Fh at r = 0 is K3 (times E)
-    float r2_small;  // s < 1  <=>  r2' < r2_small
     float inv_kappa; // u = U / kappa
-    float pe[VFMM_ERFCX_DEG + 1];  // erfcx fit in powers of 1/rho', times a
-    float q[VFMM_M2_DEG + 1];      // series: Hh = E sum q_k r2'^k,  Fh = E (K3 + r2' sum q_k r2'^k)
 };
 
-// The same constants evaluated at compile time (lam = log2 e, a = (2/sqrt pi)
-// sqrt(ln 2)), so that the pair loop takes them as instruction literals
-// (v_fmaak_f32 and the like) instead of reading them from registers: a
-// constant in a vector register can share a register bank with another
-// operand of the same instruction, which halves that instruction's issue rate.
-// The host's constants are these values (make_const).
+// Constants of the scaled cutoff (in the scaled units every one is
+// independent of sigma; the normalisation a of the cutoff is in them),
+// evaluated at compile time (lam = log2 e, a = (2/sqrt pi) sqrt(ln 2)), so
+// that the pair loop takes them as instruction literals (v_fmaak_f32 and the
+// like) instead of reading them from registers: a constant in a vector
+// register can share a register bank with another operand of the same
+// instruction, which halves that instruction's issue rate.
+//   a, ab      : a and a b, b = 2/(3 lam)
+//   K3         : the series form's Fh at r = 0 (times E)
+//   r2_small   : s < 1  <=>  r2' < r2_small
+//   pe(i)      : erfcx fit in powers of 1/rho', times a
+//   q(i)       : series, Hh = E sum q_k r2'^k,  Fh = E (K3 + r2' sum q_k r2'^k)
 namespace cutoff_ce {
 constexpr double sqrt_newton(double x) {
     double r = x > 1.0 ? x : 1.0;
@@ -689,17 +689,10 @@ static void launch_p2p64(Ctx &c, P2P64Args A) {
     VFMM_LAUNCH_CHECK();
 }
 
-// Constants of the scaled form; every one but kappa is independent of sigma.
+// The launch constant of the scaled form (the cutoff's constants are cutoff_ce).
 static P2PConst make_const(double sigma, bool var) {
     P2PConst k{};
-    namespace ce = cutoff_ce;
-    k.a = ce::a;
-    k.ab = ce::ab;
-    k.K3 = ce::K3;
-    k.r2_small = ce::r2_small;
     k.inv_kappa = var ? 1.0f : (float)(1.0 / p2p_kappa(sigma));
-    for (int i = 0; i <= VFMM_ERFCX_DEG; ++i) k.pe[i] = ce::pe(i);
-    for (int i = 0; i <= VFMM_M2_DEG; ++i) k.q[i] = ce::q(i);
     return k;
 }
 
