@@ -863,37 +863,50 @@ static size_t m2lb_lds_bytes() {
 
 // per block: sum the items' partials in item order and add to Lt.  One thread
 // per (potential, row, target slot) of a block; blockIdx.y strides over blocks.
-template <int P, class A>
-__global__ __launch_bounds__(TPB) void k_m2lb_reduce(int nblk, const int *blk_item0, const int *blk_nitem,
-                                                     const int *blk_cells, const float *partial, float2 *Lexp) {
+// Per target block, potential and chunk of RC rows: the items' partial sums of
+// each (row, slot), in item order, staged in LDS (phase 1: a wave per row,
+// lanes over the 64 slots, so the partials are read in whole rows), then
+// added to each cell's local expansion with lanes over its rows (phase 2), so
+// the read-modify-write of Lexp touches each cell's coefficients together.
+static constexpr int RC = 64;  // rows per work-group
+
+template <int P, typename A>
+__global__ __launch_bounds__(TPB) void k_m2lb_reduce(const int *blk_item0, const int *blk_nitem, const int *blk_cells,
+                                                     const float *partial, float2 *Lexp) {
     // A: accumulator type (double in the mixed precision form)
     constexpr int R = NR(P), NCP = NC(P);
-    const int idx = blockIdx.x * TPB + threadIdx.x;
-    if (idx >= 3 * R * 64) return;
-    const int lane = idx & 63;
-    const int cr = idx >> 6;  // comp * R + r
-    const int comp = cr / R, r = cr % R;
+    __shared__ A tile[RC][65];
+    const int b = blockIdx.x, comp = blockIdx.y, r0 = blockIdx.z * RC;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ni = blk_nitem[b];
+    if (ni == 0) return;
+    const size_t stride = (size_t)3 * R * 64;
+    for (int rr = wave; rr < RC; rr += TPB / 64) {
+        const int r = r0 + rr;
+        if (r >= R) break;
+        const float *p = partial + ((size_t)blk_item0[b] * 3 * R + (size_t)comp * R + r) * 64 + lane;
+        // up to 16 items' loads in flight, added in item order
+        A acc = A(0);
+        for (int i0 = 0; i0 < ni; i0 += 16) {
+            float v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = i0 + u < ni ? p[(size_t)(i0 + u) * stride] : 0.f;
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (i0 + u < ni) acc += (A)v[u];
+        }
+        tile[rr][lane] = acc;
+    }
+    __syncthreads();
+    const int r = r0 + lane;
+    if (r >= R) return;
     int k, l, im;
     decode_row(r, k, l, im);
-    const size_t stride = (size_t)3 * R * 64;
-    for (int b = blockIdx.y; b < nblk; b += gridDim.y) {
-        const int ni = blk_nitem[b];
-        const int cell = blk_cells[(size_t)b * 64 + lane];
-        if (ni == 0 || cell < 0) continue;
-        const float *p = partial + ((size_t)blk_item0[b] * 3 * R + cr) * 64 + lane;
-        A s = A(0);
-        int i = 0;
-        for (; i + 4 <= ni; i += 4) {
-            const float v0 = p[(size_t)i * stride], v1 = p[(size_t)(i + 1) * stride];
-            const float v2 = p[(size_t)(i + 2) * stride], v3 = p[(size_t)(i + 3) * stride];
-            s += (A)v0;
-            s += (A)v1;
-            s += (A)v2;
-            s += (A)v3;
-        }
-        for (; i < ni; ++i) s += (A)p[(size_t)i * stride];
+    for (int slot = wave; slot < 64; slot += TPB / 64) {
+        const int cell = blk_cells[(size_t)b * 64 + slot];
+        if (cell < 0) continue;
         float *dst = reinterpret_cast<float *>(&Lexp[((size_t)cell * 3 + comp) * NCP + CIDX(k, l)]) + im;
-        *dst = (float)((A)*dst + s);
+        *dst = (float)((A)*dst + tile[lane][slot]);
     }
 }
 
@@ -1192,12 +1205,13 @@ static void m2lb_run_p(Ctx &c) {
     VFMM_LAUNCH_CHECK();
     const int nblk = c.mb_nblk;
     int *blk_item0 = c.mb_blk.as<int>() + nblk, *blk_nitem = blk_item0 + nblk;
-    const dim3 rgrid(cdiv(3 * R * 64, TPB), std::min(nblk, 65535));
+    const dim3 rgrid(nblk, 3, cdiv(R, RC));
+    if (nblk == 0) return;
     if (c.prm.precision == VFMM_PRECISION_MIXED)
-        k_m2lb_reduce<P, double><<<rgrid, TPB, 0, s>>>(nblk, blk_item0, blk_nitem, c.mb_bcells.as<int>(),
+        k_m2lb_reduce<P, double><<<rgrid, TPB, 0, s>>>(blk_item0, blk_nitem, c.mb_bcells.as<int>(),
                                                         c.mb_partial.as<float>(), c.Lexp.as<float2>());
     else
-        k_m2lb_reduce<P, float><<<rgrid, TPB, 0, s>>>(nblk, blk_item0, blk_nitem, c.mb_bcells.as<int>(),
+        k_m2lb_reduce<P, float><<<rgrid, TPB, 0, s>>>(blk_item0, blk_nitem, c.mb_bcells.as<int>(),
                                                        c.mb_partial.as<float>(), c.Lexp.as<float2>());
     VFMM_LAUNCH_CHECK();
 }
