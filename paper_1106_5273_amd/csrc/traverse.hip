@@ -142,12 +142,18 @@ __global__ __launch_bounds__(TPB) void k_list_keys(const int4 *raw, int64_t n, u
 }
 
 // CSR offsets from the sorted targets: off[t] = first position with target >= t
+// (t = 0 .. nc), by a binary search per target: a thread per target, so a long
+// run of cells without entries (the internal cells) costs no serial loop.
 __global__ __launch_bounds__(TPB) void k_csr_bounds(const uint64_t *key, int64_t n, int nc, int *off) {
-    const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
-    if (i > n) return;
-    const int lo = (i == 0) ? 0 : (int)key[i - 1] + 1;  // targets in (key[i-1], key[i]] start at i
-    const int hi = (i == n) ? nc : (int)key[i];
-    for (int t = lo; t <= hi; ++t) off[t] = (int)i;
+    const int t = blockIdx.x * TPB + threadIdx.x;
+    if (t > nc) return;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)key[mid] < t) lo = mid + 1;
+        else hi = mid;
+    }
+    off[t] = (int)lo;
 }
 
 __global__ __launch_bounds__(TPB) void k_m2l_gather(const int4 *raw, const uint32_t *order, int64_t n, int2 *out,
@@ -271,7 +277,7 @@ static void csr_by_target(Ctx &c, const int4 *raw, int64_t n, DevBuf &off) {
     k_list_keys<<<cdiv(n, TPB), TPB, 0, s>>>(raw, n, c.lkey.as<uint64_t>(), c.lval.as<uint32_t>());
     VFMM_LAUNCH_CHECK();
     sort_pairs_u64(c, c.lkey, c.lval, c.lkey2, c.lval2, n, bits_for(nc));
-    k_csr_bounds<<<cdiv(n + 1, TPB), TPB, 0, s>>>(c.lkey.as<uint64_t>(), n, nc, off.as<int>());
+    k_csr_bounds<<<cdiv(nc + 1, TPB), TPB, 0, s>>>(c.lkey.as<uint64_t>(), n, nc, off.as<int>());
     VFMM_LAUNCH_CHECK();
 }
 
