@@ -138,6 +138,7 @@ __global__ __launch_bounds__((XferCfg<P>::THREADS)) void k_m2m(int c0, int c1, c
     constexpr int NCP = C::NCP, W = C::W;
     __shared__ V2 Mf[3][P + 1][W];   // child multipole, scaled by (s_c/s_P)^n, full orders
     __shared__ V2 Rf[P + 1][W];      // conj R_k^l(d), full orders
+    __shared__ V2 Rh[8][NCP];        // R_k^l(d) of every child, l >= 0
     const int cell = c0 + blockIdx.x;
     if (cell >= c1) return;
     const int nc = nchild[cell];
@@ -150,22 +151,26 @@ __global__ __launch_bounds__((XferCfg<P>::THREADS)) void k_m2m(int c0, int c1, c
     int n = 0, m = 0;
     decode_nm(active ? tid % NCP : 0, n, m);
     const R inv = R(1) / R(gp.w);
+    // the regular harmonics of the eight child offsets, one lane each (the
+    // recursion is serial; the children's run side by side)
+    if (tid < nc) {
+        const float4 gc = geo[f + tid];
+        V2 Rl[NCP];
+        regular_harmonics<P, R, V2>((R(gc.x) - R(gp.x)) * inv, (R(gc.y) - R(gp.y)) * inv,
+                                    (R(gc.z) - R(gp.z)) * inv, Rl);
+#pragma unroll
+        for (int q = 0; q < NCP; ++q) Rh[tid][q] = Rl[q];
+    }
     V2 acc = V2{R(0), R(0)};
     for (int k = 0; k < nc; ++k) {
         const float4 gc = geo[f + k];
         __syncthreads();
-        if (tid == 0) {
-            V2 Rl[NCP];
-            regular_harmonics<P, R, V2>((R(gc.x) - R(gp.x)) * inv, (R(gc.y) - R(gp.y)) * inv,
-                                        (R(gc.z) - R(gp.z)) * inv, Rl);
-#pragma unroll
-            for (int q = 0; q < NCP; ++q) {
-                int a, b;
-                decode_nm(q, a, b);
-                const V2 v = Rl[q];
-                Rf[a][P + b] = V2{v.x, -v.y};                                   // conj R^b
-                if (b > 0) Rf[a][P - b] = (b & 1) ? V2{-v.x, -v.y} : V2{v.x, v.y};  // conj R^{-b}
-            }
+        if (tid < NCP) {
+            int a, b;
+            decode_nm(tid, a, b);
+            const V2 v = Rh[k][tid];
+            Rf[a][P + b] = V2{v.x, -v.y};                                   // conj R^b
+            if (b > 0) Rf[a][P - b] = (b & 1) ? V2{-v.x, -v.y} : V2{v.x, v.y};  // conj R^{-b}
         }
         const R rt = R(gc.w) * inv;
         for (int i = tid; i < 3 * NCP; i += C::THREADS) {
