@@ -58,7 +58,9 @@ __global__ __launch_bounds__(64) void k_p2m(const int *leaves, const int *start,
     using V2 = typename VT<R>::V2;
     using V4 = typename VT<R>::V4;
     constexpr int NCP = NC(P);
-    constexpr int CH = sizeof(R) == 8 ? 32 : 64;
+    // particles staged per pass: 32 (17 KB of LDS in float32) lets nine
+    // one-wave work-groups share a CU; 64 (34 KB) allowed four and was slower
+    constexpr int CH = 32;
     __shared__ V2 Rs[CH][NCP];
     __shared__ V4 al[CH];
     const int lane = threadIdx.x;
