@@ -564,62 +564,65 @@ void partition_sources(Ctx &c, int64_t n_src) {
 // ---------------------------------------------------------------------------
 __device__ inline int octant_at(uint64_t key, int lchild, int KL) { return (int)((key >> (3 * (KL - lchild))) & 7); }
 
+// Eight lanes per cell, one per octant o: the end of octant o's run in the
+// cell's key range (the first index whose octant is > o) by a binary search;
+// the octants are non-decreasing along the range, so the cell's children are
+// the non-empty runs, in octant order.  The lanes of a cell are consecutive
+// lanes of one wave.
+__device__ inline int octant_end(const uint64_t *keys, int s, int end, int o, int lchild, int KL) {
+    int a = s, b = end;
+    while (a < b) {
+        const int mid = (a + b) >> 1;
+        if (octant_at(keys[mid], lchild, KL) <= o) a = mid + 1; else b = mid;
+    }
+    return a;
+}
+
 __global__ __launch_bounds__(TPB) void k_count_children(int c0, int c1, int lvl, int ncrit, int KL, const int *start,
                                                         const int *count, const uint64_t *keys, int *nchild,
                                                         Bounds *res) {
-    const int cell = c0 + blockIdx.x * TPB + threadIdx.x;
-    if (cell >= c1) return;
-    const int s = start[cell], cnt = count[cell];
-    int nc = 0;
+    const int g = blockIdx.x * TPB + threadIdx.x;
+    const int cell = c0 + g / 8, o = g % 8;
+    const bool valid = cell < c1;
+    const int s = valid ? start[cell] : 0, cnt = valid ? count[cell] : 0;
     // keys resolve no finer than level KL: such a leaf keeps all its particles
     // (coincident or nearly coincident ones), which the near field handles
-    if (cnt > ncrit && lvl >= KL) atomicAdd(&res->overfull, 1);
-    if (cnt > ncrit && lvl < KL) {
-        // octants are non-decreasing along the range: count distinct values
-        int lo = s;
-        const int end = s + cnt;
-        while (lo < end) {
-            const int o = octant_at(keys[lo], lvl + 1, KL);
-            // first index with octant > o
-            int a = lo, b = end;
-            while (a < b) {
-                const int mid = (a + b) >> 1;
-                if (octant_at(keys[mid], lvl + 1, KL) <= o) a = mid + 1; else b = mid;
-            }
-            ++nc;
-            lo = a;
-        }
-    }
-    nchild[cell - c0] = nc;
+    if (valid && o == 0 && cnt > ncrit && lvl >= KL) atomicAdd(&res->overfull, 1);
+    const bool split = valid && cnt > ncrit && lvl < KL;
+    const int e = split ? octant_end(keys, s, s + cnt, o, lvl + 1, KL) : s;
+    const int prev = __shfl_up(e, 1, 8);
+    const bool nonempty = split && e > (o == 0 ? s : prev);
+    const unsigned long long bal = __ballot(nonempty);
+    const int sh = (threadIdx.x & 63) & ~7;
+    if (valid && o == 0) nchild[cell - c0] = __popcll((bal >> sh) & 0xffull);
 }
 
 __global__ __launch_bounds__(TPB) void k_make_children(int c0, int c1, int lvl, int cnext, int KL, const int *start,
                                                        const int *count, const uint64_t *keys, const int *choff,
                                                        const int *nchild_l, int *c_start, int *c_count,
                                                        int *c_parent, int *c_child, int *c_nchild, int *c_level) {
-    const int cell = c0 + blockIdx.x * TPB + threadIdx.x;
-    if (cell >= c1) return;
-    const int nc = nchild_l[cell - c0];
-    c_nchild[cell] = nc;
-    if (nc == 0) { c_child[cell] = -1; return; }
-    const int first = cnext + choff[cell - c0];
-    c_child[cell] = first;
-    const int s = start[cell], end = s + count[cell];
-    int lo = s, k = 0;
-    while (lo < end) {
-        const int o = octant_at(keys[lo], lvl + 1, KL);
-        int a = lo, b = end;
-        while (a < b) {
-            const int mid = (a + b) >> 1;
-            if (octant_at(keys[mid], lvl + 1, KL) <= o) a = mid + 1; else b = mid;
-        }
-        const int ch = first + k;
+    const int g = blockIdx.x * TPB + threadIdx.x;
+    const int cell = c0 + g / 8, o = g % 8;
+    const bool valid = cell < c1;
+    const int nc = valid ? nchild_l[cell - c0] : 0;
+    const int s = valid ? start[cell] : 0, end = valid ? s + count[cell] : 0;
+    const int e = nc > 0 ? octant_end(keys, s, end, o, lvl + 1, KL) : s;
+    const int prev = __shfl_up(e, 1, 8);
+    const int lo = o == 0 ? s : prev;
+    const bool nonempty = nc > 0 && e > lo;
+    const unsigned long long bal = __ballot(nonempty);
+    const int sh = (threadIdx.x & 63) & ~7;
+    const int first = valid ? cnext + choff[cell - c0] : 0;
+    if (valid && o == 0) {
+        c_nchild[cell] = nc;
+        c_child[cell] = nc == 0 ? -1 : first;
+    }
+    if (nonempty) {
+        const int ch = first + __popcll((bal >> sh) & ((1ull << o) - 1));  // non-empty octants before o
         c_start[ch] = lo;
-        c_count[ch] = a - lo;
+        c_count[ch] = e - lo;
         c_parent[ch] = cell;
         c_level[ch] = lvl + 1;
-        ++k;
-        lo = a;
     }
 }
 
@@ -783,7 +786,7 @@ void build_tree(Ctx &c, int64_t n, const float *x, const float *y, const float *
         c.c_tmp.ensure(sizeof(int) * (2 * (size_t)nl + 2));
         int *nch = c.c_tmp.as<int>();
         int *off = nch + nl + 1;
-        k_count_children<<<cdiv(nl, TPB), TPB, 0, s>>>(c0, c1, lvl, c.prm.ncrit, KL, c.c_start.as<int>(),
+        k_count_children<<<cdiv(8 * (int64_t)nl, TPB), TPB, 0, s>>>(c0, c1, lvl, c.prm.ncrit, KL, c.c_start.as<int>(),
                                                         c.c_count.as<int>(), keys, nch, c.bres.as<Bounds>());
         VFMM_LAUNCH_CHECK();
         scan_excl_i32(c, nch, off, nl);
@@ -796,7 +799,7 @@ void build_tree(Ctx &c, int64_t n, const float *x, const float *y, const float *
             for (DevBuf *b : arrs) grow_keep(c, *b, sizeof(int) * ncap, sizeof(int) * (size_t)c1);
             cap = ncap;
         }
-        k_make_children<<<cdiv(nl, TPB), TPB, 0, s>>>(c0, c1, lvl, c1, KL, c.c_start.as<int>(), c.c_count.as<int>(),
+        k_make_children<<<cdiv(8 * (int64_t)nl, TPB), TPB, 0, s>>>(c0, c1, lvl, c1, KL, c.c_start.as<int>(), c.c_count.as<int>(),
                                                        keys, off, nch, c.c_start.as<int>(), c.c_count.as<int>(),
                                                        c.c_parent.as<int>(), c.c_child.as<int>(),
                                                        c.c_nchild.as<int>(), c.c_level.as<int>());
