@@ -16,7 +16,7 @@ void Ctx::release_all() {
                       &c_tmp, &leaves, &frA, &frB, &tcnt, &m2l_raw, &p2p_raw, &lkey, &lkey2, &lval, &lval2,
                       &m2l_off, &m2l_src, &p2p_off, &p2p_ent, &p2p_sh, &recp, &tgt, &c_nsrc, &part, &blocks, &pairs64, &Mexp, &Lexp, &lat_op, &far_u,
                       &far_da, &near, &dsurf, &rk, &m2l_tgt, &mb_eq, &mb_flag, &mb_pos, &mb_kid, &mb_ukey,
-                      &mb_tab, &mb_bcells, &mb_ent, &mb_groups, &mb_blk, &mb_items, &mb_mr, &mb_partial, &mb_cls, &mb_cellbs, &mb_gcnt, &mb_gid, &mb_goff, &mb_gcur, &mb_bkt, &mb_order, &mb_slots, &pid, &pbox, &poff, &tune_ref, &tune_out, &tune_part, &rbf, &spec};
+                      &mb_tab, &mb_bcells, &mb_ent, &mb_groups, &mb_blk, &mb_items, &mb_mr, &mb_partial, &mb_cls, &mb_cellbs, &mb_gcnt, &mb_gid, &mb_goff, &mb_gcur, &mb_bkt, &mb_order, &mb_slots, &gpart, &pid, &pbox, &poff, &tune_ref, &tune_out, &tune_part, &rbf, &spec};
     for (DevBuf *b : bufs) b->release();
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);

@@ -62,6 +62,7 @@ struct Ctx {
     DevBuf p2p_sh;                       // float4 per P2P entry: scaled offset between the two leaf centres
     DevBuf blocks;                       // int4 (tgt start, tgt count, list off, list count)
     DevBuf pairs64;                      // int64 reduction scratch
+    DevBuf gpart;                        // per-work-group partial pair counts of the P2P list
     // expansions
     DevBuf Mexp, Lexp;                   // float2 [ncells][3][NC(p)]
     DevBuf lat_op;                       // float [2NC x 2NC] periodic lattice operator

@@ -184,7 +184,7 @@ struct P2PEntryArgs {
 // 2 = cutoff equal to 1 in float32 for every pair (singular kernel).  The
 // float32 near field also gets the scaled offset between the leaf centres.
 __global__ __launch_bounds__(TPB) void k_p2p_gather(P2PEntryArgs A, const int4 *raw, const uint32_t *order,
-                                                    int64_t n, int4 *out, unsigned long long *pairs) {
+                                                    int64_t n, int4 *out, unsigned long long *part) {
     const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
     unsigned long long np = 0;
     if (i < n) {
@@ -227,7 +227,21 @@ __global__ __launch_bounds__(TPB) void k_p2p_gather(P2PEntryArgs A, const int4 *
         if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0 && sh[0]) atomicAdd(pairs, sh[0]);
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];  // summed by k_sum_u64 (no contended atomics)
+}
+
+// total of n unsigned 64-bit partial counts (one work-group)
+__global__ __launch_bounds__(TPB) void k_sum_u64(const unsigned long long *part, int n, unsigned long long *out) {
+    __shared__ unsigned long long sh[TPB];
+    unsigned long long v = 0;
+    for (int i = threadIdx.x; i < n; i += TPB) v += part[i];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = TPB / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
 }
 
 __global__ __launch_bounds__(TPB) void k_block_counts(const int *leaves, int nl, const int *count, int *nb) {
@@ -385,9 +399,12 @@ void traverse_and_lists(Ctx &c) {
         E.len64 = c.prm.periodic ? c.prm.box_len : 0.0;
         E.nsrc = c.n_src_part >= 0 && c.n_src_part < c.n ? c.c_nsrc.as<int>() : nullptr;
         E.sh = f32 ? c.p2p_sh.as<float4>() : nullptr;
-        k_p2p_gather<<<cdiv(n_p2p, TPB), TPB, 0, s>>>(E, c.p2p_raw.as<int4>(), c.lval.as<uint32_t>(), n_p2p,
-                                                       c.p2p_ent.as<int4>(),
-                                                       c.pairs64.as<unsigned long long>());
+        const int ngb = (int)cdiv(n_p2p, TPB);
+        c.gpart.ensure(sizeof(unsigned long long) * (size_t)ngb);
+        k_p2p_gather<<<ngb, TPB, 0, s>>>(E, c.p2p_raw.as<int4>(), c.lval.as<uint32_t>(), n_p2p, c.p2p_ent.as<int4>(),
+                                         c.gpart.as<unsigned long long>());
+        VFMM_LAUNCH_CHECK();
+        k_sum_u64<<<1, TPB, 0, s>>>(c.gpart.as<unsigned long long>(), ngb, c.pairs64.as<unsigned long long>());
         VFMM_LAUNCH_CHECK();
     }
     // ---- P2P work blocks (<= 64 targets each) ----
