@@ -36,6 +36,8 @@ void Ctx::release_all() {
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     ev_fork = ev_join = nullptr;
+    if (hpin) (void)hipHostFree(hpin);
+    hpin = nullptr;
 }
 
 static bool supported_p(int p) { return p == 4 || p == 6 || p == 8 || p == 10 || p == 12; }

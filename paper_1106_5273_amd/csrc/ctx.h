@@ -1,5 +1,6 @@
 // Library context: parameters, device buffers and host-side sizes.
 #pragma once
+#include <initializer_list>
 
 #include "common.h"
 
@@ -63,6 +64,7 @@ struct Ctx {
     DevBuf blocks;                       // int4 (tgt start, tgt count, list off, list count)
     DevBuf pairs64;                      // int64 reduction scratch
     DevBuf gpart;                        // per-work-group partial pair counts of the P2P list
+    int *hpin = nullptr;                 // pinned host ints written by k_read_ints (read_ints)
     // expansions
     DevBuf Mexp, Lexp;                   // float2 [ncells][3][NC(p)]
     DevBuf lat_op;                       // float [2NC x 2NC] periodic lattice operator
@@ -153,6 +155,10 @@ void p2p_prepare(Ctx &c);
 void p2p_near(Ctx &c, hipStream_t s);
 void finalize_near_far(Ctx &c, float *ux, float *uy, float *uz, float *dax, float *day, float *daz);
 void scan_excl_i32(Ctx &c, const int *in, int *out, int64_t n);  // out may alias in
+// Reads up to four device ints (one each at the given device addresses) into
+// dst: one small kernel writes them to pinned host memory, then the library
+// stream is synchronised (no copy engine or staging blit per value).
+void read_ints(Ctx &c, std::initializer_list<const int *> src, int *dst);
 // traverse.hip
 void traverse_and_lists(Ctx &c);
 // far.hip

@@ -961,9 +961,7 @@ static void m2lb_plan_p(Ctx &c) {
         k_key_mark<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.mb_eq.as<int4>(), f, tab);
         VFMM_LAUNCH_CHECK();
         scan_excl_i32(c, tab, tpos, tsz);
-        VFMM_HIP(hipMemcpyAsync(&h2[0], tpos + tsz - 1, 4, hipMemcpyDeviceToHost, s));
-        VFMM_HIP(hipMemcpyAsync(&h2[1], tab + tsz - 1, 4, hipMemcpyDeviceToHost, s));
-        VFMM_HIP(hipStreamSynchronize(s));
+        read_ints(c, {tpos + tsz - 1, tab + tsz - 1}, h2);
         nkeys = h2[0] + h2[1];
         c.mb_kid.ensure(sizeof(int) * n);
         c.mb_ukey.ensure(sizeof(uint64_t) * nkeys);
@@ -983,9 +981,7 @@ static void m2lb_plan_p(Ctx &c) {
         k_flag_changes<<<cdiv(n, TPB), TPB, 0, s>>>(n, c.lkey.as<uint64_t>(), flag);
         VFMM_LAUNCH_CHECK();
         scan_excl_i32(c, flag, pos, n);
-        VFMM_HIP(hipMemcpyAsync(&h2[0], pos + n - 1, 4, hipMemcpyDeviceToHost, s));
-        VFMM_HIP(hipMemcpyAsync(&h2[1], flag + n - 1, 4, hipMemcpyDeviceToHost, s));
-        VFMM_HIP(hipStreamSynchronize(s));
+        read_ints(c, {pos + n - 1, flag + n - 1}, h2);
         nkeys = h2[0] + h2[1];
         c.mb_kid.ensure(sizeof(int) * n);
         c.mb_ukey.ensure(sizeof(uint64_t) * nkeys);
@@ -1056,9 +1052,7 @@ static void m2lb_plan_p(Ctx &c) {
     k_gk_flags<<<cdiv(T, TPB), TPB, 0, s>>>(T, gcnt, gcur);  // flags, then reused as cursors
     VFMM_LAUNCH_CHECK();
     scan_excl_i32(c, gcur, gid, T);
-    VFMM_HIP(hipMemcpyAsync(&h2[0], gid + T - 1, 4, hipMemcpyDeviceToHost, s));
-    VFMM_HIP(hipMemcpyAsync(&h2[1], gcur + T - 1, 4, hipMemcpyDeviceToHost, s));
-    VFMM_HIP(hipStreamSynchronize(s));
+    read_ints(c, {gid + T - 1, gcur + T - 1}, h2);
     const int ng = h2[0] + h2[1];
     // A group costs a full 64-target operator product whether its targets are
     // all present or not; measured on gfx950 a group costs about as much as
@@ -1089,9 +1083,7 @@ static void m2lb_plan_p(Ctx &c) {
     k_item_flags<<<cdiv(ng, TPB), TPB, 0, s>>>(ng, c.mb_groups.as<int4>(), blk_first, flag);
     VFMM_LAUNCH_CHECK();
     scan_excl_i32(c, flag, pos, ng);
-    VFMM_HIP(hipMemcpyAsync(&h2[0], pos + ng - 1, 4, hipMemcpyDeviceToHost, s));
-    VFMM_HIP(hipMemcpyAsync(&h2[1], flag + ng - 1, 4, hipMemcpyDeviceToHost, s));
-    VFMM_HIP(hipStreamSynchronize(s));
+    read_ints(c, {pos + ng - 1, flag + ng - 1}, h2);
     const int nitems = h2[0] + h2[1];
     c.mb_items.ensure(sizeof(int4) * nitems);
     k_items<<<cdiv(ng, TPB), TPB, 0, s>>>(ng, c.mb_groups.as<int4>(), flag, pos, c.mb_items.as<int4>(), blk_item0,

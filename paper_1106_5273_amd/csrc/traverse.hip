@@ -415,11 +415,11 @@ void traverse_and_lists(Ctx &c) {
     k_block_counts<<<cdiv(nl, TPB), TPB, 0, s>>>(c.leaves.as<int>(), nl, c.c_count.as<int>(), nb);
     VFMM_LAUNCH_CHECK();
     scan_excl_i32(c, nb, boff, nl);
-    VFMM_HIP(hipMemcpyAsync(&h_tot[0], boff + nl - 1, sizeof(int), hipMemcpyDeviceToHost, s));
-    VFMM_HIP(hipMemcpyAsync(&h_tot[1], nb + nl - 1, sizeof(int), hipMemcpyDeviceToHost, s));
-    unsigned long long pairs = 0;
-    VFMM_HIP(hipMemcpyAsync(&pairs, c.pairs64.ptr, 8, hipMemcpyDeviceToHost, s));
-    VFMM_HIP(hipStreamSynchronize(s));
+    int h4[4];
+    read_ints(c, {boff + nl - 1, nb + nl - 1, c.pairs64.as<int>(), c.pairs64.as<int>() + 1}, h4);
+    h_tot[0] = h4[0];
+    h_tot[1] = h4[1];
+    const unsigned long long pairs = (unsigned long long)(uint32_t)h4[2] | ((unsigned long long)(uint32_t)h4[3] << 32);
     c.n_blocks = h_tot[0] + h_tot[1];
     c.p2p_pairs = (int64_t)pairs;
     c.blocks.ensure(sizeof(int4) * (size_t)std::max(c.n_blocks, 1));

@@ -154,6 +154,27 @@ void scan_excl_i32(Ctx &c, const int *in, int *out, int64_t n) {
     scan_rec(c.stream, in, out, n, c.scanC.as<int>());
 }
 
+struct IntPtrs {
+    const int *p[4];
+};
+
+__global__ __launch_bounds__(64) void k_read_ints(IntPtrs src, int n, int *out) {
+    const int i = threadIdx.x;
+    if (i < n) out[i] = *src.p[i];
+}
+
+void read_ints(Ctx &c, std::initializer_list<const int *> src, int *dst) {
+    if (src.size() == 0 || src.size() > 4) throw Error{VFMM_EINVAL, "read_ints: one to four values"};
+    if (!c.hpin) VFMM_HIP(hipHostMalloc((void **)&c.hpin, 64 * sizeof(int), hipHostMallocCoherent));
+    IntPtrs a{};
+    int n = 0;
+    for (const int *p : src) a.p[n++] = p;
+    k_read_ints<<<1, 64, 0, c.stream>>>(a, n, c.hpin);
+    VFMM_LAUNCH_CHECK();
+    VFMM_HIP(hipStreamSynchronize(c.stream));
+    for (int i = 0; i < n; ++i) dst[i] = c.hpin[i];
+}
+
 // ---------------------------------------------------------------------------
 // Bounds: min/max of positions, min/max core, float64 sums of alpha and of
 // (x - ref) x alpha, non-finite and out-of-cube counts.  Deterministic two
@@ -790,9 +811,7 @@ void build_tree(Ctx &c, int64_t n, const float *x, const float *y, const float *
                                                         c.c_count.as<int>(), keys, nch, c.bres.as<Bounds>());
         VFMM_LAUNCH_CHECK();
         scan_excl_i32(c, nch, off, nl);
-        VFMM_HIP(hipMemcpyAsync(&h_tot[0], off + nl - 1, sizeof(int), hipMemcpyDeviceToHost, s));
-        VFMM_HIP(hipMemcpyAsync(&h_tot[1], nch + nl - 1, sizeof(int), hipMemcpyDeviceToHost, s));
-        VFMM_HIP(hipStreamSynchronize(s));
+        read_ints(c, {off + nl - 1, nch + nl - 1}, h_tot);
         const int total = h_tot[0] + h_tot[1];
         if ((size_t)(c1 + total) > cap) {
             const size_t ncap = (size_t)(c1 + total) * 2;
@@ -836,11 +855,11 @@ void build_tree(Ctx &c, int64_t n, const float *x, const float *y, const float *
     k_leaf_flags<<<cdiv(nc, TPB), TPB, 0, s>>>(nc, c.c_nchild.as<int>(), flag);
     VFMM_LAUNCH_CHECK();
     scan_excl_i32(c, flag, pos, nc);
-    VFMM_HIP(hipMemcpyAsync(&h_tot[0], pos + nc - 1, sizeof(int), hipMemcpyDeviceToHost, s));
-    VFMM_HIP(hipMemcpyAsync(&h_tot[1], flag + nc - 1, sizeof(int), hipMemcpyDeviceToHost, s));
-    int h_ovf = 0;
-    VFMM_HIP(hipMemcpyAsync(&h_ovf, &c.bres.as<Bounds>()->overfull, sizeof(int), hipMemcpyDeviceToHost, s));
-    VFMM_HIP(hipStreamSynchronize(s));
+    int h3[3];
+    read_ints(c, {pos + nc - 1, flag + nc - 1, &c.bres.as<Bounds>()->overfull}, h3);
+    h_tot[0] = h3[0];
+    h_tot[1] = h3[1];
+    const int h_ovf = h3[2];
     c.nleaves = h_tot[0] + h_tot[1];
     c.overfull_leaves = h_ovf;
     c.leaves.ensure(sizeof(int) * (size_t)c.nleaves);
