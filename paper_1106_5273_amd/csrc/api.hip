@@ -152,8 +152,8 @@ static void do_build(Ctx &c, int64_t n, const float *x, const float *y, const fl
         return;
     }
     compute_bounds(c, n, x, y, z, sigma, nullptr, nullptr, nullptr, false);
-    VFMM_HIP(hipMemcpyAsync(&c.hb, c.bres.ptr, sizeof(Bounds), hipMemcpyDeviceToHost, s));
-    VFMM_HIP(hipStreamSynchronize(s));
+    static_assert(sizeof(Bounds) % sizeof(int) == 0 && sizeof(Bounds) <= 256, "Bounds read through read_words");
+    read_words(c, c.bres.ptr, sizeof(Bounds), &c.hb);
     c.build_fp = c.hb.fp;
     c.build_ptr[0] = x;
     c.build_ptr[1] = y;

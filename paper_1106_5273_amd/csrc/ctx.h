@@ -159,6 +159,12 @@ void scan_excl_i32(Ctx &c, const int *in, int *out, int64_t n);  // out may alia
 // dst: one small kernel writes them to pinned host memory, then the library
 // stream is synchronised (no copy engine or staging blit per value).
 void read_ints(Ctx &c, std::initializer_list<const int *> src, int *dst);
+// The pinned host ints (64) that a kernel may write directly, and the
+// synchronisation that hands their first n values to the host.
+int *pinned_ints(Ctx &c);
+void sync_ints(Ctx &c, int n, int *dst);
+// The same for a small device struct (at most 256 bytes, whole 4-byte words).
+void read_words(Ctx &c, const void *src, size_t bytes, void *dst);
 // traverse.hip
 void traverse_and_lists(Ctx &c);
 // far.hip

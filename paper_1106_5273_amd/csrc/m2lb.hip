@@ -940,8 +940,7 @@ static void m2lb_plan_p(Ctx &c) {
                                                  c.pairs64.as<int>());
     VFMM_LAUNCH_CHECK();
     int rng[2];
-    VFMM_HIP(hipMemcpyAsync(rng, c.pairs64.ptr, 8, hipMemcpyDeviceToHost, s));
-    VFMM_HIP(hipStreamSynchronize(s));
+    read_ints(c, {c.pairs64.as<int>(), c.pairs64.as<int>() + 1}, rng);
     KeyFmt f{};
     f.bq = bits_for_range(rng[0]);
     f.bdl = bits_for_range(rng[1]);
@@ -1018,8 +1017,7 @@ static void m2lb_plan_p(Ctx &c) {
     k_bucket_blocks<<<1, 1024, 0, s>>>(bstart, bend, boff, dnblk);
     VFMM_LAUNCH_CHECK();
     int nblk = 0;
-    VFMM_HIP(hipMemcpyAsync(&nblk, dnblk, sizeof(int), hipMemcpyDeviceToHost, s));
-    VFMM_HIP(hipStreamSynchronize(s));
+    read_ints(c, {dnblk}, &nblk);
     c.mb_nblk = nblk;
     c.mb_bcells.ensure(sizeof(int) * 64 * (size_t)nblk);
     c.mb_cellbs.ensure(sizeof(int2) * (size_t)nc);

@@ -345,11 +345,9 @@ void traverse_and_lists(Ctx &c) {
         k_trav_count<<<cdiv(nf, TPB), TPB, 0, s>>>(A, c.frA.as<int4>(), nf, split, cnt);
         VFMM_LAUNCH_CHECK();
         scan_excl_i32(c, cnt, off, 3LL * nf);
-        c.pairs64.ensure(64);
-        k_trav_totals<<<1, 1, 0, s>>>(cnt, off, nf, c.pairs64.as<int>());
+        k_trav_totals<<<1, 1, 0, s>>>(cnt, off, nf, pinned_ints(c));  // straight to pinned host memory
         VFMM_LAUNCH_CHECK();
-        VFMM_HIP(hipMemcpyAsync(h_tot, c.pairs64.ptr, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
-        VFMM_HIP(hipStreamSynchronize(s));
+        sync_ints(c, 3, h_tot);
         const int tm = h_tot[0], tp = h_tot[1], tn = h_tot[2];
         // list positions and frontier counts are 32-bit on the device: refuse before the
         // write pass rather than let an offset wrap (a pair emits at most 8 of each, so

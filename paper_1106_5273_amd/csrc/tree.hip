@@ -4,6 +4,8 @@
 // key; at most 21 levels).
 #include "ctx.h"
 
+#include <cstring>
+
 namespace vfmm {
 
 static constexpr int TPB = 256;
@@ -163,16 +165,40 @@ __global__ __launch_bounds__(64) void k_read_ints(IntPtrs src, int n, int *out) 
     if (i < n) out[i] = *src.p[i];
 }
 
+int *pinned_ints(Ctx &c) {
+    if (!c.hpin) VFMM_HIP(hipHostMalloc((void **)&c.hpin, 64 * sizeof(int), hipHostMallocCoherent));
+    return c.hpin;
+}
+
+void sync_ints(Ctx &c, int n, int *dst) {
+    VFMM_HIP(hipStreamSynchronize(c.stream));
+    for (int i = 0; i < n; ++i) dst[i] = c.hpin[i];
+}
+
+__global__ __launch_bounds__(64) void k_copy_words(const int *src, int n, int *out) {
+    const int i = threadIdx.x;
+    if (i < n) out[i] = src[i];
+}
+
+void read_words(Ctx &c, const void *src, size_t bytes, void *dst) {
+    if (bytes == 0 || bytes > 64 * sizeof(int) || bytes % sizeof(int)) throw Error{VFMM_EINVAL, "read_words: size"};
+    const int n = (int)(bytes / sizeof(int));
+    int *hp = pinned_ints(c);
+    k_copy_words<<<1, 64, 0, c.stream>>>(static_cast<const int *>(src), n, hp);
+    VFMM_LAUNCH_CHECK();
+    VFMM_HIP(hipStreamSynchronize(c.stream));
+    std::memcpy(dst, hp, bytes);
+}
+
 void read_ints(Ctx &c, std::initializer_list<const int *> src, int *dst) {
     if (src.size() == 0 || src.size() > 4) throw Error{VFMM_EINVAL, "read_ints: one to four values"};
-    if (!c.hpin) VFMM_HIP(hipHostMalloc((void **)&c.hpin, 64 * sizeof(int), hipHostMallocCoherent));
+    int *hp = pinned_ints(c);
     IntPtrs a{};
     int n = 0;
     for (const int *p : src) a.p[n++] = p;
-    k_read_ints<<<1, 64, 0, c.stream>>>(a, n, c.hpin);
+    k_read_ints<<<1, 64, 0, c.stream>>>(a, n, hp);
     VFMM_LAUNCH_CHECK();
-    VFMM_HIP(hipStreamSynchronize(c.stream));
-    for (int i = 0; i < n; ++i) dst[i] = c.hpin[i];
+    sync_ints(c, n, dst);
 }
 
 // ---------------------------------------------------------------------------
