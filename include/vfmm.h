@@ -30,7 +30,9 @@
  *   boundary.  vfmm_last_error() returns a text description of the last
  *   failure on that context.
  * - The context owns the tree, expansions, interaction lists and scratch space
- *   in device memory.  These only grow; vfmm_destroy frees them.
+ *   in device memory, and 256 bytes of pinned host memory (hipHostMalloc) that
+ *   the build reads its sizes through.  These only grow; vfmm_destroy frees
+ *   them.
  * - A context is not thread safe; calls on one context must not overlap.
  * - Depth.  Morton keys hold 21 bits per axis (Sec. 3.2), so a cell is split
  *   at most 21 times (fewer in a batch, whose keys also carry the problem id).
